@@ -1,0 +1,291 @@
+/*
+ * fp.h -- C-ABI of libfp.so: Monte Carlo frame potentials of random quantum
+ * circuit ensembles on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Liu, Liu, Alexeev, Jiang, "Estimating the randomness of quantum
+ * circuit ensembles up to 50 qubits", arXiv 2205.09900):
+ *   F^(k) = E_{U,V} |Tr(U^dagger V)|^{2k}             (Sec. I.A, frame potential)
+ *   F^(k) ~ (1/N) sum_i |Tr(U_i^dagger V_i)|^{2k}      (Sec. II.A, Monte Carlo)
+ * with every trace an exact tensor-network contraction along the qubit
+ * direction (Sec. II.A, trace as a contraction; Methods A).
+ *
+ * Conventions shared by every call
+ *   - Every call returns int: FP_OK (0) or a negative FP_E* code, and never
+ *     throws.  fp_last_error() gives a thread-local message for the last error.
+ *   - Device pointers are plain HIP device addresses (e.g. torch tensors on
+ *     cuda:N); `stream` is a hipStream_t passed as void* (NULL = null stream).
+ *     Work is asynchronous on `stream` unless the call says otherwise.
+ *   - The caller allocates and frees every buffer it passes.  The library
+ *     keeps no pointer after a call returns, except for work in flight on
+ *     `stream`.  Plans and tuning tables are cached inside the library.
+ *   - Sampling or contracting 0 pairs is a no-op returning FP_OK.
+ *   - Calls are re-entrant for distinct streams and workspaces.
+ *
+ * Qubits: q = 2, an open 1D chain of n qubits (2 <= n <= 64).  A two-qubit
+ * gate on bond b acts on qubits (b, b+1) as a 4x4 complex matrix, row-major,
+ * composite index 2*x_b + x_{b+1} (qubit b is the more significant bit),
+ * rows = outputs, columns = inputs, each complex stored as (re, im).
+ */
+#ifndef FP_H
+#define FP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+  FP_OK = 0,
+  FP_EINVAL = -1,   /* bad argument: NULL pointer, n outside 2..64, depth < 1,
+                       unknown ansatz or precision, num_pairs < 0, k_max outside
+                       1..8, num_pairs == 0 where a mean is asked for, or a
+                       buffer smaller than the call needs                      */
+  FP_ETOOBIG = -2,  /* a boundary tensor exceeds the workspace or the limits  */
+  FP_EDEVICE = -3,  /* a HIP runtime error (text in fp_last_error)            */
+  FP_ENOTIMPL = -4, /* combination not provided by this build                 */
+  FP_ENUMERIC = -5  /* a non-finite trace reached the reduction               */
+};
+
+/* ---- ensembles (Results, Fig. 2) ------------------------------------------ */
+enum {
+  FP_BRICKWORK_HAAR = 0,    /* "parallel random unitaries": layer t = 1..depth acts
+                               on bonds b = t-1 (mod 2); Haar U(4) gates          */
+  FP_LOCAL_RANDOM_HAAR = 1, /* "local random unitaries": depth = steps; each step is
+                               one Haar U(4) gate on a uniformly chosen bond      */
+  FP_HEA_RYRZ_CZ = 2        /* hardware-efficient ansatz: depth = layers; a layer is
+                               RY(theta) then RZ(phi) on every qubit, then CZ on
+                               every bond; theta, phi ~ U(0, 2 pi]                */
+};
+
+/* ---- precisions ------------------------------------------------------------ */
+enum {
+  FP_C128 = 0,  /* float64 gates, complex128 boundary                           */
+  FP_C64 = 1,   /* float32 gates, complex64 boundary, power-of-two rescale per
+                   column with the exponent kept in float64                    */
+  FP_BF16X3 = 2 /* float32 storage; transfer products as three bf16 products
+                   (hi*hi + hi*lo + lo*hi) with float32 accumulation           */
+};
+
+typedef struct {
+  int32_t ansatz;    /* FP_BRICKWORK_HAAR, FP_LOCAL_RANDOM_HAAR, FP_HEA_RYRZ_CZ */
+  int32_t n_qubits;  /* 2..64                                                    */
+  int32_t depth;     /* layers (brickwork, HEA) or steps (local random), >= 1    */
+  int32_t reserved;  /* must be 0                                                */
+} fp_ensemble_t;
+
+typedef struct {
+  int32_t ensemble_index; /* index into the ensemble array of the call          */
+  int32_t precision;      /* FP_C64 or FP_C128                                  */
+  int64_t first_pair;     /* first pair index of the group inside its gate buffer */
+  int64_t num_pairs;      /* pairs in the group                                  */
+} fp_group_t;
+
+/*
+ * fp_gate_bytes_per_pair -- bytes one (U, V) pair occupies in a gate buffer.
+ * Layout of one pair (the pair stride is this value):
+ *   Haar ensembles: [U gates][V gates], each gate 16 complex numbers (Real =
+ *     double for FP_C128, float otherwise) in time order; brickwork gates are
+ *     ordered layer by layer, bonds ascending inside a layer.
+ *   local random: followed by [U bonds][V bonds], one int32 per step.
+ *   HEA: [U angles][V angles], per layer l and qubit q the pair (theta, phi)
+ *     as Real, index ((l * n) + q) * 2.
+ * The total is padded to a multiple of 64 bytes.  Returns 0 for an invalid
+ * ensemble or precision.
+ */
+size_t fp_gate_bytes_per_pair(const fp_ensemble_t* ens, int precision);
+
+/*
+ * fp_sample_gates -- draw num_pairs independent (U, V) pairs of the ensemble
+ * (Results, Fig. 2; Methods B for the Haar gates) into d_gates.
+ * Pair i of the call is global pair first_pair + i.  Every random number
+ * comes from Philox4x32-10 (Salmon et al., SC'11) with
+ *   key = (seed low 32 bits, seed high 32 bits),
+ *   counter = (word, item, pair low 32 bits, pair bits 32..62 | circuit << 31),
+ * circuit 0 = U, 1 = V, so any split of a batch yields identical gates:
+ *   Haar gate g: item g, words 0..15 -> complex Gaussian entry (w/4, w%4) by
+ *     Box-Muller of U53(x0, x1), U53(x2, x3); the gate is the Q factor of the
+ *     QR decomposition with a positive real diagonal in R (Mezzadri 2007).
+ *   local-random step s: item s, words 16, 17, ...: first 32-bit output x with
+ *     x < 2^32 - (2^32 mod (n-1)) gives the bond x mod (n-1).
+ *   HEA layer l, qubit q: item l*n + q, word 0: theta = 2 pi U53(x0, x1),
+ *     phi = 2 pi U53(x2, x3).
+ *   U53(a, b) = ((a >> 5) * 2^26 + (b >> 6) + 1) * 2^-53.
+ * Values are computed in float64 and stored as the precision's Real.
+ * gates_bytes must be >= num_pairs * fp_gate_bytes_per_pair(ens, precision).
+ * Errors: FP_EINVAL, FP_EDEVICE.
+ */
+int fp_sample_gates(const fp_ensemble_t* ens, int64_t num_pairs, uint64_t seed,
+                    uint64_t first_pair, int precision, void* d_gates,
+                    size_t gates_bytes, void* stream);
+
+/*
+ * fp_workspace_bytes -- device workspace fp_contract_trace_batch needs for
+ * num_pairs pairs of this ensemble (plans of local random pairs and
+ * boundaries too large for on-chip memory).  Writes *out_bytes.
+ * Errors: FP_EINVAL, FP_ETOOBIG (a boundary exceeds the library limits).
+ */
+int fp_workspace_bytes(const fp_ensemble_t* ens, int64_t num_pairs, int precision,
+                       size_t* out_bytes);
+
+/*
+ * fp_contract_trace_batch -- Tr(U_i^dagger V_i) for every pair of a gate
+ * buffer laid out as fp_sample_gates writes it (Sec. II.A: the trace as a
+ * tensor contraction, contracted along the qubit direction so that few
+ * indices are exposed; Methods A: cost linear in n, memory exponential in
+ * depth).  The network of W = U^dagger V is swept one qubit column at a time;
+ * the boundary tensor after column j is indexed by the wire segments of qubit
+ * j+1 that connect to both neighbouring bonds, and in FP_C64 it is rescaled
+ * by a power of two after every column with the exponent kept in float64.
+ * d_trace receives 2*num_pairs doubles (re, im of pair i at 2i, 2i+1).
+ * Errors: FP_EINVAL, FP_ETOOBIG (workspace too small or a boundary beyond
+ * the limits; fp_workspace_bytes reports the size), FP_ENOTIMPL, FP_EDEVICE.
+ */
+int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int precision,
+                            const void* d_gates, double* d_trace, void* d_workspace,
+                            size_t workspace_bytes, void* stream);
+
+/*
+ * fp_frame_potential -- the Monte Carlo estimate
+ *   F^(k) = (1/N) sum_i |Tr_i|^{2k},  k = 1..k_max       (Sec. II.A)
+ * and its standard error (sample standard deviation / sqrt(N)) from one
+ * trace array, as the same traces serve every k (Supplementary Figures,
+ * sample sizes).  d_trace: 2*num_pairs doubles on the device.  h_F receives
+ * k_max doubles on the host; h_stderr (k_max doubles) may be NULL.
+ * Accumulation is float64 with a fixed reduction order (bitwise
+ * reproducible).  Synchronises `stream` before returning.
+ * Errors: FP_EINVAL (num_pairs < 1, k_max outside 1..8, NULL), FP_ENUMERIC
+ * (a non-finite trace), FP_EDEVICE.
+ */
+int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max,
+                       double* h_F, double* h_stderr, void* stream);
+
+/* ---- uneven batches ------------------------------------------------------- */
+/*
+ * fp_contract_trace_groups -- contract several groups of pairs with different
+ * ensembles (depths, qubit counts) in one persistent launch.  Group g reads
+ * pairs [first_pair, first_pair + num_pairs) of the buffer d_gates[g]
+ * (laid out for ens[groups[g].ensemble_index] at groups[g].precision) and
+ * writes their traces consecutively into d_trace, in group order.  Work items
+ * are ordered by their planned cost, largest first.  Tile shapes come from
+ * the tuning table (fp_autotune).  d_ws / ws_bytes as for
+ * fp_contract_trace_batch (fp_workspace_bytes_groups gives the size).
+ * Errors: as fp_contract_trace_batch.
+ */
+int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups,
+                              int n_groups, size_t* out_bytes);
+int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups,
+                             int n_groups, const void* const* d_gates, double* d_trace,
+                             void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * fp_autotune -- time the candidate tile shapes of the persistent sweep for
+ * this ensemble and precision on the current device with synthetic gates
+ * drawn by fp_sample_gates, keep the fastest in the library's tuning table,
+ * and write its id to *out_choice.  Synchronous.  Uses d_ws (ws_bytes) as
+ * scratch, which must hold fp_autotune_workspace_bytes bytes.
+ * fp_autotune_table writes the table as text (one line per tuned key) into
+ * buf (capacity cap, NUL-terminated) and fp_autotune_load reads such text.
+ * Errors: FP_EINVAL, FP_EDEVICE.
+ */
+size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision);
+int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_bytes,
+                int* out_choice, void* stream);
+int fp_autotune_table(char* buf, size_t cap);
+int fp_autotune_load(const char* text);
+
+/* ---- plan inspection (host only; no device is touched) ---------------------- */
+/*
+ * fp_plan_info -- plan the sweep of a fixed-topology ensemble (brickwork or
+ * HEA) on the host and report, per column j = 0..n-2, log2 of the boundary
+ * size after the column (out_bits, n-1 entries, may be NULL), and overall
+ * the largest boundary exponent during the sweep (*peak_bits), the number of
+ * complex multiply-adds of one contraction (*macs) and the number of
+ * program operations (*ops).  Any output pointer may be NULL.
+ * Errors: FP_EINVAL, FP_ENOTIMPL (local random ensembles are planned per pair).
+ */
+int fp_plan_info(const fp_ensemble_t* ens, int32_t* out_bits, int32_t* peak_bits,
+                 double* macs, int64_t* ops);
+
+/*
+ * fp_plan_local_random_host -- plan one local random pair from its bond
+ * lists (host arrays of `steps` int32 each) with the same planner the device
+ * runs, and report as fp_plan_info.  Host only.
+ */
+int fp_plan_local_random_host(int n_qubits, int steps, const int32_t* bonds_u,
+                              const int32_t* bonds_v, int32_t* out_bits, int32_t* peak_bits,
+                              double* macs, int64_t* ops);
+
+/*
+ * fp_plan_program_host -- the register program the sweep kernels execute for
+ * one pair of two-qubit-gate circuits with the given bond lists (steps gates
+ * per circuit, time order).  ops receives up to max_ops records of 8 bytes
+ * {uint8 type, uint8 p, uint8 q, uint8 bits; int32 arg}: type 0 = GATE on
+ * register bits (p, q) with merged gate `arg`, 1 = BELL (two new top bits
+ * holding a delta), 2 = TRACE over bits p < q (removed, higher bits move
+ * down), 3 = end of column; `bits` is the register width after the op.
+ * wgates receives (first, count) int32 pairs per merged gate and factors the
+ * factor codes (code < steps: gate `code` of V; otherwise gate
+ * 2*steps-1-code of U, conjugate-transposed), in time order.  *num_ops and
+ * *log2_factor (a factor 2 per qubit no gate touches) are written.  Host only.
+ * Errors: FP_EINVAL (bad bonds or max_ops too small), FP_ETOOBIG.
+ */
+int fp_plan_program_host(int n_qubits, int steps, const int32_t* bonds_u, const int32_t* bonds_v,
+                         void* ops, int64_t max_ops, int32_t* wgates, int32_t* factors,
+                         int64_t* num_ops, int32_t* log2_factor);
+
+/* ---- learned control variate (extension) ------------------------------------ */
+/*
+ * Surrogate network for the control variate: inputs are sin and cos of every
+ * angle of U and V (features = 8 * n * L for the HEA), three hidden layers of
+ * width H with SiLU, one linear output, float32.  Parameters live in one
+ * device buffer `d_params` of fp_mlp_param_count(n_in, H) floats, laid out
+ * as W1 (n_in x H, row-major), b1 (H), W2 (H x H), b2, W3 (H x H), b3, W4 (H),
+ * b4 (1).  The optimiser state d_adam holds 2 * param_count floats (m, v).
+ *
+ * fp_mlp_features: angles of num_pairs HEA pairs (the gate buffer of
+ *   fp_sample_gates, FP_C64 layout) -> d_x (num_pairs x n_in floats).
+ * fp_mlp_forward: d_y[i] = net(d_x[i]) for a batch; d_act may be NULL, or hold
+ *   fp_mlp_act_floats(batch, H) floats to keep the activations for backward.
+ * fp_mlp_backward: gradient of (1/batch) sum_i (y_i - t_i)^2 with respect to
+ *   the parameters into d_grad (param_count floats); *h_loss gets the loss
+ *   (synchronous when h_loss != NULL).
+ * fp_mlp_adam_step: one Adam update (step >= 1, bias-corrected).
+ * Errors: FP_EINVAL, FP_EDEVICE.
+ */
+int64_t fp_mlp_param_count(int n_in, int hidden);
+int64_t fp_mlp_act_floats(int64_t batch, int hidden);
+int fp_mlp_init(int n_in, int hidden, uint64_t seed, float* d_params, void* stream);
+int fp_mlp_features(const fp_ensemble_t* ens, int64_t num_pairs, const void* d_gates,
+                    float* d_x, void* stream);
+int fp_mlp_forward(int n_in, int hidden, int64_t batch, const float* d_params,
+                   const float* d_x, float* d_y, float* d_act, void* stream);
+int fp_mlp_backward(int n_in, int hidden, int64_t batch, const float* d_params,
+                    const float* d_x, const float* d_act, const float* d_target,
+                    float* d_grad, double* h_loss, void* stream);
+int fp_mlp_adam_step(int64_t count, float* d_params, const float* d_grad, float* d_adam,
+                     int step, float lr, float beta1, float beta2, float eps, void* stream);
+
+/*
+ * fp_frame_potential_cv -- control-variate estimate of F^(k):
+ *   F_CV = mean_B(f - c g) + c mean_C(g),  f_i = |Tr_i|^{2k}
+ * over nB exact traces d_trace_B with surrogate values d_g_B, and nC fresh
+ * surrogate values d_g_C; stderr^2 = Var_B(f - c g)/nB + c^2 Var_C(g)/nC.
+ * With c = 0 this is the plain estimator of fp_frame_potential on B.
+ * Synchronises `stream`.  Errors: FP_EINVAL, FP_ENUMERIC, FP_EDEVICE.
+ */
+int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t nB,
+                          const float* d_g_C, int64_t nC, int k, double c, double* h_F,
+                          double* h_stderr, void* stream);
+
+/* ---- misc ---------------------------------------------------------------- */
+const char* fp_last_error(void);
+int fp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FP_H */

@@ -1,0 +1,255 @@
+"""Python binding of libfp.so: frame potentials of random circuit ensembles on MI355X.
+
+Argument marshalling only: every step of the path (sampling, planning of
+local random pairs, contraction, reduction, surrogate network) runs in the
+library's HIP kernels.  Device buffers are torch tensors on a ROCm device;
+PyTorch supplies memory and streams.  The library must be built
+(``python paper_2205_09900_amd/build.py``); importing this package without it
+raises, and there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfp.so")
+
+FP_OK, FP_EINVAL, FP_ETOOBIG, FP_EDEVICE, FP_ENOTIMPL, FP_ENUMERIC = 0, -1, -2, -3, -4, -5
+BRICKWORK, LOCAL_RANDOM, HEA = 0, 1, 2
+C128, C64, BF16X3 = 0, 1, 2
+
+ERROR_NAMES = {FP_EINVAL: "FP_EINVAL", FP_ETOOBIG: "FP_ETOOBIG", FP_EDEVICE: "FP_EDEVICE",
+               FP_ENOTIMPL: "FP_ENOTIMPL", FP_ENUMERIC: "FP_ENUMERIC"}
+
+# Symbols declared in include/fp.h.
+EXPORTS = [
+    "fp_gate_bytes_per_pair", "fp_sample_gates", "fp_workspace_bytes", "fp_contract_trace_batch",
+    "fp_frame_potential", "fp_workspace_bytes_groups", "fp_contract_trace_groups",
+    "fp_autotune_workspace_bytes", "fp_autotune", "fp_autotune_table", "fp_autotune_load",
+    "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
+    "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step",
+    "fp_frame_potential_cv", "fp_last_error", "fp_version",
+]
+
+
+class FPError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Ensemble(ctypes.Structure):
+    _fields_ = [("ansatz", ctypes.c_int32), ("n_qubits", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def __init__(self, ansatz, n_qubits, depth):
+        super().__init__(int(ansatz), int(n_qubits), int(depth), 0)
+
+    def __repr__(self):
+        return f"Ensemble(ansatz={self.ansatz}, n={self.n_qubits}, depth={self.depth})"
+
+
+class Group(ctypes.Structure):
+    _fields_ = [("ensemble_index", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("first_pair", ctypes.c_int64), ("num_pairs", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python paper_2205_09900_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, U64, SZ, D = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                             ctypes.c_size_t, ctypes.c_double)
+    E = ctypes.POINTER(Ensemble)
+    sig = {
+        "fp_gate_bytes_per_pair": (SZ, [E, I]),
+        "fp_sample_gates": (I, [E, I64, U64, U64, I, P, SZ, P]),
+        "fp_workspace_bytes": (I, [E, I64, I, ctypes.POINTER(SZ)]),
+        "fp_contract_trace_batch": (I, [E, I64, I, P, P, P, SZ, P]),
+        "fp_frame_potential": (I, [P, I64, I, P, P, P]),
+        "fp_workspace_bytes_groups": (I, [E, I, ctypes.POINTER(Group), I, ctypes.POINTER(SZ)]),
+        "fp_contract_trace_groups": (I, [E, I, ctypes.POINTER(Group), I, ctypes.POINTER(P), P, P, SZ, P]),
+        "fp_autotune_workspace_bytes": (SZ, [E, I]),
+        "fp_autotune": (I, [E, I, P, SZ, ctypes.POINTER(I), P]),
+        "fp_autotune_table": (I, [ctypes.c_char_p, SZ]),
+        "fp_autotune_load": (I, [ctypes.c_char_p]),
+        "fp_plan_info": (I, [E, P, P, P, P]),
+        "fp_plan_local_random_host": (I, [I, I, P, P, P, P, P, P]),
+        "fp_plan_program_host": (I, [I, I, P, P, P, I64, P, P, P, P]),
+        "fp_mlp_param_count": (I64, [I, I]),
+        "fp_mlp_act_floats": (I64, [I64, I]),
+        "fp_mlp_init": (I, [I, I, U64, P, P]),
+        "fp_mlp_features": (I, [E, I64, P, P, P]),
+        "fp_mlp_forward": (I, [I, I, I64, P, P, P, P, P]),
+        "fp_mlp_backward": (I, [I, I, I64, P, P, P, P, P, P, P]),
+        "fp_mlp_adam_step": (I, [I64, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, P]),
+        "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
+        "fp_last_error": (ctypes.c_char_p, []),
+        "fp_version": (I, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error():
+    return lib.fp_last_error().decode()
+
+
+def _check(rc):
+    if rc != FP_OK:
+        raise FPError(rc, last_error())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("expected a device tensor")
+        return ctypes.c_void_p(t.data_ptr())
+    return t
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ens(e):
+    if isinstance(e, Ensemble):
+        return e
+    return Ensemble(*e)
+
+
+# ---- C-ABI mirrors (same names, argument marshalling only) --------------------
+
+def fp_gate_bytes_per_pair(ens, precision):
+    return int(lib.fp_gate_bytes_per_pair(ctypes.byref(_ens(ens)), int(precision)))
+
+
+def fp_sample_gates(ens, num_pairs, seed, first_pair, precision, d_gates, stream=None):
+    return _check(lib.fp_sample_gates(ctypes.byref(_ens(ens)), int(num_pairs), int(seed), int(first_pair),
+                                      int(precision), _ptr(d_gates), d_gates.numel() * d_gates.element_size(),
+                                      _stream(stream)))
+
+
+def fp_workspace_bytes(ens, num_pairs, precision):
+    out = ctypes.c_size_t(0)
+    _check(lib.fp_workspace_bytes(ctypes.byref(_ens(ens)), int(num_pairs), int(precision), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fp_contract_trace_batch(ens, num_pairs, precision, d_gates, d_trace, d_workspace=None, stream=None):
+    wsb = 0 if d_workspace is None else d_workspace.numel() * d_workspace.element_size()
+    return _check(lib.fp_contract_trace_batch(ctypes.byref(_ens(ens)), int(num_pairs), int(precision),
+                                              _ptr(d_gates), _ptr(d_trace), _ptr(d_workspace), wsb,
+                                              _stream(stream)))
+
+
+def fp_frame_potential(d_trace, num_pairs, k_max, stream=None):
+    f = (ctypes.c_double * k_max)()
+    se = (ctypes.c_double * k_max)()
+    _check(lib.fp_frame_potential(_ptr(d_trace), int(num_pairs), int(k_max), f, se, _stream(stream)))
+    return list(f), list(se)
+
+
+def fp_frame_potential_cv(d_trace_B, d_g_B, nB, d_g_C, nC, k, c, stream=None):
+    f = ctypes.c_double(0)
+    se = ctypes.c_double(0)
+    _check(lib.fp_frame_potential_cv(_ptr(d_trace_B), _ptr(d_g_B), int(nB), _ptr(d_g_C), int(nC), int(k),
+                                     float(c), ctypes.byref(f), ctypes.byref(se), _stream(stream)))
+    return f.value, se.value
+
+
+def fp_plan_info(ens):
+    e = _ens(ens)
+    bits = (ctypes.c_int32 * max(1, e.n_qubits - 1))()
+    peak = ctypes.c_int32(0)
+    macs = ctypes.c_double(0)
+    ops = ctypes.c_int64(0)
+    _check(lib.fp_plan_info(ctypes.byref(e), bits, ctypes.byref(peak), ctypes.byref(macs), ctypes.byref(ops)))
+    return {"bits": list(bits), "peak_bits": peak.value, "macs": macs.value, "ops": ops.value}
+
+
+def fp_plan_local_random_host(n_qubits, bonds_u, bonds_v):
+    import numpy as np
+    bu = np.ascontiguousarray(bonds_u, dtype=np.int32)
+    bv = np.ascontiguousarray(bonds_v, dtype=np.int32)
+    if bu.size != bv.size or bu.size < 1:
+        raise ValueError("U and V need the same, positive number of steps")
+    bits = (ctypes.c_int32 * max(1, n_qubits - 1))()
+    peak = ctypes.c_int32(0)
+    macs = ctypes.c_double(0)
+    ops = ctypes.c_int64(0)
+    _check(lib.fp_plan_local_random_host(int(n_qubits), int(bu.size), bu.ctypes.data_as(ctypes.c_void_p),
+                                         bv.ctypes.data_as(ctypes.c_void_p), bits, ctypes.byref(peak),
+                                         ctypes.byref(macs), ctypes.byref(ops)))
+    return {"bits": list(bits), "peak_bits": peak.value, "macs": macs.value, "ops": ops.value}
+
+
+OP_DTYPE = [("type", "u1"), ("p", "u1"), ("q", "u1"), ("bits", "u1"), ("arg", "<i4")]
+
+
+def fp_plan_program_host(n_qubits, bonds_u, bonds_v):
+    import numpy as np
+    bu = np.ascontiguousarray(bonds_u, dtype=np.int32)
+    bv = np.ascontiguousarray(bonds_v, dtype=np.int32)
+    if bu.size != bv.size or bu.size < 1:
+        raise ValueError("U and V need the same, positive number of steps")
+    s = int(bu.size)
+    max_ops = 10 * s + n_qubits + 8
+    ops = np.zeros(max_ops, dtype=OP_DTYPE)
+    wg = np.zeros((2 * s, 2), dtype=np.int32)
+    fac = np.zeros(2 * s, dtype=np.int32)
+    nops = ctypes.c_int64(0)
+    l2 = ctypes.c_int32(0)
+    v = ctypes.c_void_p
+    _check(lib.fp_plan_program_host(int(n_qubits), s, bu.ctypes.data_as(v), bv.ctypes.data_as(v),
+                                    ops.ctypes.data_as(v), max_ops, wg.ctypes.data_as(v), fac.ctypes.data_as(v),
+                                    ctypes.byref(nops), ctypes.byref(l2)))
+    return ops[: nops.value], wg, fac, l2.value
+
+
+# ---- convenience -------------------------------------------------------------------
+
+def alloc_gates(ens, num_pairs, precision, device="cuda"):
+    nb = fp_gate_bytes_per_pair(ens, precision)
+    if nb == 0:
+        raise FPError(FP_EINVAL, "invalid ensemble or precision")
+    return torch.empty(int(num_pairs) * nb, dtype=torch.uint8, device=device)
+
+
+def sample(ens, num_pairs, seed, first_pair=0, precision=C64, device="cuda", stream=None):
+    g = alloc_gates(ens, num_pairs, precision, device)
+    fp_sample_gates(ens, num_pairs, seed, first_pair, precision, g, stream)
+    return g
+
+
+def workspace(ens, num_pairs, precision, device="cuda"):
+    nb = fp_workspace_bytes(ens, num_pairs, precision)
+    return torch.empty(max(nb, 256), dtype=torch.uint8, device=device)
+
+
+def contract(ens, gates, num_pairs, precision, ws=None, stream=None):
+    """Traces of num_pairs pairs as a complex128 tensor."""
+    tr = torch.empty(2 * int(num_pairs), dtype=torch.float64, device=gates.device)
+    if ws is None:
+        ws = workspace(ens, num_pairs, precision, gates.device)
+    fp_contract_trace_batch(ens, num_pairs, precision, gates, tr, ws, stream)
+    return torch.view_as_complex(tr.view(-1, 2))
+
+
+def frame_potential(traces, k_max, stream=None):
+    t = torch.view_as_real(traces).reshape(-1) if traces.is_complex() else traces
+    return fp_frame_potential(t, t.numel() // 2, k_max, stream)

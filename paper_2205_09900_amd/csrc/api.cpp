@@ -1,0 +1,495 @@
+// C-ABI entry points of libfp.so (declared in include/fp.h): argument
+// checks, plan cache, workspace partitioning and kernel dispatch.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "layout.h"
+#include "plan.h"
+#include "sweep.h"
+#include "tune.h"
+
+namespace fp {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FP_OK;
+  return set_error(FP_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
+
+static int check_ensemble(const fp_ensemble_t* e) {
+  if (!e) return set_error(FP_EINVAL, "ensemble is NULL");
+  if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_HEA_RYRZ_CZ)
+    return set_error(FP_EINVAL, "unknown ansatz %d", e->ansatz);
+  if (e->n_qubits < 2 || e->n_qubits > 64) return set_error(FP_EINVAL, "n_qubits %d outside 2..64", e->n_qubits);
+  if (e->depth < 1) return set_error(FP_EINVAL, "depth %d < 1", e->depth);
+  if (e->reserved != 0) return set_error(FP_EINVAL, "reserved field must be 0");
+  if (e->ansatz == FP_LOCAL_RANDOM_HAAR && e->depth > 100000)
+    return set_error(FP_EINVAL, "depth %d too large", e->depth);
+  if (e->ansatz == FP_BRICKWORK_HAAR && e->depth > 4096) return set_error(FP_EINVAL, "depth %d too large", e->depth);
+  if (e->ansatz == FP_HEA_RYRZ_CZ && e->depth > 64) return set_error(FP_EINVAL, "depth %d too large", e->depth);
+  return FP_OK;
+}
+
+static int check_precision(int p) {
+  if (p < FP_C128 || p > FP_BF16X3) return set_error(FP_EINVAL, "unknown precision %d", p);
+  return FP_OK;
+}
+
+// ---- plans of fixed-topology ensembles (host planner, cached on device) ----
+struct HostPlan {
+  PlanHeader hdr;
+  std::vector<Op> ops;
+  std::vector<int2> wg;
+  std::vector<int32_t> fac;
+  std::vector<int32_t> bits;  // register exponent after each column
+};
+
+static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, HostPlan* out) {
+  std::vector<int32_t> scratch((size_t)plan_scratch_ints(G, n));
+  out->ops.resize((size_t)plan_max_ops(G, n));
+  out->wg.resize(2 * (size_t)G);
+  out->fac.resize(2 * (size_t)G);
+  out->hdr = plan_haar_pair(n, G, bu, bv, scratch.data(), out->ops.data(), out->wg.data(), out->fac.data());
+  if (out->hdr.status != PLAN_OK) {
+    if (out->hdr.status == PLAN_EWIDE)
+      return set_error(FP_ETOOBIG, "boundary wider than %d bits", PLAN_MAX_BITS);
+    return set_error(FP_EINVAL, "planner failed (status %d)", out->hdr.status);
+  }
+  out->ops.resize(out->hdr.num_ops);
+  out->bits.clear();
+  for (const Op& o : out->ops)
+    if (o.type == OP_COLEND) out->bits.push_back(o.bits);
+  return FP_OK;
+}
+
+static int host_plan_brickwork(int n, int depth, HostPlan* out) {
+  const int G = (int)gates_per_circuit(FP_BRICKWORK_HAAR, n, depth);
+  std::vector<int32_t> b(G);
+  for (int g = 0; g < G; ++g) b[g] = brickwork_bond(n, g);
+  return host_plan_pair(n, G, b.data(), b.data(), out);
+}
+
+struct DevPlan {
+  PlanHeader hdr;
+  Op* ops = nullptr;
+  int2* wg = nullptr;
+  int32_t* fac = nullptr;
+  PlanHeader* dhdr = nullptr;
+};
+
+static std::mutex g_plan_mu;
+static std::map<std::tuple<int, int, int>, DevPlan> g_plans;  // (device, n, depth)
+
+static int get_brickwork_plan(int n, int depth, DevPlan* out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto key = std::make_tuple(dev, n, depth);
+  auto it = g_plans.find(key);
+  if (it != g_plans.end()) {
+    *out = it->second;
+    return FP_OK;
+  }
+  HostPlan hp;
+  rc = host_plan_brickwork(n, depth, &hp);
+  if (rc) return rc;
+  DevPlan dp;
+  dp.hdr = hp.hdr;
+  const size_t bo = sizeof(Op) * hp.ops.size(), bw = sizeof(int2) * hp.wg.size(), bf = sizeof(int32_t) * hp.fac.size();
+  rc = check_hip(hipMalloc(&dp.ops, bo + 1), "hipMalloc(plan)");
+  if (!rc) rc = check_hip(hipMalloc(&dp.wg, bw + 1), "hipMalloc(plan)");
+  if (!rc) rc = check_hip(hipMalloc(&dp.fac, bf + 1), "hipMalloc(plan)");
+  if (!rc) rc = check_hip(hipMalloc(&dp.dhdr, sizeof(PlanHeader)), "hipMalloc(plan)");
+  if (!rc) rc = check_hip(hipMemcpy(dp.ops, hp.ops.data(), bo, hipMemcpyHostToDevice), "upload plan");
+  if (!rc) rc = check_hip(hipMemcpy(dp.wg, hp.wg.data(), bw, hipMemcpyHostToDevice), "upload plan");
+  if (!rc) rc = check_hip(hipMemcpy(dp.fac, hp.fac.data(), bf, hipMemcpyHostToDevice), "upload plan");
+  if (!rc) rc = check_hip(hipMemcpy(dp.dhdr, &dp.hdr, sizeof(PlanHeader), hipMemcpyHostToDevice), "upload plan");
+  if (rc) return rc;
+  g_plans[key] = dp;
+  *out = dp;
+  return FP_OK;
+}
+
+// ---- sizes -------------------------------------------------------------------
+static int lds_bits_max(int precision) { return precision == FP_C128 ? 13 : 14; }
+
+// Local random: per-pair plan region.
+struct LrLayout {
+  int64_t hdr, ops, wg, fac, scratch, per_pair;
+};
+
+static LrLayout lr_layout(int n, int G) {
+  LrLayout l;
+  l.hdr = 64;
+  l.ops = pad64(plan_max_ops(G, n) * (int64_t)sizeof(Op));
+  l.wg = pad64(2 * (int64_t)G * (int64_t)sizeof(int2));
+  l.fac = pad64(2 * (int64_t)G * 4);
+  l.scratch = pad64(plan_scratch_ints(G, n) * 4);
+  l.per_pair = l.hdr + l.ops + l.wg + l.fac + l.scratch;
+  return l;
+}
+
+constexpr int LR_SMALL_BITS = 10;  // wave per pair
+constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
+
+static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
+  int64_t per = ((int64_t)1 << bits) * elem;
+  int64_t s = POOL_BUDGET / per;
+  if (s > 512) s = 512;
+  if (s > large_pairs) s = large_pairs;
+  if (s < 1) s = 1;
+  return s;
+}
+
+// predicted largest boundary of a local random batch (bits)
+static int lr_predicted_bits(int n, int S) {
+  int b = (int)(4.0 * S / (n - 1)) + 8;
+  return b > 30 ? 30 : b;
+}
+
+static int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precision, size_t* out) {
+  const int elem = sweep_elem_bytes(precision);
+  if (e->ansatz == FP_HEA_RYRZ_CZ) {
+    *out = 0;
+    return FP_OK;
+  }
+  if (e->ansatz == FP_BRICKWORK_HAAR) {
+    DevPlan dp;
+    HostPlan hp;
+    int rc = host_plan_brickwork(e->n_qubits, e->depth, &hp);
+    if (rc) return rc;
+    (void)dp;
+    if (hp.hdr.peak_bits <= lds_bits_max(precision) || num_pairs == 0) {
+      *out = 0;
+      return FP_OK;
+    }
+    if (hp.hdr.peak_bits > 34) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
+    int64_t slots = slot_count(hp.hdr.peak_bits, elem, num_pairs);
+    *out = (size_t)(256 + slots * ((int64_t)elem << hp.hdr.peak_bits));
+    return FP_OK;
+  }
+  const int G = e->depth;
+  LrLayout l = lr_layout(e->n_qubits, G);
+  const int bits = lr_predicted_bits(e->n_qubits, e->depth);
+  int64_t pool = 0;
+  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * ((int64_t)elem << bits);
+  *out = (size_t)(256 + num_pairs * l.per_pair + pool);
+  return FP_OK;
+}
+
+static int choose_lds_tile(int bits) {
+  if (bits <= 6) return TILE_16x16;
+  if (bits <= 10) return TILE_64x4;
+  if (bits <= 12) return TILE_256x1;
+  return TILE_1024x1;
+}
+
+// LDS bytes of one workgroup for (tile, bits) must stay within 160 KiB.
+static int tile_pairs(int tile) { return tile == TILE_16x16 ? 16 : tile == TILE_64x4 ? 4 : 1; }
+
+static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
+                              double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset,
+                              int tile_override) {
+  DevPlan dp;
+  int rc = get_brickwork_plan(e->n_qubits, e->depth, &dp);
+  if (rc) return rc;
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.gates = (const unsigned char*)gates;
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.G = (int)gates_per_circuit(e->ansatz, e->n_qubits, e->depth);
+  a.ops = dp.ops;
+  a.wgates = dp.wg;
+  a.factors = dp.fac;
+  a.hdr = dp.dhdr;
+  a.trace = trace;
+  a.trace_offset = trace_offset;
+  a.num_pairs = num_pairs;
+  const int peak = dp.hdr.peak_bits;
+  const int elem = sweep_elem_bytes(precision);
+  if (peak <= lds_bits_max(precision)) {
+    int tile = tile_override >= 0 ? tile_override : tune_lookup(e, precision, choose_lds_tile(peak));
+    int cap = peak < 2 ? 2 : peak;
+    if ((int64_t)tile_pairs(tile) * ((int64_t)elem << cap) > 160 * 1024) tile = choose_lds_tile(peak);
+    a.cap_bits = cap;
+    a.min_bits = -1;
+    return launch_sweep_lds(a, precision, tile, s);
+  }
+  // HBM slots
+  const int64_t slots = slot_count(peak, elem, num_pairs);
+  const size_t need = (size_t)(256 + slots * ((int64_t)elem << peak));
+  if (!ws || ws_bytes < need)
+    return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for %d-bit boundaries", need, peak);
+  unsigned long long* counter = (unsigned long long*)ws;
+  rc = check_hip(hipMemsetAsync(counter, 0, 8, s), "memset counter");
+  if (rc) return rc;
+  a.cap_bits = 0;
+  a.min_bits = -1;
+  return launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, s);
+}
+
+static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
+                                 double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
+  const int n = e->n_qubits, G = e->depth;
+  const int elem = sweep_elem_bytes(precision);
+  const LrLayout l = lr_layout(n, G);
+  const size_t plan_bytes = (size_t)(256 + num_pairs * l.per_pair);
+  if (!ws || ws_bytes < plan_bytes)
+    return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", plan_bytes);
+  unsigned char* w = (unsigned char*)ws;
+  int* counters = (int*)w;  // max_peak, num_large, num_failed
+  unsigned long long* hbm_counter = (unsigned long long*)(w + 64);
+  unsigned char* region = w + 256;
+  PlanJob j;
+  memset(&j, 0, sizeof(j));
+  j.gates = (const unsigned char*)gates;
+  j.gate_stride = pair_bytes(e->ansatz, n, G, precision);
+  j.bonds_off = bonds_offset(n, G, precision);
+  j.n = n;
+  j.G = G;
+  j.num_pairs = num_pairs;
+  unsigned char* base = region;
+  j.hdr = (PlanHeader*)base;
+  j.ops = (Op*)(base + num_pairs * l.hdr);
+  j.wgates = (int2*)(base + num_pairs * (l.hdr + l.ops));
+  j.factors = (int32_t*)(base + num_pairs * (l.hdr + l.ops + l.wg));
+  j.scratch = (int32_t*)(base + num_pairs * (l.hdr + l.ops + l.wg + l.fac));
+  j.ops_stride = l.ops / (int64_t)sizeof(Op);
+  j.wg_stride = l.wg / (int64_t)sizeof(int2);
+  j.f_stride = l.fac / 4;
+  j.scratch_stride = l.scratch / 4;
+  j.max_peak = counters;
+  j.num_large = counters + 1;
+  j.num_failed = counters + 2;
+  j.cap_bits = lds_bits_max(precision);
+  int rc = check_hip(hipMemsetAsync(w, 0, 256, s), "memset counters");
+  if (rc) return rc;
+  rc = launch_plan_local_random(j, s);
+  if (rc) return rc;
+  int host[3];
+  rc = check_hip(hipMemcpyAsync(host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
+  if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
+  if (rc) return rc;
+  const int max_peak = host[0], num_large = host[1], num_failed = host[2];
+  SweepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.gates = j.gates;
+  a.gate_stride = j.gate_stride;
+  a.G = G;
+  a.ops = j.ops;
+  a.ops_stride = j.ops_stride;
+  a.wgates = j.wgates;
+  a.wg_stride = j.wg_stride;
+  a.factors = j.factors;
+  a.f_stride = j.f_stride;
+  a.hdr = j.hdr;
+  a.hdr_stride = l.hdr / (int64_t)sizeof(PlanHeader);
+  a.trace = trace;
+  a.trace_offset = trace_offset;
+  a.num_pairs = num_pairs;
+  // class A: wave per pair, class B: workgroup per pair, class C: HBM slots
+  a.min_bits = -1;
+  a.cap_bits = LR_SMALL_BITS < lds_bits_max(precision) ? LR_SMALL_BITS : lds_bits_max(precision);
+  rc = launch_sweep_lds(a, precision, TILE_64x4, s);
+  if (rc) return rc;
+  if (max_peak > a.cap_bits) {
+    a.min_bits = a.cap_bits;
+    a.cap_bits = lds_bits_max(precision);
+    rc = launch_sweep_lds(a, precision, TILE_1024x1, s);
+    if (rc) return rc;
+  }
+  if (num_large > 0) {
+    if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
+    const int64_t slots = slot_count(max_peak, elem, num_large);
+    const size_t need = plan_bytes + (size_t)(slots * ((int64_t)elem << max_peak));
+    if (ws_bytes < need)
+      return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)", need, max_peak);
+    rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, s), "memset counter");
+    if (rc) return rc;
+    a.min_bits = -1;
+    a.cap_bits = lds_bits_max(precision);
+    rc = launch_sweep_hbm(a, precision, hbm_counter, w + plan_bytes, max_peak, (int)slots, s);
+    if (rc) return rc;
+  }
+  if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
+  return FP_OK;
+}
+
+static int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+                        hipStream_t s, int64_t trace_offset, int tile_override) {
+  HeaArgs a;
+  a.gates = (const unsigned char*)gates;
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.n = e->n_qubits;
+  a.L = e->depth;
+  a.trace = trace;
+  a.trace_offset = trace_offset;
+  a.num_pairs = num_pairs;
+  const int m = hea_bits(e->depth);
+  if (m > lds_bits_max(precision)) return set_error(FP_ETOOBIG, "HEA boundary of %d bits exceeds LDS", m);
+  int def = m <= 6 ? TILE_16x16 : m <= 10 ? TILE_64x4 : m <= 12 ? TILE_256x1 : TILE_1024x1;
+  int tile = tile_override >= 0 ? tile_override : tune_lookup(e, precision, def);
+  const size_t elem = precision == FP_C128 ? 16 : 8;
+  if ((size_t)tile_pairs(tile) * (elem << m) > 140 * 1024) tile = def;
+  return launch_hea(a, precision, tile, s);
+}
+
+int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+                      void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset, int tile_override) {
+  if (precision == FP_BF16X3) return set_error(FP_ENOTIMPL, "BF16x3 transfer products are not built");
+  if (e->ansatz == FP_BRICKWORK_HAAR)
+    return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset, tile_override);
+  if (e->ansatz == FP_LOCAL_RANDOM_HAAR)
+    return contract_local_random(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset);
+  return contract_hea(e, num_pairs, precision, gates, trace, s, trace_offset, tile_override);
+}
+
+}  // namespace fp
+
+using namespace fp;
+
+extern "C" {
+
+const char* fp_last_error(void) { return g_err; }
+int fp_version(void) { return 1; }
+
+size_t fp_gate_bytes_per_pair(const fp_ensemble_t* ens, int precision) {
+  if (check_ensemble(ens) || check_precision(precision)) return 0;
+  return (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+}
+
+int fp_sample_gates(const fp_ensemble_t* ens, int64_t num_pairs, uint64_t seed, uint64_t first_pair, int precision,
+                    void* d_gates, size_t gates_bytes, void* stream) {
+  int rc = check_ensemble(ens);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if (num_pairs < 0) return set_error(FP_EINVAL, "num_pairs < 0");
+  if (num_pairs == 0) return FP_OK;
+  if (!d_gates) return set_error(FP_EINVAL, "d_gates is NULL");
+  const int64_t need = num_pairs * pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+  if ((int64_t)gates_bytes < need) return set_error(FP_EINVAL, "gates_bytes %zu < %lld", gates_bytes, (long long)need);
+  if (first_pair + (uint64_t)num_pairs > (1ull << 62)) return set_error(FP_EINVAL, "pair index beyond 2^62");
+  return launch_sample(ens, num_pairs, seed, first_pair, precision, d_gates, (hipStream_t)stream);
+}
+
+int fp_workspace_bytes(const fp_ensemble_t* ens, int64_t num_pairs, int precision, size_t* out_bytes) {
+  int rc = check_ensemble(ens);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if (!out_bytes) return set_error(FP_EINVAL, "out_bytes is NULL");
+  if (num_pairs < 0) return set_error(FP_EINVAL, "num_pairs < 0");
+  return workspace_bytes_impl(ens, num_pairs, precision, out_bytes);
+}
+
+int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int precision, const void* d_gates,
+                            double* d_trace, void* d_workspace, size_t workspace_bytes, void* stream) {
+  int rc = check_ensemble(ens);
+  if (rc) return rc;
+  if ((rc = check_precision(precision))) return rc;
+  if (num_pairs < 0) return set_error(FP_EINVAL, "num_pairs < 0");
+  if (num_pairs == 0) return FP_OK;
+  if (!d_gates || !d_trace) return set_error(FP_EINVAL, "NULL gates or trace buffer");
+  return contract_dispatch(ens, num_pairs, precision, d_gates, d_trace, d_workspace, workspace_bytes,
+                           (hipStream_t)stream, 0, -1);
+}
+
+int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max, double* h_F, double* h_stderr,
+                       void* stream) {
+  if (!d_trace || !h_F) return set_error(FP_EINVAL, "NULL trace or output");
+  if (num_pairs < 1) return set_error(FP_EINVAL, "num_pairs must be >= 1");
+  if (k_max < 1 || k_max > 8) return set_error(FP_EINVAL, "k_max %d outside 1..8", k_max);
+  return run_frame_potential(d_trace, num_pairs, k_max, h_F, h_stderr, (hipStream_t)stream);
+}
+
+int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t nB, const float* d_g_C, int64_t nC,
+                          int k, double c, double* h_F, double* h_stderr, void* stream) {
+  if (!d_trace_B || !d_g_B || !h_F) return set_error(FP_EINVAL, "NULL argument");
+  if (nB < 1) return set_error(FP_EINVAL, "nB must be >= 1");
+  if (nC < 0 || (nC > 0 && !d_g_C)) return set_error(FP_EINVAL, "bad surrogate set");
+  if (nC == 0 && c != 0.0) return set_error(FP_EINVAL, "c != 0 needs surrogate values");
+  if (k < 1 || k > 8) return set_error(FP_EINVAL, "k %d outside 1..8", k);
+  return run_frame_potential_cv(d_trace_B, d_g_B, nB, d_g_C, nC, k, c, h_F, h_stderr, (hipStream_t)stream);
+}
+
+int fp_plan_info(const fp_ensemble_t* ens, int32_t* out_bits, int32_t* peak_bits, double* macs, int64_t* ops) {
+  int rc = check_ensemble(ens);
+  if (rc) return rc;
+  const int n = ens->n_qubits;
+  if (ens->ansatz == FP_LOCAL_RANDOM_HAAR)
+    return set_error(FP_ENOTIMPL, "local random ensembles are planned per pair");
+  if (ens->ansatz == FP_HEA_RYRZ_CZ) {
+    const int m = hea_bits(ens->depth);
+    if (out_bits)
+      for (int j = 0; j < n - 1; ++j) out_bits[j] = m;
+    if (peak_bits) *peak_bits = m;
+    // complex additions of the transforms + products with f_q, per pair
+    if (macs) *macs = (double)(n - 1) * m * (double)(1ull << m) + (double)n * (double)(1ull << m);
+    if (ops) *ops = n;
+    return FP_OK;
+  }
+  HostPlan hp;
+  rc = host_plan_brickwork(n, ens->depth, &hp);
+  if (rc) return rc;
+  if (out_bits)
+    for (int j = 0; j < n - 1 && j < (int)hp.bits.size(); ++j) out_bits[j] = hp.bits[j];
+  if (peak_bits) *peak_bits = hp.hdr.peak_bits;
+  if (macs) *macs = hp.hdr.macs;
+  if (ops) *ops = hp.hdr.num_ops;
+  return FP_OK;
+}
+
+int fp_plan_local_random_host(int n_qubits, int steps, const int32_t* bonds_u, const int32_t* bonds_v,
+                              int32_t* out_bits, int32_t* peak_bits, double* macs, int64_t* ops) {
+  if (n_qubits < 2 || n_qubits > 64 || steps < 1 || !bonds_u || !bonds_v)
+    return set_error(FP_EINVAL, "bad arguments");
+  HostPlan hp;
+  int rc = host_plan_pair(n_qubits, steps, bonds_u, bonds_v, &hp);
+  if (rc) return rc;
+  if (out_bits)
+    for (int j = 0; j < n_qubits - 1 && j < (int)hp.bits.size(); ++j) out_bits[j] = hp.bits[j];
+  if (peak_bits) *peak_bits = hp.hdr.peak_bits;
+  if (macs) *macs = hp.hdr.macs;
+  if (ops) *ops = hp.hdr.num_ops;
+  return FP_OK;
+}
+
+int fp_plan_program_host(int n_qubits, int steps, const int32_t* bonds_u, const int32_t* bonds_v, void* ops,
+                         int64_t max_ops, int32_t* wgates, int32_t* factors, int64_t* num_ops, int32_t* log2_factor) {
+  if (n_qubits < 2 || n_qubits > 64 || steps < 1 || !bonds_u || !bonds_v || !ops || !wgates || !factors)
+    return set_error(FP_EINVAL, "bad arguments");
+  HostPlan hp;
+  int rc = host_plan_pair(n_qubits, steps, bonds_u, bonds_v, &hp);
+  if (rc) return rc;
+  if ((int64_t)hp.ops.size() > max_ops) return set_error(FP_EINVAL, "max_ops %lld < %zu", (long long)max_ops, hp.ops.size());
+  memcpy(ops, hp.ops.data(), hp.ops.size() * sizeof(Op));
+  for (int k = 0; k < hp.hdr.num_wgates; ++k) {
+    wgates[2 * k] = hp.wg[k].x;
+    wgates[2 * k + 1] = hp.wg[k].y;
+  }
+  memcpy(factors, hp.fac.data(), sizeof(int32_t) * hp.hdr.num_factors);
+  if (num_ops) *num_ops = (int64_t)hp.ops.size();
+  if (log2_factor) *log2_factor = hp.hdr.log2_factor;
+  return FP_OK;
+}
+
+}  // extern "C"

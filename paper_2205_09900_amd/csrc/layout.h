@@ -1,0 +1,46 @@
+// Gate-buffer layout and small shared definitions (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fp.h"
+
+namespace fp {
+
+__host__ __device__ inline int real_bytes(int precision) { return precision == FP_C128 ? 8 : 4; }
+
+// Two-qubit gates per circuit (Haar ensembles).
+__host__ __device__ inline int64_t gates_per_circuit(int ansatz, int n, int depth) {
+  if (ansatz == FP_LOCAL_RANDOM_HAAR) return depth;
+  if (ansatz == FP_BRICKWORK_HAAR) {
+    int64_t even = n / 2, odd = (n - 1) / 2;  // bonds 0,2,.. and 1,3,..
+    return even * ((depth + 1) / 2) + odd * (depth / 2);
+  }
+  return 0;
+}
+
+// Bond of gate g of a brickwork circuit.
+__host__ __device__ inline int brickwork_bond(int n, int g) {
+  const int even = n / 2, odd = (n - 1) / 2, two = even + odd;
+  const int blk = g / two, r = g % two;
+  (void)blk;
+  return r < even ? 2 * r : 2 * (r - even) + 1;
+}
+
+__host__ __device__ inline int64_t pad64(int64_t x) { return (x + 63) & ~(int64_t)63; }
+
+__host__ __device__ inline int64_t pair_bytes(int ansatz, int n, int depth, int precision) {
+  const int64_t rb = real_bytes(precision);
+  if (ansatz == FP_HEA_RYRZ_CZ) return pad64(2 * (int64_t)depth * n * 2 * rb);
+  const int64_t G = gates_per_circuit(ansatz, n, depth);
+  int64_t b = 2 * G * 32 * rb;
+  if (ansatz == FP_LOCAL_RANDOM_HAAR) b += 2 * G * 4;
+  return pad64(b);
+}
+
+// Byte offset of the bond arrays inside a local random pair.
+__host__ __device__ inline int64_t bonds_offset(int n, int depth, int precision) {
+  return 2 * (int64_t)depth * 32 * real_bytes(precision);
+}
+
+}  // namespace fp

@@ -1,0 +1,284 @@
+// Monte Carlo reduction of traces into frame potentials (Sec. II.A of the
+// paper: F^(k) ~ mean of |Tr|^{2k}; the same traces serve every k).
+//
+// float64 throughout.  Each thread runs Welford's update over a fixed
+// strided subset, workgroups merge by Chan's formula in a fixed tree, and a
+// single workgroup merges the per-workgroup partials in index order, so the
+// result is bitwise reproducible for a given N.  Terms are scaled by 2^-e,
+// with 2^e the largest |Tr|^2 rounded to a power of two, so that |Tr|^{2k}
+// cannot overflow before the final rescale.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace fp {
+
+constexpr int RED_THREADS = 256;
+constexpr int RED_MAX_BLOCKS = 512;
+constexpr int KMAX = 8;
+
+struct Welford {
+  double n, mean, m2;
+};
+
+__device__ __forceinline__ Welford chan_merge(Welford a, Welford b) {
+  Welford r;
+  r.n = a.n + b.n;
+  if (r.n == 0.0) {
+    r.mean = 0.0;
+    r.m2 = 0.0;
+    return r;
+  }
+  const double d = b.mean - a.mean;
+  r.mean = a.mean + d * (b.n / r.n);
+  r.m2 = a.m2 + b.m2 + d * d * (a.n * b.n / r.n);
+  return r;
+}
+
+__device__ __forceinline__ void welford_add(Welford& w, double x) {
+  w.n += 1.0;
+  const double d = x - w.mean;
+  w.mean += d / w.n;
+  w.m2 += d * (x - w.mean);
+}
+
+// Pass 1: per-workgroup max of |Tr|^2 and count of non-finite traces.
+__global__ void __launch_bounds__(RED_THREADS) red_max_kernel(const double* __restrict__ tr, int64_t n,
+                                                              double* __restrict__ part) {
+  __shared__ double smax[RED_THREADS];
+  __shared__ double sbad[RED_THREADS];
+  double m = 0.0, bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * RED_THREADS) {
+    const double re = tr[2 * i], im = tr[2 * i + 1];
+    const double a = re * re + im * im;
+    if (!isfinite(a))
+      bad += 1.0;
+    else
+      m = fmax(m, a);
+  }
+  smax[threadIdx.x] = m;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = smax[0];
+    part[2 * blockIdx.x + 1] = sbad[0];
+  }
+}
+
+// Pass 2 (one workgroup): global max -> scale exponent; bad count.
+__global__ void __launch_bounds__(RED_THREADS) red_max_final(const double* __restrict__ part, int nb,
+                                                             double* __restrict__ scale) {
+  __shared__ double smax[RED_THREADS];
+  __shared__ double sbad[RED_THREADS];
+  double m = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < nb; i += RED_THREADS) {
+    m = fmax(m, part[2 * i]);
+    bad += part[2 * i + 1];
+  }
+  smax[threadIdx.x] = m;
+  sbad[threadIdx.x] = bad;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      sbad[threadIdx.x] += sbad[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int e = 0;
+    if (smax[0] > 0.0) frexp(smax[0], &e);
+    scale[0] = (double)e;  // terms are scaled by 2^-e
+    scale[1] = sbad[0];
+  }
+}
+
+// Pass 3: per-workgroup Welford of (|Tr|^2 2^-e)^k, k = 1..k_max.
+__global__ void __launch_bounds__(RED_THREADS) red_moments_kernel(const double* __restrict__ tr, int64_t n,
+                                                                  int kmax, const double* __restrict__ scale,
+                                                                  Welford* __restrict__ part) {
+  __shared__ Welford sw[RED_THREADS];
+  const int e = (int)scale[0];
+  Welford w[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) w[k] = Welford{0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * RED_THREADS) {
+    const double re = tr[2 * i], im = tr[2 * i + 1];
+    const double a = ldexp(re * re + im * im, -e);
+    double x = 1.0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      if (k < kmax) {
+        x *= a;
+        welford_add(w[k], x);
+      }
+    }
+  }
+  for (int k = 0; k < kmax; ++k) {
+    sw[threadIdx.x] = w[k];
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sw[threadIdx.x] = chan_merge(sw[threadIdx.x], sw[threadIdx.x + s]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * KMAX + k] = sw[0];
+    __syncthreads();
+  }
+}
+
+// Pass 4 (one thread): merge workgroup partials in index order.
+__global__ void red_moments_final(const Welford* __restrict__ part, int nb, int kmax,
+                                  const double* __restrict__ scale, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int e = (int)scale[0];
+  for (int k = 0; k < kmax; ++k) {
+    Welford acc{0.0, 0.0, 0.0};
+    for (int b = 0; b < nb; ++b) acc = chan_merge(acc, part[(int64_t)b * KMAX + k]);
+    const double f = ldexp(acc.mean, e * (k + 1));
+    const double se = acc.n > 1.0 ? ldexp(sqrt(acc.m2 / (acc.n - 1.0) / acc.n), e * (k + 1)) : 0.0;
+    out[2 * k] = f;
+    out[2 * k + 1] = se;
+  }
+  out[2 * KMAX] = scale[1];
+}
+
+static int red_blocks(int64_t n) {
+  int64_t b = (n + RED_THREADS * 4 - 1) / (RED_THREADS * 4);
+  if (b < 1) b = 1;
+  if (b > RED_MAX_BLOCKS) b = RED_MAX_BLOCKS;
+  return (int)b;
+}
+
+int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
+                        hipStream_t s) {
+  const int nb = red_blocks(n);
+  const size_t bytes = sizeof(double) * (2 * (size_t)nb + 2 + 2 * KMAX + 1) + sizeof(Welford) * nb * KMAX;
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, bytes, s), "hipMallocAsync(reduce)");
+  if (rc) return rc;
+  double* part = (double*)ws;
+  double* scale = part + 2 * nb;
+  double* out = scale + 2;
+  Welford* wpart = (Welford*)(out + 2 * KMAX + 1);
+  hipLaunchKernelGGL(red_max_kernel, dim3(nb), dim3(RED_THREADS), 0, s, d_trace, n, part);
+  hipLaunchKernelGGL(red_max_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scale);
+  hipLaunchKernelGGL(red_moments_kernel, dim3(nb), dim3(RED_THREADS), 0, s, d_trace, n, kmax, scale, wpart);
+  hipLaunchKernelGGL(red_moments_final, dim3(1), dim3(64), 0, s, wpart, nb, kmax, scale, out);
+  rc = check_launch("frame_potential");
+  double host[2 * KMAX + 1];
+  if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy F");
+  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(reduce)");
+  int rc3 = check_hip(hipStreamSynchronize(s), "sync(reduce)");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  if (host[2 * KMAX] > 0.0)
+    return set_error(FP_ENUMERIC, "%.0f non-finite trace(s) in the batch", host[2 * KMAX]);
+  for (int k = 0; k < kmax; ++k) {
+    h_F[k] = host[2 * k];
+    if (h_se) h_se[k] = host[2 * k + 1];
+  }
+  return FP_OK;
+}
+
+// ---- control variate ----------------------------------------------------------
+// Welford of r_i = |Tr_i|^{2k} - c g_B[i] over B and of g_C over C.
+__global__ void __launch_bounds__(RED_THREADS) cv_kernel(const double* __restrict__ trB,
+                                                         const float* __restrict__ gB, int64_t nB,
+                                                         const float* __restrict__ gC, int64_t nC, int k,
+                                                         double c, Welford* __restrict__ part,
+                                                         double* __restrict__ badp) {
+  __shared__ Welford sw[RED_THREADS];
+  __shared__ double sbad[RED_THREADS];
+  Welford wr{0.0, 0.0, 0.0}, wg{0.0, 0.0, 0.0};
+  double bad = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nB;
+       i += (int64_t)gridDim.x * RED_THREADS) {
+    const double re = trB[2 * i], im = trB[2 * i + 1];
+    const double a = re * re + im * im;
+    double f = 1.0;
+    for (int j = 0; j < k; ++j) f *= a;
+    const double r = f - c * (double)gB[i];
+    if (!isfinite(r)) bad += 1.0;
+    welford_add(wr, r);
+  }
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < nC;
+       i += (int64_t)gridDim.x * RED_THREADS) {
+    const double g = (double)gC[i];
+    if (!isfinite(g)) bad += 1.0;
+    welford_add(wg, g);
+  }
+  for (int which = 0; which < 2; ++which) {
+    sw[threadIdx.x] = which == 0 ? wr : wg;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        sw[threadIdx.x] = chan_merge(sw[threadIdx.x], sw[threadIdx.x + s]);
+        sbad[threadIdx.x] += sbad[threadIdx.x + s];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      part[2 * blockIdx.x + which] = sw[0];
+      if (which == 0) badp[blockIdx.x] = sbad[0];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void cv_final(const Welford* __restrict__ part, const double* __restrict__ badp, int nb,
+                         double c, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Welford r{0.0, 0.0, 0.0}, g{0.0, 0.0, 0.0};
+  double bad = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    r = chan_merge(r, part[2 * b]);
+    g = chan_merge(g, part[2 * b + 1]);
+    bad += badp[b];
+  }
+  const double est = r.mean + c * g.mean;
+  double var = r.n > 1.0 ? r.m2 / (r.n - 1.0) / r.n : 0.0;
+  if (g.n > 1.0) var += c * c * (g.m2 / (g.n - 1.0) / g.n);
+  out[0] = est;
+  out[1] = sqrt(var);
+  out[2] = bad;
+}
+
+int run_frame_potential_cv(const double* trB, const float* gB, int64_t nB, const float* gC, int64_t nC,
+                           int k, double c, double* h_F, double* h_se, hipStream_t s) {
+  const int nb = red_blocks(nB > nC ? nB : nC);
+  const size_t bytes = sizeof(Welford) * 2 * nb + sizeof(double) * (nb + 3);
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, bytes, s), "hipMallocAsync(cv)");
+  if (rc) return rc;
+  Welford* part = (Welford*)ws;
+  double* badp = (double*)(part + 2 * nb);
+  double* out = badp + nb;
+  hipLaunchKernelGGL(cv_kernel, dim3(nb), dim3(RED_THREADS), 0, s, trB, gB, nB, gC, nC, k, c, part, badp);
+  hipLaunchKernelGGL(cv_final, dim3(1), dim3(64), 0, s, part, badp, nb, c, out);
+  rc = check_launch("frame_potential_cv");
+  double host[3];
+  if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy CV");
+  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(cv)");
+  int rc3 = check_hip(hipStreamSynchronize(s), "sync(cv)");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  if (host[2] > 0.0) return set_error(FP_ENUMERIC, "%.0f non-finite value(s) in the CV inputs", host[2]);
+  *h_F = host[0];
+  if (h_se) *h_se = host[1];
+  return FP_OK;
+}
+
+}  // namespace fp

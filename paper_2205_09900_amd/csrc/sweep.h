@@ -1,0 +1,77 @@
+// Launch descriptors shared between the sweep kernels and the host API.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan.h"
+
+namespace fp {
+
+// Tile shapes of the LDS sweep: lanes per pair x pairs per workgroup.
+enum { TILE_16x16 = 0, TILE_64x4 = 1, TILE_64x1 = 2, TILE_256x1 = 3, TILE_512x1 = 4, TILE_1024x1 = 5,
+       NUM_TILES = 6 };
+
+struct SweepArgs {
+  const unsigned char* gates;
+  int64_t gate_stride;  // bytes per pair
+  int G;                // gates per circuit
+  const Op* ops;
+  int64_t ops_stride;   // per pair (0: one program shared by all pairs)
+  const int2* wgates;
+  int64_t wg_stride;
+  const int32_t* factors;
+  int64_t f_stride;
+  const PlanHeader* hdr;
+  int64_t hdr_stride;
+  double* trace;
+  int64_t trace_offset;
+  int64_t num_pairs;
+  int cap_bits;         // LDS capacity per pair (log2 of complex entries)
+  int min_bits;         // pairs whose peak is <= min_bits belong to another launch
+};
+
+struct PlanJob {
+  const unsigned char* gates;
+  int64_t gate_stride;
+  int64_t bonds_off;
+  int n, G;
+  int64_t num_pairs;
+  int32_t* scratch;
+  int64_t scratch_stride;
+  Op* ops;
+  int64_t ops_stride;
+  int2* wgates;
+  int64_t wg_stride;
+  int32_t* factors;
+  int64_t f_stride;
+  PlanHeader* hdr;
+  int* max_peak;
+  int* num_large;
+  int* num_failed;
+  int cap_bits;
+};
+
+int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
+int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
+                     int slot_bits, int num_slots, hipStream_t s);
+int launch_plan_local_random(const PlanJob& j, hipStream_t s);
+int sweep_elem_bytes(int precision);
+
+// HEA (diagonal CZ ladders -> Walsh-Hadamard column transfer)
+struct HeaArgs {
+  const unsigned char* gates;
+  int64_t gate_stride;
+  int n, L;
+  double* trace;
+  int64_t trace_offset;
+  int64_t num_pairs;
+};
+int launch_hea(const HeaArgs& a, int precision, int tile, hipStream_t s);
+int hea_bits(int L);
+
+int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
+                        hipStream_t s);
+int run_frame_potential_cv(const double* trB, const float* gB, int64_t nB, const float* gC, int64_t nC,
+                           int k, double c, double* h_F, double* h_se, hipStream_t s);
+
+}  // namespace fp

@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Both sides draw their own gates from the same counter-based stream (the
+oracle with its own Philox implementation), so no oracle input comes from
+the device.  Tolerances (per pair, floored relative error of the trace):
+1e-12 for complex128 and 1e-5 for complex64, with the floor
+max(|Tr|, 1e-3 * rms|Tr|) for traces near zero.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import closed_forms, dense, estimator, mpo, sampler
+from oracle.weingarten import brickwork_frame_potential
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2205_09900_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def floored_err(got, want):
+    got = np.asarray(got, dtype=np.complex128)
+    want = np.asarray(want, dtype=np.complex128)
+    rms = math.sqrt(float(np.mean(np.abs(want) ** 2))) if want.size else 1.0
+    floor = np.maximum(np.abs(want), 1e-3 * rms)
+    return float(np.max(np.abs(got - want) / floor))
+
+
+def gpu_traces(fp, ens, n_pairs, seed, prec, first_pair=0):
+    g = fp.sample(ens, n_pairs, seed, first_pair, prec)
+    tr = fp.contract(ens, g, n_pairs, prec)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy()
+
+
+def oracle_traces(ansatz, n, depth, seed, n_pairs, prec, first_pair=0, method="dense"):
+    pairs = sampler.sample_pairs(ansatz, n, depth, seed, first_pair, n_pairs, fp32=(prec != 0))
+    mod = dense if method == "dense" else mpo
+    return mod.traces(pairs)
+
+
+def unpack_haar(fp, ens, buf, prec):
+    """Gate matrices (and bonds) of a device gate buffer, for the sampler parity check."""
+    a = buf.cpu().numpy()
+    nb = fp.fp_gate_bytes_per_pair(ens, prec)
+    npairs = a.size // nb
+    real = np.float64 if prec == 0 else np.float32
+    n, d = ens[1], ens[2]
+    G = len(sampler.brickwork_layout(n, d)) if ens[0] == 0 else d
+    out = []
+    for p in range(npairs):
+        blk = a[p * nb:(p + 1) * nb]
+        m = np.frombuffer(blk[: 2 * G * 32 * np.dtype(real).itemsize].tobytes(), dtype=real)
+        m = m.astype(np.float64).reshape(2, G, 4, 4, 2)
+        m = m[..., 0] + 1j * m[..., 1]
+        bonds = None
+        if ens[0] == 1:
+            off = 2 * G * 32 * np.dtype(real).itemsize
+            bonds = np.frombuffer(blk[off: off + 8 * G].tobytes(), dtype=np.int32).reshape(2, G)
+        out.append((m, bonds))
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sampler_haar_matches_oracle(fp, prec):
+    for ens in [(0, 6, 3), (1, 7, 9)]:
+        seed = synth.workload_seed(9, ens[2])
+        buf = fp.sample(ens, 5, seed, 3, prec)
+        got = unpack_haar(fp, ens, buf, prec)
+        want = sampler.sample_pairs(ens[0], ens[1], ens[2], seed, 3, 5, fp32=(prec != 0))
+        for p in range(5):
+            for c in range(2):
+                gm = np.array([g for _, g in want[p][c]["gates"]])
+                tol = 1e-12 if prec == 0 else 1.5e-7
+                assert np.max(np.abs(got[p][0][c] - gm)) <= tol
+                if ens[0] == 1:
+                    assert list(got[p][1][c]) == [b for b, _ in want[p][c]["gates"]]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sampler_hea_matches_oracle(fp, prec):
+    ens = (2, 5, 3)
+    seed = 1234
+    buf = fp.sample(ens, 4, seed, 10, prec).cpu().numpy()
+    nb = fp.fp_gate_bytes_per_pair(ens, prec)
+    real = np.float64 if prec == 0 else np.float32
+    want = sampler.sample_pairs(2, 5, 3, seed, 10, 4, fp32=(prec != 0))
+    for p in range(4):
+        a = np.frombuffer(buf[p * nb:(p + 1) * nb].tobytes(), dtype=real)[: 2 * 3 * 5 * 2]
+        a = a.astype(np.float64).reshape(2, 3, 5, 2)
+        for c in range(2):
+            assert np.max(np.abs(a[c, :, :, 0] - want[p][c]["theta"])) <= (1e-15 if prec == 0 else 5e-7)
+            assert np.max(np.abs(a[c, :, :, 1] - want[p][c]["phi"])) <= (1e-15 if prec == 0 else 5e-7)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_brickwork_n6_all_depths_vs_dense(fp, prec):
+    for d in range(1, 7):
+        seed = synth.workload_seed(1, d)
+        got = gpu_traces(fp, (0, 6, d), 37, seed, prec)
+        want = oracle_traces(0, 6, d, seed, 37, prec)
+        assert floored_err(got, want) <= TOL[prec], (d, floored_err(got, want))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_local_random_vs_dense(fp, prec):
+    for n, s in [(2, 5), (3, 7), (8, 6), (8, 24), (10, 40)]:
+        seed = synth.workload_seed(4, s) + n
+        got = gpu_traces(fp, (1, n, s), 29, seed, prec)
+        want = oracle_traces(1, n, s, seed, 29, prec)
+        assert floored_err(got, want) <= TOL[prec], (n, s, floored_err(got, want))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_hea_vs_dense(fp, prec):
+    for n, L in [(2, 1), (5, 1), (6, 2), (6, 3), (7, 4), (5, 6)]:
+        seed = synth.workload_seed(3, L) + n
+        got = gpu_traces(fp, (2, n, L), 33, seed, prec)
+        want = oracle_traces(2, n, L, seed, 33, prec)
+        assert floored_err(got, want) <= TOL[prec], (n, L, floored_err(got, want))
+
+
+def test_brickwork_hbm_path_vs_dense(fp):
+    # depth 9 on 10 qubits: a 16-bit boundary, beyond LDS, runs in HBM slots
+    ens = (0, 10, 9)
+    assert fp.fp_plan_info(ens)["peak_bits"] == 16
+    seed = 77
+    got = gpu_traces(fp, ens, 3, seed, 0)
+    want = oracle_traces(0, 10, 9, seed, 3, 0)
+    assert floored_err(got, want) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wide_circuits_vs_mpo(fp, prec):
+    cases = [(0, 20, 3, 6), (1, 50, 50, 4), (2, 40, 2, 6), (1, 30, 60, 3)]
+    for ansatz, n, d, npairs in cases:
+        seed = synth.workload_seed(7, d) + n
+        got = gpu_traces(fp, (ansatz, n, d), npairs, seed, prec)
+        want = oracle_traces(ansatz, n, d, seed, npairs, prec, method="mpo")
+        assert floored_err(got, want) <= TOL[prec], (ansatz, n, d, floored_err(got, want))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_identical_circuits_give_dimension(fp, prec):
+    # U = V: Tr = 2^n for any circuit, at the full width of the local random workload
+    for ens in [(1, 50, 100), (0, 20, 6), (2, 40, 6)]:
+        nb = fp.fp_gate_bytes_per_pair(ens, prec)
+        g = fp.sample(ens, 8, 5, 0, prec).view(8, nb)
+        rb = 8 if prec == 0 else 4
+        if ens[0] == 2:
+            half = ens[2] * ens[1] * 2 * rb
+            g[:, half:2 * half] = g[:, :half]
+        else:
+            G = ens[2] if ens[0] == 1 else len(sampler.brickwork_layout(ens[1], ens[2]))
+            half = G * 32 * rb
+            g[:, half:2 * half] = g[:, :half]
+            if ens[0] == 1:
+                boff = 2 * half
+                g[:, boff + 4 * G: boff + 8 * G] = g[:, boff: boff + 4 * G]
+        tr = fp.contract(ens, g.reshape(-1), 8, prec).cpu().numpy()
+        want = 2.0 ** ens[1]
+        assert np.max(np.abs(tr - want)) <= TOL[prec] * want, (ens, tr[:3])
+
+
+def test_one_gate_difference_at_50_qubits(fp):
+    # U, V equal except one gate: Tr = 2^(n-2) Tr(G^dag G')
+    ens, prec = (1, 50, 120), 0
+    g = fp.sample(ens, 4, 9, 0, prec).view(4, -1)
+    G = 120
+    half = G * 32 * 8
+    gate_bytes = 32 * 8
+    g2 = g.clone()
+    g2[:, half:2 * half] = g[:, :half]
+    boff = 2 * half
+    g2[:, boff + 4 * G: boff + 8 * G] = g[:, boff: boff + 4 * G]
+    k = 57   # replace V's gate k by V's original gate k
+    g2[:, half + k * gate_bytes: half + (k + 1) * gate_bytes] = g[:, half + k * gate_bytes: half + (k + 1) * gate_bytes]
+    tr = fp.contract(ens, g2.reshape(-1), 4, prec).cpu().numpy()
+    a = g2.cpu().numpy()
+    for p in range(4):
+        gu = np.frombuffer(a[p, k * gate_bytes:(k + 1) * gate_bytes].tobytes(), np.float64).reshape(4, 4, 2)
+        gv = np.frombuffer(a[p, half + k * gate_bytes: half + (k + 1) * gate_bytes].tobytes(), np.float64).reshape(4, 4, 2)
+        gu = gu[..., 0] + 1j * gu[..., 1]
+        gv = gv[..., 0] + 1j * gv[..., 1]
+        want = closed_forms.one_gate_difference(50, gu, gv)
+        assert abs(tr[p] - want) <= 1e-11 * abs(want)
+
+
+def test_frame_potential_vs_numpy(fp):
+    for n, kmax in [(1, 1), (7, 3), (1000, 4), (300001, 8)]:
+        z = synth.heavy_tailed_traces(n + 3, n, scale=3.0)
+        d = torch.from_numpy(np.stack([z.real, z.imag], 1).reshape(-1)).cuda()
+        f, se = fp.fp_frame_potential(d, n, kmax)
+        wf, wse = estimator.frame_potential(z, kmax)
+        for k in range(kmax):
+            assert abs(f[k] - wf[k]) <= 1e-12 * abs(wf[k])
+            if n > 1:
+                assert abs(se[k] - wse[k]) <= 1e-9 * abs(wse[k])
+
+
+def test_frame_potential_flags_nonfinite(fp):
+    d = torch.zeros(20, dtype=torch.float64, device="cuda")
+    d[7] = float("nan")
+    with pytest.raises(fp.FPError) as e:
+        fp.fp_frame_potential(d, 10, 2)
+    assert e.value.code == fp.FP_ENUMERIC
+
+
+def test_determinism_and_batch_split(fp):
+    ens, prec = (1, 30, 80), 1
+    a = gpu_traces(fp, ens, 300, 42, prec)
+    b = gpu_traces(fp, ens, 300, 42, prec)
+    assert np.array_equal(a, b)
+    c = np.concatenate([gpu_traces(fp, ens, 120, 42, prec, 0), gpu_traces(fp, ens, 180, 42, prec, 120)])
+    assert np.array_equal(a, c)
+
+
+def test_brickwork_n6_full_workload(fp):
+    """n = 6, depths 1..6, 2000 pairs per depth, complex128: every trace against the
+    dense oracle, and F^(k) within the bootstrap interval of the exact value."""
+    for d in range(1, 7):
+        seed = synth.workload_seed(1, d)
+        g = fp.sample((0, 6, d), 2000, seed, 0, 0)
+        tr = fp.contract((0, 6, d), g, 2000, 0)
+        f, se = fp.frame_potential(tr, 2)
+        got = tr.cpu().numpy()
+        want = oracle_traces(0, 6, d, seed, 2000, 0)
+        assert floored_err(got, want) <= 1e-12, d
+        wf, _ = estimator.frame_potential(want, 2)
+        for k in (1, 2):
+            assert abs(f[k - 1] - wf[k - 1]) <= 1e-10 * wf[k - 1]
+            boot = estimator.bootstrap(want, k, resamples=300, seed=d)
+            exact = brickwork_frame_potential(6, d, k)
+            lo, hi = np.quantile(boot, [0.0005, 0.9995])
+            assert lo <= exact <= hi or abs(f[k - 1] - exact) <= 4 * se[k - 1], (d, k, f, exact, lo, hi)
