@@ -1,0 +1,208 @@
+"""Benchmark of the frame-potential hot path on one MI355X.
+
+Workload: local random circuits on n = 50 qubits (one Haar U(4) gate per step
+on a uniformly chosen bond), S steps per circuit, 10^4 (U, V) pairs per
+batch, complex64 with float64 scales and reduction.  One step = the whole
+path over one batch: sample the gates, plan every pair on the device,
+contract Tr(U^dagger V) for every pair, reduce F^(k), k = 1..3 (the reduction
+returns the estimates to the host, which ends the step).  Inputs are
+synthetic and seeded; the gate buffers of a step are resident in HBM before
+the contraction starts.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Tr(U†V) contractions/s at n=50; time-to-1%-rel-err F^(2), CV vs plain"
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector, published
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--depth", type=int, default=100, help="steps per circuit of the headline workload")
+    ap.add_argument("--pairs", type=int, default=10000)
+    ap.add_argument("--n", type=int, default=50)
+    ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--per-depth", default="50,100,150,200",
+                    help="comma list of step counts measured besides the headline ('' = none)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="also run one 256 MiB device copy (counter calibration for PMC runs)")
+    return ap.parse_args()
+
+
+def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base):
+    ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
+    gates = fp.alloc_gates(ens, pairs, prec)
+    trace = torch.empty(2 * pairs, dtype=torch.float64, device="cuda")
+    wsb = fp.fp_workspace_bytes(ens, pairs, prec)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    seed = seed_base | (depth << 32)
+
+    def step(i):
+        fp.fp_sample_gates(ens, pairs, seed, i * pairs, prec, gates)
+        fp.fp_contract_trace_batch(ens, pairs, prec, gates, trace, ws)
+        return fp.fp_frame_potential(trace, pairs, 3)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    fp.fp_profile_begin()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    f = None
+    for i in range(steps):
+        f = step(warmup + i)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = fp.fp_profile_end()
+    return {"wall_s": wall, "event_ms": ev0.elapsed_time(ev1), "prof": prof, "F": f[0], "SE": f[1],
+            "ws_bytes": wsb}
+
+
+def bits_stats(fp, np, n, depth, pairs, seed_base, sample=400):
+    """Boundary sizes of a sample of the workload (host planner on the bonds)."""
+    ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
+    g = fp.sample(ens, sample, seed_base | (depth << 32), 0, fp.C64).view(sample, -1).cpu().numpy()
+    off = 2 * depth * 32 * 4
+    peaks = []
+    for p in range(sample):
+        b = np.frombuffer(g[p, off: off + 8 * depth].tobytes(), dtype=np.int32).reshape(2, depth)
+        peaks.append(fp.fp_plan_local_random_host(n, b[0], b[1])["peak_bits"])
+    peaks = np.array(peaks)
+    return {"median_bits": int(np.median(peaks)), "p99_bits": int(np.quantile(peaks, 0.99)),
+            "max_bits": int(peaks.max()), "sample_pairs": sample}
+
+
+def _cpu_worker(args):
+    depth, n, seed, first, count, deadline = args
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:
+        pass
+    from oracle import mpo, sampler
+    done = 0
+    for i in range(count):
+        if time.time() > deadline:
+            break
+        pr = sampler.sample_pairs(sampler.LOCAL_RANDOM, n, depth, seed, first + i, 1, fp32=False)
+        mpo.trace_pair(pr[0][0], pr[0][1])
+        done += 1
+    return done
+
+
+def cpu_baseline(n, depth, seconds, seed_base):
+    """The oracle (MPO-zip, complex128, with its own sampler) on a time-bounded sample."""
+    import multiprocessing as mp
+    workers = min(16, os.cpu_count() or 1)
+    seed = seed_base | (depth << 32)
+    deadline = time.time() + seconds
+    jobs = [(depth, n, seed, w * 100000, 100000, deadline) for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        done = pool.map(_cpu_worker, jobs)
+    el = time.perf_counter() - t0
+    total = int(sum(done))
+    return {"value": total / el, "unit": "contractions/s", "cores": workers, "kind": "oracle",
+            "sample": f"{total} pairs of local random n={n} S={depth} (own Philox sampler + MPO-zip, "
+                      f"complex128), {workers} processes x 1 thread, {el:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2205_09900_amd as fp
+    import synth
+
+    torch.cuda.set_device(0)
+    prec = fp.C64 if args.precision == "c64" else fp.C128
+    seed_base = synth.workload_seed(4, 0)
+    if args.with_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    head = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base)
+    value = args.pairs * args.steps / head["wall_s"]
+    prof = head["prof"]
+    dom = max(prof, key=lambda c: prof[c]["ms"])
+    d = prof[dom]
+    achieved = (d["flops"] / d["launches"]) / (d["ms"] / d["launches"] * 1e-3) / 1e12 if d["launches"] else 0.0
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS if prec == fp.C64 else 78.6,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32_TFLOPS if prec == fp.C64 else 78.6),
+                "traffic": None, "kernel_class": dom,
+                "kernel_ms_per_launch": d["ms"] / max(1, d["launches"]),
+                "flops_per_launch": d["flops"] / max(1, d["launches"]),
+                "classes": prof}
+
+    per_depth = {}
+    if args.per_depth:
+        for s in [int(x) for x in args.per_depth.split(",") if x]:
+            r = run_workload(fp, torch, args.n, s, args.pairs, prec, max(2, args.steps // 2), 1, seed_base)
+            flops = sum(v["flops"] for v in r["prof"].values())
+            kms = sum(v["ms"] for v in r["prof"].values())
+            per_depth[str(s)] = {
+                "contractions_per_s": args.pairs * max(2, args.steps // 2) / r["wall_s"],
+                "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
+                "F": r["F"], "SE": r["SE"],
+                "kernel_ms": {k: v["ms"] for k, v in r["prof"].items() if v["launches"]},
+            }
+            try:
+                per_depth[str(s)].update(bits_stats(fp, np, args.n, s, args.pairs, seed_base, sample=200))
+            except Exception as e:  # statistics only
+                per_depth[str(s)]["bits_error"] = str(e)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.n, args.depth, args.cpu_seconds, seed_base)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "contractions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["wall_s"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == fp.C64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"local_random_n{args.n}_S{args.depth}", "n_qubits": args.n,
+                   "steps_per_circuit": args.depth, "pairs_per_step": args.pairs, "k_max": 3,
+                   "precision": args.precision, "F_k": head["F"], "SE_k": head["SE"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_depth": per_depth,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

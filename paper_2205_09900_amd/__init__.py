@@ -30,7 +30,7 @@ EXPORTS = [
     "fp_autotune_workspace_bytes", "fp_autotune", "fp_autotune_table", "fp_autotune_load",
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
     "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step",
-    "fp_frame_potential_cv", "fp_last_error", "fp_version",
+    "fp_frame_potential_cv", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
 
@@ -87,6 +87,8 @@ def _load():
         "fp_mlp_adam_step": (I, [I64, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
+        "fp_profile_begin": (I, []),
+        "fp_profile_end": (I, [P, P, P]),
         "fp_last_error": (ctypes.c_char_p, []),
         "fp_version": (I, []),
     }
@@ -196,6 +198,21 @@ def fp_plan_local_random_host(n_qubits, bonds_u, bonds_v):
                                          bv.ctypes.data_as(ctypes.c_void_p), bits, ctypes.byref(peak),
                                          ctypes.byref(macs), ctypes.byref(ops)))
     return {"bits": list(bits), "peak_bits": peak.value, "macs": macs.value, "ops": ops.value}
+
+
+KERNEL_CLASSES = ("lds_multi", "lds_single", "hbm", "hea")
+
+
+def fp_profile_begin():
+    return _check(lib.fp_profile_begin())
+
+
+def fp_profile_end():
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    fl = (ctypes.c_double * 4)()
+    _check(lib.fp_profile_end(ms, n, fl))
+    return {c: {"ms": ms[i], "launches": n[i], "flops": fl[i]} for i, c in enumerate(KERNEL_CLASSES)}
 
 
 OP_DTYPE = [("type", "u1"), ("p", "u1"), ("q", "u1"), ("bits", "u1"), ("arg", "<i4")]

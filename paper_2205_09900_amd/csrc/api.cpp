@@ -163,7 +163,7 @@ static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
 
 // predicted largest boundary of a local random batch (bits)
 static int lr_predicted_bits(int n, int S) {
-  int b = (int)(4.0 * S / (n - 1)) + 8;
+  int b = (int)(4.0 * S / (n - 1)) + 10;
   return b > 30 ? 30 : b;
 }
 
@@ -233,7 +233,11 @@ static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int pre
     if ((int64_t)tile_pairs(tile) * ((int64_t)elem << cap) > 160 * 1024) tile = choose_lds_tile(peak);
     a.cap_bits = cap;
     a.min_bits = -1;
-    return launch_sweep_lds(a, precision, tile, s);
+    const int kc = tile_pairs(tile) > 1 ? KCLASS_LDS_SMALL : KCLASS_LDS_LARGE;
+    profile_launch_begin(kc, s);
+    rc = launch_sweep_lds(a, precision, tile, s);
+    profile_launch_end(kc, 8.0 * dp.hdr.macs * (double)num_pairs, s);
+    return rc;
   }
   // HBM slots
   const int64_t slots = slot_count(peak, elem, num_pairs);
@@ -245,7 +249,10 @@ static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int pre
   if (rc) return rc;
   a.cap_bits = 0;
   a.min_bits = -1;
-  return launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, s);
+  profile_launch_begin(KCLASS_HBM, s);
+  rc = launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, s);
+  profile_launch_end(KCLASS_HBM, 8.0 * dp.hdr.macs * (double)num_pairs, s);
+  return rc;
 }
 
 static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
@@ -257,7 +264,7 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   if (!ws || ws_bytes < plan_bytes)
     return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", plan_bytes);
   unsigned char* w = (unsigned char*)ws;
-  int* counters = (int*)w;  // max_peak, num_large, num_failed
+  int* counters = (int*)w;  // max_peak, num_large, num_failed; then 3 doubles of class MACs at +16
   unsigned long long* hbm_counter = (unsigned long long*)(w + 64);
   unsigned char* region = w + 256;
   PlanJob j;
@@ -282,15 +289,20 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   j.num_large = counters + 1;
   j.num_failed = counters + 2;
   j.cap_bits = lds_bits_max(precision);
+  j.small_bits = LR_SMALL_BITS < j.cap_bits ? LR_SMALL_BITS : j.cap_bits;
+  j.class_macs = (double*)(w + 16);
   int rc = check_hip(hipMemsetAsync(w, 0, 256, s), "memset counters");
   if (rc) return rc;
   rc = launch_plan_local_random(j, s);
   if (rc) return rc;
-  int host[3];
-  rc = check_hip(hipMemcpyAsync(host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
+  struct {
+    int v[4];
+    double macs[3];
+  } host;
+  rc = check_hip(hipMemcpyAsync(&host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
   if (rc) return rc;
-  const int max_peak = host[0], num_large = host[1], num_failed = host[2];
+  const int max_peak = host.v[0], num_large = host.v[1], num_failed = host.v[2];
   SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.gates = j.gates;
@@ -309,30 +321,50 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   a.num_pairs = num_pairs;
   // class A: wave per pair, class B: workgroup per pair, class C: HBM slots
   a.min_bits = -1;
-  a.cap_bits = LR_SMALL_BITS < lds_bits_max(precision) ? LR_SMALL_BITS : lds_bits_max(precision);
+  a.cap_bits = j.small_bits;
+  profile_launch_begin(KCLASS_LDS_SMALL, s);
   rc = launch_sweep_lds(a, precision, TILE_64x4, s);
+  profile_launch_end(KCLASS_LDS_SMALL, 8.0 * host.macs[0], s);
   if (rc) return rc;
   if (max_peak > a.cap_bits) {
     a.min_bits = a.cap_bits;
     a.cap_bits = lds_bits_max(precision);
+    profile_launch_begin(KCLASS_LDS_LARGE, s);
     rc = launch_sweep_lds(a, precision, TILE_1024x1, s);
+    profile_launch_end(KCLASS_LDS_LARGE, 8.0 * host.macs[1], s);
     if (rc) return rc;
   }
   if (num_large > 0) {
     if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
-    const int64_t slots = slot_count(max_peak, elem, num_large);
-    const size_t need = plan_bytes + (size_t)(slots * ((int64_t)elem << max_peak));
-    if (ws_bytes < need)
-      return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)", need, max_peak);
+    // as many slots as the workspace holds (fewer slots only lower the parallelism)
+    const int64_t slot_bytes = (int64_t)elem << max_peak;
+    int64_t slots = slot_count(max_peak, elem, num_large);
+    const int64_t avail = ((int64_t)ws_bytes - (int64_t)plan_bytes) / slot_bytes;
+    if (avail < 1)
+      return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
+                       plan_bytes + (size_t)slot_bytes, max_peak);
+    if (slots > avail) slots = avail;
     rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, s), "memset counter");
     if (rc) return rc;
     a.min_bits = -1;
     a.cap_bits = lds_bits_max(precision);
+    profile_launch_begin(KCLASS_HBM, s);
     rc = launch_sweep_hbm(a, precision, hbm_counter, w + plan_bytes, max_peak, (int)slots, s);
+    profile_launch_end(KCLASS_HBM, 8.0 * host.macs[2], s);
     if (rc) return rc;
   }
   if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
   return FP_OK;
+}
+
+// Algorithmic flops of one HEA trace: n-1 transforms of m butterfly stages
+// (one complex addition, 2 flops, per entry and stage) and n pointwise
+// complex products (6 flops per entry).
+static double hea_flops_per_pair(int n, int L) {
+  const int m = hea_bits(L);
+  if (m == 0) return 6.0 * n;
+  const double chi = (double)(1ull << m);
+  return (double)(n - 1) * m * chi * 2.0 + (double)n * chi * 6.0;
 }
 
 static int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
@@ -351,7 +383,10 @@ static int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision
   int tile = tile_override >= 0 ? tile_override : tune_lookup(e, precision, def);
   const size_t elem = precision == FP_C128 ? 16 : 8;
   if ((size_t)tile_pairs(tile) * (elem << m) > 140 * 1024) tile = def;
-  return launch_hea(a, precision, tile, s);
+  profile_launch_begin(KCLASS_HEA, s);
+  int rc = launch_hea(a, precision, tile, s);
+  profile_launch_end(KCLASS_HEA, hea_flops_per_pair(e->n_qubits, e->depth) * (double)num_pairs, s);
+  return rc;
 }
 
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,

@@ -48,7 +48,9 @@ struct PlanJob {
   int* max_peak;
   int* num_large;
   int* num_failed;
-  int cap_bits;
+  int cap_bits;    // largest boundary run in LDS
+  int small_bits;  // largest boundary run by the wave-per-pair launch
+  double* class_macs;  // complex MACs per launch class (small LDS, large LDS, HBM)
 };
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
@@ -56,6 +58,12 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
                      int slot_bits, int num_slots, hipStream_t s);
 int launch_plan_local_random(const PlanJob& j, hipStream_t s);
 int sweep_elem_bytes(int precision);
+
+// Event timing of the sweep launches (enabled by fp_profile_begin).
+enum { KCLASS_LDS_SMALL = 0, KCLASS_LDS_LARGE = 1, KCLASS_HBM = 2, KCLASS_HEA = 3, KCLASS_COUNT = 4 };
+bool profiling();
+void profile_launch_begin(int kclass, hipStream_t s);
+void profile_launch_end(int kclass, double flops, hipStream_t s);
 
 // HEA (diagonal CZ ladders -> Walsh-Hadamard column transfer)
 struct HeaArgs {

@@ -308,6 +308,8 @@ __global__ void __launch_bounds__(64) plan_local_random_kernel(PlanJob j) {
   if (h.status == 0) {
     atomicMax(j.max_peak, h.peak_bits);
     if (h.peak_bits > j.cap_bits) atomicAdd(j.num_large, 1);
+    const int cls = h.peak_bits <= j.small_bits ? 0 : h.peak_bits <= j.cap_bits ? 1 : 2;
+    atomicAdd(&j.class_macs[cls], h.macs);
   } else {
     atomicAdd(j.num_failed, 1);
   }
