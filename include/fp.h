@@ -285,12 +285,13 @@ int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t n
  * fp_profile_begin / fp_profile_end -- while enabled, every sweep launch of
  * fp_contract_trace_batch is bracketed by HIP events on its stream.
  * fp_profile_end disables timing, waits for the recorded events and writes,
- * per launch class (0: LDS, several pairs per workgroup; 1: LDS, one pair per
- * workgroup; 2: boundaries in HBM; 3: HEA transform sweep), the summed kernel
- * time in milliseconds, the number of launches and the algorithmic flops
- * (8 real flops per complex multiply-add of the plan; for the HEA sweep
- * 2 per complex addition of the transforms and 6 per pointwise product).
- * Each output array has 4 entries and may be NULL.  Not re-entrant.
+ * per launch class (boundary in LDS with 0: 16 lanes, 1: 64 lanes, 2: 256
+ * lanes, 3: 1024 lanes per pair; 4: boundaries in HBM; 5: HEA transform
+ * sweep), the summed kernel time in milliseconds, the number of launches and
+ * the algorithmic flops (8 real flops per complex multiply-add of the plan;
+ * for the HEA sweep 2 per complex addition of the transforms and 6 per
+ * pointwise product).  Each output array has 6 entries and may be NULL.
+ * Not re-entrant.
  */
 int fp_profile_begin(void);
 int fp_profile_end(double* kernel_ms, int64_t* launches, double* flops);

@@ -200,7 +200,7 @@ def fp_plan_local_random_host(n_qubits, bonds_u, bonds_v):
     return {"bits": list(bits), "peak_bits": peak.value, "macs": macs.value, "ops": ops.value}
 
 
-KERNEL_CLASSES = ("lds_multi", "lds_single", "hbm", "hea")
+KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
 
 
 def fp_profile_begin():
@@ -208,9 +208,9 @@ def fp_profile_begin():
 
 
 def fp_profile_end():
-    ms = (ctypes.c_double * 4)()
-    n = (ctypes.c_int64 * 4)()
-    fl = (ctypes.c_double * 4)()
+    ms = (ctypes.c_double * 6)()
+    n = (ctypes.c_int64 * 6)()
+    fl = (ctypes.c_double * 6)()
     _check(lib.fp_profile_end(ms, n, fl))
     return {c: {"ms": ms[i], "launches": n[i], "flops": fl[i]} for i, c in enumerate(KERNEL_CLASSES)}
 

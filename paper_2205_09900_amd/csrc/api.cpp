@@ -42,9 +42,8 @@ static int check_ensemble(const fp_ensemble_t* e) {
   if (e->n_qubits < 2 || e->n_qubits > 64) return set_error(FP_EINVAL, "n_qubits %d outside 2..64", e->n_qubits);
   if (e->depth < 1) return set_error(FP_EINVAL, "depth %d < 1", e->depth);
   if (e->reserved != 0) return set_error(FP_EINVAL, "reserved field must be 0");
-  if (e->ansatz == FP_LOCAL_RANDOM_HAAR && e->depth > 100000)
-    return set_error(FP_EINVAL, "depth %d too large", e->depth);
-  if (e->ansatz == FP_BRICKWORK_HAAR && e->depth > 4096) return set_error(FP_EINVAL, "depth %d too large", e->depth);
+  if (e->ansatz != FP_HEA_RYRZ_CZ && gates_per_circuit(e->ansatz, e->n_qubits, e->depth) > PLAN_MAX_GATES)
+    return set_error(FP_EINVAL, "more than %d gates per circuit", PLAN_MAX_GATES);
   if (e->ansatz == FP_HEA_RYRZ_CZ && e->depth > 64) return set_error(FP_EINVAL, "depth %d too large", e->depth);
   return FP_OK;
 }
@@ -64,11 +63,19 @@ struct HostPlan {
 };
 
 static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, HostPlan* out) {
-  std::vector<int32_t> scratch((size_t)plan_scratch_ints(G, n));
+  if (G > PLAN_MAX_GATES) return set_error(FP_EINVAL, "%d gates per circuit exceed %d", G, PLAN_MAX_GATES);
+  std::vector<int16_t> scratch((size_t)plan_scratch_elems(G, n));
+  std::vector<int16_t> b16(2 * (size_t)G);
+  for (int i = 0; i < G; ++i) {
+    b16[i] = (bu[i] >= 0 && bu[i] <= n - 2) ? (int16_t)bu[i] : (int16_t)-1;
+    b16[G + i] = (bv[i] >= 0 && bv[i] <= n - 2) ? (int16_t)bv[i] : (int16_t)-1;
+  }
   out->ops.resize((size_t)plan_max_ops(G, n));
   out->wg.resize(2 * (size_t)G);
   out->fac.resize(2 * (size_t)G);
-  out->hdr = plan_haar_pair(n, G, bu, bv, scratch.data(), out->ops.data(), out->wg.data(), out->fac.data());
+  int32_t tags[64];
+  out->hdr = plan_haar_pair(n, G, b16.data(), b16.data() + G, scratch.data(), out->ops.data(), out->wg.data(),
+                            out->fac.data(), tags);
   if (out->hdr.status != PLAN_OK) {
     if (out->hdr.status == PLAN_EWIDE)
       return set_error(FP_ETOOBIG, "boundary wider than %d bits", PLAN_MAX_BITS);
@@ -77,7 +84,7 @@ static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, Ho
   out->ops.resize(out->hdr.num_ops);
   out->bits.clear();
   for (const Op& o : out->ops)
-    if (o.type == OP_COLEND) out->bits.push_back(o.bits);
+    if ((o.type & OP_TYPE_MASK) == OP_COLEND) out->bits.push_back(o.bits);
   return FP_OK;
 }
 
@@ -130,12 +137,45 @@ static int get_brickwork_plan(int n, int depth, DevPlan* out) {
   return FP_OK;
 }
 
+// ---- auxiliary streams: the sweep classes of one batch touch disjoint pairs
+// and run side by side (all streams at the default priority) --------------------
+constexpr int NUM_AUX = 4;
+struct Aux {
+  hipStream_t s[NUM_AUX];
+  hipEvent_t fork, join[NUM_AUX];
+};
+static std::mutex g_aux_mu;
+static std::map<int, Aux> g_aux;
+
+static int get_aux(Aux* out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  auto it = g_aux.find(dev);
+  if (it != g_aux.end()) {
+    *out = it->second;
+    return FP_OK;
+  }
+  Aux a;
+  for (int i = 0; i < NUM_AUX; ++i) {
+    rc = check_hip(hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking), "hipStreamCreate");
+    if (!rc) rc = check_hip(hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming), "hipEventCreate");
+    if (rc) return rc;
+  }
+  rc = check_hip(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming), "hipEventCreate");
+  if (rc) return rc;
+  g_aux[dev] = a;
+  *out = a;
+  return FP_OK;
+}
+
 // ---- sizes -------------------------------------------------------------------
 static int lds_bits_max(int precision) { return precision == FP_C128 ? 13 : 14; }
 
 // Local random: per-pair plan region.
 struct LrLayout {
-  int64_t hdr, ops, wg, fac, scratch, per_pair;
+  int64_t hdr, ops, wg, fac, per_pair;
 };
 
 static LrLayout lr_layout(int n, int G) {
@@ -144,12 +184,13 @@ static LrLayout lr_layout(int n, int G) {
   l.ops = pad64(plan_max_ops(G, n) * (int64_t)sizeof(Op));
   l.wg = pad64(2 * (int64_t)G * (int64_t)sizeof(int2));
   l.fac = pad64(2 * (int64_t)G * 4);
-  l.scratch = pad64(plan_scratch_ints(G, n) * 4);
-  l.per_pair = l.hdr + l.ops + l.wg + l.fac + l.scratch;
+  l.per_pair = l.hdr + l.ops + l.wg + l.fac;
   return l;
 }
 
+constexpr int LR_TINY_BITS = 8;    // 16 lanes per pair
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
+constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
 
 static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
@@ -233,7 +274,10 @@ static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int pre
     if ((int64_t)tile_pairs(tile) * ((int64_t)elem << cap) > 160 * 1024) tile = choose_lds_tile(peak);
     a.cap_bits = cap;
     a.min_bits = -1;
-    const int kc = tile_pairs(tile) > 1 ? KCLASS_LDS_SMALL : KCLASS_LDS_LARGE;
+    const int kc = tile == TILE_16x16   ? KCLASS_LDS16
+                   : tile == TILE_64x4  ? KCLASS_LDS64
+                   : tile == TILE_256x1 ? KCLASS_LDS256
+                                        : KCLASS_LDS1024;
     profile_launch_begin(kc, s);
     rc = launch_sweep_lds(a, precision, tile, s);
     profile_launch_end(kc, 8.0 * dp.hdr.macs * (double)num_pairs, s);
@@ -280,16 +324,16 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   j.ops = (Op*)(base + num_pairs * l.hdr);
   j.wgates = (int2*)(base + num_pairs * (l.hdr + l.ops));
   j.factors = (int32_t*)(base + num_pairs * (l.hdr + l.ops + l.wg));
-  j.scratch = (int32_t*)(base + num_pairs * (l.hdr + l.ops + l.wg + l.fac));
   j.ops_stride = l.ops / (int64_t)sizeof(Op);
   j.wg_stride = l.wg / (int64_t)sizeof(int2);
   j.f_stride = l.fac / 4;
-  j.scratch_stride = l.scratch / 4;
   j.max_peak = counters;
   j.num_large = counters + 1;
   j.num_failed = counters + 2;
   j.cap_bits = lds_bits_max(precision);
   j.small_bits = LR_SMALL_BITS < j.cap_bits ? LR_SMALL_BITS : j.cap_bits;
+  j.tiny_bits = LR_TINY_BITS;
+  j.mid_bits = LR_MID_BITS < j.cap_bits ? LR_MID_BITS : j.cap_bits;
   j.class_macs = (double*)(w + 16);
   int rc = check_hip(hipMemsetAsync(w, 0, 256, s), "memset counters");
   if (rc) return rc;
@@ -297,7 +341,7 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   if (rc) return rc;
   struct {
     int v[4];
-    double macs[3];
+    double macs[5];
   } host;
   rc = check_hip(hipMemcpyAsync(&host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
@@ -319,40 +363,80 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
   a.trace = trace;
   a.trace_offset = trace_offset;
   a.num_pairs = num_pairs;
-  // class A: wave per pair, class B: workgroup per pair, class C: HBM slots
-  a.min_bits = -1;
-  a.cap_bits = j.small_bits;
-  profile_launch_begin(KCLASS_LDS_SMALL, s);
-  rc = launch_sweep_lds(a, precision, TILE_64x4, s);
-  profile_launch_end(KCLASS_LDS_SMALL, 8.0 * host.macs[0], s);
+  // Launch classes by the largest boundary of a pair: 16 lanes, one
+  // wavefront, 256 lanes and 1024 lanes per pair with the boundary in LDS,
+  // then HBM slots.  Each class runs on its own stream; all join into s.
+  Aux aux;
+  rc = get_aux(&aux);
   if (rc) return rc;
-  if (max_peak > a.cap_bits) {
-    a.min_bits = a.cap_bits;
-    a.cap_bits = lds_bits_max(precision);
-    profile_launch_begin(KCLASS_LDS_LARGE, s);
-    rc = launch_sweep_lds(a, precision, TILE_1024x1, s);
-    profile_launch_end(KCLASS_LDS_LARGE, 8.0 * host.macs[1], s);
-    if (rc) return rc;
-  }
-  if (num_large > 0) {
+  int64_t slots = 0;
+  const bool need_hbm = num_large > 0;
+  if (need_hbm) {
     if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
     // as many slots as the workspace holds (fewer slots only lower the parallelism)
     const int64_t slot_bytes = (int64_t)elem << max_peak;
-    int64_t slots = slot_count(max_peak, elem, num_large);
+    slots = slot_count(max_peak, elem, num_large);
     const int64_t avail = ((int64_t)ws_bytes - (int64_t)plan_bytes) / slot_bytes;
     if (avail < 1)
       return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
                        plan_bytes + (size_t)slot_bytes, max_peak);
     if (slots > avail) slots = avail;
-    rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, s), "memset counter");
-    if (rc) return rc;
-    a.min_bits = -1;
-    a.cap_bits = lds_bits_max(precision);
-    profile_launch_begin(KCLASS_HBM, s);
-    rc = launch_sweep_hbm(a, precision, hbm_counter, w + plan_bytes, max_peak, (int)slots, s);
-    profile_launch_end(KCLASS_HBM, 8.0 * host.macs[2], s);
+  }
+  struct Cls {
+    int lo, hi, tile, kclass;
+  };
+  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
+                      {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64},
+                      {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256},
+                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024}};
+  bool used[NUM_AUX] = {false, false, false, false};
+  int naux = 0;
+  for (int c = 1; c < 4; ++c) naux += (max_peak > cls[c].lo && cls[c].hi > cls[c].lo) ? 1 : 0;
+  naux += need_hbm ? 1 : 0;
+  if (naux > 0) {
+    rc = check_hip(hipEventRecord(aux.fork, s), "fork");
     if (rc) return rc;
   }
+  int next_aux = 0;
+  if (need_hbm) {
+    hipStream_t sc = aux.s[next_aux];
+    rc = check_hip(hipStreamWaitEvent(sc, aux.fork, 0), "fork wait");
+    if (!rc) rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, sc), "memset counter");
+    if (rc) return rc;
+    SweepArgs ac = a;
+    ac.min_bits = -1;
+    ac.cap_bits = lds_bits_max(precision);
+    profile_launch_begin(KCLASS_HBM, sc);
+    rc = launch_sweep_hbm(ac, precision, hbm_counter, w + plan_bytes, max_peak, (int)slots, sc);
+    profile_launch_end(KCLASS_HBM, 8.0 * host.macs[4], sc);
+    if (!rc) rc = check_hip(hipEventRecord(aux.join[next_aux], sc), "join");
+    if (rc) return rc;
+    used[next_aux++] = true;
+  }
+  for (int c = 3; c >= 0; --c) {
+    if (c > 0 && !(max_peak > cls[c].lo && cls[c].hi > cls[c].lo)) continue;
+    hipStream_t sx = s;
+    if (c > 0) {
+      sx = aux.s[next_aux];
+      rc = check_hip(hipStreamWaitEvent(sx, aux.fork, 0), "fork wait");
+      if (rc) return rc;
+    }
+    SweepArgs ax = a;
+    ax.min_bits = cls[c].lo;
+    ax.cap_bits = cls[c].hi;
+    profile_launch_begin(cls[c].kclass, sx);
+    rc = launch_sweep_lds(ax, precision, cls[c].tile, sx);
+    profile_launch_end(cls[c].kclass, 8.0 * host.macs[c], sx);
+    if (rc) return rc;
+    if (c > 0) {
+      rc = check_hip(hipEventRecord(aux.join[next_aux], sx), "join");
+      if (rc) return rc;
+      used[next_aux++] = true;
+    }
+  }
+  for (int i = 0; i < NUM_AUX && !rc; ++i)
+    if (used[i]) rc = check_hip(hipStreamWaitEvent(s, aux.join[i], 0), "join wait");
+  if (rc) return rc;
   if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
   return FP_OK;
 }

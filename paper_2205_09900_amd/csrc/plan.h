@@ -35,6 +35,10 @@
 namespace fp {
 
 enum : uint8_t { OP_GATE = 0, OP_BELL = 1, OP_TRACE = 2, OP_COLEND = 3 };
+// Flag in Op::type: the next op ends the column, so the kernels record the
+// largest magnitude this op writes (for the column's power-of-two rescale).
+constexpr uint8_t OP_TYPE_MASK = 0x3;
+constexpr uint8_t OP_FLAG_TRACK = 0x80;
 
 struct Op {
   uint8_t type;
@@ -80,9 +84,13 @@ __host__ __device__ inline FactorRef decode_factor(int32_t code, int32_t G) {
   return f;
 }
 
-__host__ __device__ inline int64_t plan_scratch_ints(int G, int n) {
+// Gates per circuit the planner accepts (its indices are 16-bit).
+constexpr int PLAN_MAX_GATES = 16000;
+
+// Scratch of one pair, in 16-bit entries.
+__host__ __device__ inline int64_t plan_scratch_elems(int G, int n) {
   const int64_t W = 2 * (int64_t)G;
-  return 12 * W + 6 * (int64_t)(n + 2) + 16;
+  return 17 * W + 6 * (int64_t)(n + 2) + 16;
 }
 
 __host__ __device__ inline int64_t plan_max_ops(int G, int n) { return 10 * (int64_t)G + n + 8; }
@@ -90,10 +98,16 @@ __host__ __device__ inline int64_t plan_max_ops(int G, int n) { return 10 * (int
 struct PlanCtx {
   int n, G, W;
   int nw;  // merged gates
-  int32_t *mbond, *head, *tail, *cnt, *nextf, *dead;
-  int32_t *non0, *non1, *pon0, *pon1;  // next / previous gate on lower (0) / upper (1) qubit
-  int32_t *colgates;                   // gates of each bond in time order
-  int32_t *lastq, *firstq, *colstart, *colfill, *lastb, *firstb;
+  int16_t *mbond, *head, *tail, *cnt, *nextf, *dead;
+  int16_t *non0, *non1, *pon0, *pon1;  // next / previous gate on lower (0) / upper (1) qubit
+  int16_t *colgates;                   // gates of each bond in time order
+  int16_t *lastq, *firstq, *colstart, *colfill, *lastb, *firstb;
+  // register: tags of the live bits and, per tag, its bit position (-1 = none)
+  int32_t* tag;
+  int b;
+  int16_t *lab, *outp, *pendp;  // plain labels (2 per gate), Bell out-ends, pending legs
+  int16_t *gflags;              // per gate of the current column: internal-segment flags
+  int16_t first_pos, tmp_pos;
   // outputs
   Op* ops;
   int2* wgates;  // (first factor, count)
@@ -105,30 +119,46 @@ struct PlanCtx {
   int peak;
 };
 
-// ---- register (tags of the live bits) ----
-struct Reg {
-  int32_t tag[64];
-  int b;
-};
-
-__host__ __device__ inline int reg_find(const Reg& r, int32_t t) {
-  for (int i = 0; i < r.b; ++i)
-    if (r.tag[i] == t) return i;
-  return -1;
-}
-
-__host__ __device__ inline void reg_remove2(Reg& r, int p, int q) {
-  int lo = p < q ? p : q, hi = p < q ? q : p;
-  int w = 0;
-  for (int i = 0; i < r.b; ++i)
-    if (i != lo && i != hi) r.tag[w++] = r.tag[i];
-  r.b = w;
-}
-
 constexpr int32_t TAG_OUT = 1 << 27;
 constexpr int32_t TAG_PEND = 1 << 28;
 constexpr int32_t TAG_FIRST = 1 << 29;
 constexpr int32_t TAG_TMP = 1 << 30;
+constexpr int32_t TAG_KEY = TAG_OUT - 1;
+
+// ---- register: positions are looked up through per-tag tables (O(1)) ----
+__host__ __device__ inline int16_t* reg_slot(PlanCtx& c, int32_t t) {
+  if (t & TAG_TMP) return &c.tmp_pos;
+  if (t & TAG_FIRST) return &c.first_pos;
+  const int k = t & TAG_KEY;
+  if (t & TAG_OUT) return &c.outp[k >> 1];
+  if (t & TAG_PEND) return &c.pendp[k >> 1];
+  return &c.lab[k];
+}
+
+__host__ __device__ inline int reg_find(PlanCtx& c, int32_t t) { return *reg_slot(c, t); }
+
+__host__ __device__ inline void reg_set(PlanCtx& c, int pos, int32_t t) {
+  c.tag[pos] = t;
+  *reg_slot(c, t) = (int16_t)pos;
+}
+
+// Retag bit `pos` (its old tag no longer names it).
+__host__ __device__ inline void reg_retag(PlanCtx& c, int pos, int32_t t) {
+  *reg_slot(c, c.tag[pos]) = -1;
+  reg_set(c, pos, t);
+}
+
+// Remove bits lo < hi; the bits above move down.
+__host__ __device__ inline void reg_remove2(PlanCtx& c, int lo, int hi) {
+  *reg_slot(c, c.tag[lo]) = -1;
+  *reg_slot(c, c.tag[hi]) = -1;
+  int w = lo;
+  for (int i = lo + 1; i < c.b; ++i) {
+    if (i == hi) continue;
+    reg_set(c, w++, c.tag[i]);
+  }
+  c.b = w;
+}
 
 __host__ __device__ inline int32_t seg_key(int e, int side) { return 2 * e + side; }
 
@@ -137,6 +167,7 @@ __host__ __device__ inline void emit(PlanCtx& c, uint8_t type, int p, int q, int
     c.status = PLAN_ECAP;
     return;
   }
+  if (type == OP_COLEND && c.num_ops > 0) c.ops[c.num_ops - 1].type |= OP_FLAG_TRACK;
   Op o;
   o.type = type;
   o.p = (uint8_t)p;
@@ -149,37 +180,42 @@ __host__ __device__ inline void emit(PlanCtx& c, uint8_t type, int p, int q, int
   if (type == OP_GATE) c.macs += 4.0 * sz;
 }
 
-// Largest register along the walk of column `col` started at gate index s.
-__host__ __device__ inline int walk_peak(const PlanCtx& c, int col, const int32_t* cg, int m, int s,
-                                         int b0) {
+// Per-gate flags of a column: which of the gate's four legs sit on internal
+// segments (ends on another gate of the same bond).
+enum { GF_IN = 1, GF_OUT = 2, GF_C1IN = 4, GF_C1OUT = 8 };
+
+// Largest register along the walk of the column started at gate index s.
+__host__ __device__ inline int walk_peak(const int16_t* fl, int m, int s, int b0) {
   int b = b0, peak = b0;
-  const int first = cg[s];
   for (int t = 0; t < m; ++t) {
-    int g = cg[(s + t) % m];
-    bool in_int = c.mbond[c.pon0[g]] == col;
-    bool out_int = c.mbond[c.non0[g]] == col;
-    bool c1in_int = c.mbond[c.pon1[g]] == col;
-    bool c1out_int = c.mbond[c.non1[g]] == col;
-    if (in_int && t == 0) b += 2;
-    if (out_int && c.non0[g] != first) b += 2;
+    const int i = s + t < m ? s + t : s + t - m;
+    const int f = fl[i];
+    const int nxt = i + 1 < m ? i + 1 : 0;
+    if ((f & GF_IN) && t == 0) b += 2;
+    if ((f & GF_OUT) && nxt != s) b += 2;
     if (b > peak) peak = b;
-    if (c1in_int && t != 0) b -= 2;
-    if (c1out_int && c.non1[g] == first) b -= 2;
+    if ((f & GF_C1IN) && t != 0) b -= 2;
+    if ((f & GF_C1OUT) && nxt == s) b -= 2;
   }
   return peak;
 }
 
-__host__ __device__ inline void plan_column(PlanCtx& c, Reg& r, int col) {
+__host__ __device__ inline void plan_column(PlanCtx& c, int col) {
   const int m = c.colstart[col + 1] - c.colstart[col];
-  const int32_t* cg = c.colgates + c.colstart[col];
+  const int16_t* cg = c.colgates + c.colstart[col];
   if (m == 0) {
-    if (r.b != 0) c.status = PLAN_EINTERNAL;
-    emit(c, OP_COLEND, 0, 0, r.b, col);
+    if (c.b != 0) c.status = PLAN_EINTERNAL;
+    emit(c, OP_COLEND, 0, 0, c.b, col);
     return;
+  }
+  for (int i = 0; i < m; ++i) {
+    const int g = cg[i];
+    c.gflags[i] = (int16_t)((c.mbond[c.pon0[g]] == col ? GF_IN : 0) | (c.mbond[c.non0[g]] == col ? GF_OUT : 0) |
+                            (c.mbond[c.pon1[g]] == col ? GF_C1IN : 0) | (c.mbond[c.non1[g]] == col ? GF_C1OUT : 0));
   }
   int best = 0, bestpeak = 1 << 30;
   for (int s = 0; s < m; ++s) {
-    int pk = walk_peak(c, col, cg, m, s, r.b);
+    const int pk = walk_peak(c.gflags, m, s, c.b);
     if (pk < bestpeak) {
       bestpeak = pk;
       best = s;
@@ -192,94 +228,95 @@ __host__ __device__ inline void plan_column(PlanCtx& c, Reg& r, int col) {
   const int first = cg[best];
   for (int t = 0; t < m && c.status == PLAN_OK; ++t) {
     const int g = cg[(best + t) % m];
-    // input leg on qubit col
-    if (r.b + 4 > 64) {
+    if (c.b + 4 > 64) {
       c.status = PLAN_EWIDE;
       return;
     }
-    int pin = reg_find(r, seg_key(g, 0));
+    // input leg on qubit col
+    int pin = reg_find(c, seg_key(g, 0));
     if (pin < 0) {
       if (!(t == 0 && c.mbond[c.pon0[g]] == col)) {
         c.status = PLAN_EINTERNAL;
         return;
       }
-      r.tag[r.b] = seg_key(g, 0);
-      r.tag[r.b + 1] = seg_key(g, 0) | TAG_OUT;
-      pin = r.b;
-      r.b += 2;
-      emit(c, OP_BELL, 0, 0, r.b, 0);
+      reg_set(c, c.b, seg_key(g, 0));
+      reg_set(c, c.b + 1, seg_key(g, 0) | TAG_OUT);
+      pin = c.b;
+      c.b += 2;
+      emit(c, OP_BELL, 0, 0, c.b, 0);
     }
     // output leg on qubit col
     const int X = c.non0[g];
     int pout;
     if (c.mbond[X] == col - 1) {
-      pout = reg_find(r, seg_key(X, 1));
+      pout = reg_find(c, seg_key(X, 1));
       if (pout < 0) {
         c.status = PLAN_EINTERNAL;
         return;
       }
     } else {
-      pout = reg_find(r, seg_key(X, 0) | TAG_OUT);
+      pout = reg_find(c, seg_key(X, 0) | TAG_OUT);
       if (pout < 0) {
-        r.tag[r.b] = seg_key(X, 0);
-        r.tag[r.b + 1] = seg_key(X, 0) | TAG_OUT;
-        pout = r.b + 1;
-        r.b += 2;
-        emit(c, OP_BELL, 0, 0, r.b, 0);
+        reg_set(c, c.b, seg_key(X, 0));
+        reg_set(c, c.b + 1, seg_key(X, 0) | TAG_OUT);
+        pout = c.b + 1;
+        c.b += 2;
+        emit(c, OP_BELL, 0, 0, c.b, 0);
       }
     }
-    if (r.b > c.peak) c.peak = r.b;
-    emit(c, OP_GATE, pin, pout, r.b, g);
+    if (c.b > c.peak) c.peak = c.b;
+    emit(c, OP_GATE, pin, pout, c.b, g);
     // pin now holds the input leg on qubit col+1, pout the output leg.
-    r.tag[pout] = TAG_TMP;
+    reg_retag(c, pout, TAG_TMP);
     const int Y = c.pon1[g];
     if (c.mbond[Y] == col + 1) {
-      r.tag[pin] = seg_key(g, 1);
+      reg_retag(c, pin, seg_key(g, 1));
     } else {
-      int partner = reg_find(r, seg_key(g, 1) | TAG_PEND);
+      const int partner = reg_find(c, seg_key(g, 1) | TAG_PEND);
       if (partner >= 0) {
-        int lo = pin < partner ? pin : partner, hi = pin < partner ? partner : pin;
-        reg_remove2(r, lo, hi);
-        emit(c, OP_TRACE, lo, hi, r.b, 0);
+        const int lo = pin < partner ? pin : partner, hi = pin < partner ? partner : pin;
+        reg_remove2(c, lo, hi);
+        emit(c, OP_TRACE, lo, hi, c.b, 0);
       } else {
-        r.tag[pin] = seg_key(g, 1) | TAG_FIRST;
+        reg_retag(c, pin, seg_key(g, 1) | TAG_FIRST);
       }
     }
-    pout = reg_find(r, TAG_TMP);
+    pout = reg_find(c, TAG_TMP);
     const int Z = c.non1[g];
     if (c.mbond[Z] == col + 1) {
-      r.tag[pout] = seg_key(Z, 0);
+      reg_retag(c, pout, seg_key(Z, 0));
     } else if (Z == first) {
-      int partner = reg_find(r, seg_key(Z, 1) | TAG_FIRST);
+      const int partner = reg_find(c, seg_key(Z, 1) | TAG_FIRST);
       if (partner < 0) {
         c.status = PLAN_EINTERNAL;
         return;
       }
-      int lo = pout < partner ? pout : partner, hi = pout < partner ? partner : pout;
-      reg_remove2(r, lo, hi);
-      emit(c, OP_TRACE, lo, hi, r.b, 0);
+      const int lo = pout < partner ? pout : partner, hi = pout < partner ? partner : pout;
+      reg_remove2(c, lo, hi);
+      emit(c, OP_TRACE, lo, hi, c.b, 0);
     } else {
-      r.tag[pout] = seg_key(Z, 1) | TAG_PEND;
+      reg_retag(c, pout, seg_key(Z, 1) | TAG_PEND);
     }
   }
   // only labels for the next column may remain
-  for (int i = 0; i < r.b; ++i)
-    if (r.tag[i] & (TAG_OUT | TAG_PEND | TAG_FIRST | TAG_TMP)) c.status = PLAN_EINTERNAL;
-  emit(c, OP_COLEND, 0, 0, r.b, col);
+  for (int i = 0; i < c.b; ++i)
+    if (c.tag[i] & (TAG_OUT | TAG_PEND | TAG_FIRST | TAG_TMP)) c.status = PLAN_EINTERNAL;
+  emit(c, OP_COLEND, 0, 0, c.b, col);
 }
 
-// Plan one pair.  bond_u, bond_v: G bonds each (time order).  scratch:
-// plan_scratch_ints(G, n) int32.  ops: plan_max_ops(G, n) entries; wgates: 2G;
-// factors: 2G.  Returns the header (status != 0 on failure).
-__host__ __device__ inline PlanHeader plan_haar_pair(int n, int G, const int32_t* bond_u,
-                                                     const int32_t* bond_v, int32_t* scratch, Op* ops,
-                                                     int2* wgates, int32_t* factors) {
+// Plan one pair.  bond_u, bond_v: G bonds each (time order; G <= PLAN_MAX_GATES).
+// scratch: plan_scratch_elems(G, n) entries; tag_store: 64 entries.  ops:
+// plan_max_ops(G, n) entries; wgates: 2G; factors: 2G.  Returns the header
+// (status != 0 on failure).
+__host__ __device__ inline PlanHeader plan_haar_pair(int n, int G, const int16_t* bond_u,
+                                                     const int16_t* bond_v, int16_t* scratch, Op* ops,
+                                                     int2* wgates, int32_t* factors, int32_t* tag_store) {
   PlanCtx c;
   c.n = n;
   c.G = G;
   c.W = 2 * G;
   const int W = c.W;
-  int32_t* s = scratch;
+  int16_t* s = scratch;
   c.mbond = s;
   s += W;
   c.head = s;
@@ -314,6 +351,19 @@ __host__ __device__ inline PlanHeader plan_haar_pair(int n, int G, const int32_t
   s += n + 2;
   c.firstb = s;
   s += n + 2;
+  c.lab = s;
+  s += 2 * W;
+  c.outp = s;
+  s += W;
+  c.pendp = s;
+  s += W;
+  c.gflags = s;
+  s += W;
+  for (int i = 0; i < 4 * W; ++i) c.lab[i] = -1;  // lab, outp, pendp
+  c.first_pos = -1;
+  c.tmp_pos = -1;
+  c.tag = tag_store;
+  c.b = 0;
   c.ops = ops;
   c.wgates = wgates;
   c.factors = factors;
@@ -335,6 +385,10 @@ __host__ __device__ inline PlanHeader plan_haar_pair(int n, int G, const int32_t
   h.macs = 0.0;
   h.elems = 0.0;
 
+  if (G > PLAN_MAX_GATES) {
+    h.status = PLAN_ECAP;
+    return h;
+  }
   for (int i = 0; i < W; ++i) {
     int b = i < G ? bond_v[i] : bond_u[2 * G - 1 - i];
     if (b < 0 || b > n - 2) {
@@ -429,10 +483,8 @@ __host__ __device__ inline PlanHeader plan_haar_pair(int n, int G, const int32_t
     for (int f = c.head[k]; f >= 0; f = c.nextf[f]) factors[nf++] = f;
   }
   // ---- columns ----
-  Reg r;
-  r.b = 0;
-  for (int col = 0; col < n - 1 && c.status == PLAN_OK; ++col) plan_column(c, r, col);
-  if (c.status == PLAN_OK && r.b != 0) c.status = PLAN_EINTERNAL;
+  for (int col = 0; col < n - 1 && c.status == PLAN_OK; ++col) plan_column(c, col);
+  if (c.status == PLAN_OK && c.b != 0) c.status = PLAN_EINTERNAL;
 
   h.num_ops = c.num_ops;
   h.num_wgates = c.nw;

@@ -36,8 +36,6 @@ struct PlanJob {
   int64_t bonds_off;
   int n, G;
   int64_t num_pairs;
-  int32_t* scratch;
-  int64_t scratch_stride;
   Op* ops;
   int64_t ops_stride;
   int2* wgates;
@@ -49,18 +47,22 @@ struct PlanJob {
   int* num_large;
   int* num_failed;
   int cap_bits;    // largest boundary run in LDS
-  int small_bits;  // largest boundary run by the wave-per-pair launch
-  double* class_macs;  // complex MACs per launch class (small LDS, large LDS, HBM)
+  int tiny_bits;   // largest boundary run with 16 lanes per pair
+  int small_bits;  // largest boundary run with one wavefront per pair
+  int mid_bits;    // largest boundary run with 256 lanes per pair
+  double* class_macs;  // complex MACs per launch class (16, 64, 256, 1024 lanes, HBM)
 };
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
                      int slot_bits, int num_slots, hipStream_t s);
 int launch_plan_local_random(const PlanJob& j, hipStream_t s);
+size_t plan_lds_bytes(int G, int n);
 int sweep_elem_bytes(int precision);
 
 // Event timing of the sweep launches (enabled by fp_profile_begin).
-enum { KCLASS_LDS_SMALL = 0, KCLASS_LDS_LARGE = 1, KCLASS_HBM = 2, KCLASS_HEA = 3, KCLASS_COUNT = 4 };
+enum { KCLASS_LDS16 = 0, KCLASS_LDS64 = 1, KCLASS_LDS256 = 2, KCLASS_LDS1024 = 3, KCLASS_HBM = 4, KCLASS_HEA = 5,
+       KCLASS_COUNT = 6 };
 bool profiling();
 void profile_launch_begin(int kclass, hipStream_t s);
 void profile_launch_end(int kclass, double flops, hipStream_t s);

@@ -29,7 +29,7 @@ def _interpret(ops, wg, fac, l2, gates_u, gates_v):
         return m
 
     for op in ops:
-        t, p, q = int(op["type"]), int(op["p"]), int(op["q"])
+        t, p, q = int(op["type"]) & 3, int(op["p"]), int(op["q"])
         if t == 0:
             m = mat(int(op["arg"]))
             # R[(y_in, y_out), (x_in, x_out)] = M[2 x_out + y_out, 2 x_in + y_in]
