@@ -40,6 +40,8 @@ def parse():
                     help="comma list of step counts measured besides the headline ('' = none)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cv", action="store_true", help="skip the control-variate experiment (HEA n=40, L=6)")
+    ap.add_argument("--cv-surrogate", type=int, default=1000000)
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for PMC runs)")
     return ap.parse_args()
@@ -177,6 +179,13 @@ def main():
             except Exception as e:  # statistics only
                 per_depth[str(s)]["bits_error"] = str(e)
 
+    cv_res = None
+    if not args.no_cv:
+        from paper_2205_09900_amd import cv
+        cv_res = cv.experiment(n=40, layers=6, k=2, hidden=256, n_train=65536, n_exact=10000,
+                               n_surrogate=args.cv_surrogate, epochs=30)
+        cv_res.pop("history", None)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.n, args.depth, args.cpu_seconds, seed_base)
@@ -200,6 +209,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_depth": per_depth,
+        "control_variate": cv_res,
     }
     print(json.dumps(out))
 

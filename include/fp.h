@@ -267,6 +267,26 @@ int fp_mlp_backward(int n_in, int hidden, int64_t batch, const float* d_params,
                     float* d_grad, double* h_loss, void* stream);
 int fp_mlp_adam_step(int64_t count, float* d_params, const float* d_grad, float* d_adam,
                      int step, float lr, float beta1, float beta2, float eps, void* stream);
+/*
+ * fp_mlp_gemm -- the dense product the network runs on the MFMA units:
+ * C (M x N, row-major, ldc) = op(A) op(B), op(A) = A (M x K, lda) or, with
+ * trans_a, A^T for A stored K x M; likewise B (K x N).  float32 with float32
+ * accumulation.  Errors: FP_EINVAL, FP_EDEVICE.
+ */
+int fp_mlp_gemm(int M, int N, int K, const float* d_A, int lda, int trans_a, const float* d_B, int ldb,
+                int trans_b, float* d_C, int ldc, void* stream);
+
+/*
+ * fp_mlp_targets -- training targets t_i = scale * |Tr_i|^{2k} (float32) from a
+ * device trace array (2*num_pairs doubles).  Errors: FP_EINVAL, FP_EDEVICE.
+ * fp_cv_coefficient -- c = Cov(f, g) / Var(g) with f_i = |Tr_i|^{2k}, float64,
+ * fixed reduction order, written to *h_c (0 when g is constant).  Meant for
+ * a hold-out set disjoint from the pairs the estimate uses, so that the
+ * estimator stays unbiased.  Synchronises `stream`.
+ */
+int fp_mlp_targets(const double* d_trace, int64_t num_pairs, int k, double scale, float* d_t, void* stream);
+int fp_cv_coefficient(const double* d_trace, const float* d_g, int64_t num_pairs, int k, double* h_c,
+                      void* stream);
 
 /*
  * fp_frame_potential_cv -- control-variate estimate of F^(k):

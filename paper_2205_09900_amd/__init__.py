@@ -29,7 +29,7 @@ EXPORTS = [
     "fp_frame_potential", "fp_workspace_bytes_groups", "fp_contract_trace_groups",
     "fp_autotune_workspace_bytes", "fp_autotune", "fp_autotune_table", "fp_autotune_load",
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
-    "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step",
+    "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient",
     "fp_frame_potential_cv", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
@@ -86,6 +86,9 @@ def _load():
         "fp_mlp_backward": (I, [I, I, I64, P, P, P, P, P, P, P]),
         "fp_mlp_adam_step": (I, [I64, P, P, P, I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, P]),
+        "fp_mlp_gemm": (I, [I, I, I, P, I, I, P, I, I, P, I, P]),
+        "fp_mlp_targets": (I, [P, I64, I, D, P, P]),
+        "fp_cv_coefficient": (I, [P, P, I64, I, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_profile_begin": (I, []),
         "fp_profile_end": (I, [P, P, P]),
@@ -198,6 +201,59 @@ def fp_plan_local_random_host(n_qubits, bonds_u, bonds_v):
                                          bv.ctypes.data_as(ctypes.c_void_p), bits, ctypes.byref(peak),
                                          ctypes.byref(macs), ctypes.byref(ops)))
     return {"bits": list(bits), "peak_bits": peak.value, "macs": macs.value, "ops": ops.value}
+
+
+def fp_mlp_param_count(n_in, hidden):
+    return int(lib.fp_mlp_param_count(int(n_in), int(hidden)))
+
+
+def fp_mlp_act_floats(batch, hidden):
+    return int(lib.fp_mlp_act_floats(int(batch), int(hidden)))
+
+
+def fp_mlp_init(n_in, hidden, seed, d_params, stream=None):
+    return _check(lib.fp_mlp_init(int(n_in), int(hidden), int(seed), _ptr(d_params), _stream(stream)))
+
+
+def fp_mlp_features(ens, num_pairs, d_gates, d_x, stream=None):
+    return _check(lib.fp_mlp_features(ctypes.byref(_ens(ens)), int(num_pairs), _ptr(d_gates), _ptr(d_x),
+                                      _stream(stream)))
+
+
+def fp_mlp_forward(n_in, hidden, batch, d_params, d_x, d_y, d_act=None, stream=None):
+    return _check(lib.fp_mlp_forward(int(n_in), int(hidden), int(batch), _ptr(d_params), _ptr(d_x), _ptr(d_y),
+                                     _ptr(d_act), _stream(stream)))
+
+
+def fp_mlp_backward(n_in, hidden, batch, d_params, d_x, d_act, d_target, d_grad, want_loss=True, stream=None):
+    loss = ctypes.c_double(0)
+    _check(lib.fp_mlp_backward(int(n_in), int(hidden), int(batch), _ptr(d_params), _ptr(d_x), _ptr(d_act),
+                               _ptr(d_target), _ptr(d_grad), ctypes.byref(loss) if want_loss else None,
+                               _stream(stream)))
+    return loss.value if want_loss else None
+
+
+def fp_mlp_adam_step(count, d_params, d_grad, d_adam, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                     stream=None):
+    return _check(lib.fp_mlp_adam_step(int(count), _ptr(d_params), _ptr(d_grad), _ptr(d_adam), int(step),
+                                       float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+
+def fp_mlp_gemm(M, N, K, d_A, lda, trans_a, d_B, ldb, trans_b, d_C, ldc, stream=None):
+    return _check(lib.fp_mlp_gemm(int(M), int(N), int(K), _ptr(d_A), int(lda), int(trans_a), _ptr(d_B), int(ldb),
+                                  int(trans_b), _ptr(d_C), int(ldc), _stream(stream)))
+
+
+def fp_mlp_targets(d_trace, num_pairs, k, scale, d_t, stream=None):
+    return _check(lib.fp_mlp_targets(_ptr(d_trace), int(num_pairs), int(k), float(scale), _ptr(d_t),
+                                     _stream(stream)))
+
+
+def fp_cv_coefficient(d_trace, d_g, num_pairs, k, stream=None):
+    c = ctypes.c_double(0)
+    _check(lib.fp_cv_coefficient(_ptr(d_trace), _ptr(d_g), int(num_pairs), int(k), ctypes.byref(c),
+                                 _stream(stream)))
+    return c.value
 
 
 KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")

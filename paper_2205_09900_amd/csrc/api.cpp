@@ -550,6 +550,19 @@ int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t n
   return run_frame_potential_cv(d_trace_B, d_g_B, nB, d_g_C, nC, k, c, h_F, h_stderr, (hipStream_t)stream);
 }
 
+int fp_mlp_targets(const double* d_trace, int64_t num_pairs, int k, double scale, float* d_t, void* stream) {
+  if (!d_trace || !d_t) return set_error(FP_EINVAL, "NULL buffer");
+  if (num_pairs < 0 || k < 1 || k > 8) return set_error(FP_EINVAL, "bad arguments");
+  if (num_pairs == 0) return FP_OK;
+  return run_targets(d_trace, num_pairs, k, scale, d_t, (hipStream_t)stream);
+}
+
+int fp_cv_coefficient(const double* d_trace, const float* d_g, int64_t num_pairs, int k, double* h_c, void* stream) {
+  if (!d_trace || !d_g || !h_c) return set_error(FP_EINVAL, "NULL argument");
+  if (num_pairs < 2 || k < 1 || k > 8) return set_error(FP_EINVAL, "bad arguments");
+  return run_cv_coefficient(d_trace, d_g, num_pairs, k, h_c, (hipStream_t)stream);
+}
+
 int fp_plan_info(const fp_ensemble_t* ens, int32_t* out_bits, int32_t* peak_bits, double* macs, int64_t* ops) {
   int rc = check_ensemble(ens);
   if (rc) return rc;

@@ -24,22 +24,4 @@ int fp_autotune_table(char* buf, size_t cap) {
   return FP_OK;
 }
 int fp_autotune_load(const char*) { return set_error(FP_ENOTIMPL, "not built"); }
-int64_t fp_mlp_param_count(int n_in, int hidden) {
-  return (int64_t)n_in * hidden + hidden + 2 * ((int64_t)hidden * hidden + hidden) + hidden + 1;
-}
-int64_t fp_mlp_act_floats(int64_t batch, int hidden) { return batch * hidden * 6; }
-int fp_mlp_init(int, int, uint64_t, float*, void*) { return set_error(FP_ENOTIMPL, "not built"); }
-int fp_mlp_features(const fp_ensemble_t*, int64_t, const void*, float*, void*) {
-  return set_error(FP_ENOTIMPL, "not built");
-}
-int fp_mlp_forward(int, int, int64_t, const float*, const float*, float*, float*, void*) {
-  return set_error(FP_ENOTIMPL, "not built");
-}
-int fp_mlp_backward(int, int, int64_t, const float*, const float*, const float*, const float*, float*, double*,
-                    void*) {
-  return set_error(FP_ENOTIMPL, "not built");
-}
-int fp_mlp_adam_step(int64_t, float*, const float*, float*, int, float, float, float, float, void*) {
-  return set_error(FP_ENOTIMPL, "not built");
-}
 }

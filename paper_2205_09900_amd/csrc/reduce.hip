@@ -281,4 +281,92 @@ int run_frame_potential_cv(const double* trB, const float* gB, int64_t nB, const
   return FP_OK;
 }
 
+// ---- surrogate targets and the control-variate coefficient ----------------------
+__global__ void __launch_bounds__(256) targets_kernel(const double* __restrict__ tr, int64_t n, int k, double scale,
+                                                      float* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double a = tr[2 * i] * tr[2 * i] + tr[2 * i + 1] * tr[2 * i + 1];
+  double f = 1.0;
+  for (int j = 0; j < k; ++j) f *= a;
+  t[i] = (float)(scale * f);
+}
+
+struct Co {
+  double n, mf, mg, cfg, m2g;
+};
+
+__device__ __forceinline__ Co co_merge(Co a, Co b) {
+  Co r;
+  r.n = a.n + b.n;
+  if (r.n == 0.0) return Co{0.0, 0.0, 0.0, 0.0, 0.0};
+  const double df = b.mf - a.mf, dg = b.mg - a.mg, w = a.n * b.n / r.n;
+  r.mf = a.mf + df * (b.n / r.n);
+  r.mg = a.mg + dg * (b.n / r.n);
+  r.cfg = a.cfg + b.cfg + df * dg * w;
+  r.m2g = a.m2g + b.m2g + dg * dg * w;
+  return r;
+}
+
+// Per-workgroup co-moments of f = |Tr|^{2k} and g.
+__global__ void __launch_bounds__(RED_THREADS) cvcoef_kernel(const double* __restrict__ tr, const float* __restrict__ g,
+                                                             int64_t n, int k, Co* __restrict__ part) {
+  __shared__ Co sh[RED_THREADS];
+  Co c{0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
+    const double a = tr[2 * i] * tr[2 * i] + tr[2 * i + 1] * tr[2 * i + 1];
+    double f = 1.0;
+    for (int j = 0; j < k; ++j) f *= a;
+    const double gv = (double)g[i];
+    c.n += 1.0;
+    const double df = f - c.mf, dg = gv - c.mg;
+    c.mf += df / c.n;
+    c.mg += dg / c.n;
+    c.cfg += df * (gv - c.mg);
+    c.m2g += dg * (gv - c.mg);
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  for (int s2 = RED_THREADS / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sh[threadIdx.x] = co_merge(sh[threadIdx.x], sh[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void cvcoef_final(const Co* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Co a{0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b) a = co_merge(a, part[b]);
+  out[0] = a.m2g > 0.0 ? a.cfg / a.m2g : 0.0;
+  out[1] = a.mf;
+  out[2] = a.mg;
+}
+
+int run_targets(const double* tr, int64_t n, int k, double scale, float* t, hipStream_t s) {
+  hipLaunchKernelGGL(targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tr, n, k, scale, t);
+  return check_launch("targets");
+}
+
+int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, double* c_out, hipStream_t s) {
+  const int nb = red_blocks(n);
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, sizeof(Co) * nb + 4 * sizeof(double), s), "hipMallocAsync(cvcoef)");
+  if (rc) return rc;
+  Co* part = (Co*)ws;
+  double* out = (double*)(part + nb);
+  hipLaunchKernelGGL(cvcoef_kernel, dim3(nb), dim3(RED_THREADS), 0, s, tr, g, n, k, part);
+  hipLaunchKernelGGL(cvcoef_final, dim3(1), dim3(64), 0, s, part, nb, out);
+  rc = check_launch("cv_coefficient");
+  double host[3] = {0.0, 0.0, 0.0};
+  if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy c");
+  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(cvcoef)");
+  int rc3 = check_hip(hipStreamSynchronize(s), "sync(cvcoef)");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  *c_out = host[0];
+  return FP_OK;
+}
+
 }  // namespace fp
