@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate experiment (HEA n=40, L=6)")
+    ap.add_argument("--no-suite", action="store_true", help="skip the other ensembles (brickwork n=6, n=20; HEA n=30)")
+    ap.add_argument("--suite-pairs", type=int, default=100000)
     ap.add_argument("--cv-surrogate", type=int, default=1000000)
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for PMC runs)")
@@ -77,6 +79,79 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base):
     prof = fp.fp_profile_end()
     return {"wall_s": wall, "event_ms": ev0.elapsed_time(ev1), "prof": prof, "F": f[0], "SE": f[1],
             "ws_bytes": wsb}
+
+
+def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None):
+    """Throughput of sample + contract + reduce for one fixed-topology ensemble; traces of the
+    last step are returned for the precision comparison."""
+    ens = fp.Ensemble(ansatz, n, depth)
+    chunk = chunk or pairs
+    gates = fp.alloc_gates(ens, chunk, prec)
+    trace = torch.empty(2 * pairs, dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(256, fp.fp_workspace_bytes(ens, chunk, prec)), dtype=torch.uint8, device="cuda")
+
+    def step():
+        for o in range(0, pairs, chunk):
+            m = min(chunk, pairs - o)
+            fp.fp_sample_gates(ens, m, seed, o, prec, gates)
+            fp.fp_contract_trace_batch(ens, m, prec, gates, trace[2 * o: 2 * (o + m)], ws)
+        return fp.fp_frame_potential(trace, pairs, 3)
+
+    step()
+    torch.cuda.synchronize()
+    fp.fp_profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = fp.fp_profile_end()
+    kms = sum(v["ms"] for v in prof.values())
+    flops = sum(v["flops"] for v in prof.values())
+    return {"contractions_per_s": pairs * steps / wall, "F": f[0], "SE": f[1],
+            "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
+            "kernel_ms_per_step": kms / steps}, trace
+
+
+def precision_error(np, t32, t64, f32, f64):
+    a = t32.cpu().numpy().reshape(-1, 2)
+    b = t64.cpu().numpy().reshape(-1, 2)
+    za, zb = a[:, 0] + 1j * a[:, 1], b[:, 0] + 1j * b[:, 1]
+    rms = float(np.sqrt(np.mean(np.abs(zb) ** 2)))
+    rel = np.abs(za - zb) / np.maximum(np.abs(zb), 1e-3 * rms)
+    return {"max_floored_rel_trace_err": float(rel.max()), "median_rel_trace_err": float(np.median(rel)),
+            "p99_rel_trace_err": float(np.quantile(rel, 0.99)),
+            "rel_err_F_k": [abs(x - y) / abs(y) for x, y in zip(f32, f64)]}
+
+
+def suite(fp, torch, np, synth, pairs):
+    out = {}
+    # brickwork n = 6, depths 1..6, 2000 pairs, complex128
+    r = {}
+    for d in range(1, 7):
+        r[str(d)], _ = fixed_topology(fp, torch, fp.BRICKWORK, 6, d, 2000, fp.C128, synth.workload_seed(1, d))
+    out["brickwork_n6_c128"] = r
+    # brickwork n = 20, depths 2..10, complex64 against complex128 on the same gates' seeds
+    r = {}
+    for d in range(2, 11):
+        np_ = pairs if d <= 8 else max(1000, pairs // 20)
+        seed = synth.workload_seed(2, d)
+        steps = 3 if d <= 8 else 1
+        r32, t32 = fixed_topology(fp, torch, fp.BRICKWORK, 20, d, np_, fp.C64, seed, steps=steps,
+                                  chunk=min(np_, 20000))
+        r64, t64 = fixed_topology(fp, torch, fp.BRICKWORK, 20, d, np_, fp.C128, seed, steps=1,
+                                  chunk=min(np_, 20000))
+        r32["pairs"] = np_
+        r32["c128_contractions_per_s"] = r64["contractions_per_s"]
+        r32["c64_vs_c128"] = precision_error(np, t32, t64, r32["F"], r64["F"])
+        r[str(d)] = r32
+    out["brickwork_n20"] = r
+    # HEA n = 30, layers 1..8, complex64
+    r = {}
+    for L in range(1, 9):
+        r[str(L)], _ = fixed_topology(fp, torch, fp.HEA, 30, L, pairs, fp.C64, synth.workload_seed(3, L))
+    out["hea_n30"] = r
+    return out
 
 
 def bits_stats(fp, np, n, depth, pairs, seed_base, sample=400):
@@ -179,6 +254,10 @@ def main():
             except Exception as e:  # statistics only
                 per_depth[str(s)]["bits_error"] = str(e)
 
+    suite_res = None
+    if not args.no_suite:
+        suite_res = suite(fp, torch, np, synth, args.suite_pairs)
+
     cv_res = None
     if not args.no_cv:
         from paper_2205_09900_amd import cv
@@ -210,6 +289,7 @@ def main():
         "cpu_baseline": cpu,
         "per_depth": per_depth,
         "control_variate": cv_res,
+        "ensembles": suite_res,
     }
     print(json.dumps(out))
 

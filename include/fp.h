@@ -287,6 +287,23 @@ int fp_mlp_gemm(int M, int N, int K, const float* d_A, int lda, int trans_a, con
 int fp_mlp_targets(const double* d_trace, int64_t num_pairs, int k, double scale, float* d_t, void* stream);
 int fp_cv_coefficient(const double* d_trace, const float* d_g, int64_t num_pairs, int k, double* h_c,
                       void* stream);
+/*
+ * Log-space fitting of the surrogate (|Tr|^2 is close to a product over
+ * qubits, so its logarithm is close to additive in the angles):
+ * fp_log_moments -- mean and sample standard deviation (float64) of
+ *   L_i = log(|Tr_i|^2 + eps) over a device trace array.  Synchronises.
+ * fp_mlp_log_targets -- t_i = (L_i - mean) / std_dev as float32.
+ * fp_mlp_link -- g_i = exp(k (mean + std_dev y_i) - shift) as float32: the
+ *   network output y mapped back to |Tr|^{2k} in units of e^shift (the
+ *   exponent is capped at 80).
+ * Errors: FP_EINVAL, FP_EDEVICE.
+ */
+int fp_log_moments(const double* d_trace, int64_t num_pairs, double eps, double* h_mean, double* h_std,
+                   void* stream);
+int fp_mlp_log_targets(const double* d_trace, int64_t num_pairs, double eps, double mean, double std_dev,
+                       float* d_t, void* stream);
+int fp_mlp_link(const float* d_y, int64_t n, int k, double mean, double std_dev, double shift, float* d_g,
+                void* stream);
 
 /*
  * fp_frame_potential_cv -- control-variate estimate of F^(k):

@@ -29,7 +29,8 @@ EXPORTS = [
     "fp_frame_potential", "fp_workspace_bytes_groups", "fp_contract_trace_groups",
     "fp_autotune_workspace_bytes", "fp_autotune", "fp_autotune_table", "fp_autotune_load",
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
-    "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient",
+    "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient", "fp_log_moments",
+    "fp_mlp_log_targets", "fp_mlp_link",
     "fp_frame_potential_cv", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
@@ -89,6 +90,9 @@ def _load():
         "fp_mlp_gemm": (I, [I, I, I, P, I, I, P, I, I, P, I, P]),
         "fp_mlp_targets": (I, [P, I64, I, D, P, P]),
         "fp_cv_coefficient": (I, [P, P, I64, I, P, P]),
+        "fp_log_moments": (I, [P, I64, D, P, P, P]),
+        "fp_mlp_log_targets": (I, [P, I64, D, D, D, P, P]),
+        "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_profile_begin": (I, []),
         "fp_profile_end": (I, [P, P, P]),
@@ -254,6 +258,24 @@ def fp_cv_coefficient(d_trace, d_g, num_pairs, k, stream=None):
     _check(lib.fp_cv_coefficient(_ptr(d_trace), _ptr(d_g), int(num_pairs), int(k), ctypes.byref(c),
                                  _stream(stream)))
     return c.value
+
+
+def fp_log_moments(d_trace, num_pairs, eps=1e-30, stream=None):
+    m = ctypes.c_double(0)
+    sd = ctypes.c_double(0)
+    _check(lib.fp_log_moments(_ptr(d_trace), int(num_pairs), float(eps), ctypes.byref(m), ctypes.byref(sd),
+                              _stream(stream)))
+    return m.value, sd.value
+
+
+def fp_mlp_log_targets(d_trace, num_pairs, eps, mean, std_dev, d_t, stream=None):
+    return _check(lib.fp_mlp_log_targets(_ptr(d_trace), int(num_pairs), float(eps), float(mean), float(std_dev),
+                                         _ptr(d_t), _stream(stream)))
+
+
+def fp_mlp_link(d_y, n, k, mean, std_dev, shift, d_g, stream=None):
+    return _check(lib.fp_mlp_link(_ptr(d_y), int(n), int(k), float(mean), float(std_dev), float(shift), _ptr(d_g),
+                                  _stream(stream)))
 
 
 KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")

@@ -557,6 +557,26 @@ int fp_mlp_targets(const double* d_trace, int64_t num_pairs, int k, double scale
   return run_targets(d_trace, num_pairs, k, scale, d_t, (hipStream_t)stream);
 }
 
+int fp_log_moments(const double* d_trace, int64_t num_pairs, double eps, double* h_mean, double* h_std,
+                   void* stream) {
+  if (!d_trace || !h_mean || !h_std || num_pairs < 2 || !(eps >= 0.0)) return set_error(FP_EINVAL, "bad arguments");
+  return run_log_moments(d_trace, num_pairs, eps, h_mean, h_std, (hipStream_t)stream);
+}
+
+int fp_mlp_log_targets(const double* d_trace, int64_t num_pairs, double eps, double mean, double std_dev, float* d_t,
+                       void* stream) {
+  if (!d_trace || !d_t || num_pairs < 0 || !(eps >= 0.0)) return set_error(FP_EINVAL, "bad arguments");
+  if (num_pairs == 0) return FP_OK;
+  return run_log_targets(d_trace, num_pairs, eps, mean, std_dev, d_t, (hipStream_t)stream);
+}
+
+int fp_mlp_link(const float* d_y, int64_t n, int k, double mean, double std_dev, double shift, float* d_g,
+                void* stream) {
+  if (!d_y || !d_g || n < 0 || k < 1 || k > 8) return set_error(FP_EINVAL, "bad arguments");
+  if (n == 0) return FP_OK;
+  return run_link(d_y, n, k, mean, std_dev, shift, d_g, (hipStream_t)stream);
+}
+
 int fp_cv_coefficient(const double* d_trace, const float* d_g, int64_t num_pairs, int k, double* h_c, void* stream) {
   if (!d_trace || !d_g || !h_c) return set_error(FP_EINVAL, "NULL argument");
   if (num_pairs < 2 || k < 1 || k > 8) return set_error(FP_EINVAL, "bad arguments");

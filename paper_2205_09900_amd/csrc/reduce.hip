@@ -369,4 +369,79 @@ int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, doubl
   return FP_OK;
 }
 
+// ---- log-space targets of the surrogate -------------------------------------------
+// Moments of L_i = log(|Tr_i|^2 + eps) (Welford, float64, fixed order).
+__global__ void __launch_bounds__(RED_THREADS) logmom_kernel(const double* __restrict__ tr, int64_t n, double eps,
+                                                             Welford* __restrict__ part) {
+  __shared__ Welford sw[RED_THREADS];
+  Welford w{0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS)
+    welford_add(w, log(tr[2 * i] * tr[2 * i] + tr[2 * i + 1] * tr[2 * i + 1] + eps));
+  sw[threadIdx.x] = w;
+  __syncthreads();
+  for (int s2 = RED_THREADS / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sw[threadIdx.x] = chan_merge(sw[threadIdx.x], sw[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sw[0];
+}
+
+__global__ void logmom_final(const Welford* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Welford a{0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b) a = chan_merge(a, part[b]);
+  out[0] = a.mean;
+  out[1] = a.n > 1.0 ? sqrt(a.m2 / (a.n - 1.0)) : 0.0;
+}
+
+// t_i = (log(|Tr_i|^2 + eps) - mu) / sigma
+__global__ void __launch_bounds__(256) logtargets_kernel(const double* __restrict__ tr, int64_t n, double eps, double mu,
+                                                         double inv_sigma, float* __restrict__ t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  t[i] = (float)((log(tr[2 * i] * tr[2 * i] + tr[2 * i + 1] * tr[2 * i + 1] + eps) - mu) * inv_sigma);
+}
+
+// g_i = exp(k (mu + sigma y_i) - shift): |Tr|^{2k} predicted from the log-space output, in units of e^shift.
+__global__ void __launch_bounds__(256) link_kernel(const float* __restrict__ y, int64_t n, int k, double mu,
+                                                   double sigma, double shift, float* __restrict__ g) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = (double)k * (mu + sigma * (double)y[i]) - shift;
+  g[i] = (float)exp(v < 80.0 ? v : 80.0);
+}
+
+int run_log_moments(const double* tr, int64_t n, double eps, double* mu, double* sigma, hipStream_t s) {
+  const int nb = red_blocks(n);
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, sizeof(Welford) * nb + 2 * sizeof(double), s), "hipMallocAsync(logmom)");
+  if (rc) return rc;
+  Welford* part = (Welford*)ws;
+  double* out = (double*)(part + nb);
+  hipLaunchKernelGGL(logmom_kernel, dim3(nb), dim3(RED_THREADS), 0, s, tr, n, eps, part);
+  hipLaunchKernelGGL(logmom_final, dim3(1), dim3(64), 0, s, part, nb, out);
+  rc = check_launch("log_moments");
+  double host[2] = {0.0, 0.0};
+  if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy moments");
+  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(logmom)");
+  int rc3 = check_hip(hipStreamSynchronize(s), "sync(logmom)");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  *mu = host[0];
+  *sigma = host[1];
+  return FP_OK;
+}
+
+int run_log_targets(const double* tr, int64_t n, double eps, double mu, double sigma, float* t, hipStream_t s) {
+  hipLaunchKernelGGL(logtargets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tr, n, eps, mu,
+                     sigma > 0.0 ? 1.0 / sigma : 1.0, t);
+  return check_launch("log_targets");
+}
+
+int run_link(const float* y, int64_t n, int k, double mu, double sigma, double shift, float* g, hipStream_t s) {
+  hipLaunchKernelGGL(link_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, n, k, mu, sigma, shift, g);
+  return check_launch("link");
+}
+
 }  // namespace fp

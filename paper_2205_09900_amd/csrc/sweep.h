@@ -81,6 +81,9 @@ int hea_bits(int L);
 
 int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
                         hipStream_t s);
+int run_log_moments(const double* tr, int64_t n, double eps, double* mu, double* sigma, hipStream_t s);
+int run_log_targets(const double* tr, int64_t n, double eps, double mu, double sigma, float* t, hipStream_t s);
+int run_link(const float* y, int64_t n, int k, double mu, double sigma, double shift, float* g, hipStream_t s);
 int run_targets(const double* tr, int64_t n, int k, double scale, float* t, hipStream_t s);
 int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, double* c_out, hipStream_t s);
 int run_frame_potential_cv(const double* trB, const float* gB, int64_t nB, const float* gC, int64_t nC,

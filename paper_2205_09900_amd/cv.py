@@ -1,7 +1,11 @@
 """Learned control variate for F^(k) of the hardware-efficient ansatz.
 
 A small network g predicts |Tr(U^dagger V)|^{2k} from the sines and cosines
-of the circuit angles.  It is trained on exact traces that the method
+of the circuit angles.  By default it is fitted in log space: it learns the
+standardised log |Tr|^2 (close to a sum over qubits, since the trace of a
+shallow ansatz is close to a product of per-qubit factors), and
+g = exp(k * prediction) is the control variate; target="power" fits
+|Tr|^{2k} / F directly.  It is trained on exact traces that the method
 computes, the coefficient c = Cov(f, g)/Var(g) is fixed on a hold-out set,
 and then
     F_CV = mean_B(f - c g) + c mean_C(g)
@@ -21,9 +25,11 @@ import numpy as np
 import torch
 
 from . import (C64, HEA, Ensemble, fp_contract_trace_batch, fp_cv_coefficient, fp_frame_potential,
-               fp_frame_potential_cv, fp_mlp_act_floats, fp_mlp_adam_step, fp_mlp_backward, fp_mlp_features,
-               fp_mlp_forward, fp_mlp_init, fp_mlp_param_count, fp_mlp_targets, fp_sample_gates, alloc_gates,
-               workspace)
+               fp_frame_potential_cv, fp_log_moments, fp_mlp_act_floats, fp_mlp_adam_step, fp_mlp_backward,
+               fp_mlp_features, fp_mlp_forward, fp_mlp_init, fp_mlp_link, fp_mlp_log_targets, fp_mlp_param_count,
+               fp_mlp_targets, fp_sample_gates, alloc_gates, workspace)
+
+LOG_EPS = 1e-30
 
 
 def _sync():
@@ -71,8 +77,17 @@ def predict(n_in, hidden, params, x, chunk=65536):
     return y
 
 
+def link(model, y):
+    """Network output -> control variate g in units of the training F^(k)."""
+    if model["target"] == "power":
+        return y
+    g = torch.empty_like(y)
+    fp_mlp_link(y, y.numel(), model["k"], model["log_mean"], model["log_std"], model["log_shift"], g)
+    return g
+
+
 def train_surrogate(ens, k=2, hidden=256, n_train=65536, holdout_frac=0.1, batch=1024, epochs=30, lr=1e-3,
-                    seed=0xC0FFEE, patience=4, log=None):
+                    seed=0xC0FFEE, patience=4, log=None, target="log"):
     """Train g on exact |Tr|^{2k} of n_train fresh pairs; returns a dict with the
     parameters (best hold-out loss), the target scale, c on the hold-out and timings."""
     t0 = time.perf_counter()
@@ -81,7 +96,12 @@ def train_surrogate(ens, k=2, hidden=256, n_train=65536, holdout_frac=0.1, batch
     f_mean, _ = fp_frame_potential(tr, n_train, k)
     scale = 1.0 / f_mean[k - 1]
     t = torch.empty(n_train, dtype=torch.float32, device="cuda")
-    fp_mlp_targets(tr, n_train, k, scale, t)
+    log_mean = log_std = 0.0
+    if target == "log":
+        log_mean, log_std = fp_log_moments(tr, n_train, LOG_EPS)
+        fp_mlp_log_targets(tr, n_train, LOG_EPS, log_mean, log_std, t)
+    else:
+        fp_mlp_targets(tr, n_train, k, scale, t)
     n_hold = int(n_train * holdout_frac)
     n_fit = n_train - n_hold
     _sync()
@@ -124,16 +144,19 @@ def train_surrogate(ens, k=2, hidden=256, n_train=65536, holdout_frac=0.1, batch
                 break
     _sync()
     t_train = time.perf_counter() - t1
-    # c on the hold-out, with g in the network's units
-    g_hold = predict(n_in, hidden, best_p, x[n_fit:])
+    model = {"target": target, "k": k, "log_mean": log_mean, "log_std": log_std,
+             "log_shift": math.log(f_mean[k - 1])}
+    # c on the hold-out
+    g_hold = link(model, predict(n_in, hidden, best_p, x[n_fit:]))
     c = fp_cv_coefficient(tr[2 * n_fit:], g_hold, n_hold, k)
     # correlation on the hold-out (diagnostic)
     f_hold = torch.empty(n_hold, dtype=torch.float32, device="cuda")
-    fp_mlp_targets(tr[2 * n_fit:], n_hold, k, scale, f_hold)
+    fp_mlp_targets(tr[2 * n_fit:], n_hold, k, scale, f_hold)   # f / F_train, same units as g
     rho = float(torch.corrcoef(torch.stack([f_hold.double(), g_hold.double()]))[0, 1])
-    return {"params": best_p, "n_in": n_in, "hidden": hidden, "scale": scale, "c": c, "rho_holdout": rho,
+    model.update({"params": best_p, "n_in": n_in, "hidden": hidden, "scale": scale, "c": c, "rho_holdout": rho,
             "holdout_mse": best, "epochs_run": len(history), "history": history,
-            "t_data_s": t_data, "t_train_s": t_train, "n_train": n_train}
+            "t_data_s": t_data, "t_train_s": t_train, "n_train": n_train})
+    return model
 
 
 def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB0B, seed_surr=0xCAFE):
@@ -142,11 +165,11 @@ def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB
     _sync()
     t0 = time.perf_counter()
     tr, x = exact_traces(ens, n_exact, seed_exact, 0, with_features=True)
-    g_b = predict(n_in, hidden, params, x)
+    g_b = link(model, predict(n_in, hidden, params, x))
     _sync()
     t_exact = time.perf_counter() - t0
     t1 = time.perf_counter()
-    g_c = surrogate_values(ens, params, hidden, n_surrogate, seed_surr)
+    g_c = link(model, surrogate_values(ens, params, hidden, n_surrogate, seed_surr))
     _sync()
     t_surr = time.perf_counter() - t1
     f_cv, se_cv = fp_frame_potential_cv(tr, g_b, n_exact, g_c, n_surrogate, k, c)
@@ -172,10 +195,11 @@ def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB
 
 
 def experiment(n=40, layers=6, k=2, hidden=256, n_train=65536, n_exact=10000, n_surrogate=1000000, epochs=30,
-               log=None):
+               log=None, target="log"):
     ens = Ensemble(HEA, n, layers)
-    model = train_surrogate(ens, k=k, hidden=hidden, n_train=n_train, epochs=epochs, log=log)
+    model = train_surrogate(ens, k=k, hidden=hidden, n_train=n_train, epochs=epochs, log=log, target=target)
     res = estimate(ens, model, k=k, n_exact=n_exact, n_surrogate=n_surrogate)
     res.update({k_: v for k_, v in model.items() if k_ not in ("params",)})
+    res["rho_holdout_link"] = model["rho_holdout"]
     res["workload"] = f"hea_n{n}_L{layers}_cv"
     return res
