@@ -175,6 +175,16 @@ def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB
     f_cv, se_cv = fp_frame_potential_cv(tr, g_b, n_exact, g_c, n_surrogate, k, c)
     f_pl, se_pl = fp_frame_potential(tr, n_exact, k)
     f_pl, se_pl = f_pl[k - 1], se_pl[k - 1]
+    # Fallback rule, decided from the hold-out only (so it cannot bias the estimate):
+    # with correlation rho and unit costs tau_e (exact) and tau_s (surrogate), the best
+    # allocation needs time proportional to (sqrt((1-rho^2) tau_e) + |rho| sqrt(tau_s))^2
+    # against tau_e for the plain mean; use the control variate only if that is smaller.
+    rho = model["rho_holdout"]
+    rho = 0.0 if rho != rho else rho
+    tau_e0, tau_s0 = t_exact / n_exact, t_surr / n_surrogate
+    predicted_ratio = (math.sqrt(max(1.0 - rho * rho, 0.0) * tau_e0) + abs(rho) * math.sqrt(tau_s0)) ** 2 / tau_e0
+    use_cv = predicted_ratio < 1.0
+    f_used, se_used = (f_cv, se_cv) if use_cv else (f_pl, se_pl)
     # variance components (diagnostics for the time-to-precision extrapolation)
     var_g = float(g_c.double().var())
     var_r = max(se_cv ** 2 - c * c * var_g / n_surrogate, 0.0) * n_exact
@@ -184,7 +194,9 @@ def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB
     target = (0.01 * f_pl) ** 2
     t_plain_1pct = var_f / target * tau_e
     t_cv_1pct = (math.sqrt(var_r * tau_e) + abs(c) * math.sqrt(var_g * tau_s)) ** 2 / target
-    return {"F_cv": f_cv, "SE_cv": se_cv, "F_plain": f_pl, "SE_plain": se_pl, "c": c,
+    return {"F": f_used, "SE": se_used, "used_control_variate": use_cv,
+            "predicted_time_ratio_from_holdout": predicted_ratio,
+            "F_cv": f_cv, "SE_cv": se_cv, "F_plain": f_pl, "SE_plain": se_pl, "c": c,
             "t_exact_s": t_exact, "t_surrogate_s": t_surr, "n_exact": n_exact, "n_surrogate": n_surrogate,
             "sec_per_exact_pair": tau_e, "sec_per_surrogate": tau_s,
             "var_f": var_f, "var_residual": var_r, "var_g": var_g,
