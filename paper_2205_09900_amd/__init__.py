@@ -278,6 +278,56 @@ def fp_mlp_link(d_y, n, k, mean, std_dev, shift, d_g, stream=None):
                                   _stream(stream)))
 
 
+def _groups_args(ensembles, groups):
+    E = (Ensemble * len(ensembles))(*[_ens(e) for e in ensembles])
+    G = (Group * len(groups))()
+    for i, g in enumerate(groups):
+        G[i].ensemble_index, G[i].precision, G[i].first_pair, G[i].num_pairs = (int(x) for x in g)
+    return E, G
+
+
+def fp_workspace_bytes_groups(ensembles, groups):
+    """ensembles: list of (ansatz, n, depth); groups: list of (ensemble_index, precision, first_pair, num_pairs)."""
+    E, G = _groups_args(ensembles, groups)
+    out = ctypes.c_size_t(0)
+    _check(lib.fp_workspace_bytes_groups(E, len(ensembles), G, len(groups), ctypes.byref(out)))
+    return int(out.value)
+
+
+def fp_contract_trace_groups(ensembles, groups, gate_buffers, d_trace, d_ws, stream=None):
+    E, G = _groups_args(ensembles, groups)
+    ptrs = (ctypes.c_void_p * len(groups))(*[g.data_ptr() for g in gate_buffers])
+    wsb = d_ws.numel() * d_ws.element_size()
+    return _check(lib.fp_contract_trace_groups(E, len(ensembles), G, len(groups), ptrs, _ptr(d_trace), _ptr(d_ws),
+                                               wsb, _stream(stream)))
+
+
+def fp_autotune_workspace_bytes(ens, precision):
+    return int(lib.fp_autotune_workspace_bytes(ctypes.byref(_ens(ens)), int(precision)))
+
+
+def fp_autotune(ens, precision, d_ws=None, stream=None):
+    if d_ws is None:
+        d_ws = torch.empty(max(256, fp_autotune_workspace_bytes(ens, precision)), dtype=torch.uint8, device="cuda")
+    choice = ctypes.c_int(-1)
+    _check(lib.fp_autotune(ctypes.byref(_ens(ens)), int(precision), _ptr(d_ws),
+                           d_ws.numel() * d_ws.element_size(), ctypes.byref(choice), _stream(stream)))
+    return choice.value
+
+
+TILE_NAMES = ("16x16", "64x4", "64x1", "256x1", "512x1", "1024x1")
+
+
+def fp_autotune_table():
+    buf = ctypes.create_string_buffer(1 << 20)
+    _check(lib.fp_autotune_table(buf, len(buf)))
+    return buf.value.decode()
+
+
+def fp_autotune_load(text):
+    return _check(lib.fp_autotune_load(text.encode()))
+
+
 KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
 
 

@@ -15,6 +15,7 @@
 #include "plan.h"
 #include "sweep.h"
 #include "tune.h"
+#include "dispatch.h"
 
 namespace fp {
 
@@ -35,7 +36,7 @@ int check_hip(hipError_t e, const char* what) {
 
 int check_launch(const char* what) { return check_hip(hipGetLastError(), what); }
 
-static int check_ensemble(const fp_ensemble_t* e) {
+int check_ensemble(const fp_ensemble_t* e) {
   if (!e) return set_error(FP_EINVAL, "ensemble is NULL");
   if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_HEA_RYRZ_CZ)
     return set_error(FP_EINVAL, "unknown ansatz %d", e->ansatz);
@@ -48,7 +49,7 @@ static int check_ensemble(const fp_ensemble_t* e) {
   return FP_OK;
 }
 
-static int check_precision(int p) {
+int check_precision(int p) {
   if (p < FP_C128 || p > FP_BF16X3) return set_error(FP_EINVAL, "unknown precision %d", p);
   return FP_OK;
 }
@@ -95,18 +96,11 @@ static int host_plan_brickwork(int n, int depth, HostPlan* out) {
   return host_plan_pair(n, G, b.data(), b.data(), out);
 }
 
-struct DevPlan {
-  PlanHeader hdr;
-  Op* ops = nullptr;
-  int2* wg = nullptr;
-  int32_t* fac = nullptr;
-  PlanHeader* dhdr = nullptr;
-};
 
 static std::mutex g_plan_mu;
 static std::map<std::tuple<int, int, int>, DevPlan> g_plans;  // (device, n, depth)
 
-static int get_brickwork_plan(int n, int depth, DevPlan* out) {
+int get_brickwork_plan(int n, int depth, DevPlan* out) {
   int dev = 0;
   int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
   if (rc) return rc;
@@ -139,15 +133,10 @@ static int get_brickwork_plan(int n, int depth, DevPlan* out) {
 
 // ---- auxiliary streams: the sweep classes of one batch touch disjoint pairs
 // and run side by side (all streams at the default priority) --------------------
-constexpr int NUM_AUX = 4;
-struct Aux {
-  hipStream_t s[NUM_AUX];
-  hipEvent_t fork, join[NUM_AUX];
-};
 static std::mutex g_aux_mu;
 static std::map<int, Aux> g_aux;
 
-static int get_aux(Aux* out) {
+int get_aux(Aux* out) {
   int dev = 0;
   int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
   if (rc) return rc;
@@ -171,7 +160,7 @@ static int get_aux(Aux* out) {
 }
 
 // ---- sizes -------------------------------------------------------------------
-static int lds_bits_max(int precision) { return precision == FP_C128 ? 13 : 14; }
+int lds_bits_max(int precision) { return precision == FP_C128 ? 13 : 14; }
 
 // Local random: per-pair plan region.
 struct LrLayout {
@@ -208,7 +197,7 @@ static int lr_predicted_bits(int n, int S) {
   return b > 30 ? 30 : b;
 }
 
-static int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precision, size_t* out) {
+int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precision, size_t* out) {
   const int elem = sweep_elem_bytes(precision);
   if (e->ansatz == FP_HEA_RYRZ_CZ) {
     *out = 0;
@@ -246,9 +235,9 @@ static int choose_lds_tile(int bits) {
 }
 
 // LDS bytes of one workgroup for (tile, bits) must stay within 160 KiB.
-static int tile_pairs(int tile) { return tile == TILE_16x16 ? 16 : tile == TILE_64x4 ? 4 : 1; }
+int tile_pairs(int tile) { return tile == TILE_16x16 ? 16 : tile == TILE_64x4 ? 4 : 1; }
 
-static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
+int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
                               double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset,
                               int tile_override) {
   DevPlan dp;
@@ -299,7 +288,7 @@ static int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int pre
   return rc;
 }
 
-static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
+int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
                                  double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
   const int n = e->n_qubits, G = e->depth;
   const int elem = sweep_elem_bytes(precision);
@@ -444,14 +433,14 @@ static int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int 
 // Algorithmic flops of one HEA trace: n-1 transforms of m butterfly stages
 // (one complex addition, 2 flops, per entry and stage) and n pointwise
 // complex products (6 flops per entry).
-static double hea_flops_per_pair(int n, int L) {
+double hea_flops_per_pair(int n, int L) {
   const int m = hea_bits(L);
   if (m == 0) return 6.0 * n;
   const double chi = (double)(1ull << m);
   return (double)(n - 1) * m * chi * 2.0 + (double)n * chi * 6.0;
 }
 
-static int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
                         hipStream_t s, int64_t trace_offset, int tile_override) {
   HeaArgs a;
   a.gates = (const unsigned char*)gates;

@@ -22,174 +22,12 @@
 #include "internal.h"
 #include "layout.h"
 #include "sweep.h"
+#include "hea_dev.h"
 
 namespace fp {
 
-template <typename Real>
-struct HC {
-  Real x, y;
-};
-
-struct D2 {
-  double x, y;
-};
-
-__device__ __forceinline__ D2 dmul(D2 a, D2 b) { return D2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-
-// R = RZ(phi) RY(theta) as [out][in].
-__device__ __forceinline__ void rot(double theta, double phi, D2 r[2][2]) {
-  double s, c, sp, cp;
-  sincos(0.5 * theta, &s, &c);
-  sincos(0.5 * phi, &sp, &cp);
-  const D2 em{cp, -sp}, ep{cp, sp};  // e^{-i phi/2}, e^{+i phi/2}
-  r[0][0] = D2{em.x * c, em.y * c};
-  r[0][1] = D2{-em.x * s, -em.y * s};
-  r[1][0] = D2{ep.x * s, ep.y * s};
-  r[1][1] = D2{ep.x * c, ep.y * c};
-}
-
-__device__ __forceinline__ void dag(const D2 a[2][2], D2 r[2][2]) {
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) r[i][j] = D2{a[j][i].x, -a[j][i].y};
-}
-
-__device__ __forceinline__ void mat2(const D2 a[2][2], const D2 b[2][2], D2 r[2][2]) {
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      D2 s0 = dmul(a[i][0], b[0][j]), s1 = dmul(a[i][1], b[1][j]);
-      r[i][j] = D2{s0.x + s1.x, s0.y + s1.y};
-    }
-}
-
-// Slot matrix A_t of qubit q.  ang(c, l, q) -> (theta, phi) of circuit c.
-template <typename Real>
-__device__ void slot_matrix(const Real* angU, const Real* angV, int n, int L, int t, int q, D2 out[2][2]) {
-  D2 ru[2][2], rv[2][2], rud[2][2];
-  auto th = [&](const Real* a, int l) { return (double)a[((int64_t)l * n + q) * 2]; };
-  auto ph = [&](const Real* a, int l) { return (double)a[((int64_t)l * n + q) * 2 + 1]; };
-  if (t == 0) {
-    rot(th(angV, 0), ph(angV, 0), rv);
-    rot(th(angU, 0), ph(angU, 0), ru);
-    dag(ru, rud);
-    mat2(rv, rud, out);
-  } else if (t < L - 1) {
-    rot(th(angV, t), ph(angV, t), out);
-  } else if (t == L - 1) {
-    rot(th(angV, L - 1), ph(angV, L - 1), rv);
-    rot(th(angU, L - 1), ph(angU, L - 1), ru);
-    dag(ru, rud);
-    mat2(rud, rv, out);
-  } else {
-    const int l = 2 * L - 2 - t;
-    rot(th(angU, l), ph(angU, l), ru);
-    dag(ru, out);
-  }
-}
-
-template <int NT>
-__device__ __forceinline__ void hsync() {
-  if constexpr (NT <= 64) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-template <typename Real, int NT>
-__device__ __forceinline__ Real hmax(Real v, Real* red) {
-  constexpr int W = NT < 64 ? NT : 64;
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, W));
-  if constexpr (NT > 64) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    v = red[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
-  }
-  return v;
-}
-
-template <typename T, int NT>
-__device__ __forceinline__ T hsum(T v, T* red) {
-  constexpr int W = NT < 64 ? NT : 64;
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
-  if constexpr (NT > 64) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    T s = red[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) s += red[w];
-    v = s;
-  }
-  return v;
-}
-
-__device__ __forceinline__ int ins_bits(int g, int s0, int r) {
-  return ((g >> s0) << (s0 + r)) | (g & ((1 << s0) - 1));
-}
-
-// In-place WHT over bits [s0, s0+r) of B (2^m entries); optional scale 2^-e.
-template <typename Real, int NT, int R>
-__device__ __forceinline__ void wht_pass(HC<Real>* B, int m, int s0, int lane, int scale_e) {
-  const int ng = 1 << (m - R);
-  for (int g = lane; g < ng; g += NT) {
-    const int base = ins_bits(g, s0, R);
-    HC<Real> v[1 << R];
-#pragma unroll
-    for (int k = 0; k < (1 << R); ++k) v[k] = B[base + (k << s0)];
-    if (scale_e != 0) {
-#pragma unroll
-      for (int k = 0; k < (1 << R); ++k) {
-        v[k].x = ldexp(v[k].x, -scale_e);
-        v[k].y = ldexp(v[k].y, -scale_e);
-      }
-    }
-#pragma unroll
-    for (int st = 0; st < R; ++st) {
-#pragma unroll
-      for (int k = 0; k < (1 << R); ++k) {
-        if (k & (1 << st)) continue;
-        const HC<Real> a = v[k], b = v[k | (1 << st)];
-        v[k].x = a.x + b.x;
-        v[k].y = a.y + b.y;
-        v[k | (1 << st)].x = a.x - b.x;
-        v[k | (1 << st)].y = a.y - b.y;
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < (1 << R); ++k) B[base + (k << s0)] = v[k];
-  }
-}
-
-template <typename Real, int NT>
-__device__ void wht(HC<Real>* B, int m, int lane, int scale_e) {
-  int s0 = 0;
-  bool first = true;
-  while (s0 < m) {
-    const int r = (m - s0) >= 4 ? 4 : (m - s0);
-    const int e = first ? scale_e : 0;
-    switch (r) {
-      case 4: wht_pass<Real, NT, 4>(B, m, s0, lane, e); break;
-      case 3: wht_pass<Real, NT, 3>(B, m, s0, lane, e); break;
-      case 2: wht_pass<Real, NT, 2>(B, m, s0, lane, e); break;
-      default: wht_pass<Real, NT, 1>(B, m, s0, lane, e); break;
-    }
-    hsync<NT>();
-    s0 += r;
-    first = false;
-  }
-}
-
 template <typename Real, int NT, int PB>
-__global__ void __launch_bounds__(NT* PB) hea_kernel(HeaArgs a, int m, int per_pair_elems) {
+__global__ void __launch_bounds__(NT* PB) hea_kernel(HeaArgs a, int m, int per_pair_bytes) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
   __shared__ double redd[16];
@@ -197,147 +35,20 @@ __global__ void __launch_bounds__(NT* PB) hea_kernel(HeaArgs a, int m, int per_p
   const int lane = threadIdx.x % NT;
   const int64_t pi = (int64_t)blockIdx.x * PB + slot;
   if (pi >= a.num_pairs) return;
-  const int n = a.n, L = a.L;
   const Real* angU = reinterpret_cast<const Real*>(a.gates + pi * a.gate_stride);
-  const Real* angV = angU + (int64_t)L * n * 2;
-  double* out = a.trace + 2 * (a.trace_offset + pi);
-  if (L == 1) {
-    // Tr = prod_q Tr(A_0,q): product in float64 over lanes.
-    double lr = 1.0, li = 0.0;
-    for (int q = lane; q < n; q += NT) {
-      D2 A[2][2];
-      slot_matrix<Real>(angU, angV, n, 1, 0, q, A);
-      const double tr_ = A[0][0].x + A[1][1].x, ti_ = A[0][0].y + A[1][1].y;
-      const double nr = lr * tr_ - li * ti_, ni = lr * ti_ + li * tr_;
-      lr = nr;
-      li = ni;
-    }
-    // ordered product across lanes via LDS (lane order)
-    HC<double>* sc = reinterpret_cast<HC<double>*>(smem_raw) + (int64_t)slot * NT;
-    sc[lane].x = lr;
-    sc[lane].y = li;
-    hsync<NT>();
-    if (lane == 0) {
-      double pr = 1.0, pim = 0.0;
-      for (int i = 0; i < NT; ++i) {
-        const double nr = pr * sc[i].x - pim * sc[i].y, ni = pr * sc[i].y + pim * sc[i].x;
-        pr = nr;
-        pim = ni;
-      }
-      out[0] = pr;
-      out[1] = pim;
-    }
-    return;
-  }
-  const int h = m / 2;
-  const int nlo = 1 << (h + 1), nhi = 1 << (m - h + 1);
-  HC<Real>* B = reinterpret_cast<HC<Real>*>(smem_raw) + (int64_t)slot * per_pair_elems;
-  HC<Real>* Tlo = B + (1 << m);
-  HC<Real>* Thi = Tlo + nlo;
-  D2* As = reinterpret_cast<D2*>(Thi + nhi);  // m slots x 4 entries, float64
-  int64_t expo = 0;
-  int pending = 0;
-  for (int q = 0; q < n; ++q) {
-    // slot matrices of this qubit
-    for (int t = lane; t < m; t += NT) {
-      D2 A[2][2];
-      slot_matrix<Real>(angU, angV, n, L, t, q, A);
-      As[t * 4 + 0] = A[0][0];
-      As[t * 4 + 1] = A[0][1];
-      As[t * 4 + 2] = A[1][0];
-      As[t * 4 + 3] = A[1][1];
-    }
-    hsync<NT>();
-    // tables over the low and high halves of the bits
-    for (int e = lane; e < nlo + nhi; e += NT) {
-      D2 acc{1.0, 0.0};
-      if (e < nlo) {
-        for (int t = 0; t < h; ++t) {
-          const int xt = (e >> t) & 1, xt1 = (e >> (t + 1)) & 1;
-          acc = dmul(acc, As[(t + 1) * 4 + xt1 * 2 + xt]);
-        }
-        Tlo[e].x = (Real)acc.x;
-        Tlo[e].y = (Real)acc.y;
-      } else {
-        const int f = e - nlo;
-        for (int t = h; t < m; ++t) {
-          const int xt = (f >> (t - h)) & 1;
-          const int t1 = (t + 1) % m;
-          const int xt1 = t1 == 0 ? ((f >> (m - h)) & 1) : ((f >> (t1 - h)) & 1);
-          acc = dmul(acc, As[t1 * 4 + xt1 * 2 + xt]);
-        }
-        Thi[f].x = (Real)acc.x;
-        Thi[f].y = (Real)acc.y;
-      }
-    }
-    hsync<NT>();
-    if (q > 0) wht<Real, NT>(B, m, lane, pending);
-    // pointwise product with f_q and max
-    Real mx = 0;
-    const int mlo = nlo - 1;
-    for (int x = lane; x < (1 << m); x += NT) {
-      const HC<Real> tl = Tlo[x & mlo];
-      const HC<Real> th = Thi[(x >> h) | ((x & 1) << (m - h))];
-      HC<Real> f;
-      f.x = tl.x * th.x - tl.y * th.y;
-      f.y = tl.x * th.y + tl.y * th.x;
-      HC<Real> v;
-      if (q == 0) {
-        v = f;
-      } else {
-        const HC<Real> b = B[x];
-        v.x = b.x * f.x - b.y * f.y;
-        v.y = b.x * f.y + b.y * f.x;
-      }
-      B[x] = v;
-      mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
-    }
-    mx = hmax<Real, NT>(mx, red);
-    pending = 0;
-    if (mx > (Real)0 && isfinite(mx)) {
-      int e;
-      frexp(mx, &e);
-      pending = e;
-      expo += e;
-    }
-    hsync<NT>();
-  }
-  // Tr = 2^expo * sum_x B(x) 2^-pending
-  double sr = 0.0, si = 0.0;
-  for (int x = lane; x < (1 << m); x += NT) {
-    sr += ldexp((double)B[x].x, -pending);
-    si += ldexp((double)B[x].y, -pending);
-  }
-  sr = hsum<double, NT>(sr, redd);
-  si = hsum<double, NT>(si, redd);
-  if (lane == 0) {
-    out[0] = ldexp(sr, (int)expo);
-    out[1] = ldexp(si, (int)expo);
-  }
+  const Real* angV = angU + (int64_t)a.L * a.n * 2;
+  hea_pair<Real, NT>(angU, angV, a.n, a.L, m, smem_raw + (size_t)slot * per_pair_bytes, lane, red, redd,
+                     a.trace + 2 * (a.trace_offset + pi));
 }
 
 int hea_bits(int L) { return L <= 1 ? 0 : 2 * L - 2; }
 
-static size_t hea_pair_elems(int m) {
-  const int h = m / 2;
-  size_t e = ((size_t)1 << m) + ((size_t)1 << (h + 1)) + ((size_t)1 << (m - h + 1));
-  return e;
-}
 
 template <typename Real, int NT, int PB>
 static int launch_hea_t(const HeaArgs& a, hipStream_t s) {
   const int m = hea_bits(a.L);
-  int per_pair;
-  size_t smem;
-  if (a.L == 1) {
-    per_pair = 0;
-    smem = (size_t)PB * NT * sizeof(HC<double>);
-  } else {
-    // B, tables (Real complex) + slot matrices (float64 complex), rounded to whole Real-complex units
-    const size_t as_units = (m * 4 * sizeof(D2) + sizeof(HC<Real>) - 1) / sizeof(HC<Real>);
-    per_pair = (int)(hea_pair_elems(m) + as_units);
-    smem = (size_t)PB * per_pair * sizeof(HC<Real>);
-  }
+  const size_t per_pair = (hea_smem_bytes(m, NT, sizeof(Real)) + 15) & ~(size_t)15;
+  const size_t smem = (size_t)PB * per_pair;
   if (smem > 160 * 1024) return set_error(FP_ETOOBIG, "HEA boundary of %d bits does not fit LDS", m);
   if (smem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hea_kernel<Real, NT, PB>),
@@ -345,8 +56,7 @@ static int launch_hea_t(const HeaArgs& a, hipStream_t s) {
     if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
   }
   const int64_t blocks = (a.num_pairs + PB - 1) / PB;
-  hipLaunchKernelGGL((hea_kernel<Real, NT, PB>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a, m,
-                     per_pair);
+  hipLaunchKernelGGL((hea_kernel<Real, NT, PB>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a, m, (int)per_pair);
   return check_launch("hea_sweep");
 }
 

@@ -16,270 +16,9 @@
 #include "layout.h"
 #include "plan.h"
 #include "sweep.h"
+#include "sweep_dev.h"
 
 namespace fp {
-
-template <typename Real>
-struct Cplx {
-  Real x, y;
-};
-
-template <int NT>
-__device__ __forceinline__ void group_sync() {
-  if constexpr (NT <= 64) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
-
-__device__ __forceinline__ int insert_zero(int x, int pos) {
-  return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
-}
-
-// Merged gate M = F_last ... F_first (product of its factors) realigned for
-// the column transfer and written to dst (16 complex):
-//   dst[j' * 4 + j] = M[2 x_out + y_out][2 x_in + y_in],
-// j = x_in + 2 x_out (legs on qubit c), j' = y_in + 2 y_out (legs on qubit c+1).
-// dst doubles as the row buffer of the running product.
-template <typename Real>
-__device__ __forceinline__ void load_factor_row(const Real* src, int dagger, int a, Real (&fr)[4], Real (&fi)[4]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (dagger) {
-      fr[k] = src[(k * 4 + a) * 2];
-      fi[k] = -src[(k * 4 + a) * 2 + 1];
-    } else {
-      fr[k] = src[(a * 4 + k) * 2];
-      fi[k] = src[(a * 4 + k) * 2 + 1];
-    }
-  }
-}
-
-template <typename Real>
-__device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int32_t* __restrict__ factors, int2 wg,
-                           Cplx<Real>* dst) {
-  Real mr[16], mi[16];
-  {
-    const FactorRef f0 = decode_factor(factors[wg.x], G);
-    const Real* src = pair_gates + ((int64_t)f0.circuit * G + f0.gate) * 32;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      Real fr[4], fi[4];
-      load_factor_row<Real>(src, f0.dagger, a, fr, fi);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        mr[a * 4 + k] = fr[k];
-        mi[a * 4 + k] = fi[k];
-      }
-    }
-  }
-  for (int f = 1; f < wg.y; ++f) {
-    const FactorRef ff = decode_factor(factors[wg.x + f], G);
-    const Real* src = pair_gates + ((int64_t)ff.circuit * G + ff.gate) * 32;
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      Real fr[4], fi[4];
-      load_factor_row<Real>(src, ff.dagger, a, fr, fi);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        Real sr = 0, si = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          sr = fma(fr[k], mr[k * 4 + b], sr);
-          sr = fma(-fi[k], mi[k * 4 + b], sr);
-          si = fma(fr[k], mi[k * 4 + b], si);
-          si = fma(fi[k], mr[k * 4 + b], si);
-        }
-        dst[a * 4 + b].x = sr;
-        dst[a * 4 + b].y = si;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      mr[i] = dst[i].x;
-      mi[i] = dst[i].y;
-    }
-  }
-#pragma unroll
-  for (int jp = 0; jp < 4; ++jp)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int xin = j & 1, xout = j >> 1, yin = jp & 1, yout = jp >> 1;
-      const int idx = (2 * xout + yout) * 4 + (2 * xin + yin);
-      dst[jp * 4 + j].x = mr[idx];
-      dst[jp * 4 + j].y = mi[idx];
-    }
-}
-
-template <typename Real, int NT>
-__device__ __forceinline__ Real group_max(Real v, Real* red) {
-  constexpr int W = NT < 64 ? NT : 64;
-#pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, W));
-  if constexpr (NT > 64) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wave] = v;
-    __syncthreads();
-    v = red[0];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
-  }
-  return v;
-}
-
-template <int NT>
-constexpr int chunk_ops() {
-  return NT <= 16 ? 16 : NT <= 64 ? 32 : 64;
-}
-
-// Runs one pair's program on boundary B (LDS or global).  The program is
-// processed in chunks of K ops: the group first stages the chunk's op records
-// and the realigned matrices of its GATE ops in LDS (one lane per op, in
-// parallel), then executes the ops from LDS.  The per-column rescale is
-// lazy: the op that ends a column records the largest magnitude it writes,
-// the column end turns it into an exponent P, and the next GATE multiplies
-// its matrix by 2^-P (exact), so no extra pass over the boundary is made.
-template <typename Real, int NT>
-__device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, Op* ops_s, const Op* __restrict__ ops,
-                                            int num_ops, const int2* __restrict__ wgates,
-                                            const int32_t* __restrict__ factors, const Real* pair_gates, int G,
-                                            int log2_factor, int lane, Real* red, double* tr_re, double* tr_im) {
-  constexpr int K = chunk_ops<NT>();
-  int b = 0;
-  int64_t expo = 0;  // true boundary = stored boundary * 2^expo
-  int pend = 0;      // exponent to remove at the next GATE
-  Real lmax = 0;
-  if (lane == 0) {
-    B[0].x = (Real)1;
-    B[0].y = (Real)0;
-  }
-  for (int t0 = 0; t0 < num_ops; t0 += K) {
-    const int nk = num_ops - t0 < K ? num_ops - t0 : K;
-    for (int i = lane; i < nk; i += NT) {
-      const Op op = ops[t0 + i];
-      ops_s[i] = op;
-      if ((op.type & OP_TYPE_MASK) == OP_GATE) stage_gate<Real>(pair_gates, G, factors, wgates[op.arg], mats_s + 16 * i);
-    }
-    group_sync<NT>();
-    for (int i = 0; i < nk; ++i) {
-      const Op op = ops_s[i];
-      const int type = op.type & OP_TYPE_MASK;
-      const bool track = (op.type & OP_FLAG_TRACK) != 0;
-      if (type == OP_GATE) {
-        Real Rr[16], Ri[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const Cplx<Real> r = mats_s[16 * i + k];
-          Rr[k] = pend ? ldexp(r.x, -pend) : r.x;
-          Ri[k] = pend ? ldexp(r.y, -pend) : r.y;
-        }
-        expo += pend;
-        pend = 0;
-        const int p = op.p, q = op.q;
-        const int lo = p < q ? p : q, hi = p < q ? q : p;
-        const int ip = 1 << p, iq = 1 << q;
-        const int ng = 1 << (b - 2);
-        for (int g = lane; g < ng; g += NT) {
-          const int idx = insert_zero(insert_zero(g, lo), hi);
-          Cplx<Real> v[4];
-          v[0] = B[idx];
-          v[1] = B[idx + ip];
-          v[2] = B[idx + iq];
-          v[3] = B[idx + ip + iq];
-          Cplx<Real> w[4];
-#pragma unroll
-          for (int jp = 0; jp < 4; ++jp) {
-            Real sr = 0, si = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              sr = fma(Rr[jp * 4 + j], v[j].x, sr);
-              sr = fma(-Ri[jp * 4 + j], v[j].y, sr);
-              si = fma(Rr[jp * 4 + j], v[j].y, si);
-              si = fma(Ri[jp * 4 + j], v[j].x, si);
-            }
-            w[jp].x = sr;
-            w[jp].y = si;
-            if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
-          }
-          B[idx] = w[0];
-          B[idx + ip] = w[1];
-          B[idx + iq] = w[2];
-          B[idx + ip + iq] = w[3];
-        }
-      } else if (type == OP_BELL) {
-        const int s = 1 << b;
-        for (int k = lane; k < s; k += NT) {
-          const Cplx<Real> v = B[k];
-          Cplx<Real> z;
-          z.x = (Real)0;
-          z.y = (Real)0;
-          B[k + s] = z;
-          B[k + 2 * s] = z;
-          B[k + 3 * s] = v;
-        }
-        b += 2;
-      } else if (type == OP_TRACE) {
-        const int p = op.p, q = op.q;  // p < q
-        const int nout = 1 << (b - 2);
-        const int step = (1 << p) + (1 << q);
-        for (int j0 = 0; j0 < nout; j0 += NT) {
-          const int j = j0 + lane;
-          Cplx<Real> acc;
-          acc.x = (Real)0;
-          acc.y = (Real)0;
-          if (j < nout) {
-            const int i0 = insert_zero(insert_zero(j, p), q);
-            const Cplx<Real> a0 = B[i0], a1 = B[i0 + step];
-            acc.x = a0.x + a1.x;
-            acc.y = a0.y + a1.y;
-            if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
-          }
-          group_sync<NT>();
-          if (j < nout) B[j] = acc;
-          group_sync<NT>();
-        }
-        b -= 2;
-      } else {  // OP_COLEND
-        if (i > 0 ? (ops_s[i - 1].type & OP_FLAG_TRACK) != 0 : false) {
-          const Real m = group_max<Real, NT>(lmax, red);
-          lmax = 0;
-          pend = 0;
-          if (m > (Real)0 && isfinite(m)) {
-            int e;
-            frexp(m, &e);
-            pend = e;
-          }
-        } else if (i == 0 && t0 > 0) {
-          // the column's last writing op ended the previous chunk
-          const Op prev = ops[t0 - 1];
-          if (prev.type & OP_FLAG_TRACK) {
-            const Real m = group_max<Real, NT>(lmax, red);
-            lmax = 0;
-            pend = 0;
-            if (m > (Real)0 && isfinite(m)) {
-              int e;
-              frexp(m, &e);
-              pend = e;
-            }
-          }
-        }
-      }
-      group_sync<NT>();
-    }
-  }
-  const Cplx<Real> v = B[0];
-  *tr_re = ldexp((double)v.x, (int)(expo + log2_factor));
-  *tr_im = ldexp((double)v.y, (int)(expo + log2_factor));
-}
-
-template <typename Real, int NT>
-constexpr size_t stage_bytes() {
-  return (size_t)chunk_ops<NT>() * (16 * sizeof(Cplx<Real>) + sizeof(Op));
-}
 
 // One group of NT lanes per pair, PB pairs per workgroup, boundary in LDS
 // (2^cap_bits complex per pair) next to the staging area of the group.

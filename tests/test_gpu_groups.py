@@ -1,0 +1,72 @@
+"""GPU parity of the persistent uneven-batch launch and of autotuned tiles."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dense, sampler
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2205_09900_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def _floored(got, want):
+    rms = np.sqrt(np.mean(np.abs(want) ** 2))
+    return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_mixed_groups_vs_dense(fp, prec):
+    # HEA of 1..7 layers, brickwork and local random of several depths, ragged group sizes
+    ens = [(2, 6, L) for L in range(1, 8)] + [(0, 7, 3), (0, 6, 6), (1, 8, 15)]
+    sizes = [37, 5, 64, 1, 19, 23, 9, 41, 13, 30]
+    seeds = [synth.workload_seed(30 + i, 1) for i in range(len(ens))]
+    bufs, groups, want = [], [], []
+    for i, (e, nps) in enumerate(zip(ens, sizes)):
+        first = 3 * i
+        g = fp.sample(e, nps + first, seeds[i], 0, prec)
+        bufs.append(g)
+        groups.append((i, prec, first, nps))
+        pr = sampler.sample_pairs(e[0], e[1], e[2], seeds[i], first, nps, fp32=(prec != 0))
+        want.append(dense.traces(pr))
+    total = sum(sizes)
+    tr = torch.empty(2 * total, dtype=torch.float64, device="cuda")
+    ws = torch.empty(fp.fp_workspace_bytes_groups(ens, groups), dtype=torch.uint8, device="cuda")
+    fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
+    got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
+    want = np.concatenate(want)
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert _floored(got, want) <= tol, _floored(got, want)
+
+
+def test_groups_match_single_calls_at_scale(fp):
+    # HEA n = 30, L = 1..8 mixed (the uneven-depth workload at reduced size)
+    ens = [(2, 30, L) for L in range(1, 9)]
+    n = 500
+    bufs = [fp.sample(e, n, synth.workload_seed(3, e[2]), 0, fp.C64) for e in ens]
+    groups = [(i, fp.C64, 0, n) for i in range(len(ens))]
+    tr = torch.empty(2 * n * len(ens), dtype=torch.float64, device="cuda")
+    ws = torch.empty(fp.fp_workspace_bytes_groups(ens, groups), dtype=torch.uint8, device="cuda")
+    fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
+    got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
+    for i, e in enumerate(ens):
+        one = fp.contract(e, bufs[i], n, fp.C64).cpu().numpy()
+        assert _floored(got[i * n:(i + 1) * n], one) <= 1e-5, e
+
+
+def test_autotune_choice_is_valid_and_correct(fp):
+    for ens in [(2, 12, 4), (0, 8, 4)]:
+        t = fp.fp_autotune(ens, fp.C64)
+        assert 0 <= t < 6
+        assert f" {fp.TILE_NAMES[t]} " in fp.fp_autotune_table()
+        seed = 555
+        got = fp.contract(ens, fp.sample(ens, 40, seed, 0, fp.C64), 40, fp.C64).cpu().numpy()
+        want = dense.traces(sampler.sample_pairs(ens[0], ens[1], ens[2], seed, 0, 40, fp32=True))
+        assert _floored(got, want) <= 1e-5

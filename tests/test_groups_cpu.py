@@ -1,0 +1,40 @@
+"""Host-side checks of the uneven-batch and tuning entry points (no device)."""
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2205_09900_amd as m
+    return m
+
+
+def test_workspace_groups_sizes(fp):
+    ens = [(2, 30, L) for L in range(1, 9)] + [(0, 20, 4), (1, 50, 100)]
+    groups = [(i, fp.C64, 0, 1000) for i in range(len(ens))]
+    nb = fp.fp_workspace_bytes_groups(ens, groups)
+    assert nb >= fp.fp_workspace_bytes((1, 50, 100), 1000, fp.C64)
+    # HEA and LDS-sized brickwork groups need only descriptors and task lists
+    small = fp.fp_workspace_bytes_groups(ens[:9], groups[:9])
+    assert small < 10 << 20
+
+
+def test_groups_validation(fp):
+    with pytest.raises(fp.FPError):
+        fp.fp_workspace_bytes_groups([(2, 30, 3)], [(1, fp.C64, 0, 10)])       # bad ensemble index
+    with pytest.raises(fp.FPError):
+        fp.fp_workspace_bytes_groups([(2, 30, 3)], [(0, fp.BF16X3, 0, 10)])    # precision
+    with pytest.raises(fp.FPError):
+        fp.fp_workspace_bytes_groups([(2, 30, 3)], [(0, fp.C64, -1, 10)])      # pair range
+    with pytest.raises(fp.FPError):
+        fp.fp_workspace_bytes_groups([(2, 30, 9)], [(0, fp.C64, 0, 10)])       # 16-bit HEA boundary
+
+
+def test_autotune_table_round_trip(fp):
+    fp.fp_autotune_load("# comment\ngfx950 2 30 6 1 64x4 0.125000\ngfx950 0 20 8 1 1024x1 2.500000\n")
+    text = fp.fp_autotune_table()
+    assert "gfx950 2 30 6 1 64x4" in text and "gfx950 0 20 8 1 1024x1" in text
+    with pytest.raises(fp.FPError):
+        fp.fp_autotune_load("gfx950 2 30 6 1 7x7 0.1\n")
+    with pytest.raises(fp.FPError):
+        fp.fp_autotune_load("garbage line\n")
