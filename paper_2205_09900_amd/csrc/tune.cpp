@@ -120,9 +120,16 @@ size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision) {
          ((ws + 255) & ~(size_t)255) + 512;
 }
 
+// The device timing loop below is switched off: its first run on the GPU
+// stopped responding and the cause has not been found.  Tables written
+// elsewhere can still be loaded with fp_autotune_load and are used by the
+// dispatch.
+static const bool kTimingEnabled = false;
+
 int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_bytes, int* out_choice, void* stream) {
   int rc = check_ensemble(ens);
   if (rc) return rc;
+  if (!kTimingEnabled) return set_error(FP_ENOTIMPL, "device timing of the autotuner is switched off in this build");
   if ((rc = check_precision(precision))) return rc;
   if (precision == FP_BF16X3) return set_error(FP_ENOTIMPL, "no tiles to tune for BF16x3");
   if (ens->ansatz == FP_LOCAL_RANDOM_HAAR)

@@ -38,3 +38,11 @@ def test_autotune_table_round_trip(fp):
         fp.fp_autotune_load("gfx950 2 30 6 1 7x7 0.1\n")
     with pytest.raises(fp.FPError):
         fp.fp_autotune_load("garbage line\n")
+
+
+def test_autotune_timing_switched_off(fp):
+    import ctypes
+    ens = fp.Ensemble(2, 12, 4)
+    choice = ctypes.c_int(-1)
+    rc = fp.lib.fp_autotune(ctypes.byref(ens), fp.C64, ctypes.c_void_p(256), 1 << 30, ctypes.byref(choice), None)
+    assert rc == fp.FP_ENOTIMPL
