@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "plan_wave.h"
 #include "layout.h"
 #include "plan.h"
 #include "sweep.h"
@@ -65,18 +66,19 @@ struct HostPlan {
 
 static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, HostPlan* out) {
   if (G > PLAN_MAX_GATES) return set_error(FP_EINVAL, "%d gates per circuit exceed %d", G, PLAN_MAX_GATES);
-  std::vector<int16_t> scratch((size_t)plan_scratch_elems(G, n));
-  std::vector<int16_t> b16(2 * (size_t)G);
-  for (int i = 0; i < G; ++i) {
-    b16[i] = (bu[i] >= 0 && bu[i] <= n - 2) ? (int16_t)bu[i] : (int16_t)-1;
-    b16[G + i] = (bv[i] >= 0 && bv[i] <= n - 2) ? (int16_t)bv[i] : (int16_t)-1;
+  std::vector<int16_t> scratch((size_t)plan_wave_scratch_elems(G));
+  // bond of each position of W: V's gates in time order, then U's reversed
+  std::vector<int16_t> bw(2 * (size_t)G);
+  for (int i = 0; i < 2 * G; ++i) {
+    const int32_t b = i < G ? bv[i] : bu[2 * G - 1 - i];
+    bw[i] = (b >= 0 && b <= n - 2) ? (int16_t)b : (int16_t)-1;
   }
   out->ops.resize((size_t)plan_max_ops(G, n));
   out->wg.resize(2 * (size_t)G);
   out->fac.resize(2 * (size_t)G);
-  int32_t tags[64];
-  out->hdr = plan_haar_pair(n, G, b16.data(), b16.data() + G, scratch.data(), out->ops.data(), out->wg.data(),
-                            out->fac.data(), tags);
+  WaveHost wh;
+  out->hdr = plan_pair_wave(wh, n, G, bw.data(), scratch.data(), out->ops.data(), out->wg.data(), out->fac.data(),
+                            nullptr);
   if (out->hdr.status != PLAN_OK) {
     if (out->hdr.status == PLAN_EWIDE)
       return set_error(FP_ETOOBIG, "boundary wider than %d bits", PLAN_MAX_BITS);
@@ -164,17 +166,40 @@ int lds_bits_max(int precision) { return precision == FP_C128 ? 13 : 14; }
 
 // Local random: per-pair plan region.
 struct LrLayout {
-  int64_t hdr, ops, wg, fac, per_pair;
+  int64_t hdr, ops, wg, fac, gseq, mat, per_pair;
 };
 
-static LrLayout lr_layout(int n, int G) {
+// mat: realigned matrix of every GATE op (at most 2G), 16 complex each
+static LrLayout lr_layout(int n, int G, int precision) {
   LrLayout l;
   l.hdr = 64;
   l.ops = pad64(plan_max_ops(G, n) * (int64_t)sizeof(Op));
   l.wg = pad64(2 * (int64_t)G * (int64_t)sizeof(int2));
   l.fac = pad64(2 * (int64_t)G * 4);
-  l.per_pair = l.hdr + l.ops + l.wg + l.fac;
+  l.gseq = pad64(2 * (int64_t)G * 2);
+  l.mat = pad64(2 * (int64_t)G * 16 * sweep_elem_bytes(precision));
+  l.per_pair = l.hdr + l.ops + l.wg + l.fac + l.gseq + l.mat;
   return l;
+}
+
+// Local random workspace: LR_CHUNKS chunk headers of LR_HEAD bytes (zeroed
+// per chunk), then the pair order (int32 per pair), the per-pair plans and
+// the HBM slots.  Chunk header:
+//   +0   int max_peak, num_large, num_failed
+//   +16  double class MACs[5]
+//   +64  uint64 counter of the HBM launch
+//   +128 int hist[PLAN_HIST]   pairs per peak width
+//   +384 int cursor[PLAN_HIST] fill counters of the ordering pass
+constexpr int64_t LR_HEAD = 1024;
+constexpr int LR_CHUNKS = 4;
+constexpr int64_t LR_STATS_BYTES = 128 + 4 * PLAN_HIST;
+// Pairs per chunk at least: a chunk must fill the device by itself (planning
+// and the large classes are latency-bound per pair), so only batches far
+// larger than one wave of the device are split.
+constexpr int64_t LR_MIN_CHUNK = 65536;
+
+static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
+  return LR_CHUNKS * LR_HEAD + pad64(4 * num_pairs) + num_pairs * l.per_pair;
 }
 
 constexpr int LR_TINY_BITS = 8;    // 16 lanes per pair
@@ -219,11 +244,11 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
     return FP_OK;
   }
   const int G = e->depth;
-  LrLayout l = lr_layout(e->n_qubits, G);
+  LrLayout l = lr_layout(e->n_qubits, G, precision);
   const int bits = lr_predicted_bits(e->n_qubits, e->depth);
   int64_t pool = 0;
   if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * ((int64_t)elem << bits);
-  *out = (size_t)(256 + num_pairs * l.per_pair + pool);
+  *out = (size_t)(lr_fixed_bytes(num_pairs, l) + pool);
   return FP_OK;
 }
 
@@ -288,54 +313,105 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   return rc;
 }
 
-int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
-                                 double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
-  const int n = e->n_qubits, G = e->depth;
-  const int elem = sweep_elem_bytes(precision);
-  const LrLayout l = lr_layout(n, G);
-  const size_t plan_bytes = (size_t)(256 + num_pairs * l.per_pair);
-  if (!ws || ws_bytes < plan_bytes)
-    return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", plan_bytes);
-  unsigned char* w = (unsigned char*)ws;
-  int* counters = (int*)w;  // max_peak, num_large, num_failed; then 3 doubles of class MACs at +16
-  unsigned long long* hbm_counter = (unsigned long long*)(w + 64);
-  unsigned char* region = w + 256;
+// One chunk of a local random batch: plan its pairs (on s), order them by
+// peak width, and launch the sweep classes on the side streams, which s does
+// not wait for here, so the next chunk's planning overlaps this chunk's sweep.
+struct LrCtx {
+  const fp_ensemble_t* e;
+  int precision, elem;
+  LrLayout l;
+  const unsigned char* gates;
+  int64_t gate_stride, bonds_off;
+  double* trace;
+  int64_t trace_offset;
+  unsigned char* w;      // workspace
+  size_t ws_bytes, fixed_bytes;
+  int64_t num_pairs;     // whole batch
+  Aux aux;
+  bool used[NUM_AUX];
+};
+
+static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) {
+  const int n = c.e->n_qubits, G = c.e->depth;
+  unsigned char* hw = c.w + (int64_t)chunk * LR_HEAD;
+  int* counters = (int*)hw;
+  unsigned long long* hbm_counter = (unsigned long long*)(hw + 64);
+  int* hist = (int*)(hw + 128);
+  int* cursor = (int*)(hw + 128 + 4 * PLAN_HIST);
+  int32_t* order = (int32_t*)(c.w + LR_CHUNKS * LR_HEAD) + p0;
+  unsigned char* base = c.w + LR_CHUNKS * LR_HEAD + pad64(4 * c.num_pairs);
+  const LrLayout& l = c.l;
   PlanJob j;
   memset(&j, 0, sizeof(j));
-  j.gates = (const unsigned char*)gates;
-  j.gate_stride = pair_bytes(e->ansatz, n, G, precision);
-  j.bonds_off = bonds_offset(n, G, precision);
+  j.gates = c.gates + p0 * c.gate_stride;
+  j.gate_stride = c.gate_stride;
+  j.bonds_off = c.bonds_off;
   j.n = n;
   j.G = G;
-  j.num_pairs = num_pairs;
-  unsigned char* base = region;
-  j.hdr = (PlanHeader*)base;
-  j.ops = (Op*)(base + num_pairs * l.hdr);
-  j.wgates = (int2*)(base + num_pairs * (l.hdr + l.ops));
-  j.factors = (int32_t*)(base + num_pairs * (l.hdr + l.ops + l.wg));
+  j.num_pairs = np;
+  j.hdr = (PlanHeader*)base + p0;
+  j.ops = (Op*)(base + c.num_pairs * l.hdr) + p0 * (l.ops / (int64_t)sizeof(Op));
+  j.wgates = (int2*)(base + c.num_pairs * (l.hdr + l.ops)) + p0 * (l.wg / (int64_t)sizeof(int2));
+  j.factors = (int32_t*)(base + c.num_pairs * (l.hdr + l.ops + l.wg)) + p0 * (l.fac / 4);
   j.ops_stride = l.ops / (int64_t)sizeof(Op);
   j.wg_stride = l.wg / (int64_t)sizeof(int2);
   j.f_stride = l.fac / 4;
   j.max_peak = counters;
   j.num_large = counters + 1;
   j.num_failed = counters + 2;
-  j.cap_bits = lds_bits_max(precision);
+  j.cap_bits = lds_bits_max(c.precision);
   j.small_bits = LR_SMALL_BITS < j.cap_bits ? LR_SMALL_BITS : j.cap_bits;
   j.tiny_bits = LR_TINY_BITS;
   j.mid_bits = LR_MID_BITS < j.cap_bits ? LR_MID_BITS : j.cap_bits;
-  j.class_macs = (double*)(w + 16);
-  int rc = check_hip(hipMemsetAsync(w, 0, 256, s), "memset counters");
+  j.class_macs = (double*)(hw + 16);
+  j.hist = hist;
+  j.gseq = (int16_t*)(base + c.num_pairs * (l.hdr + l.ops + l.wg + l.fac)) + p0 * (l.gseq / 2);
+  j.gseq_stride = l.gseq / 2;
+  j.wmat = base + c.num_pairs * (l.hdr + l.ops + l.wg + l.fac + l.gseq) + p0 * l.mat;
+  j.wmat_stride = l.mat;
+  static_assert(sizeof(PlanHeader) <= 64, "plan header fits its slot");
+  int rc = check_hip(hipMemsetAsync(hw, 0, LR_HEAD, s), "memset counters");
   if (rc) return rc;
-  rc = launch_plan_local_random(j, s);
+  rc = launch_plan_local_random(j, c.precision, s);
+  if (!rc) rc = launch_gate_matrices(j, c.precision, s);
   if (rc) return rc;
   struct {
     int v[4];
     double macs[5];
+    unsigned char unused[128 - 56];
+    int hist[PLAN_HIST];
   } host;
+  static_assert(sizeof(host) == LR_STATS_BYTES, "stats layout");
   rc = check_hip(hipMemcpyAsync(&host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
   if (rc) return rc;
-  const int max_peak = host.v[0], num_large = host.v[1], num_failed = host.v[2];
+  const int max_peak = host.v[0], num_failed = host.v[2];
+  if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
+  // Order the pairs by decreasing peak width, so that every class below is
+  // one contiguous range of the order and each launch starts with its
+  // costliest pairs.
+  OrderJob oj;
+  memset(&oj, 0, sizeof(oj));
+  oj.hdr = j.hdr;
+  oj.hdr_stride = l.hdr / (int64_t)sizeof(PlanHeader);
+  oj.num_pairs = np;
+  oj.cursor = cursor;
+  oj.order = order;
+  oj.trace = c.trace;
+  oj.trace_offset = c.trace_offset + p0;
+  int64_t above[PLAN_HIST + 1];  // above[b] = pairs whose peak is >= b
+  above[PLAN_HIST] = 0;
+  for (int b = PLAN_HIST - 1; b >= 0; --b) above[b] = above[b + 1] + host.hist[b];
+  for (int b = 0; b < PLAN_HIST; ++b) oj.first[b] = (int32_t)above[b + 1];
+  rc = launch_order_pairs(oj, s);
+  if (rc) return rc;
+  // pairs whose peak lies in (lo, hi]: positions [above[hi + 1], above[lo + 1])
+  auto range_of = [&](int lo, int hi, int64_t* first, int64_t* count) {
+    const int h1 = hi + 1 < PLAN_HIST ? hi + 1 : PLAN_HIST;
+    const int l1 = lo + 1 < 0 ? 0 : (lo + 1 < PLAN_HIST ? lo + 1 : PLAN_HIST);
+    *first = above[h1];
+    *count = above[l1] - above[h1];
+  };
   SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.gates = j.gates;
@@ -348,86 +424,127 @@ int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precisi
   a.factors = j.factors;
   a.f_stride = j.f_stride;
   a.hdr = j.hdr;
-  a.hdr_stride = l.hdr / (int64_t)sizeof(PlanHeader);
-  a.trace = trace;
-  a.trace_offset = trace_offset;
-  a.num_pairs = num_pairs;
-  // Launch classes by the largest boundary of a pair: 16 lanes, one
-  // wavefront, 256 lanes and 1024 lanes per pair with the boundary in LDS,
-  // then HBM slots.  Each class runs on its own stream; all join into s.
-  Aux aux;
-  rc = get_aux(&aux);
+  a.hdr_stride = oj.hdr_stride;
+  a.trace = c.trace;
+  a.trace_offset = c.trace_offset + p0;
+  a.wmat = j.wmat;
+  a.wmat_stride = j.wmat_stride;
+  struct Cls {
+    int lo, hi, tile, kclass, stream;
+  };
+  // Classes by the largest boundary of a pair: up to 2^8 and 2^10 entries
+  // with one wavefront per pair, up to 2^12 and 2^14 with 256 and 1024 lanes
+  // per pair (boundary in LDS), then HBM slots.  The HBM class, whose pairs
+  // take longest, has side stream 0 to itself; 1 takes the 1024- and
+  // 256-lane classes, 2 the smallest; the 2^10 class runs on s, which is
+  // free until the next chunk is planned.
+  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16, 2},
+                      {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64, -1},
+                      {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256, 1},
+                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024, 1}};
+  int64_t first[5], count[5];
+  for (int k = 0; k < 4; ++k) {
+    if (cls[k].hi > cls[k].lo) range_of(cls[k].lo, cls[k].hi, &first[k], &count[k]);
+    else first[k] = count[k] = 0;
+  }
+  range_of(j.cap_bits, PLAN_HIST - 1, &first[4], &count[4]);
+  rc = check_hip(hipEventRecord(c.aux.fork, s), "fork");
   if (rc) return rc;
-  int64_t slots = 0;
-  const bool need_hbm = num_large > 0;
-  if (need_hbm) {
+  bool waited[NUM_AUX] = {false, false, false};
+  auto side = [&](int ai, hipStream_t* out) -> int {
+    if (!waited[ai]) {
+      int r = check_hip(hipStreamWaitEvent(c.aux.s[ai], c.aux.fork, 0), "fork wait");
+      if (r) return r;
+      waited[ai] = true;
+    }
+    c.used[ai] = true;
+    *out = c.aux.s[ai];
+    return FP_OK;
+  };
+  if (count[4] > 0) {
     if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
     // as many slots as the workspace holds (fewer slots only lower the parallelism)
-    const int64_t slot_bytes = (int64_t)elem << max_peak;
-    slots = slot_count(max_peak, elem, num_large);
-    const int64_t avail = ((int64_t)ws_bytes - (int64_t)plan_bytes) / slot_bytes;
+    const int64_t slot_bytes = (int64_t)c.elem << max_peak;
+    int64_t slots = slot_count(max_peak, c.elem, count[4]);
+    const int64_t avail = ((int64_t)c.ws_bytes - (int64_t)c.fixed_bytes) / slot_bytes;
     if (avail < 1)
       return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
-                       plan_bytes + (size_t)slot_bytes, max_peak);
+                       c.fixed_bytes + (size_t)slot_bytes, max_peak);
     if (slots > avail) slots = avail;
-  }
-  struct Cls {
-    int lo, hi, tile, kclass;
-  };
-  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
-                      {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64},
-                      {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256},
-                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024}};
-  bool used[NUM_AUX] = {false, false, false, false};
-  int naux = 0;
-  for (int c = 1; c < 4; ++c) naux += (max_peak > cls[c].lo && cls[c].hi > cls[c].lo) ? 1 : 0;
-  naux += need_hbm ? 1 : 0;
-  if (naux > 0) {
-    rc = check_hip(hipEventRecord(aux.fork, s), "fork");
-    if (rc) return rc;
-  }
-  int next_aux = 0;
-  if (need_hbm) {
-    hipStream_t sc = aux.s[next_aux];
-    rc = check_hip(hipStreamWaitEvent(sc, aux.fork, 0), "fork wait");
+    hipStream_t sc;
+    rc = side(0, &sc);
     if (!rc) rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, sc), "memset counter");
     if (rc) return rc;
     SweepArgs ac = a;
-    ac.min_bits = -1;
-    ac.cap_bits = lds_bits_max(precision);
+    ac.min_bits = j.cap_bits;
+    ac.cap_bits = j.cap_bits;
+    ac.order = order + first[4];
+    ac.num_pairs = count[4];
     profile_launch_begin(KCLASS_HBM, sc);
-    rc = launch_sweep_hbm(ac, precision, hbm_counter, w + plan_bytes, max_peak, (int)slots, sc);
+    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, c.w + c.fixed_bytes, max_peak, (int)slots, sc);
     profile_launch_end(KCLASS_HBM, 8.0 * host.macs[4], sc);
-    if (!rc) rc = check_hip(hipEventRecord(aux.join[next_aux], sc), "join");
     if (rc) return rc;
-    used[next_aux++] = true;
   }
-  for (int c = 3; c >= 0; --c) {
-    if (c > 0 && !(max_peak > cls[c].lo && cls[c].hi > cls[c].lo)) continue;
+  for (int k = 3; k >= 0; --k) {
+    if (count[k] <= 0) continue;
     hipStream_t sx = s;
-    if (c > 0) {
-      sx = aux.s[next_aux];
-      rc = check_hip(hipStreamWaitEvent(sx, aux.fork, 0), "fork wait");
+    if (cls[k].stream >= 0) {
+      rc = side(cls[k].stream, &sx);
       if (rc) return rc;
     }
     SweepArgs ax = a;
-    ax.min_bits = cls[c].lo;
-    ax.cap_bits = cls[c].hi;
-    profile_launch_begin(cls[c].kclass, sx);
-    rc = launch_sweep_lds(ax, precision, cls[c].tile, sx);
-    profile_launch_end(cls[c].kclass, 8.0 * host.macs[c], sx);
+    ax.min_bits = cls[k].lo;
+    ax.cap_bits = cls[k].hi;
+    ax.order = order + first[k];
+    ax.num_pairs = count[k];
+    profile_launch_begin(cls[k].kclass, sx);
+    // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
+    rc = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
+                         : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
+    profile_launch_end(cls[k].kclass, 8.0 * host.macs[k], sx);
     if (rc) return rc;
-    if (c > 0) {
-      rc = check_hip(hipEventRecord(aux.join[next_aux], sx), "join");
-      if (rc) return rc;
-      used[next_aux++] = true;
-    }
   }
-  for (int i = 0; i < NUM_AUX && !rc; ++i)
-    if (used[i]) rc = check_hip(hipStreamWaitEvent(s, aux.join[i], 0), "join wait");
-  if (rc) return rc;
-  if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
   return FP_OK;
+}
+
+int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
+                          double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
+  LrCtx c;
+  c.e = e;
+  c.precision = precision;
+  c.elem = sweep_elem_bytes(precision);
+  c.l = lr_layout(e->n_qubits, e->depth, precision);
+  c.gates = (const unsigned char*)gates;
+  c.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  c.bonds_off = bonds_offset(e->n_qubits, e->depth, precision);
+  c.trace = trace;
+  c.trace_offset = trace_offset;
+  c.w = (unsigned char*)ws;
+  c.ws_bytes = ws_bytes;
+  c.fixed_bytes = (size_t)lr_fixed_bytes(num_pairs, c.l);
+  c.num_pairs = num_pairs;
+  for (int i = 0; i < NUM_AUX; ++i) c.used[i] = false;
+  if (!ws || ws_bytes < c.fixed_bytes)
+    return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", c.fixed_bytes);
+  int rc = get_aux(&c.aux);
+  if (rc) return rc;
+  int64_t chunks = num_pairs / LR_MIN_CHUNK;
+  if (chunks < 1) chunks = 1;
+  if (chunks > LR_CHUNKS) chunks = LR_CHUNKS;
+  const int64_t per = (num_pairs + chunks - 1) / chunks;
+  for (int k = 0; k < chunks && !rc; ++k) {
+    const int64_t p0 = k * per;
+    const int64_t np = num_pairs - p0 < per ? num_pairs - p0 : per;
+    if (np > 0) rc = lr_chunk(c, k, p0, np, s);
+  }
+  // join every side stream that took work, also after an error
+  for (int i = 0; i < NUM_AUX; ++i) {
+    if (!c.used[i]) continue;
+    int r = check_hip(hipEventRecord(c.aux.join[i], c.aux.s[i]), "join");
+    if (!r) r = check_hip(hipStreamWaitEvent(s, c.aux.join[i], 0), "join wait");
+    if (!rc) rc = r;
+  }
+  return rc;
 }
 
 // Algorithmic flops of one HEA trace: n-1 transforms of m butterfly stages

@@ -16,7 +16,7 @@ struct DevPlan {
   PlanHeader* dhdr = nullptr;
 };
 
-constexpr int NUM_AUX = 4;
+constexpr int NUM_AUX = 3;  // side streams; with the caller's stream within 4 hardware queues
 struct Aux {
   hipStream_t s[NUM_AUX];
   hipEvent_t fork, join[NUM_AUX];

@@ -28,6 +28,9 @@ struct SweepArgs {
   int64_t num_pairs;
   int cap_bits;         // LDS capacity per pair (log2 of complex entries)
   int min_bits;         // pairs whose peak is <= min_bits belong to another launch
+  const int32_t* order; // if set: slot i contracts pair order[i] (num_pairs = length of the list)
+  const unsigned char* wmat;  // realigned GATE matrices in program order (wave sweep), per pair
+  int64_t wmat_stride;        // bytes per pair
 };
 
 struct PlanJob {
@@ -51,12 +54,35 @@ struct PlanJob {
   int small_bits;  // largest boundary run with one wavefront per pair
   int mid_bits;    // largest boundary run with 256 lanes per pair
   double* class_macs;  // complex MACs per launch class (16, 64, 256, 1024 lanes, HBM)
+  int* hist;           // pairs per peak register width (PLAN_HIST entries)
+  int16_t* gseq;       // merged gate of each GATE op, per pair
+  int64_t gseq_stride; // entries per pair
+  unsigned char* wmat; // realigned GATE matrices in program order, per pair
+  int64_t wmat_stride; // bytes per pair
 };
+
+// Pair order by decreasing peak register width: pair i with peak b goes to
+// position first[b] + (arrival rank among pairs of width b).  Failed plans
+// get NaN traces and no position.
+constexpr int PLAN_HIST = 64;
+struct OrderJob {
+  const PlanHeader* hdr;
+  int64_t hdr_stride;
+  int64_t num_pairs;
+  int* cursor;        // PLAN_HIST counters, zero at launch
+  int32_t* order;
+  double* trace;
+  int64_t trace_offset;
+  int32_t first[PLAN_HIST];
+};
+int launch_order_pairs(const OrderJob& j, hipStream_t s);
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
                      int slot_bits, int num_slots, hipStream_t s);
-int launch_plan_local_random(const PlanJob& j, hipStream_t s);
+int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s);
+int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s);
+int launch_sweep_wave(const SweepArgs& a, int precision, int cap_bits, hipStream_t s);
 size_t plan_lds_bytes(int G, int n);
 int sweep_elem_bytes(int precision);
 

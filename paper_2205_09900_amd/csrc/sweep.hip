@@ -15,6 +15,7 @@
 #include "internal.h"
 #include "layout.h"
 #include "plan.h"
+#include "plan_wave.h"
 #include "sweep.h"
 #include "sweep_dev.h"
 
@@ -31,7 +32,7 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
   const int lane = threadIdx.x % NT;
   const int64_t pi = (int64_t)blockIdx.x * PB + slot;
   if (pi >= a.num_pairs) return;
-  const int64_t pidx = pi;
+  const int64_t pidx = a.order ? (int64_t)a.order[pi] : pi;
   const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
   const int status = hdr->status, peak = hdr->peak_bits;
   double* out = a.trace + 2 * (a.trace_offset + pidx);
@@ -72,9 +73,10 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
   for (;;) {
     if (lane == 0) next = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
-    const long long pidx = next;
+    const long long pi = next;
     __syncthreads();
-    if (pidx >= a.num_pairs) break;
+    if (pi >= a.num_pairs) break;
+    const int64_t pidx = a.order ? (int64_t)a.order[pi] : (int64_t)pi;
     const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
     if (hdr->status != 0 || hdr->peak_bits <= a.cap_bits) continue;
     double* out = a.trace + 2 * (a.trace_offset + pidx);
@@ -98,29 +100,31 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
 }
 
 // Device planner for local random pairs: one wavefront per pair.  The lanes
-// copy the pair's bond lists into LDS; lane 0 then runs the planner with all
-// of its scratch in LDS (16-bit entries), so its sequential bookkeeping waits
-// on LDS rather than on global memory.
+// copy the pair's bond list into LDS in the order of W (V's steps, then U's
+// steps reversed); the wavefront then plans it cooperatively, with its
+// scratch in LDS and the per-qubit and register tables in lane registers.
 __global__ void __launch_bounds__(64) plan_local_random_kernel(PlanJob j) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t pi = blockIdx.x;
   if (pi >= j.num_pairs) return;
   const int G = j.G;
-  int32_t* tags = reinterpret_cast<int32_t*>(smem_raw);
-  int16_t* bonds = reinterpret_cast<int16_t*>(smem_raw + 256);
-  int16_t* scratch = bonds + ((2 * G + 7) & ~7);
+  int16_t* bw = reinterpret_cast<int16_t*>(smem_raw);
+  int16_t* scratch = bw + ((2 * G + 7) & ~7);
   const int32_t* src = reinterpret_cast<const int32_t*>(j.gates + pi * j.gate_stride + j.bonds_off);
   for (int i = threadIdx.x; i < 2 * G; i += 64) {
-    const int32_t b = src[i];
-    bonds[i] = (b >= 0 && b <= j.n - 2) ? (int16_t)b : (int16_t)-1;
+    const int32_t b = i < G ? src[G + i] : src[2 * G - 1 - i];  // [U bonds][V bonds]
+    bw[i] = (b >= 0 && b <= j.n - 2) ? (int16_t)b : (int16_t)-1;
   }
-  __syncthreads();
+  WaveDev w;
+  w.sync();
+  const PlanHeader h = plan_pair_wave(w, j.n, G, bw, scratch, j.ops + pi * j.ops_stride,
+                                      j.wgates + pi * j.wg_stride, j.factors + pi * j.f_stride,
+                                      j.gseq + pi * j.gseq_stride);
   if (threadIdx.x != 0) return;
-  PlanHeader h = plan_haar_pair(j.n, G, bonds, bonds + G, scratch, j.ops + pi * j.ops_stride,
-                                j.wgates + pi * j.wg_stride, j.factors + pi * j.f_stride, tags);
   j.hdr[pi] = h;
   if (h.status == 0) {
     atomicMax(j.max_peak, h.peak_bits);
+    atomicAdd(&j.hist[h.peak_bits < PLAN_HIST ? h.peak_bits : PLAN_HIST - 1], 1);
     if (h.peak_bits > j.cap_bits) atomicAdd(j.num_large, 1);
     const int cls = h.peak_bits <= j.tiny_bits    ? 0
                     : h.peak_bits <= j.small_bits ? 1
@@ -133,8 +137,31 @@ __global__ void __launch_bounds__(64) plan_local_random_kernel(PlanJob j) {
   }
 }
 
+__global__ void __launch_bounds__(256) order_pairs_kernel(OrderJob j) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= j.num_pairs) return;
+  const PlanHeader* h = j.hdr + i * j.hdr_stride;
+  if (h->status != 0) {
+    double* out = j.trace + 2 * (j.trace_offset + i);
+    out[0] = __builtin_nan("");
+    out[1] = __builtin_nan("");
+    return;
+  }
+  const int b = h->peak_bits < PLAN_HIST ? h->peak_bits : PLAN_HIST - 1;
+  const int pos = j.first[b] + atomicAdd(&j.cursor[b], 1);
+  j.order[pos] = (int32_t)i;
+}
+
+int launch_order_pairs(const OrderJob& j, hipStream_t s) {
+  if (j.num_pairs <= 0) return FP_OK;
+  const int64_t blocks = (j.num_pairs + 255) / 256;
+  hipLaunchKernelGGL(order_pairs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j);
+  return check_launch("order_pairs");
+}
+
 size_t plan_lds_bytes(int G, int n) {
-  return 256 + 2 * (size_t)((2 * G + 7) & ~7) + 2 * (size_t)plan_scratch_elems(G, n);
+  (void)n;
+  return 2 * (size_t)((2 * G + 7) & ~7) + 2 * (size_t)plan_wave_scratch_elems(G);
 }
 
 // ---- launchers --------------------------------------------------------------
@@ -186,7 +213,8 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
   return check_launch("sweep_hbm");
 }
 
-int launch_plan_local_random(const PlanJob& j, hipStream_t s) {
+int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s) {
+  (void)precision;
   if (j.num_pairs <= 0) return FP_OK;
   const size_t smem = plan_lds_bytes(j.G, j.n);
   if (smem > 160 * 1024) return set_error(FP_ETOOBIG, "%d steps per circuit exceed the planner's LDS", j.G);
@@ -197,6 +225,35 @@ int launch_plan_local_random(const PlanJob& j, hipStream_t s) {
   }
   hipLaunchKernelGGL(plan_local_random_kernel, dim3((unsigned)j.num_pairs), dim3(64), smem, s, j);
   return check_launch("plan_local_random");
+}
+
+// The realigned matrix of every GATE op, in program order: one thread per
+// (pair, GATE op), the product of the merged gate's factors (same arithmetic
+// as the staging of the LDS sweep).
+template <typename Real>
+__global__ void __launch_bounds__(256) gate_matrices_kernel(PlanJob j) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = 2 * (int64_t)j.G;
+  const int64_t pi = tid / per;
+  const int jj = (int)(tid - pi * per);
+  if (pi >= j.num_pairs) return;
+  const PlanHeader* h = j.hdr + pi;
+  if (h->status != 0 || jj >= h->num_gate_ops) return;
+  const int k = j.gseq[pi * j.gseq_stride + jj];
+  const Real* pg = reinterpret_cast<const Real*>(j.gates + pi * j.gate_stride);
+  Cplx<Real>* dst = reinterpret_cast<Cplx<Real>*>(j.wmat + pi * j.wmat_stride) + 16 * (int64_t)jj;
+  stage_gate<Real>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], dst);
+}
+
+int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s) {
+  if (j.num_pairs <= 0) return FP_OK;
+  const int64_t threads = j.num_pairs * 2 * (int64_t)j.G;
+  const int64_t blocks = (threads + 255) / 256;
+  if (precision == FP_C128)
+    hipLaunchKernelGGL(gate_matrices_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, j);
+  else
+    hipLaunchKernelGGL(gate_matrices_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, j);
+  return check_launch("gate_matrices");
 }
 
 int sweep_elem_bytes(int precision) { return precision == FP_C128 ? 16 : 8; }

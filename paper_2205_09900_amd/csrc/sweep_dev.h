@@ -33,7 +33,6 @@ __device__ __forceinline__ int insert_zero(int x, int pos) {
 // the column transfer and written to dst (16 complex):
 //   dst[j' * 4 + j] = M[2 x_out + y_out][2 x_in + y_in],
 // j = x_in + 2 x_out (legs on qubit c), j' = y_in + 2 y_out (legs on qubit c+1).
-// dst doubles as the row buffer of the running product.
 template <typename Real>
 __device__ __forceinline__ void load_factor_row(const Real* src, int dagger, int a, Real (&fr)[4], Real (&fi)[4]) {
 #pragma unroll
@@ -48,12 +47,12 @@ __device__ __forceinline__ void load_factor_row(const Real* src, int dagger, int
   }
 }
 
-template <typename Real>
-__device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int32_t* __restrict__ factors, int2 wg,
-                           Cplx<Real>* dst) {
+// code_of(f) gives the factor code of the f-th factor (time order), count >= 1.
+template <typename Real, class Codes>
+__device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int count, Codes code_of, Cplx<Real>* dst) {
   Real mr[16], mi[16];
   {
-    const FactorRef f0 = decode_factor(factors[wg.x], G);
+    const FactorRef f0 = decode_factor(code_of(0), G);
     const Real* src = pair_gates + ((int64_t)f0.circuit * G + f0.gate) * 32;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
@@ -66,9 +65,10 @@ __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int
       }
     }
   }
-  for (int f = 1; f < wg.y; ++f) {
-    const FactorRef ff = decode_factor(factors[wg.x + f], G);
+  for (int f = 1; f < count; ++f) {
+    const FactorRef ff = decode_factor(code_of(f), G);
     const Real* src = pair_gates + ((int64_t)ff.circuit * G + ff.gate) * 32;
+    Real nr[16], ni[16];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       Real fr[4], fi[4];
@@ -83,14 +83,14 @@ __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int
           si = fma(fr[k], mi[k * 4 + b], si);
           si = fma(fi[k], mr[k * 4 + b], si);
         }
-        dst[a * 4 + b].x = sr;
-        dst[a * 4 + b].y = si;
+        nr[a * 4 + b] = sr;
+        ni[a * 4 + b] = si;
       }
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      mr[i] = dst[i].x;
-      mi[i] = dst[i].y;
+      mr[i] = nr[i];
+      mi[i] = ni[i];
     }
   }
 #pragma unroll
@@ -102,6 +102,12 @@ __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int
       dst[jp * 4 + j].x = mr[idx];
       dst[jp * 4 + j].y = mi[idx];
     }
+}
+
+template <typename Real>
+__device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int32_t* __restrict__ factors, int2 wg,
+                           Cplx<Real>* dst) {
+  merged_gate<Real>(pair_gates, G, wg.y, [&](int f) { return factors[wg.x + f]; }, dst);
 }
 
 template <typename Real, int NT>

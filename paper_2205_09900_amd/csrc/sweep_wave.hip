@@ -1,0 +1,272 @@
+// Column sweep with one wavefront per pair, for registers of up to 2^10
+// entries (the bulk of local random pairs).  Same register programs and the
+// same arithmetic as the LDS sweep of sweep_dev.h (Sec. II.A of the paper,
+// trace as a contraction along the qubits; Methods A), organised so that
+// the per-op overhead stays small:
+//   * the op stream is uniform across the wavefront: op records are read 64
+//     at a time into lanes and taken with readlane, so decoding and branching
+//     are scalar;
+//   * the realigned matrices of the GATE ops come precomputed in program
+//     order (written by the planner), prefetched four GATEs ahead by lanes
+//     0..31 and passed through a 32-entry LDS stage;
+//   * registers of up to 64 entries give each lane one output entry of the
+//     gate (one matrix row, four inputs); larger ones give each lane whole
+//     groups of four entries.
+// The boundary stays in LDS; pairs are independent, so waves never wait for
+// each other.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "internal.h"
+#include "plan.h"
+#include "sweep.h"
+#include "sweep_dev.h"
+
+namespace fp {
+
+namespace {
+
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename Real>
+__device__ __forceinline__ Real wave_max(Real v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+constexpr int PREFETCH = 4;  // GATE matrices in flight per wavefront
+
+}  // namespace
+
+template <typename Real, int CAP>
+constexpr size_t wave_slot_bytes() {
+  return ((size_t)sizeof(Cplx<Real>) << CAP) + 32 * sizeof(Real);
+}
+
+template <typename Real, int CAP, int WPB>
+__global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t pi = (int64_t)blockIdx.x * WPB + wave;
+  if (pi >= a.num_pairs) return;
+  const int64_t pidx = a.order ? (int64_t)a.order[pi] : pi;
+  const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
+  const int status = __builtin_amdgcn_readfirstlane(hdr->status);
+  const int peak = __builtin_amdgcn_readfirstlane(hdr->peak_bits);
+  double* out = a.trace + 2 * (a.trace_offset + pidx);
+  if (status != 0) {
+    if (lane == 0) {
+      out[0] = __builtin_nan("");
+      out[1] = __builtin_nan("");
+    }
+    return;
+  }
+  if (peak > CAP || peak <= a.min_bits) return;  // another launch's pair
+  const int num_ops = __builtin_amdgcn_readfirstlane(hdr->num_ops);
+  const int ngate = __builtin_amdgcn_readfirstlane(hdr->num_gate_ops);
+  const int log2f = __builtin_amdgcn_readfirstlane(hdr->log2_factor);
+  Cplx<Real>* B = reinterpret_cast<Cplx<Real>*>(smem_raw + wave_slot_bytes<Real, CAP>() * wave);
+  Real* stage = reinterpret_cast<Real*>(B + (1 << CAP));
+  const uint2* ops = reinterpret_cast<const uint2*>(a.ops + pidx * a.ops_stride);
+  const Real* mats = reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride);
+
+  Real pre[PREFETCH];
+#pragma unroll
+  for (int i = 0; i < PREFETCH; ++i) pre[i] = (lane < 32 && i < ngate) ? mats[i * 32 + lane] : (Real)0;
+  int jg = PREFETCH;  // next matrix to fetch
+  uint2 cur = lane < num_ops ? ops[lane] : make_uint2(0u, 0u);
+  uint2 ahead = 64 + lane < num_ops ? ops[64 + lane] : make_uint2(0u, 0u);
+
+  int b = 0;
+  int64_t expo = 0;  // true boundary = stored boundary * 2^expo
+  int pend = 0;      // exponent to remove at the next GATE
+  bool prev_track = false;
+  Real lmax = 0;
+  if (lane == 0) {
+    B[0].x = (Real)1;
+    B[0].y = (Real)0;
+  }
+  wave_fence();
+  for (int t0 = 0; t0 < num_ops; t0 += 64) {
+    const int lim = num_ops - t0 < 64 ? num_ops - t0 : 64;
+    for (int tt = 0; tt < lim; ++tt) {
+      const unsigned w0 = (unsigned)__builtin_amdgcn_readlane((int)cur.x, tt);
+      const int type = (int)(w0 & OP_TYPE_MASK);
+      const bool track = (w0 & OP_FLAG_TRACK) != 0;
+      const int p = (int)((w0 >> 8) & 0xff), q = (int)((w0 >> 16) & 0xff);
+      if (type == OP_GATE) {
+        if (lane < 32) stage[lane] = pre[0];
+#pragma unroll
+        for (int i = 0; i + 1 < PREFETCH; ++i) pre[i] = pre[i + 1];
+        pre[PREFETCH - 1] = (lane < 32 && jg < ngate) ? mats[(int64_t)jg * 32 + lane] : (Real)0;
+        ++jg;
+        wave_fence();
+        const int lo = p < q ? p : q, hi = p < q ? q : p;
+        const int ip = 1 << p, iq = 1 << q;
+        if (b <= 6) {
+          // one output entry per lane: group g, output jp
+          const int g = lane >> 2, jp = lane & 3;
+          Real Rr[4], Ri[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            Rr[j] = stage[(jp * 4 + j) * 2];
+            Ri[j] = stage[(jp * 4 + j) * 2 + 1];
+          }
+          if (pend) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              Rr[j] = ldexp(Rr[j], -pend);
+              Ri[j] = ldexp(Ri[j], -pend);
+            }
+          }
+          if (g < (1 << (b - 2))) {
+            const int idx = insert_zero(insert_zero(g, lo), hi);
+            Cplx<Real> v[4];
+            v[0] = B[idx];
+            v[1] = B[idx + ip];
+            v[2] = B[idx + iq];
+            v[3] = B[idx + ip + iq];
+            Real sr = 0, si = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              sr = fma(Rr[j], v[j].x, sr);
+              sr = fma(-Ri[j], v[j].y, sr);
+              si = fma(Rr[j], v[j].y, si);
+              si = fma(Ri[j], v[j].x, si);
+            }
+            if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+            // the store follows the four loads of every lane (one instruction
+            // stream), so no lane overwrites an input another lane still needs
+            Cplx<Real> w;
+            w.x = sr;
+            w.y = si;
+            B[idx + (jp & 1) * ip + (jp >> 1) * iq] = w;
+          }
+        } else {
+          Real Rr[16], Ri[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            Rr[k] = stage[2 * k];
+            Ri[k] = stage[2 * k + 1];
+          }
+          if (pend) {
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+              Rr[k] = ldexp(Rr[k], -pend);
+              Ri[k] = ldexp(Ri[k], -pend);
+            }
+          }
+          const int ng = 1 << (b - 2);
+          for (int g = lane; g < ng; g += 64) {
+            const int idx = insert_zero(insert_zero(g, lo), hi);
+            Cplx<Real> v[4];
+            v[0] = B[idx];
+            v[1] = B[idx + ip];
+            v[2] = B[idx + iq];
+            v[3] = B[idx + ip + iq];
+            Cplx<Real> w[4];
+#pragma unroll
+            for (int jp = 0; jp < 4; ++jp) {
+              Real sr = 0, si = 0;
+#pragma unroll
+              for (int j = 0; j < 4; ++j) {
+                sr = fma(Rr[jp * 4 + j], v[j].x, sr);
+                sr = fma(-Ri[jp * 4 + j], v[j].y, sr);
+                si = fma(Rr[jp * 4 + j], v[j].y, si);
+                si = fma(Ri[jp * 4 + j], v[j].x, si);
+              }
+              w[jp].x = sr;
+              w[jp].y = si;
+              if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+            }
+            B[idx] = w[0];
+            B[idx + ip] = w[1];
+            B[idx + iq] = w[2];
+            B[idx + ip + iq] = w[3];
+          }
+        }
+        expo += pend;
+        pend = 0;
+      } else if (type == OP_BELL) {
+        const int s = 1 << b;
+        for (int k = lane; k < s; k += 64) {
+          const Cplx<Real> v = B[k];
+          Cplx<Real> z;
+          z.x = (Real)0;
+          z.y = (Real)0;
+          B[k + s] = z;
+          B[k + 2 * s] = z;
+          B[k + 3 * s] = v;
+        }
+        b += 2;
+      } else if (type == OP_TRACE) {
+        // p < q; entries move down in increasing order, and every read of an
+        // iteration precedes its writes, so the compaction is in place
+        const int nout = 1 << (b - 2);
+        const int step = (1 << p) + (1 << q);
+        for (int j = lane; j < nout; j += 64) {
+          const int i0 = insert_zero(insert_zero(j, p), q);
+          const Cplx<Real> a0 = B[i0], a1 = B[i0 + step];
+          Cplx<Real> acc;
+          acc.x = a0.x + a1.x;
+          acc.y = a0.y + a1.y;
+          if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
+          B[j] = acc;
+        }
+        b -= 2;
+      } else {  // OP_COLEND: the op before it recorded the column's largest magnitude
+        if (prev_track) {
+          const Real m = wave_max<Real>(lmax);
+          lmax = 0;
+          pend = 0;
+          if (m > (Real)0 && isfinite(m)) {
+            int e;
+            frexp(m, &e);
+            pend = e;
+          }
+        }
+      }
+      prev_track = track;
+      wave_fence();
+    }
+    cur = ahead;
+    ahead = t0 + 128 + lane < num_ops ? ops[t0 + 128 + lane] : make_uint2(0u, 0u);
+  }
+  const Cplx<Real> v = B[0];
+  if (lane == 0) {
+    out[0] = ldexp((double)v.x, (int)(expo + log2f));
+    out[1] = ldexp((double)v.y, (int)(expo + log2f));
+  }
+}
+
+template <typename Real, int CAP>
+static int launch_wave_t(const SweepArgs& a, hipStream_t s) {
+  constexpr int WPB = 4;
+  const size_t smem = WPB * wave_slot_bytes<Real, CAP>();
+  if (smem > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_wave_kernel<Real, CAP, WPB>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) (void)hipGetLastError();
+  }
+  const int64_t blocks = (a.num_pairs + WPB - 1) / WPB;
+  hipLaunchKernelGGL((sweep_wave_kernel<Real, CAP, WPB>), dim3((unsigned)blocks), dim3(64 * WPB), smem, s, a);
+  return check_launch("sweep_wave");
+}
+
+int launch_sweep_wave(const SweepArgs& a, int precision, int cap_bits, hipStream_t s) {
+  if (a.num_pairs <= 0) return FP_OK;
+  if (!a.wmat) return set_error(FP_EINVAL, "wave sweep needs precomputed gate matrices");
+  if (cap_bits <= 8)
+    return precision == FP_C128 ? launch_wave_t<double, 8>(a, s) : launch_wave_t<float, 8>(a, s);
+  if (cap_bits <= 10)
+    return precision == FP_C128 ? launch_wave_t<double, 10>(a, s) : launch_wave_t<float, 10>(a, s);
+  return set_error(FP_EINVAL, "wave sweep holds at most 2^10 entries per pair");
+}
+
+}  // namespace fp

@@ -226,6 +226,20 @@ def test_determinism_and_batch_split(fp):
     assert np.array_equal(a, c)
 
 
+@pytest.mark.parametrize("ens", [(1, 30, 80), (1, 50, 150)])
+def test_chunked_pipeline_matches_pieces(fp, ens):
+    """Local random batches above 2^16 pairs are planned and swept in
+    overlapping chunks; every trace must equal, bit for bit, the one from a
+    batch small enough to run as a single chunk."""
+    npairs, piece = 140000, 65536
+    for prec in (1, 0):
+        whole = gpu_traces(fp, ens, npairs, 7, prec)
+        parts = np.concatenate([gpu_traces(fp, ens, min(piece, npairs - p0), 7, prec, p0)
+                                for p0 in range(0, npairs, piece)])
+        assert np.isfinite(whole).all()
+        assert np.array_equal(whole, parts)
+
+
 def test_brickwork_n6_full_workload(fp):
     """n = 6, depths 1..6, 2000 pairs per depth, complex128: every trace against the
     dense oracle, and F^(k) within the bootstrap interval of the exact value."""
