@@ -430,24 +430,36 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   a.wmat = j.wmat;
   a.wmat_stride = j.wmat_stride;
   struct Cls {
-    int lo, hi, tile, kclass, stream;
+    int lo, hi, tile, kclass;
   };
   // Classes by the largest boundary of a pair: up to 2^8 and 2^10 entries
   // with one wavefront per pair, up to 2^12 and 2^14 with 256 and 1024 lanes
-  // per pair (boundary in LDS), then HBM slots.  The HBM class, whose pairs
-  // take longest, has side stream 0 to itself; 1 takes the 1024- and
-  // 256-lane classes, 2 the smallest; the 2^10 class runs on s, which is
-  // free until the next chunk is planned.
-  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16, 2},
-                      {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64, -1},
-                      {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256, 1},
-                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024, 1}};
+  // per pair (boundary in LDS), then HBM slots.  Each class gets its own
+  // stream (s or a side stream) by planned MACs, heaviest first; with five
+  // classes the two lightest share one, the larger registers first.
+  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
+                      {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64},
+                      {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256},
+                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024}};
   int64_t first[5], count[5];
   for (int k = 0; k < 4; ++k) {
     if (cls[k].hi > cls[k].lo) range_of(cls[k].lo, cls[k].hi, &first[k], &count[k]);
     else first[k] = count[k] = 0;
   }
   range_of(j.cap_bits, PLAN_HIST - 1, &first[4], &count[4]);
+  int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
+  {
+    int act[5], na = 0;
+    for (int k = 0; k < 5; ++k)
+      if (count[k] > 0) act[na++] = k;
+    for (int x = 1; x < na; ++x)  // by MACs, heaviest first
+      for (int y = x; y > 0 && host.macs[act[y]] > host.macs[act[y - 1]]; --y) {
+        const int t = act[y];
+        act[y] = act[y - 1];
+        act[y - 1] = t;
+      }
+    for (int x = 0; x < na; ++x) slot_of[act[x]] = x < 4 ? x - 1 : slot_of[act[3]];
+  }
   rc = check_hip(hipEventRecord(c.aux.fork, s), "fork");
   if (rc) return rc;
   bool waited[NUM_AUX] = {false, false, false};
@@ -471,8 +483,8 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
       return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
                        c.fixed_bytes + (size_t)slot_bytes, max_peak);
     if (slots > avail) slots = avail;
-    hipStream_t sc;
-    rc = side(0, &sc);
+    hipStream_t sc = s;
+    if (slot_of[4] >= 0) rc = side(slot_of[4], &sc);
     if (!rc) rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, sc), "memset counter");
     if (rc) return rc;
     SweepArgs ac = a;
@@ -488,8 +500,8 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   for (int k = 3; k >= 0; --k) {
     if (count[k] <= 0) continue;
     hipStream_t sx = s;
-    if (cls[k].stream >= 0) {
-      rc = side(cls[k].stream, &sx);
+    if (slot_of[k] >= 0) {
+      rc = side(slot_of[k], &sx);
       if (rc) return rc;
     }
     SweepArgs ax = a;

@@ -42,6 +42,11 @@ struct LanesHost {
     for (int i = 0; i < WAVE; ++i) a[i] = f(i);
   }
   int at(int q) const { return a[q]; }
+  void put(int q, int x) { a[q] = x; }
+  void set2(int q1, int q2, int x) {
+    a[q1] = x;
+    a[q2] = x;
+  }
   int shfl_at(int q) const { return a[q & (WAVE - 1)]; }
   int find(int t, int b) const {
     for (int i = 0; i < b; ++i)
@@ -93,6 +98,7 @@ struct WaveHost {
     return 0;
   }
   bool any(bool p) const { return p; }
+  void atomic_add(int32_t* p, int v) const { *p += v; }
 };
 
 // ---- the device form ---------------------------------------------------------------
@@ -111,6 +117,11 @@ struct LanesDev {
     v = f(lane());
   }
   __device__ int at(int) const { return v; }
+  __device__ void put(int, int x) { v = x; }
+  __device__ void set2(int q1, int q2, int x) {
+    const int l = lane();
+    v = (l == q1 || l == q2) ? x : v;
+  }
   __device__ int shfl_at(int q) const { return __shfl(v, q & (WAVE - 1), WAVE); }
   __device__ int find(int t, int b) const {
     const unsigned long long m = __ballot(v == t && lane() < b);
@@ -173,10 +184,12 @@ struct WaveDev {
     return x - v;
   }
   __device__ bool any(bool p) const { return __ballot(p) != 0ull; }
+  __device__ void atomic_add(int32_t* p, int v) const { atomicAdd(p, v); }
 };
 
-// Scratch of the wave planner, in 16-bit entries (W = 2G merged-gate slots).
-__host__ __device__ inline int64_t plan_wave_scratch_elems(int G) { return 12 * 2 * (int64_t)G; }
+// Scratch of the wave planner, in 16-bit entries: 16 arrays of W = 2G entries,
+// one int32 array of W, and per-qubit tables.
+__host__ __device__ inline int64_t plan_wave_scratch_elems(int G) { return 18 * 2 * (int64_t)G + 256; }
 
 // Ops are written one behind, so that the end of a column can mark the op
 // before it (OP_FLAG_TRACK) without reading it back.
@@ -235,26 +248,47 @@ __host__ __device__ inline void wave_flush(const P& w, WaveEmitter& e) {
 
 // Plan one pair.  bw: bond of each position of W (2G entries: V's gates in
 // time order, then U's gates in reverse order); scratch: plan_wave_scratch_elems(G)
-// entries; ops: plan_max_ops(G, n); wgates, factors: 2G each; gseq (may be
-// null): 2G entries, the merged gate applied by each GATE op in program order.
-// n <= 64.
+// entries (4-byte aligned); ops: plan_max_ops(G, n); wgates, factors: 2G each;
+// gseq (may be null): 2G entries, the merged gate applied by each GATE op in
+// program order.  n <= 64.
+//
+// A position of W belongs to the same merged gate as the previous position on
+// its lower qubit when that position is also the previous one on its upper
+// qubit and lies on the same bond; merged gates are numbered by their first
+// position.  Neighbours on a qubit follow from the previous position on that
+// qubit; the gate merged across the wrap of the trace (the last gate of a bond
+// whose qubits see no other gate after it nor before the bond's first gate)
+// drops out of the neighbour lists, its factors going in front of the first.
 template <class P>
 __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, const int16_t* bw, int16_t* scratch,
                                                      Op* ops, int2* wgates, int32_t* factors, int16_t* gseq) {
   using Lanes = typename P::Lanes;
   const int W = 2 * G;
-  int16_t* mbond = scratch;
-  int16_t* head = scratch + W;
-  int16_t* tail = scratch + 2 * W;
-  int16_t* cnt = scratch + 3 * W;
-  int16_t* dead = scratch + 4 * W;
-  int16_t* nextf = scratch + 5 * W;
-  int16_t* non0 = scratch + 6 * W;
-  int16_t* non1 = scratch + 7 * W;
-  int16_t* pon0 = scratch + 8 * W;
-  int16_t* pon1 = scratch + 9 * W;
-  int16_t* colg = scratch + 10 * W;
-  int16_t* gfl = scratch + 11 * W;
+  int16_t* prev0 = scratch;  // previous position on the lower / upper qubit of a position
+  int16_t* prev1 = scratch + W;
+  int16_t* gid = scratch + 2 * W;   // merged gate of a position
+  int16_t* root = scratch + 3 * W;  // first position of its merged gate
+  int16_t* mbond = scratch + 4 * W;
+  int16_t* head = scratch + 5 * W;
+  int16_t* tail = scratch + 6 * W;
+  int16_t* dead = scratch + 7 * W;
+  int16_t* nextf = scratch + 8 * W;
+  int16_t* non0 = scratch + 9 * W;
+  int16_t* non1 = scratch + 10 * W;
+  int16_t* pon0 = scratch + 11 * W;
+  int16_t* pon1 = scratch + 12 * W;
+  int16_t* colg = scratch + 13 * W;
+  int16_t* gfl = scratch + 14 * W;
+  int16_t* cnt = scratch + 15 * W;
+  int32_t* cnt32 = reinterpret_cast<int32_t*>(scratch + 16 * W);
+  int16_t* firstpos = scratch + 18 * W;
+  int16_t* larr = firstpos + WAVE;
+  int32_t* bcnt32 = reinterpret_cast<int32_t*>(larr + WAVE);
+  // walk tables of the columns, once the neighbours are linked
+  int16_t* wk_g = prev0;
+  int16_t* wk_X = prev1;
+  int16_t* wk_Z = root;
+  int16_t* wk_f = gid;
 
   PlanHeader h;
   h.num_ops = 0;
@@ -279,136 +313,164 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
     }
   }
 
-  // ---- merge pass over W in time order; per-qubit state in lanes ----
-  // lastg[q]: gate holding the last position that touches q; lastb[q]: its
-  // bond; lastp[q]: that position; lastc[q]: that gate's factor count.
-  Lanes lastg, lastb, lastp, lastc, firstg;
-  lastg.fill(-1);
-  lastb.fill(-1);
+  // ---- 1. previous position on each qubit, one qubit per lane ----
+  Lanes lastp;
   lastp.fill(-1);
-  lastc.fill(0);
-  firstg.fill(-1);
-  int nw = 0;
   for (int i0 = 0; i0 < W; i0 += WAVE) {
-    Lanes bch;
+    Lanes bch, pv0, pv1;
     bch.fill_by([&](int j) { return i0 + j < W ? (int)bw[i0 + j] : -1; });
+    pv0.fill(-1);
+    pv1.fill(-1);
     const int lim = W - i0 < WAVE ? W - i0 : WAVE;
     for (int jj = 0; jj < lim; ++jj) {
-      const int i = i0 + jj;
       const int b = bch.get(jj);
-      const int kp = lastg.get(b);
-      if (kp >= 0 && lastg.get(b + 1) == kp && lastb.get(b) == b) {
-        const int tp = lastp.get(b);
-        const int c1 = lastc.get(b) + 1;
-        w.single([&] {
-          nextf[tp] = (int16_t)i;
-          nextf[i] = -1;
-          tail[kp] = (int16_t)i;
-          cnt[kp] = (int16_t)c1;
-        });
-        lastp.set(b, i);
-        lastp.set(b + 1, i);
-        lastc.set(b, c1);
-        lastc.set(b + 1, c1);
-      } else {
-        const int k = nw++;
-        w.single([&] {
-          mbond[k] = (int16_t)b;
-          head[k] = (int16_t)i;
-          tail[k] = (int16_t)i;
-          cnt[k] = 1;
-          dead[k] = 0;
-          nextf[i] = -1;
-        });
-        if (firstg.get(b) < 0) firstg.set(b, k);
-        if (firstg.get(b + 1) < 0) firstg.set(b + 1, k);
-        lastg.set(b, k);
-        lastg.set(b + 1, k);
-        lastb.set(b, b);
-        lastb.set(b + 1, b);
-        lastp.set(b, i);
-        lastp.set(b + 1, i);
-        lastc.set(b, 1);
-        lastc.set(b + 1, 1);
+      pv0.set(jj, lastp.get(b));
+      pv1.set(jj, lastp.get(b + 1));
+      lastp.set2(b, b + 1, i0 + jj);
+    }
+    for (int j = w.first(); j < lim; j += P::step) {
+      prev0[i0 + j] = (int16_t)pv0.at(j);
+      prev1[i0 + j] = (int16_t)pv1.at(j);
+    }
+  }
+  for (int q = w.first(); q < WAVE; q += P::step) {
+    firstpos[q] = -1;
+    bcnt32[q] = 0;
+  }
+  w.sync();
+  // ---- 2. merged gates: flags, numbering by first position, chains ----
+  int nw = 0;
+  for (int i0 = 0; i0 < W; i0 += P::step) {
+    const int i = i0 + w.first();
+    int hd = 0;
+    if (i < W) {
+      const int b = bw[i], p0 = prev0[i];
+      const bool mf = p0 >= 0 && p0 == prev1[i] && bw[p0] == b;
+      hd = mf ? 0 : 1;
+      root[i] = (int16_t)(mf ? p0 : i);
+      nextf[i] = -1;
+      if (prev0[i] < 0) firstpos[b] = (int16_t)i;
+      if (prev1[i] < 0) firstpos[b + 1] = (int16_t)i;
+    }
+    int tot;
+    const int ex = w.scan_excl(hd, &tot);
+    if (i < W && hd) gid[i] = (int16_t)(nw + ex);
+    nw += tot;
+  }
+  w.sync();
+  for (;;) {  // pointer jumping to the first position of each chain
+    bool ch = false;
+    for (int i = w.first(); i < W; i += P::step) {
+      const int r = root[i], rr = root[r];
+      if (rr != r) {
+        root[i] = (int16_t)rr;
+        ch = true;
       }
+    }
+    w.sync();
+    if (!w.any(ch)) break;
+  }
+  for (int i = w.first(); i < W; i += P::step) {
+    const int r = root[i];
+    if (r != i) {
+      gid[i] = gid[r];
+      nextf[prev0[i]] = (int16_t)i;
+    } else {
+      const int k = gid[i];
+      mbond[k] = bw[i];
+      head[k] = (int16_t)i;
+      dead[k] = 0;
+      cnt32[k] = 0;
     }
   }
   w.sync();
-  // ---- merge across the wrap of the trace, one bond per lane ----
+  for (int i = w.first(); i < W; i += P::step) {
+    w.atomic_add(&cnt32[gid[i]], 1);
+    if (nextf[i] < 0) tail[gid[i]] = (int16_t)i;
+  }
+  w.sync();
+  for (int k = w.first(); k < nw; k += P::step) cnt[k] = (int16_t)cnt32[k];
+  Lanes firstg, lastg;
+  firstg.fill_by([&](int q) { return q < n && firstpos[q] >= 0 ? (int)gid[firstpos[q]] : -1; });
+  lastg.fill_by([&](int q) { return q < n && lastp.at(q) >= 0 ? (int)gid[lastp.at(q)] : -1; });
+  // ---- 3. merges across the wrap of the trace, one bond per lane ----
+  Lanes wx, wy;
   for (int q = w.first(); q < WAVE; q += P::step) {
     const int x = firstg.at(q), y = lastg.at(q);
     const int x1 = firstg.shfl_at(q + 1), y1 = lastg.shfl_at(q + 1);
+    int mx = -1, my = -1;
     if (q < n - 1 && x >= 0 && x != y && x1 == x && y1 == y && mbond[x] == q && mbond[y] == q) {
-      // y precedes x around the loop: factors of y, then of x, at x's position
-      nextf[tail[y]] = head[x];
-      head[x] = head[y];
-      cnt[x] = (int16_t)(cnt[x] + cnt[y]);
+      mx = x;
+      my = y;
       dead[y] = 1;
     }
+    wx.put(q, mx);
+    wy.put(q, my);
   }
   w.sync();
-  // ---- cyclic neighbours of the surviving gates on each qubit ----
-  Lanes lg, lgb, fg, fgb, ccount;
-  lg.fill(-1);
-  lgb.fill(-1);
-  fg.fill(-1);
-  fgb.fill(-1);
-  ccount.fill(0);
-  for (int k0 = 0; k0 < nw; k0 += WAVE) {
-    Lanes bk;
-    bk.fill_by([&](int j) { return k0 + j < nw && !dead[k0 + j] ? (int)mbond[k0 + j] : -1; });
-    const int lim = nw - k0 < WAVE ? nw - k0 : WAVE;
-    for (int jj = 0; jj < lim; ++jj) {
-      const int b = bk.get(jj);
-      if (b < 0) continue;
-      const int k = k0 + jj;
-      for (int side = 0; side < 2; ++side) {
-        const int q = b + side;
-        const int pk = lg.get(q);
-        if (pk >= 0) {
-          const int pside = lgb.get(q) == q ? 0 : 1;
-          w.single([&] {
-            (pside == 0 ? non0 : non1)[pk] = (int16_t)k;
-            (side == 0 ? pon0 : pon1)[k] = (int16_t)pk;
-          });
-        } else {
-          fg.set(q, k);
-          fgb.set(q, b);
-        }
-        lg.set(q, k);
-        lgb.set(q, b);
+  // last surviving gate on each qubit
+  for (int q = w.first(); q < WAVE; q += P::step) {
+    int L = -1;
+    const int y = lastg.at(q);
+    if (q < n && y >= 0) {
+      if (!dead[y]) {
+        L = y;
+      } else {
+        const int pp = (mbond[y] == q ? prev0 : prev1)[head[y]];
+        L = pp >= 0 ? (int)gid[pp] : -1;
       }
-      ccount.set(b, ccount.get(b) + 1);
     }
+    larr[q] = (int16_t)L;
+  }
+  w.sync();
+  // ---- 4. cyclic neighbours of the surviving gates on each qubit ----
+  for (int k = w.first(); k < nw; k += P::step) {
+    if (dead[k]) continue;
+    const int b = mbond[k], hp = head[k];
+    for (int side = 0; side < 2; ++side) {
+      const int q = b + side;
+      const int pp = (side == 0 ? prev0 : prev1)[hp];
+      const int pk = pp >= 0 ? (int)gid[pp] : (int)larr[q];
+      (side == 0 ? pon0 : pon1)[k] = (int16_t)pk;
+      const int pside = mbond[pk] == q ? 0 : 1;
+      (pside == 0 ? non0 : non1)[pk] = (int16_t)k;
+    }
+    w.atomic_add(&bcnt32[b], 1);
   }
   w.sync();
   for (int q = w.first(); q < WAVE; q += P::step) {
-    const int f = fg.at(q), l = lg.at(q);
-    if (q < n && f >= 0) {
-      const int lside = lgb.at(q) == q ? 0 : 1;
-      const int fside = fgb.at(q) == q ? 0 : 1;
-      (lside == 0 ? non0 : non1)[l] = (int16_t)f;
-      (fside == 0 ? pon0 : pon1)[f] = (int16_t)l;
+    const int x = wx.at(q), y = wy.at(q);
+    if (x >= 0) {  // y precedes x around the loop: factors of y, then of x
+      nextf[tail[y]] = head[x];
+      head[x] = head[y];
+      cnt[x] = (int16_t)(cnt[x] + cnt[y]);
     }
   }
-  const int touched = fg.count_nonneg(n);
-  // ---- gates of each bond, in time order ----
+  const int touched = firstg.count_nonneg(n);
+  w.sync();
+  // ---- 5. gates of each bond in gate order ----
+  Lanes ccount;
+  ccount.fill_by([&](int q) { return (int)bcnt32[q]; });
   const Lanes cstart = ccount.scan_excl();
-  Lanes cfill = cstart;
-  for (int k0 = 0; k0 < nw; k0 += WAVE) {
-    Lanes bk;
-    bk.fill_by([&](int j) { return k0 + j < nw && !dead[k0 + j] ? (int)mbond[k0 + j] : -1; });
-    const int lim = nw - k0 < WAVE ? nw - k0 : WAVE;
-    for (int jj = 0; jj < lim; ++jj) {
-      const int b = bk.get(jj);
-      if (b < 0) continue;
-      const int pos = cfill.get(b);
-      const int k = k0 + jj;
-      w.single([&] { colg[pos] = (int16_t)k; });
-      cfill.set(b, pos + 1);
+  {
+    Lanes cfill = cstart;
+    for (int k0 = 0; k0 < nw; k0 += WAVE) {
+      Lanes bk, posl;
+      bk.fill_by([&](int j) { return k0 + j < nw && !dead[k0 + j] ? (int)mbond[k0 + j] : -1; });
+      posl.fill(0);
+      const int lim = nw - k0 < WAVE ? nw - k0 : WAVE;
+      for (int jj = 0; jj < lim; ++jj) {
+        const int b = bk.get(jj);
+        if (b < 0) continue;
+        const int pos = cfill.get(b);
+        posl.set(jj, pos);
+        cfill.set(b, pos + 1);
+      }
+      for (int j = w.first(); j < lim; j += P::step)
+        if (bk.at(j) >= 0) colg[posl.at(j)] = (int16_t)(k0 + j);
     }
   }
-  // ---- merged-gate table: factor lists in gate order ----
+  // ---- 6. merged-gate table: factor lists in gate order ----
   int carry = 0;
   for (int k0 = 0; k0 < nw; k0 += P::step) {
     const int k = k0 + w.first();
@@ -429,8 +491,43 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
     carry += tot;
   }
   w.sync();
+  // ---- 7. per column: walk start with the smallest peak, walk tables ----
+  Lanes relpk, firstc;
+  for (int c = w.first(); c < WAVE; c += P::step) {
+    int rp = 0, fg = -1;
+    const int m = ccount.at(c), cs = cstart.at(c);
+    if (c < n - 1 && m > 0) {
+      for (int i = 0; i < m; ++i) {
+        const int g = colg[cs + i];
+        gfl[cs + i] = (int16_t)((mbond[pon0[g]] == c ? GF_IN : 0) | (mbond[non0[g]] == c ? GF_OUT : 0) |
+                                (mbond[pon1[g]] == c ? GF_C1IN : 0) | (mbond[non1[g]] == c ? GF_C1OUT : 0));
+      }
+      int best = 0, bestpk = 0x7fffffff;
+      for (int st = 0; st < m; ++st) {
+        const int pk = walk_peak(gfl + cs, m, st, 0);
+        if (pk < bestpk) {
+          bestpk = pk;
+          best = st;
+        }
+      }
+      for (int t = 0; t < m; ++t) {
+        const int idx = best + t < m ? best + t : best + t - m;
+        const int g = colg[cs + idx];
+        wk_g[cs + t] = (int16_t)g;
+        wk_X[cs + t] = non0[g];
+        wk_Z[cs + t] = non1[g];
+        wk_f[cs + t] = (int16_t)((mbond[pon0[g]] == c ? 1 : 0) | (mbond[non0[g]] == c - 1 ? 2 : 0) |
+                                 (mbond[pon1[g]] == c + 1 ? 4 : 0) | (mbond[non1[g]] == c + 1 ? 8 : 0));
+      }
+      rp = bestpk;
+      fg = colg[cs + best];
+    }
+    relpk.put(c, rp);
+    firstc.put(c, fg);
+  }
+  w.sync();
 
-  // ---- columns ----
+  // ---- 8. the walks: register programs ----
   WaveEmitter e;
   e.ops = ops;
   e.gseq = gseq;
@@ -444,6 +541,8 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
   int b = 0, peak = 0;
   Lanes tag;  // tag of each register position (-1: none)
   tag.fill(-1);
+  Lanes ig, iX, iZ, ifl;  // walk tables from flat index c0
+  int c0 = -WAVE;
   for (int col = 0; col < n - 1 && status == PLAN_OK; ++col) {
     const int m = ccount.get(col);
     const int cs = cstart.get(col);
@@ -452,132 +551,103 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
       wave_emit(w, e, status, OP_COLEND, 0, 0, b, col);
       continue;
     }
-    // flags of the column's gates: which legs end on another gate of this bond
-    for (int i = w.first(); i < m; i += P::step) {
-      const int g = colg[cs + i];
-      gfl[i] = (int16_t)((mbond[pon0[g]] == col ? GF_IN : 0) | (mbond[non0[g]] == col ? GF_OUT : 0) |
-                         (mbond[pon1[g]] == col ? GF_C1IN : 0) | (mbond[non1[g]] == col ? GF_C1OUT : 0));
-    }
-    w.sync();
-    // walk start with the smallest peak (first such start on ties)
-    int key = 0x7fffffff;
-    for (int s = w.first(); s < m; s += P::step) {
-      int pk = walk_peak(gfl, m, s, b);
-      if (pk > 0x7ffe) pk = 0x7ffe;
-      const int kk = (pk << 16) | s;
-      key = kk < key ? kk : key;
-    }
-    key = w.min_i32(key);
-    const int best = key & 0xffff, bestpeak = key >> 16;
-    if (bestpeak > PLAN_MAX_BITS) {
+    if (b + relpk.get(col) > PLAN_MAX_BITS) {
       status = PLAN_EWIDE;
       break;
     }
-    const int first = colg[cs + best];
-    for (int t0 = 0; t0 < m && status == PLAN_OK; t0 += WAVE) {
-      // per-gate facts of the next (up to) 64 gates of the walk
-      Lanes ig, iX, iZ, ifl;
-      ig.fill_by([&](int j) {
-        const int t = t0 + j;
-        if (t >= m) return -1;
-        const int idx = best + t < m ? best + t : best + t - m;
-        return (int)colg[cs + idx];
-      });
-      iX.fill_by([&](int j) { return t0 + j < m ? (int)non0[ig.at(j)] : -1; });
-      iZ.fill_by([&](int j) { return t0 + j < m ? (int)non1[ig.at(j)] : -1; });
-      ifl.fill_by([&](int j) {
-        if (t0 + j >= m) return 0;
-        const int g = ig.at(j);
-        return (mbond[pon0[g]] == col ? 1 : 0) | (mbond[non0[g]] == col - 1 ? 2 : 0) |
-               (mbond[pon1[g]] == col + 1 ? 4 : 0) | (mbond[non1[g]] == col + 1 ? 8 : 0);
-      });
-      const int lim = m - t0 < WAVE ? m - t0 : WAVE;
-      for (int jj = 0; jj < lim && status == PLAN_OK; ++jj) {
-        const int t = t0 + jj;
-        const int g = ig.get(jj), X = iX.get(jj), Z = iZ.get(jj), fl = ifl.get(jj);
-        if (b + 4 > WAVE) {
-          status = PLAN_EWIDE;
-          break;
-        }
-        // input leg on qubit col
-        int pin = tag.find(seg_key(g, 0), b);
-        if (pin < 0) {
-          if (!(t == 0 && (fl & 1))) {
-            status = PLAN_EINTERNAL;
-            break;
-          }
-          tag.set(b, seg_key(g, 0));
-          tag.set(b + 1, seg_key(g, 0) | TAG_OUT);
-          pin = b;
-          b += 2;
-          wave_emit(w, e, status, OP_BELL, 0, 0, b, 0);
-        }
-        // output leg on qubit col
-        int pout;
-        if (fl & 2) {
-          pout = tag.find(seg_key(X, 1), b);
-          if (pout < 0) {
-            status = PLAN_EINTERNAL;
-            break;
-          }
-        } else {
-          pout = tag.find(seg_key(X, 0) | TAG_OUT, b);
-          if (pout < 0) {
-            tag.set(b, seg_key(X, 0));
-            tag.set(b + 1, seg_key(X, 0) | TAG_OUT);
-            pout = b + 1;
-            b += 2;
-            wave_emit(w, e, status, OP_BELL, 0, 0, b, 0);
-          }
-        }
-        if (pin >= b || pout >= b || pin == pout) {
+    const int first = firstc.get(col);
+    for (int t = 0; t < m && status == PLAN_OK; ++t) {
+      const int ft = cs + t;
+      if (ft >= c0 + WAVE) {
+        c0 = ft;
+        ig.fill_by([&](int j) { return c0 + j < W ? (int)wk_g[c0 + j] : -1; });
+        iX.fill_by([&](int j) { return c0 + j < W ? (int)wk_X[c0 + j] : -1; });
+        iZ.fill_by([&](int j) { return c0 + j < W ? (int)wk_Z[c0 + j] : -1; });
+        ifl.fill_by([&](int j) { return c0 + j < W ? (int)wk_f[c0 + j] : 0; });
+      }
+      const int jj = ft - c0;
+      const int g = ig.get(jj), X = iX.get(jj), Z = iZ.get(jj), fl = ifl.get(jj);
+      if (b + 4 > WAVE) {
+        status = PLAN_EWIDE;
+        break;
+      }
+      // input leg on qubit col
+      int pin = tag.find(seg_key(g, 0), b);
+      if (pin < 0) {
+        if (!(t == 0 && (fl & 1))) {
           status = PLAN_EINTERNAL;
           break;
         }
-        if (b > peak) peak = b;
-        wave_emit(w, e, status, OP_GATE, pin, pout, b, g);
-        // pin now holds the input leg on qubit col+1, pout the output leg
-        tag.set(pout, TAG_TMP);
-        if (fl & 4) {
-          tag.set(pin, seg_key(g, 1));
-        } else {
-          const int partner = tag.find(seg_key(g, 1) | TAG_PEND, b);
-          if (partner >= 0) {
-            const int lo = pin < partner ? pin : partner, hi = pin < partner ? partner : pin;
-            tag.remove2(lo, hi, b);
-            b -= 2;
-            wave_emit(w, e, status, OP_TRACE, lo, hi, b, 0);
-          } else {
-            tag.set(pin, seg_key(g, 1) | TAG_FIRST);
-          }
-        }
-        pout = tag.find_flag(TAG_TMP, b);
+        tag.set(b, seg_key(g, 0));
+        tag.set(b + 1, seg_key(g, 0) | TAG_OUT);
+        pin = b;
+        b += 2;
+        wave_emit(w, e, status, OP_BELL, 0, 0, b, 0);
+      }
+      // output leg on qubit col
+      int pout;
+      if (fl & 2) {
+        pout = tag.find(seg_key(X, 1), b);
         if (pout < 0) {
           status = PLAN_EINTERNAL;
           break;
         }
-        if (fl & 8) {
-          tag.set(pout, seg_key(Z, 0));
-        } else if (Z == first) {
-          const int partner = tag.find_flag(TAG_FIRST, b);
-          if (partner < 0 || partner == pout) {
-            status = PLAN_EINTERNAL;
-            break;
-          }
-          const int lo = pout < partner ? pout : partner, hi = pout < partner ? partner : pout;
+      } else {
+        pout = tag.find(seg_key(X, 0) | TAG_OUT, b);
+        if (pout < 0) {
+          tag.set(b, seg_key(X, 0));
+          tag.set(b + 1, seg_key(X, 0) | TAG_OUT);
+          pout = b + 1;
+          b += 2;
+          wave_emit(w, e, status, OP_BELL, 0, 0, b, 0);
+        }
+      }
+      if (pin >= b || pout >= b || pin == pout) {
+        status = PLAN_EINTERNAL;
+        break;
+      }
+      if (b > peak) peak = b;
+      wave_emit(w, e, status, OP_GATE, pin, pout, b, g);
+      // pin now holds the input leg on qubit col+1, pout the output leg
+      tag.set(pout, TAG_TMP);
+      if (fl & 4) {
+        tag.set(pin, seg_key(g, 1));
+      } else {
+        const int partner = tag.find(seg_key(g, 1) | TAG_PEND, b);
+        if (partner >= 0) {
+          const int lo = pin < partner ? pin : partner, hi = pin < partner ? partner : pin;
           tag.remove2(lo, hi, b);
           b -= 2;
           wave_emit(w, e, status, OP_TRACE, lo, hi, b, 0);
         } else {
-          tag.set(pout, seg_key(Z, 1) | TAG_PEND);
+          tag.set(pin, seg_key(g, 1) | TAG_FIRST);
         }
+      }
+      pout = tag.find_flag(TAG_TMP, b);
+      if (pout < 0) {
+        status = PLAN_EINTERNAL;
+        break;
+      }
+      if (fl & 8) {
+        tag.set(pout, seg_key(Z, 0));
+      } else if (Z == first) {
+        const int partner = tag.find_flag(TAG_FIRST, b);
+        if (partner < 0 || partner == pout) {
+          status = PLAN_EINTERNAL;
+          break;
+        }
+        const int lo = pout < partner ? pout : partner, hi = pout < partner ? partner : pout;
+        tag.remove2(lo, hi, b);
+        b -= 2;
+        wave_emit(w, e, status, OP_TRACE, lo, hi, b, 0);
+      } else {
+        tag.set(pout, seg_key(Z, 1) | TAG_PEND);
       }
     }
     if (status != PLAN_OK) break;
     // only labels for the next column may remain
     if (tag.any_flag(TAG_OUT | TAG_PEND | TAG_FIRST | TAG_TMP, b)) status = PLAN_EINTERNAL;
     wave_emit(w, e, status, OP_COLEND, 0, 0, b, col);
-    w.sync();
   }
   if (status == PLAN_OK && b != 0) status = PLAN_EINTERNAL;
   wave_flush(w, e);

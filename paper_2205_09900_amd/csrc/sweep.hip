@@ -139,17 +139,32 @@ __global__ void __launch_bounds__(64) plan_local_random_kernel(PlanJob j) {
 
 __global__ void __launch_bounds__(256) order_pairs_kernel(OrderJob j) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= j.num_pairs) return;
-  const PlanHeader* h = j.hdr + i * j.hdr_stride;
-  if (h->status != 0) {
-    double* out = j.trace + 2 * (j.trace_offset + i);
-    out[0] = __builtin_nan("");
-    out[1] = __builtin_nan("");
-    return;
+  int b = -1;
+  if (i < j.num_pairs) {
+    const PlanHeader* h = j.hdr + i * j.hdr_stride;
+    if (h->status != 0) {
+      double* out = j.trace + 2 * (j.trace_offset + i);
+      out[0] = __builtin_nan("");
+      out[1] = __builtin_nan("");
+    } else {
+      b = h->peak_bits < PLAN_HIST ? h->peak_bits : PLAN_HIST - 1;
+    }
   }
-  const int b = h->peak_bits < PLAN_HIST ? h->peak_bits : PLAN_HIST - 1;
-  const int pos = j.first[b] + atomicAdd(&j.cursor[b], 1);
-  j.order[pos] = (int32_t)i;
+  // one atomic per distinct width and wavefront: the lanes of equal width
+  // take consecutive places after the block reserved by their leader
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  unsigned long long todo = __ballot(b >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int v = __shfl(b, leader, 64);
+    const unsigned long long same = __ballot(b == v);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&j.cursor[v], __popcll(same));
+    base = __shfl(base, leader, 64);
+    if (b == v) j.order[j.first[v] + base + __popcll(same & below)] = (int32_t)i;
+    todo &= ~same;
+  }
 }
 
 int launch_order_pairs(const OrderJob& j, hipStream_t s) {
@@ -227,6 +242,17 @@ int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s) {
   return check_launch("plan_local_random");
 }
 
+__device__ __forceinline__ void store_matrix(const Cplx<float> (&m)[16], float* dst) {
+  float4* v = reinterpret_cast<float4*>(dst);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = make_float4(m[2 * i].x, m[2 * i].y, m[2 * i + 1].x, m[2 * i + 1].y);
+}
+__device__ __forceinline__ void store_matrix(const Cplx<double> (&m)[16], double* dst) {
+  double2* v = reinterpret_cast<double2*>(dst);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = make_double2(m[i].x, m[i].y);
+}
+
 // The realigned matrix of every GATE op, in program order: one thread per
 // (pair, GATE op), the product of the merged gate's factors (same arithmetic
 // as the staging of the LDS sweep).
@@ -241,8 +267,9 @@ __global__ void __launch_bounds__(256) gate_matrices_kernel(PlanJob j) {
   if (h->status != 0 || jj >= h->num_gate_ops) return;
   const int k = j.gseq[pi * j.gseq_stride + jj];
   const Real* pg = reinterpret_cast<const Real*>(j.gates + pi * j.gate_stride);
-  Cplx<Real>* dst = reinterpret_cast<Cplx<Real>*>(j.wmat + pi * j.wmat_stride) + 16 * (int64_t)jj;
-  stage_gate<Real>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], dst);
+  Cplx<Real> m[16];
+  stage_gate<Real>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], m);
+  store_matrix(m, reinterpret_cast<Real*>(j.wmat + pi * j.wmat_stride) + 32 * (int64_t)jj);
 }
 
 int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s) {

@@ -33,17 +33,38 @@ __device__ __forceinline__ int insert_zero(int x, int pos) {
 // the column transfer and written to dst (16 complex):
 //   dst[j' * 4 + j] = M[2 x_out + y_out][2 x_in + y_in],
 // j = x_in + 2 x_out (legs on qubit c), j' = y_in + 2 y_out (legs on qubit c+1).
+// One 4x4 complex gate (32 reals, 16-byte aligned) into registers with
+// 16-byte loads.
+__device__ __forceinline__ void load_gate(const float* src, float (&g)[32]) {
+  const float4* v = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const float4 x = v[i];
+    g[4 * i] = x.x;
+    g[4 * i + 1] = x.y;
+    g[4 * i + 2] = x.z;
+    g[4 * i + 3] = x.w;
+  }
+}
+__device__ __forceinline__ void load_gate(const double* src, double (&g)[32]) {
+  const double2* v = reinterpret_cast<const double2*>(src);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const double2 x = v[i];
+    g[2 * i] = x.x;
+    g[2 * i + 1] = x.y;
+  }
+}
+
+// Row a of a gate (or of its conjugate transpose) from its registers.
 template <typename Real>
-__device__ __forceinline__ void load_factor_row(const Real* src, int dagger, int a, Real (&fr)[4], Real (&fi)[4]) {
+__device__ __forceinline__ void factor_row(const Real (&g)[32], int dagger, int a, Real (&fr)[4], Real (&fi)[4]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (dagger) {
-      fr[k] = src[(k * 4 + a) * 2];
-      fi[k] = -src[(k * 4 + a) * 2 + 1];
-    } else {
-      fr[k] = src[(a * 4 + k) * 2];
-      fi[k] = src[(a * 4 + k) * 2 + 1];
-    }
+    const Real dr = g[(k * 4 + a) * 2], di = g[(k * 4 + a) * 2 + 1];
+    const Real nr = g[(a * 4 + k) * 2], ni = g[(a * 4 + k) * 2 + 1];
+    fr[k] = dagger ? dr : nr;
+    fi[k] = dagger ? -di : ni;
   }
 }
 
@@ -53,11 +74,12 @@ __device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int coun
   Real mr[16], mi[16];
   {
     const FactorRef f0 = decode_factor(code_of(0), G);
-    const Real* src = pair_gates + ((int64_t)f0.circuit * G + f0.gate) * 32;
+    Real g[32];
+    load_gate(pair_gates + ((int64_t)f0.circuit * G + f0.gate) * 32, g);
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       Real fr[4], fi[4];
-      load_factor_row<Real>(src, f0.dagger, a, fr, fi);
+      factor_row<Real>(g, f0.dagger, a, fr, fi);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         mr[a * 4 + k] = fr[k];
@@ -67,12 +89,13 @@ __device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int coun
   }
   for (int f = 1; f < count; ++f) {
     const FactorRef ff = decode_factor(code_of(f), G);
-    const Real* src = pair_gates + ((int64_t)ff.circuit * G + ff.gate) * 32;
+    Real g[32];
+    load_gate(pair_gates + ((int64_t)ff.circuit * G + ff.gate) * 32, g);
     Real nr[16], ni[16];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       Real fr[4], fi[4];
-      load_factor_row<Real>(src, ff.dagger, a, fr, fi);
+      factor_row<Real>(g, ff.dagger, a, fr, fi);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         Real sr = 0, si = 0;
@@ -108,6 +131,61 @@ template <typename Real>
 __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int32_t* __restrict__ factors, int2 wg,
                            Cplx<Real>* dst) {
   merged_gate<Real>(pair_gates, G, wg.y, [&](int f) { return factors[wg.x + f]; }, dst);
+}
+
+// Applies the realigned 4x4 matrix (Rr, Ri) to the groups of four entries
+// g = first, first + stride, ... < ng (bits lo < hi of the group index are the
+// gate's bits).  Up to U groups per round: distinct groups touch distinct
+// entries, so all loads of a round are issued before its stores and their
+// latencies overlap.  Same arithmetic per group as one group at a time.
+template <typename Real, int U>
+__device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo,
+                                            int hi, int ip, int iq, int ng, int first, int stride, bool track,
+                                            Real& lmax) {
+  for (int g0 = first; g0 < ng; g0 += stride * U) {
+    Cplx<Real> v[U][4];
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int g = g0 + u * stride;
+      idx[u] = insert_zero(insert_zero(g, lo), hi);
+      if (g < ng) {
+        v[u][0] = B[idx[u]];
+        v[u][1] = B[idx[u] + ip];
+        v[u][2] = B[idx[u] + iq];
+        v[u][3] = B[idx[u] + ip + iq];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (g0 + u * stride >= ng) break;
+      Cplx<Real> w[4];
+#pragma unroll
+      for (int jp = 0; jp < 4; ++jp) {
+        Real sr = 0, si = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          sr = fma(Rr[jp * 4 + j], v[u][j].x, sr);
+          sr = fma(-Ri[jp * 4 + j], v[u][j].y, sr);
+          si = fma(Rr[jp * 4 + j], v[u][j].y, si);
+          si = fma(Ri[jp * 4 + j], v[u][j].x, si);
+        }
+        w[jp].x = sr;
+        w[jp].y = si;
+        if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+      }
+      B[idx[u]] = w[0];
+      B[idx[u] + ip] = w[1];
+      B[idx[u] + iq] = w[2];
+      B[idx[u] + ip + iq] = w[3];
+    }
+  }
+}
+
+// Groups per round of gate_groups: fewer for float64 (register pressure).
+template <typename Real>
+constexpr int gate_batch() {
+  return sizeof(Real) == 4 ? 4 : 2;
 }
 
 template <typename Real, int NT>
@@ -178,34 +256,7 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
-        const int ng = 1 << (b - 2);
-        for (int g = lane; g < ng; g += NT) {
-          const int idx = insert_zero(insert_zero(g, lo), hi);
-          Cplx<Real> v[4];
-          v[0] = B[idx];
-          v[1] = B[idx + ip];
-          v[2] = B[idx + iq];
-          v[3] = B[idx + ip + iq];
-          Cplx<Real> w[4];
-#pragma unroll
-          for (int jp = 0; jp < 4; ++jp) {
-            Real sr = 0, si = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              sr = fma(Rr[jp * 4 + j], v[j].x, sr);
-              sr = fma(-Ri[jp * 4 + j], v[j].y, sr);
-              si = fma(Rr[jp * 4 + j], v[j].y, si);
-              si = fma(Ri[jp * 4 + j], v[j].x, si);
-            }
-            w[jp].x = sr;
-            w[jp].y = si;
-            if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
-          }
-          B[idx] = w[0];
-          B[idx + ip] = w[1];
-          B[idx + iq] = w[2];
-          B[idx + ip + iq] = w[3];
-        }
+        gate_groups<Real, gate_batch<Real>()>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, NT, track, lmax);
       } else if (type == OP_BELL) {
         const int s = 1 << b;
         for (int k = lane; k < s; k += NT) {

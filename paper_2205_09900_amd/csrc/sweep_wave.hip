@@ -11,7 +11,7 @@
 //     0..31 and passed through a 32-entry LDS stage;
 //   * registers of up to 64 entries give each lane one output entry of the
 //     gate (one matrix row, four inputs); larger ones give each lane whole
-//     groups of four entries.
+//     groups of four entries, several loaded at once.
 // The boundary stays in LDS; pairs are independent, so waves never wait for
 // each other.
 #include <hip/hip_runtime.h>
@@ -162,34 +162,7 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
               Ri[k] = ldexp(Ri[k], -pend);
             }
           }
-          const int ng = 1 << (b - 2);
-          for (int g = lane; g < ng; g += 64) {
-            const int idx = insert_zero(insert_zero(g, lo), hi);
-            Cplx<Real> v[4];
-            v[0] = B[idx];
-            v[1] = B[idx + ip];
-            v[2] = B[idx + iq];
-            v[3] = B[idx + ip + iq];
-            Cplx<Real> w[4];
-#pragma unroll
-            for (int jp = 0; jp < 4; ++jp) {
-              Real sr = 0, si = 0;
-#pragma unroll
-              for (int j = 0; j < 4; ++j) {
-                sr = fma(Rr[jp * 4 + j], v[j].x, sr);
-                sr = fma(-Ri[jp * 4 + j], v[j].y, sr);
-                si = fma(Rr[jp * 4 + j], v[j].y, si);
-                si = fma(Ri[jp * 4 + j], v[j].x, si);
-              }
-              w[jp].x = sr;
-              w[jp].y = si;
-              if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
-            }
-            B[idx] = w[0];
-            B[idx + ip] = w[1];
-            B[idx + iq] = w[2];
-            B[idx + ip + iq] = w[3];
-          }
+          gate_groups<Real, gate_batch<Real>()>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, 64, track, lmax);
         }
         expo += pend;
         pend = 0;
