@@ -24,7 +24,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Tr(U†V) contractions/s at n=50; time-to-1%-rel-err F^(2), CV vs plain"
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector, published
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
 PEAK_HBM_GBS = 8000.0
+SWEEP_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
+# kernel of each sweep class for local random batches (names as rocprofv3 shows them)
+LR_KERNELS = {
+    "lds16": "fp::sweep_wave_kernel<{r}, 8, 4>", "lds64": "fp::sweep_wave_kernel<{r}, 10, 4>",
+    "lds256": "fp::sweep_lds_kernel<{r}, 256, 1>", "lds1024": "fp::sweep_lds_kernel<{r}, {big}, 1>",
+    "hbm": "fp::sweep_hbm_kernel<{r}, {big}>"}
 
 
 def parse():
@@ -106,8 +113,8 @@ def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chun
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = fp.fp_profile_end()
-    kms = sum(v["ms"] for v in prof.values())
-    flops = sum(v["flops"] for v in prof.values())
+    kms = sum(prof[c]["ms"] for c in SWEEP_CLASSES)
+    flops = sum(prof[c]["flops"] for c in SWEEP_CLASSES)
     return {"contractions_per_s": pairs * steps / wall, "F": f[0], "SE": f[1],
             "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
             "kernel_ms_per_step": kms / steps}, trace
@@ -227,27 +234,40 @@ def main():
     head = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base)
     value = args.pairs * args.steps / head["wall_s"]
     prof = head["prof"]
-    dom = max(prof, key=lambda c: prof[c]["ms"])
+    # roofline of the sweep kernel with the largest event time (the sweeps
+    # hold the method's arithmetic; planning, matrix preparation and sampling
+    # are listed in step_kernels_ms)
+    dom = max(SWEEP_CLASSES, key=lambda c: prof[c]["ms"])
     d = prof[dom]
+    peak = PEAK_FP32_TFLOPS if prec == fp.C64 else PEAK_FP64_TFLOPS
     achieved = (d["flops"] / d["launches"]) / (d["ms"] / d["launches"] * 1e-3) / 1e12 if d["launches"] else 0.0
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS if prec == fp.C64 else 78.6,
-                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP32_TFLOPS if prec == fp.C64 else 78.6),
-                "traffic": None, "kernel_class": dom,
+    kname = LR_KERNELS[dom].format(r="float" if prec == fp.C64 else "double",
+                                   big=1024 if prec == fp.C64 else 512)
+    traffic = None
+    from paper_2205_09900_amd import profile_summary
+    summ = profile_summary.load_traffic(os.path.join(ROOT, "profiles", f"local_random_n{args.n}_S{args.depth}.md"))
+    if summ and summ.get("workload") == f"local_random_n{args.n}_S{args.depth}_{args.precision}":
+        traffic = summ["bytes_per_dispatch"].get(kname)
+    roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic, "kernel": kname, "kernel_class": dom,
                 "kernel_ms_per_launch": d["ms"] / max(1, d["launches"]),
-                "flops_per_launch": d["flops"] / max(1, d["launches"]),
-                "classes": prof}
+                "flops_per_launch": d["flops"] / max(1, d["launches"])}
+    step_kernels = {c: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                        "gflop_per_step": v["flops"] / args.steps / 1e9, "gb_per_step": v["bytes"] / args.steps / 1e9}
+                    for c, v in prof.items() if v["launches"]}
 
     per_depth = {}
     if args.per_depth:
         for s in [int(x) for x in args.per_depth.split(",") if x]:
             r = run_workload(fp, torch, args.n, s, args.pairs, prec, max(2, args.steps // 2), 1, seed_base)
-            flops = sum(v["flops"] for v in r["prof"].values())
-            kms = sum(v["ms"] for v in r["prof"].values())
+            flops = sum(r["prof"][c]["flops"] for c in SWEEP_CLASSES)
+            kms = sum(r["prof"][c]["ms"] for c in SWEEP_CLASSES)
             per_depth[str(s)] = {
                 "contractions_per_s": args.pairs * max(2, args.steps // 2) / r["wall_s"],
                 "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
                 "F": r["F"], "SE": r["SE"],
-                "kernel_ms": {k: v["ms"] for k, v in r["prof"].items() if v["launches"]},
+                "kernel_ms_per_step": {k: v["ms"] / max(2, args.steps // 2) for k, v in r["prof"].items()
+                                       if v["launches"]},
             }
             try:
                 per_depth[str(s)].update(bits_stats(fp, np, args.n, s, args.pairs, seed_base, sample=200))
@@ -286,6 +306,7 @@ def main():
                    "steps_per_circuit": args.depth, "pairs_per_step": args.pairs, "k_max": 3,
                    "precision": args.precision, "F_k": head["F"], "SE_k": head["SE"]},
         "roofline": roofline,
+        "step_kernels_ms": step_kernels,
         "cpu_baseline": cpu,
         "per_depth": per_depth,
         "control_variate": cv_res,

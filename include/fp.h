@@ -319,19 +319,29 @@ int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t n
 
 /* ---- measurement ----------------------------------------------------------- */
 /*
- * fp_profile_begin / fp_profile_end -- while enabled, every sweep launch of
- * fp_contract_trace_batch is bracketed by HIP events on its stream.
+ * fp_profile_begin / fp_profile_end -- while enabled, every kernel launch of
+ * fp_sample_gates and fp_contract_trace_batch (sampling, planning, matrix
+ * preparation, sweeps) is bracketed by HIP events on its stream.
  * fp_profile_end disables timing, waits for the recorded events and writes,
- * per launch class (boundary in LDS with 0: 16 lanes, 1: 64 lanes, 2: 256
- * lanes, 3: 1024 lanes per pair; 4: boundaries in HBM; 5: HEA transform
- * sweep), the summed kernel time in milliseconds, the number of launches and
- * the algorithmic flops (8 real flops per complex multiply-add of the plan;
- * for the HEA sweep 2 per complex addition of the transforms and 6 per
- * pointwise product).  Each output array has 6 entries and may be NULL.
+ * per launch class, the summed kernel time in milliseconds, the number of
+ * launches, the algorithmic flops and the algorithmic bytes.  Classes:
+ *   0..3  sweeps with the boundary in LDS (local random: registers up to
+ *         2^8 and 2^10 entries with one wavefront per pair, up to 2^12 and
+ *         2^14 with 256 and 1024 lanes per pair; fixed topologies: 16, 64,
+ *         256, 1024 lanes per pair);
+ *   4     boundaries in HBM;          5  HEA transform sweep;
+ *   6     local random planning;      7  GATE matrix preparation;
+ *   8     gate sampling.
+ * Flops: 8 real flops per complex multiply-add of the plan; for the HEA sweep
+ * 2 per complex addition of the transforms and 6 per pointwise product; 0 for
+ * classes 6..8.  Bytes: for classes 6..8 the data each launch must read and
+ * write (bond lists and plans; gates and matrices; gates); 0 otherwise.
+ * Each output array has FP_PROFILE_CLASSES entries and may be NULL.
  * Not re-entrant.
  */
+#define FP_PROFILE_CLASSES 9
 int fp_profile_begin(void);
-int fp_profile_end(double* kernel_ms, int64_t* launches, double* flops);
+int fp_profile_end(double* kernel_ms, int64_t* launches, double* flops, double* bytes);
 
 /* ---- misc ---------------------------------------------------------------- */
 const char* fp_last_error(void);

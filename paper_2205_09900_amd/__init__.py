@@ -95,7 +95,7 @@ def _load():
         "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_profile_begin": (I, []),
-        "fp_profile_end": (I, [P, P, P]),
+        "fp_profile_end": (I, [P, P, P, P]),
         "fp_last_error": (ctypes.c_char_p, []),
         "fp_version": (I, []),
     }
@@ -328,7 +328,10 @@ def fp_autotune_load(text):
     return _check(lib.fp_autotune_load(text.encode()))
 
 
-KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
+# Launch classes of fp_profile_end (include/fp.h).  For local random batches
+# classes 0 and 1 are the one-wavefront-per-pair sweeps (registers up to 2^8
+# and 2^10 entries); for fixed topologies they are 16- and 64-lane tiles.
+KERNEL_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea", "plan", "prep", "sample")
 
 
 def fp_profile_begin():
@@ -336,11 +339,13 @@ def fp_profile_begin():
 
 
 def fp_profile_end():
-    ms = (ctypes.c_double * 6)()
-    n = (ctypes.c_int64 * 6)()
-    fl = (ctypes.c_double * 6)()
-    _check(lib.fp_profile_end(ms, n, fl))
-    return {c: {"ms": ms[i], "launches": n[i], "flops": fl[i]} for i, c in enumerate(KERNEL_CLASSES)}
+    k = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * k)()
+    n = (ctypes.c_int64 * k)()
+    fl = (ctypes.c_double * k)()
+    by = (ctypes.c_double * k)()
+    _check(lib.fp_profile_end(ms, n, fl, by))
+    return {c: {"ms": ms[i], "launches": n[i], "flops": fl[i], "bytes": by[i]} for i, c in enumerate(KERNEL_CLASSES)}
 
 
 OP_DTYPE = [("type", "u1"), ("p", "u1"), ("q", "u1"), ("bits", "u1"), ("arg", "<i4")]

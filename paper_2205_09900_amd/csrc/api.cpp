@@ -372,8 +372,16 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   static_assert(sizeof(PlanHeader) <= 64, "plan header fits its slot");
   int rc = check_hip(hipMemsetAsync(hw, 0, LR_HEAD, s), "memset counters");
   if (rc) return rc;
+  // algorithmic bytes: the planner reads the bond lists and writes the plans;
+  // the preparation reads the gate buffer and writes one matrix per GATE op
+  const double gate_bytes = (double)np * (double)c.gate_stride;
+  profile_launch_begin(KCLASS_PLAN, s);
   rc = launch_plan_local_random(j, c.precision, s);
-  if (!rc) rc = launch_gate_matrices(j, c.precision, s);
+  profile_launch_end(KCLASS_PLAN, 0.0, s, (double)np * (8.0 * G + (double)(l.hdr + l.ops + l.wg + l.fac + l.gseq)));
+  if (rc) return rc;
+  profile_launch_begin(KCLASS_PREP, s);
+  rc = launch_gate_matrices(j, c.precision, s);
+  profile_launch_end(KCLASS_PREP, 0.0, s, gate_bytes + (double)np * (double)l.mat);
   if (rc) return rc;
   struct {
     int v[4];
@@ -626,7 +634,10 @@ int fp_sample_gates(const fp_ensemble_t* ens, int64_t num_pairs, uint64_t seed, 
   const int64_t need = num_pairs * pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
   if ((int64_t)gates_bytes < need) return set_error(FP_EINVAL, "gates_bytes %zu < %lld", gates_bytes, (long long)need);
   if (first_pair + (uint64_t)num_pairs > (1ull << 62)) return set_error(FP_EINVAL, "pair index beyond 2^62");
-  return launch_sample(ens, num_pairs, seed, first_pair, precision, d_gates, (hipStream_t)stream);
+  profile_launch_begin(KCLASS_SAMPLE, (hipStream_t)stream);
+  rc = launch_sample(ens, num_pairs, seed, first_pair, precision, d_gates, (hipStream_t)stream);
+  profile_launch_end(KCLASS_SAMPLE, 0.0, (hipStream_t)stream, (double)need);
+  return rc;
 }
 
 int fp_workspace_bytes(const fp_ensemble_t* ens, int64_t num_pairs, int precision, size_t* out_bytes) {

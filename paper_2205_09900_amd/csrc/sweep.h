@@ -53,7 +53,7 @@ struct PlanJob {
   int tiny_bits;   // largest boundary run with 16 lanes per pair
   int small_bits;  // largest boundary run with one wavefront per pair
   int mid_bits;    // largest boundary run with 256 lanes per pair
-  double* class_macs;  // complex MACs per launch class (16, 64, 256, 1024 lanes, HBM)
+  double* class_macs;  // complex MACs per launch class (16, 64, 256, 1024 lanes, HBM), then GATE ops
   int* hist;           // pairs per peak register width (PLAN_HIST entries)
   int16_t* gseq;       // merged gate of each GATE op, per pair
   int64_t gseq_stride; // entries per pair
@@ -88,10 +88,10 @@ int sweep_elem_bytes(int precision);
 
 // Event timing of the sweep launches (enabled by fp_profile_begin).
 enum { KCLASS_LDS16 = 0, KCLASS_LDS64 = 1, KCLASS_LDS256 = 2, KCLASS_LDS1024 = 3, KCLASS_HBM = 4, KCLASS_HEA = 5,
-       KCLASS_COUNT = 6 };
+       KCLASS_PLAN = 6, KCLASS_PREP = 7, KCLASS_SAMPLE = 8, KCLASS_COUNT = 9 };
 bool profiling();
 void profile_launch_begin(int kclass, hipStream_t s);
-void profile_launch_end(int kclass, double flops, hipStream_t s);
+void profile_launch_end(int kclass, double flops, hipStream_t s, double bytes = 0.0);
 
 // HEA (diagonal CZ ladders -> Walsh-Hadamard column transfer)
 struct HeaArgs {

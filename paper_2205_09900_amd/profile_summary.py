@@ -1,0 +1,128 @@
+"""Turns rocprofv3 output of the benchmark into a short text summary.
+
+Inputs: the directory of a ``--kernel-trace --stats --output-format csv`` run
+and the directories of two counter runs (``--pmc FETCH_SIZE`` and
+``--pmc WRITE_SIZE``) of the same command, which also ran one device copy of
+256 MiB (``bench.py --with-copy``).  The copy calibrates the counters: its
+true traffic is 256 MiB read and 256 MiB written, so
+
+    bytes(kernel) = counter(kernel) [KiB] * 1024 * 256 MiB / (counter(copy) [KiB] * 1024).
+
+The summary lists per-kernel average durations and calibrated HBM bytes per
+dispatch, and ends with one ``traffic-json:`` line that ``bench.py`` reads.
+That line carries a hash of the kernel sources: once any source changes the
+counters no longer describe the kernels and ``bench.py`` reports no traffic.
+
+    python -m paper_2205_09900_amd.profile_summary --trace T --fetch F --write W \\
+        --workload NAME --command "CMD" --out profiles/NAME.md
+"""
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+COPY_BYTES = 256 << 20
+CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+
+
+def sources_hash():
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _counters(path):
+    rows = list(csv.DictReader(open(os.path.join(path, "run_counter_collection.csv"))))
+    per = collections.defaultdict(list)
+    for r in rows:
+        per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return per
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "")
+
+
+def summarize(trace, fetch, write):
+    stats = list(csv.DictReader(open(os.path.join(trace, "run_kernel_stats.csv"))))
+    fe, wr = _counters(fetch), _counters(write)
+    copy = "__amd_rocclr_copyBuffer"
+    f_scale = COPY_BYTES / (max(fe[copy]) * 1024.0)
+    w_scale = COPY_BYTES / (max(wr[copy]) * 1024.0)
+    kernels = []
+    for r in stats:
+        name = r["Name"]
+        if name.startswith("__amd_rocclr"):
+            continue
+        f = fe.get(name, [])
+        w = wr.get(name, [])
+        kernels.append({
+            "kernel": _short(name),
+            "calls": int(r["Calls"]),
+            "avg_us": float(r["AverageNs"]) / 1e3,
+            "percent": float(r["Percentage"]),
+            "fetch_bytes": sum(f) / len(f) * 1024.0 * f_scale if f else None,
+            "write_bytes": sum(w) / len(w) * 1024.0 * w_scale if w else None,
+        })
+    return {"fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
+
+
+def render(s, workload, command, trace_cmd):
+    lines = [f"# rocprofv3 summary: {workload}", "",
+             "Commands (repository root, one MI355X):", "",
+             f"    {trace_cmd}",
+             f"    {command.replace('PMC', 'FETCH_SIZE')}",
+             f"    {command.replace('PMC', 'WRITE_SIZE')}", "",
+             "Counter calibration by the 256 MiB copy of the same run: FETCH_SIZE x "
+             f"{s['fetch_scale']:.3f}, WRITE_SIZE x {s['write_scale']:.3f}.", "",
+             "| kernel | calls | avg us | % time | HBM read MB/dispatch | HBM write MB/dispatch |",
+             "|---|---|---|---|---|---|"]
+    for k in s["kernels"]:
+        fr = "-" if k["fetch_bytes"] is None else f"{k['fetch_bytes'] / 1e6:.2f}"
+        wr = "-" if k["write_bytes"] is None else f"{k['write_bytes'] / 1e6:.2f}"
+        lines.append(f"| {k['kernel']} | {k['calls']} | {k['avg_us']:.1f} | {k['percent']:.2f} | {fr} | {wr} |")
+    lines += ["", "traffic-json: " + json.dumps({
+        "workload": workload, "sources": sources_hash(),
+        "bytes_per_dispatch": {k["kernel"]: (k["fetch_bytes"] or 0.0) + (k["write_bytes"] or 0.0)
+                               for k in s["kernels"] if k["fetch_bytes"] is not None}})]
+    return "\n".join(lines) + "\n"
+
+
+def load_traffic(path):
+    """The traffic-json line of a summary, or None if missing or stale."""
+    try:
+        with open(path) as f:
+            for line in f:
+                if line.startswith("traffic-json: "):
+                    d = json.loads(line[len("traffic-json: "):])
+                    return d if d.get("sources") == sources_hash() else None
+    except OSError:
+        return None
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", required=True, help="counter command with PMC in place of the counter name")
+    ap.add_argument("--trace-command", required=True)
+    ap.add_argument("--out", required=True)
+    a = ap.parse_args()
+    text = render(summarize(a.trace, a.fetch, a.write), a.workload, a.command, a.trace_command)
+    with open(a.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
