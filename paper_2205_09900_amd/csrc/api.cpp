@@ -202,7 +202,6 @@ static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
   return LR_CHUNKS * LR_HEAD + pad64(4 * num_pairs) + num_pairs * l.per_pair;
 }
 
-constexpr int LR_TINY_BITS = 8;    // 16 lanes per pair
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
@@ -361,7 +360,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   j.num_failed = counters + 2;
   j.cap_bits = lds_bits_max(c.precision);
   j.small_bits = LR_SMALL_BITS < j.cap_bits ? LR_SMALL_BITS : j.cap_bits;
-  j.tiny_bits = LR_TINY_BITS;
+  j.tiny_bits = -1;  // registers up to 2^10 entries form one class (one wavefront per pair)
   j.mid_bits = LR_MID_BITS < j.cap_bits ? LR_MID_BITS : j.cap_bits;
   j.class_macs = (double*)(hw + 16);
   j.hist = hist;
@@ -440,11 +439,12 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   struct Cls {
     int lo, hi, tile, kclass;
   };
-  // Classes by the largest boundary of a pair: up to 2^8 and 2^10 entries
-  // with one wavefront per pair, up to 2^12 and 2^14 with 256 and 1024 lanes
-  // per pair (boundary in LDS), then HBM slots.  Each class gets its own
-  // stream (s or a side stream) by planned MACs, heaviest first; with five
-  // classes the two lightest share one, the larger registers first.
+  // Classes by the largest boundary of a pair: up to 2^10 entries with one
+  // wavefront per pair (class 0 stays empty: the VGPRs of the wavefront
+  // sweep, not its LDS, bound its occupancy, so one class serves all small
+  // registers), up to 2^12 and 2^14 with 256 and 1024 lanes per pair
+  // (boundary in LDS), then HBM slots.  Each class gets its own stream (s or
+  // a side stream), heaviest by planned MACs first.
   const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
                       {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64},
                       {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256},

@@ -43,6 +43,14 @@ struct LanesHost {
   }
   int at(int q) const { return a[q]; }
   void put(int q, int x) { a[q] = x; }
+  void or_at(int q, int x) { a[q] |= x; }
+  void add_at(int q, int x) { a[q] += x; }
+  // sum over lanes of a[i] * 2^i (exact while below 2^53)
+  double pow2_sum() const {
+    double s = 0.0;
+    for (int i = 0; i < WAVE; ++i) s += (double)a[i] * (double)(1ull << i);
+    return s;
+  }
   void set2(int q1, int q2, int x) {
     a[q1] = x;
     a[q2] = x;
@@ -118,6 +126,14 @@ struct LanesDev {
   }
   __device__ int at(int) const { return v; }
   __device__ void put(int, int x) { v = x; }
+  __device__ void or_at(int q, int x) { v = lane() == q ? (v | x) : v; }
+  __device__ void add_at(int q, int x) { v = lane() == q ? (v + x) : v; }
+  __device__ double pow2_sum() const {
+    double s = (double)v * (double)(1ull << lane());
+#pragma unroll
+    for (int off = WAVE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+    return s;
+  }
   __device__ void set2(int q1, int q2, int x) {
     const int l = lane();
     v = (l == q1 || l == q2) ? x : v;
@@ -191,59 +207,78 @@ struct WaveDev {
 // one int32 array of W, and per-qubit tables.
 __host__ __device__ inline int64_t plan_wave_scratch_elems(int G) { return 18 * 2 * (int64_t)G + 256; }
 
-// Ops are written one behind, so that the end of a column can mark the op
-// before it (OP_FLAG_TRACK) without reading it back.
+// Emitted ops are buffered in lanes, 64 at a time (lane j holds op j of the
+// chunk), and stored together; the end of a column marks the op before it
+// (OP_FLAG_TRACK) in the buffer.  The merged gate of each GATE op is buffered
+// the same way.  MACs and register sizes are counted per register width.
+template <class P>
 struct WaveEmitter {
+  using Lanes = typename P::Lanes;
   Op* ops;
   int16_t* gseq;  // merged gate of each GATE op (optional)
   int64_t max_ops;
-  int num;
-  int ngate;
-  bool has;
-  Op pend;
-  double macs, elems;
+  int num;    // ops emitted
+  int ngate;  // GATE ops emitted
+  Lanes w0, w1;           // chunk of packed ops: type | p << 8 | q << 16 | bits << 24, arg
+  Lanes gq;               // chunk of merged-gate indices
+  Lanes nops, ngates;     // ops and GATE ops per register width
 };
 
 template <class P>
-__host__ __device__ inline void wave_emit(const P& w, WaveEmitter& e, int& status, uint8_t type, int p, int q,
+__host__ __device__ inline void wave_store_ops(const P& w, WaveEmitter<P>& e, int first, int count) {
+  for (int j = w.first(); j < count; j += P::step) {
+    const unsigned x = (unsigned)e.w0.at(j);
+    Op o;
+    o.type = (uint8_t)(x & 0xff);
+    o.p = (uint8_t)((x >> 8) & 0xff);
+    o.q = (uint8_t)((x >> 16) & 0xff);
+    o.bits = (uint8_t)(x >> 24);
+    o.arg = e.w1.at(j);
+    e.ops[first + j] = o;
+  }
+}
+
+template <class P>
+__host__ __device__ inline void wave_store_gseq(const P& w, WaveEmitter<P>& e, int first, int count) {
+  if (!e.gseq) return;
+  for (int j = w.first(); j < count; j += P::step) e.gseq[first + j] = (int16_t)e.gq.at(j);
+}
+
+template <class P>
+__host__ __device__ inline void wave_emit(const P& w, WaveEmitter<P>& e, int& status, uint8_t type, int p, int q,
                                           int bits, int32_t arg) {
   if (e.num >= e.max_ops) {
     status = PLAN_ECAP;
     return;
   }
-  if (e.has) {
-    if (type == OP_COLEND) e.pend.type |= OP_FLAG_TRACK;
-    const Op o = e.pend;
-    Op* dst = e.ops + e.num - 1;
-    w.single([&] { *dst = o; });
+  const int slot = e.num & (WAVE - 1);
+  if (slot == 0 && e.num > 0) {  // the chunk is full: finish its last op, store it
+    if (type == OP_COLEND) e.w0.or_at(WAVE - 1, OP_FLAG_TRACK);
+    wave_store_ops(w, e, e.num - WAVE, WAVE);
+  } else if (type == OP_COLEND && e.num > 0) {
+    e.w0.or_at(slot - 1, OP_FLAG_TRACK);
   }
-  e.pend.type = type;
-  e.pend.p = (uint8_t)p;
-  e.pend.q = (uint8_t)q;
-  e.pend.bits = (uint8_t)bits;
-  e.pend.arg = arg;
-  e.has = true;
-  e.num += 1;
-  const double sz = (double)(1ull << bits);
-  e.elems += sz;
+  e.w0.set(slot, (int)((unsigned)type | ((unsigned)p << 8) | ((unsigned)q << 16) | ((unsigned)bits << 24)));
+  e.w1.set(slot, arg);
+  e.nops.add_at(bits, 1);
   if (type == OP_GATE) {
-    e.macs += 4.0 * sz;
-    if (e.gseq) {
-      int16_t* gs = e.gseq + e.ngate;
-      w.single([&] { *gs = (int16_t)arg; });
-    }
+    const int gs = e.ngate & (WAVE - 1);
+    e.gq.set(gs, arg);
+    if (gs == WAVE - 1) wave_store_gseq(w, e, e.ngate - (WAVE - 1), WAVE);
     e.ngate += 1;
+    e.ngates.add_at(bits, 1);
   }
+  e.num += 1;
 }
 
 template <class P>
-__host__ __device__ inline void wave_flush(const P& w, WaveEmitter& e) {
-  if (e.has) {
-    const Op o = e.pend;
-    Op* dst = e.ops + e.num - 1;
-    w.single([&] { *dst = o; });
-    e.has = false;
+__host__ __device__ inline void wave_flush(const P& w, WaveEmitter<P>& e) {
+  if (e.num > 0) {
+    const int rem = ((e.num - 1) & (WAVE - 1)) + 1;
+    wave_store_ops(w, e, e.num - rem, rem);
   }
+  const int grem = e.ngate & (WAVE - 1);
+  if (grem) wave_store_gseq(w, e, e.ngate - grem, grem);
 }
 
 // Plan one pair.  bw: bond of each position of W (2G entries: V's gates in
@@ -528,15 +563,17 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
   w.sync();
 
   // ---- 8. the walks: register programs ----
-  WaveEmitter e;
+  WaveEmitter<P> e;
   e.ops = ops;
   e.gseq = gseq;
   e.max_ops = plan_max_ops(G, n);
   e.num = 0;
   e.ngate = 0;
-  e.has = false;
-  e.macs = 0.0;
-  e.elems = 0.0;
+  e.w0.fill(0);
+  e.w1.fill(0);
+  e.gq.fill(0);
+  e.nops.fill(0);
+  e.ngates.fill(0);
   int status = PLAN_OK;
   int b = 0, peak = 0;
   Lanes tag;  // tag of each register position (-1: none)
@@ -659,8 +696,8 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
   h.log2_factor = n - touched;
   h.status = status;
   h.num_gate_ops = e.ngate;
-  h.macs = e.macs;
-  h.elems = e.elems;
+  h.macs = 4.0 * e.ngates.pow2_sum();
+  h.elems = e.nops.pow2_sum();
   return h;
 }
 
