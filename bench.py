@@ -138,7 +138,7 @@ def suite(fp, torch, np, synth, pairs):
     for d in range(1, 7):
         r[str(d)], _ = fixed_topology(fp, torch, fp.BRICKWORK, 6, d, 2000, fp.C128, synth.workload_seed(1, d))
     out["brickwork_n6_c128"] = r
-    # brickwork n = 20, depths 2..10, complex64 against complex128 on the same gates' seeds
+    # brickwork n = 20, depths 2..10, complex64 and BF16x3 against complex128 on the same seeds
     r = {}
     for d in range(2, 11):
         np_ = pairs if d <= 8 else max(1000, pairs // 20)
@@ -148,9 +148,13 @@ def suite(fp, torch, np, synth, pairs):
                                   chunk=min(np_, 20000))
         r64, t64 = fixed_topology(fp, torch, fp.BRICKWORK, 20, d, np_, fp.C128, seed, steps=1,
                                   chunk=min(np_, 20000))
+        rb3, tb3 = fixed_topology(fp, torch, fp.BRICKWORK, 20, d, np_, fp.BF16X3, seed, steps=1,
+                                  chunk=min(np_, 20000))
         r32["pairs"] = np_
         r32["c128_contractions_per_s"] = r64["contractions_per_s"]
+        r32["bf16x3_contractions_per_s"] = rb3["contractions_per_s"]
         r32["c64_vs_c128"] = precision_error(np, t32, t64, r32["F"], r64["F"])
+        r32["bf16x3_vs_c128"] = precision_error(np, tb3, t64, rb3["F"], r64["F"])
         r[str(d)] = r32
     out["brickwork_n20"] = r
     # HEA n = 30, layers 1..8, complex64

@@ -65,8 +65,14 @@ enum {
   FP_C128 = 0,  /* float64 gates, complex128 boundary                           */
   FP_C64 = 1,   /* float32 gates, complex64 boundary, power-of-two rescale per
                    column with the exponent kept in float64                    */
-  FP_BF16X3 = 2 /* float32 storage; transfer products as three bf16 products
-                   (hi*hi + hi*lo + lo*hi) with float32 accumulation           */
+  FP_BF16X3 = 2 /* float32 storage (gates, boundary) as FP_C64; every complex
+                   multiply-add of the contraction (merged-gate products, GATE
+                   ops, HEA pointwise products) takes each real product as
+                   hi_a hi_b + hi_a lo_b + lo_a hi_b with x = hi + lo, hi and
+                   lo bf16 (round to nearest even), float32 accumulation.
+                   Expected error vs FP_C128 about 2^-16 per product; the
+                   HEA one-layer case (a product of 2x2 traces in float64)
+                   is the same as FP_C64                                        */
 };
 
 typedef struct {

@@ -279,6 +279,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   a.trace = trace;
   a.trace_offset = trace_offset;
   a.num_pairs = num_pairs;
+  a.bf3 = precision == FP_BF16X3 ? 1 : 0;
   const int peak = dp.hdr.peak_bits;
   const int elem = sweep_elem_bytes(precision);
   if (peak <= lds_bits_max(precision)) {
@@ -368,6 +369,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   j.gseq_stride = l.gseq / 2;
   j.wmat = base + c.num_pairs * (l.hdr + l.ops + l.wg + l.fac + l.gseq) + p0 * l.mat;
   j.wmat_stride = l.mat;
+  j.bf3 = c.precision == FP_BF16X3 ? 1 : 0;
   static_assert(sizeof(PlanHeader) <= 64, "plan header fits its slot");
   int rc = check_hip(hipMemsetAsync(hw, 0, LR_HEAD, s), "memset counters");
   if (rc) return rc;
@@ -436,6 +438,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   a.trace_offset = c.trace_offset + p0;
   a.wmat = j.wmat;
   a.wmat_stride = j.wmat_stride;
+  a.bf3 = j.bf3;
   struct Cls {
     int lo, hi, tile, kclass;
   };
@@ -587,6 +590,7 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
   a.trace = trace;
   a.trace_offset = trace_offset;
   a.num_pairs = num_pairs;
+  a.bf3 = precision == FP_BF16X3 ? 1 : 0;
   const int m = hea_bits(e->depth);
   if (m > lds_bits_max(precision)) return set_error(FP_ETOOBIG, "HEA boundary of %d bits exceeds LDS", m);
   int def = m <= 6 ? TILE_16x16 : m <= 10 ? TILE_64x4 : m <= 12 ? TILE_256x1 : TILE_1024x1;
@@ -601,7 +605,6 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
 
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
                       void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset, int tile_override) {
-  if (precision == FP_BF16X3) return set_error(FP_ENOTIMPL, "BF16x3 transfer products are not built");
   if (e->ansatz == FP_BRICKWORK_HAAR)
     return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset, tile_override);
   if (e->ansatz == FP_LOCAL_RANDOM_HAAR)

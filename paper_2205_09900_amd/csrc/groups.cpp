@@ -97,8 +97,7 @@ int check_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups, 
   for (int g = 0; g < n_groups; ++g) {
     const fp_group_t& gr = groups[g];
     if (gr.ensemble_index < 0 || gr.ensemble_index >= n_ens) return set_error(FP_EINVAL, "group %d: bad ensemble", g);
-    if (gr.precision != FP_C64 && gr.precision != FP_C128)
-      return set_error(FP_EINVAL, "group %d: precision must be FP_C64 or FP_C128", g);
+    if (check_precision(gr.precision)) return set_error(FP_EINVAL, "group %d: unknown precision %d", g, gr.precision);
     if (gr.num_pairs < 0 || gr.first_pair < 0) return set_error(FP_EINVAL, "group %d: bad pair range", g);
   }
   return FP_OK;
@@ -129,7 +128,7 @@ int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_grou
     else
       ntasks += gp.ntasks;
   }
-  total += (size_t)ntasks * sizeof(Task) + 4 * 256;
+  total += (size_t)ntasks * sizeof(Task) + 6 * 256;
   *out_bytes = total;
   return FP_OK;
 }
@@ -148,9 +147,9 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
 
   std::vector<GroupPlan> gps(n_groups);
   std::vector<GroupDesc> descs(n_groups);
-  // tasks per (precision index, class): precision index 0 = c128, 1 = c64
-  std::vector<Task> tasks[2][2];
-  int slot_bytes[2][2] = {{0, 0}, {0, 0}};
+  // tasks per (precision index, class): precision index 0 = c128, 1 = c64, 2 = bf16x3
+  std::vector<Task> tasks[3][2];
+  int slot_bytes[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   int64_t offset = 0;
   for (int g = 0; g < n_groups; ++g) {
     const fp_ensemble_t* e = &ens[groups[g].ensemble_index];
@@ -169,6 +168,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
     d.stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, gr.precision);
     d.gate_first = gr.first_pair;
     d.trace_offset = offset;
+    d.bf3 = gr.precision == FP_BF16X3 ? 1 : 0;
     if (e->ansatz == FP_HEA_RYRZ_CZ) {
       d.kind = GROUP_HEA;
     } else {
@@ -179,7 +179,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
       d.hdr = gp.plan.dhdr;
     }
     if (gp.route == ROUTE_PERSISTENT && gr.num_pairs > 0) {
-      const int pi = gr.precision == FP_C128 ? 0 : 1;
+      const int pi = gr.precision == FP_C128 ? 0 : gr.precision == FP_C64 ? 1 : 2;
       const int rb = gr.precision == FP_C128 ? 8 : 4;
       const int nt = gp.cls == PCLASS_SMALL ? 64 : (gr.precision == FP_C128 ? 512 : 1024);
       const size_t sb = e->ansatz == FP_HEA_RYRZ_CZ ? ((hea_smem_bytes(gp.bits, nt, rb) + 15) & ~(size_t)15)
@@ -196,7 +196,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
     offset += gr.num_pairs;
   }
   // largest first
-  for (int pi = 0; pi < 2; ++pi)
+  for (int pi = 0; pi < 3; ++pi)
     for (int c = 0; c < 2; ++c)
       std::stable_sort(tasks[pi][c].begin(), tasks[pi][c].end(), [&](const Task& a, const Task& b) {
         return gps[a.group].pair_cost * a.count > gps[b.group].pair_cost * b.count;
@@ -206,8 +206,8 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
   unsigned int* counters = (unsigned int*)w;
   GroupDesc* d_desc = (GroupDesc*)(w + 256);
   size_t off = (256 + (size_t)n_groups * sizeof(GroupDesc) + 255) & ~(size_t)255;
-  Task* d_tasks[2][2];
-  for (int pi = 0; pi < 2; ++pi)
+  Task* d_tasks[3][2];
+  for (int pi = 0; pi < 3; ++pi)
     for (int c = 0; c < 2; ++c) {
       d_tasks[pi][c] = (Task*)(w + off);
       off += ((tasks[pi][c].size() * sizeof(Task)) + 255) & ~(size_t)255;
@@ -215,7 +215,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
   rc = check_hip(hipMemsetAsync(counters, 0, 256, s), "memset counters");
   if (!rc) rc = check_hip(hipMemcpyAsync(d_desc, descs.data(), sizeof(GroupDesc) * n_groups, hipMemcpyHostToDevice, s),
                           "upload groups");
-  for (int pi = 0; pi < 2 && !rc; ++pi)
+  for (int pi = 0; pi < 3 && !rc; ++pi)
     for (int c = 0; c < 2 && !rc; ++c)
       if (!tasks[pi][c].empty())
         rc = check_hip(hipMemcpyAsync(d_tasks[pi][c], tasks[pi][c].data(), sizeof(Task) * tasks[pi][c].size(),
@@ -241,9 +241,9 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
       rc = check_hip(hipStreamWaitEvent(sx, aux.fork, 0), "fork wait");
       if (rc) return rc;
     }
-    for (int pi = 0; pi < 2; ++pi) {
+    for (int pi = 0; pi < 3; ++pi) {
       if (tasks[pi][c].empty()) continue;
-      const int prec = pi == 0 ? FP_C128 : FP_C64;
+      const int prec = pi == 0 ? FP_C128 : pi == 1 ? FP_C64 : FP_BF16X3;
       profile_launch_begin(c == 0 ? KCLASS_LDS64 : KCLASS_LDS1024, sx);
       rc = launch_persistent(prec, c, d_desc, d_tasks[pi][c], (int)tasks[pi][c].size(), counters + 4 * (2 * pi + c),
                              d_trace, slot_bytes[pi][c], num_cus, sx);

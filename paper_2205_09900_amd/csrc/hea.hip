@@ -26,7 +26,7 @@
 
 namespace fp {
 
-template <typename Real, int NT, int PB>
+template <typename Real, int NT, int PB, bool BF3>
 __global__ void __launch_bounds__(NT* PB) hea_kernel(HeaArgs a, int m, int per_pair_bytes) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
@@ -37,45 +37,46 @@ __global__ void __launch_bounds__(NT* PB) hea_kernel(HeaArgs a, int m, int per_p
   if (pi >= a.num_pairs) return;
   const Real* angU = reinterpret_cast<const Real*>(a.gates + pi * a.gate_stride);
   const Real* angV = angU + (int64_t)a.L * a.n * 2;
-  hea_pair<Real, NT>(angU, angV, a.n, a.L, m, smem_raw + (size_t)slot * per_pair_bytes, lane, red, redd,
-                     a.trace + 2 * (a.trace_offset + pi));
+  hea_pair<Real, NT, BF3>(angU, angV, a.n, a.L, m, smem_raw + (size_t)slot * per_pair_bytes, lane, red, redd,
+                          a.trace + 2 * (a.trace_offset + pi));
 }
 
 int hea_bits(int L) { return L <= 1 ? 0 : 2 * L - 2; }
 
 
-template <typename Real, int NT, int PB>
+template <typename Real, int NT, int PB, bool BF3>
 static int launch_hea_t(const HeaArgs& a, hipStream_t s) {
   const int m = hea_bits(a.L);
   const size_t per_pair = (hea_smem_bytes(m, NT, sizeof(Real)) + 15) & ~(size_t)15;
   const size_t smem = (size_t)PB * per_pair;
   if (smem > 160 * 1024) return set_error(FP_ETOOBIG, "HEA boundary of %d bits does not fit LDS", m);
   if (smem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hea_kernel<Real, NT, PB>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(hea_kernel<Real, NT, PB, BF3>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
   }
   const int64_t blocks = (a.num_pairs + PB - 1) / PB;
-  hipLaunchKernelGGL((hea_kernel<Real, NT, PB>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a, m, (int)per_pair);
+  hipLaunchKernelGGL((hea_kernel<Real, NT, PB, BF3>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a, m, (int)per_pair);
   return check_launch("hea_sweep");
 }
 
-template <typename Real>
+template <typename Real, bool BF3>
 static int launch_hea_real(const HeaArgs& a, int tile, hipStream_t s) {
   switch (tile) {
-    case TILE_16x16: return launch_hea_t<Real, 16, 16>(a, s);
-    case TILE_64x4: return launch_hea_t<Real, 64, 4>(a, s);
-    case TILE_64x1: return launch_hea_t<Real, 64, 1>(a, s);
-    case TILE_256x1: return launch_hea_t<Real, 256, 1>(a, s);
-    case TILE_512x1: return launch_hea_t<Real, 512, 1>(a, s);
-    case TILE_1024x1: return launch_hea_t<Real, 1024, 1>(a, s);
+    case TILE_16x16: return launch_hea_t<Real, 16, 16, BF3>(a, s);
+    case TILE_64x4: return launch_hea_t<Real, 64, 4, BF3>(a, s);
+    case TILE_64x1: return launch_hea_t<Real, 64, 1, BF3>(a, s);
+    case TILE_256x1: return launch_hea_t<Real, 256, 1, BF3>(a, s);
+    case TILE_512x1: return launch_hea_t<Real, 512, 1, BF3>(a, s);
+    case TILE_1024x1: return launch_hea_t<Real, 1024, 1, BF3>(a, s);
     default: return set_error(FP_EINVAL, "unknown HEA tile %d", tile);
   }
 }
 
 int launch_hea(const HeaArgs& a, int precision, int tile, hipStream_t s) {
   if (a.num_pairs <= 0) return FP_OK;
-  return precision == FP_C128 ? launch_hea_real<double>(a, tile, s) : launch_hea_real<float>(a, tile, s);
+  if (precision == FP_C128) return launch_hea_real<double, false>(a, tile, s);
+  return a.bf3 ? launch_hea_real<float, true>(a, tile, s) : launch_hea_real<float, false>(a, tile, s);
 }
 
 }  // namespace fp

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "sweep_dev.h"
+
 namespace fp {
 
 template <typename Real>
@@ -172,7 +174,7 @@ __device__ void wht(HC<Real>* B, int m, int lane, int scale_e) {
 // Trace of one HEA pair (angles of U and V as stored by the sampler) with
 // NT lanes; smem is the pair's LDS area (hea_smem_bytes(m, NT)).  The result
 // is written to out[0], out[1] by lane 0.
-template <typename Real, int NT>
+template <typename Real, int NT, bool BF3 = false>
 __device__ void hea_pair(const Real* angU, const Real* angV, int n, int L, int m, unsigned char* smem, int lane,
                          Real* red, double* redd, double* out) {
   if (L == 1) {
@@ -252,16 +254,29 @@ __device__ void hea_pair(const Real* angU, const Real* angV, int n, int L, int m
     for (int x = lane; x < (1 << m); x += NT) {
       const HC<Real> tl = Tlo[x & mlo];
       const HC<Real> th = Thi[(x >> h) | ((x & 1) << (m - h))];
-      HC<Real> f;
-      f.x = tl.x * th.x - tl.y * th.y;
-      f.y = tl.x * th.y + tl.y * th.x;
-      HC<Real> v;
-      if (q == 0) {
-        v = f;
+      HC<Real> f, v;
+      if constexpr (BF3) {  // both products as three bf16 products each (float32 storage)
+        f.x = 0;
+        f.y = 0;
+        cmac<Real, true>(tl.x, tl.y, th.x, th.y, f.x, f.y);
+        if (q == 0) {
+          v = f;
+        } else {
+          const HC<Real> b = B[x];
+          v.x = 0;
+          v.y = 0;
+          cmac<Real, true>(b.x, b.y, f.x, f.y, v.x, v.y);
+        }
       } else {
-        const HC<Real> b = B[x];
-        v.x = b.x * f.x - b.y * f.y;
-        v.y = b.x * f.y + b.y * f.x;
+        f.x = tl.x * th.x - tl.y * th.y;
+        f.y = tl.x * th.y + tl.y * th.x;
+        if (q == 0) {
+          v = f;
+        } else {
+          const HC<Real> b = B[x];
+          v.x = b.x * f.x - b.y * f.y;
+          v.y = b.x * f.y + b.y * f.x;
+        }
       }
       B[x] = v;
       mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));

@@ -25,6 +25,7 @@ struct GroupDesc {
   int64_t f_stride;
   const PlanHeader* hdr;
   int64_t hdr_stride;
+  int32_t bf3;  // float32 storage with BF16x3 products (also selects the launch)
 };
 
 struct Task {

@@ -31,6 +31,7 @@ struct SweepArgs {
   const int32_t* order; // if set: slot i contracts pair order[i] (num_pairs = length of the list)
   const unsigned char* wmat;  // realigned GATE matrices in program order (wave sweep), per pair
   int64_t wmat_stride;        // bytes per pair
+  int bf3;                    // float32 storage with BF16x3 products
 };
 
 struct PlanJob {
@@ -59,6 +60,7 @@ struct PlanJob {
   int64_t gseq_stride; // entries per pair
   unsigned char* wmat; // realigned GATE matrices in program order, per pair
   int64_t wmat_stride; // bytes per pair
+  int bf3;             // float32 storage with BF16x3 products
 };
 
 // Pair order by decreasing peak register width: pair i with peak b goes to
@@ -98,6 +100,7 @@ struct HeaArgs {
   const unsigned char* gates;
   int64_t gate_stride;
   int n, L;
+  int bf3;  // float32 storage with BF16x3 products
   double* trace;
   int64_t trace_offset;
   int64_t num_pairs;

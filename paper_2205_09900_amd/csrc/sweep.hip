@@ -24,7 +24,7 @@ namespace fp {
 // One group of NT lanes per pair, PB pairs per workgroup, boundary in LDS
 // (2^cap_bits complex per pair) next to the staging area of the group.
 // Pairs whose plan needs more are left to the next launch; failed plans give NaN.
-template <typename Real, int NT, int PB>
+template <typename Real, int NT, int PB, bool BF3>
 __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
@@ -51,8 +51,9 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
   Op* ops_s = reinterpret_cast<Op*>(mats + 16 * chunk_ops<NT>());
   const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
   double re, im;
-  run_program<Real, NT>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops, a.wgates + pidx * a.wg_stride,
-                        a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red, &re, &im);
+  run_program<Real, NT, BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+                             a.wgates + pidx * a.wg_stride, a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor,
+                             lane, red, &re, &im);
   if (lane == 0) {
     out[0] = re;
     out[1] = im;
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
 
 // Large boundaries: one workgroup per pair at a time, boundary in the HBM
 // slot of the workgroup, staging in LDS, pairs taken from a shared counter.
-template <typename Real, int NT>
+template <typename Real, int NT, bool BF3>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter,
                                                        unsigned char* slots, int slot_bits) {
   __shared__ Real red[16];
@@ -89,8 +90,9 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
     }
     const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
     double re, im;
-    run_program<Real, NT>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops, a.wgates + pidx * a.wg_stride,
-                          a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red, &re, &im);
+    run_program<Real, NT, BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+                               a.wgates + pidx * a.wg_stride, a.factors + pidx * a.f_stride, pg, a.G,
+                               hdr->log2_factor, lane, red, &re, &im);
     if (lane == 0) {
       out[0] = re;
       out[1] = im;
@@ -181,49 +183,53 @@ size_t plan_lds_bytes(int G, int n) {
 
 // ---- launchers --------------------------------------------------------------
 
-template <typename Real, int NT, int PB>
+template <typename Real, int NT, int PB, bool BF3>
 static int launch_lds_t(const SweepArgs& a, hipStream_t s) {
   const size_t smem = (size_t)PB * ((((size_t)1 << a.cap_bits) * sizeof(Cplx<Real>)) + stage_bytes<Real, NT>());
   const int64_t blocks = (a.num_pairs + PB - 1) / PB;
   if (smem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_lds_kernel<Real, NT, PB>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_lds_kernel<Real, NT, PB, BF3>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
   }
-  hipLaunchKernelGGL((sweep_lds_kernel<Real, NT, PB>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a);
+  hipLaunchKernelGGL((sweep_lds_kernel<Real, NT, PB, BF3>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a);
   return check_launch("sweep_lds");
 }
 
 // Tile choice -> (lanes per pair, pairs per workgroup); LDS bits come from the caller.
-template <typename Real>
+template <typename Real, bool BF3>
 static int launch_lds_real(const SweepArgs& a, int tile, hipStream_t s) {
   switch (tile) {
-    case TILE_16x16: return launch_lds_t<Real, 16, 16>(a, s);
-    case TILE_64x4: return launch_lds_t<Real, 64, 4>(a, s);
-    case TILE_64x1: return launch_lds_t<Real, 64, 1>(a, s);
-    case TILE_256x1: return launch_lds_t<Real, 256, 1>(a, s);
-    case TILE_512x1: return launch_lds_t<Real, 512, 1>(a, s);
+    case TILE_16x16: return launch_lds_t<Real, 16, 16, BF3>(a, s);
+    case TILE_64x4: return launch_lds_t<Real, 64, 4, BF3>(a, s);
+    case TILE_64x1: return launch_lds_t<Real, 64, 1, BF3>(a, s);
+    case TILE_256x1: return launch_lds_t<Real, 256, 1, BF3>(a, s);
+    case TILE_512x1: return launch_lds_t<Real, 512, 1, BF3>(a, s);
     case TILE_1024x1:
       // float64 needs more than the 128 registers a 1024-lane workgroup allows
-      if constexpr (sizeof(Real) == 8) return launch_lds_t<Real, 512, 1>(a, s);
-      else return launch_lds_t<Real, 1024, 1>(a, s);
+      if constexpr (sizeof(Real) == 8) return launch_lds_t<Real, 512, 1, BF3>(a, s);
+      else return launch_lds_t<Real, 1024, 1, BF3>(a, s);
     default: return set_error(FP_EINVAL, "unknown sweep tile %d", tile);
   }
 }
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s) {
   if (a.num_pairs <= 0) return FP_OK;
-  return precision == FP_C128 ? launch_lds_real<double>(a, tile, s) : launch_lds_real<float>(a, tile, s);
+  if (precision == FP_C128) return launch_lds_real<double, false>(a, tile, s);
+  return a.bf3 ? launch_lds_real<float, true>(a, tile, s) : launch_lds_real<float, false>(a, tile, s);
 }
 
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
                      int slot_bits, int num_slots, hipStream_t s) {
   if (a.num_pairs <= 0 || num_slots <= 0) return FP_OK;
   if (precision == FP_C128)
-    hipLaunchKernelGGL((sweep_hbm_kernel<double, 512>), dim3(num_slots), dim3(512), 0, s, a, counter,
+    hipLaunchKernelGGL((sweep_hbm_kernel<double, 512, false>), dim3(num_slots), dim3(512), 0, s, a, counter,
+                       (unsigned char*)slots, slot_bits);
+  else if (a.bf3)
+    hipLaunchKernelGGL((sweep_hbm_kernel<float, 1024, true>), dim3(num_slots), dim3(1024), 0, s, a, counter,
                        (unsigned char*)slots, slot_bits);
   else
-    hipLaunchKernelGGL((sweep_hbm_kernel<float, 1024>), dim3(num_slots), dim3(1024), 0, s, a, counter,
+    hipLaunchKernelGGL((sweep_hbm_kernel<float, 1024, false>), dim3(num_slots), dim3(1024), 0, s, a, counter,
                        (unsigned char*)slots, slot_bits);
   return check_launch("sweep_hbm");
 }
@@ -256,7 +262,7 @@ __device__ __forceinline__ void store_matrix(const Cplx<double> (&m)[16], double
 // The realigned matrix of every GATE op, in program order: one thread per
 // (pair, GATE op), the product of the merged gate's factors (same arithmetic
 // as the staging of the LDS sweep).
-template <typename Real>
+template <typename Real, bool BF3>
 __global__ void __launch_bounds__(256) gate_matrices_kernel(PlanJob j) {
   const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t per = 2 * (int64_t)j.G;
@@ -268,7 +274,7 @@ __global__ void __launch_bounds__(256) gate_matrices_kernel(PlanJob j) {
   const int k = j.gseq[pi * j.gseq_stride + jj];
   const Real* pg = reinterpret_cast<const Real*>(j.gates + pi * j.gate_stride);
   Cplx<Real> m[16];
-  stage_gate<Real>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], m);
+  stage_gate<Real, BF3>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], m);
   store_matrix(m, reinterpret_cast<Real*>(j.wmat + pi * j.wmat_stride) + 32 * (int64_t)jj);
 }
 
@@ -277,9 +283,11 @@ int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s) {
   const int64_t threads = j.num_pairs * 2 * (int64_t)j.G;
   const int64_t blocks = (threads + 255) / 256;
   if (precision == FP_C128)
-    hipLaunchKernelGGL(gate_matrices_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, j);
+    hipLaunchKernelGGL((gate_matrices_kernel<double, false>), dim3((unsigned)blocks), dim3(256), 0, s, j);
+  else if (j.bf3)
+    hipLaunchKernelGGL((gate_matrices_kernel<float, true>), dim3((unsigned)blocks), dim3(256), 0, s, j);
   else
-    hipLaunchKernelGGL(gate_matrices_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, j);
+    hipLaunchKernelGGL((gate_matrices_kernel<float, false>), dim3((unsigned)blocks), dim3(256), 0, s, j);
   return check_launch("gate_matrices");
 }
 

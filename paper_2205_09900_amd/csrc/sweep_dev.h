@@ -29,6 +29,53 @@ __device__ __forceinline__ int insert_zero(int x, int pos) {
   return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
 }
 
+// BF16x3 products: x = hi + lo with hi = bf16(x) (round to nearest even)
+// and lo = bf16(x - hi); a*b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b.
+// Products of bf16 values are exact in float32, so only the accumulation
+// rounds, as in a bf16 matrix core product with float32 accumulation.
+struct Bf3 {
+  float h, l;
+};
+
+__device__ __forceinline__ float bf16_round(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xffff0000u);
+}
+
+__device__ __forceinline__ Bf3 bf3_split(float x) {
+  Bf3 s;
+  s.h = bf16_round(x);
+  s.l = bf16_round(x - s.h);
+  return s;
+}
+
+__device__ __forceinline__ float bf3_fma(Bf3 a, Bf3 b, float c) {
+  c = fma(a.h, b.h, c);
+  c = fma(a.h, b.l, c);
+  c = fma(a.l, b.h, c);
+  return c;
+}
+
+// sr += ar br - ai bi, si += ar bi + ai br in the arithmetic of the precision
+// (the same fused order for both)
+template <typename Real, bool BF3>
+__device__ __forceinline__ void cmac(Real ar, Real ai, Real br, Real bi, Real& sr, Real& si) {
+  if constexpr (BF3 && sizeof(Real) == 4) {
+    const Bf3 a = bf3_split(ar), b = bf3_split(ai), c = bf3_split(br), d = bf3_split(bi);
+    const Bf3 nb = {-b.h, -b.l};
+    sr = bf3_fma(a, c, sr);
+    sr = bf3_fma(nb, d, sr);
+    si = bf3_fma(a, d, si);
+    si = bf3_fma(b, c, si);
+  } else {
+    sr = fma(ar, br, sr);
+    sr = fma(-ai, bi, sr);
+    si = fma(ar, bi, si);
+    si = fma(ai, br, si);
+  }
+}
+
 // Merged gate M = F_last ... F_first (product of its factors) realigned for
 // the column transfer and written to dst (16 complex):
 //   dst[j' * 4 + j] = M[2 x_out + y_out][2 x_in + y_in],
@@ -69,7 +116,7 @@ __device__ __forceinline__ void factor_row(const Real (&g)[32], int dagger, int 
 }
 
 // code_of(f) gives the factor code of the f-th factor (time order), count >= 1.
-template <typename Real, class Codes>
+template <typename Real, bool BF3, class Codes>
 __device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int count, Codes code_of, Cplx<Real>* dst) {
   Real mr[16], mi[16];
   {
@@ -100,12 +147,7 @@ __device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int coun
       for (int b = 0; b < 4; ++b) {
         Real sr = 0, si = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          sr = fma(fr[k], mr[k * 4 + b], sr);
-          sr = fma(-fi[k], mi[k * 4 + b], sr);
-          si = fma(fr[k], mi[k * 4 + b], si);
-          si = fma(fi[k], mr[k * 4 + b], si);
-        }
+        for (int k = 0; k < 4; ++k) cmac<Real, BF3>(fr[k], fi[k], mr[k * 4 + b], mi[k * 4 + b], sr, si);
         nr[a * 4 + b] = sr;
         ni[a * 4 + b] = si;
       }
@@ -127,10 +169,10 @@ __device__ void merged_gate(const Real* __restrict__ pair_gates, int G, int coun
     }
 }
 
-template <typename Real>
+template <typename Real, bool BF3 = false>
 __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int32_t* __restrict__ factors, int2 wg,
                            Cplx<Real>* dst) {
-  merged_gate<Real>(pair_gates, G, wg.y, [&](int f) { return factors[wg.x + f]; }, dst);
+  merged_gate<Real, BF3>(pair_gates, G, wg.y, [&](int f) { return factors[wg.x + f]; }, dst);
 }
 
 // Applies the realigned 4x4 matrix (Rr, Ri) to the groups of four entries
@@ -138,7 +180,7 @@ __device__ void stage_gate(const Real* __restrict__ pair_gates, int G, const int
 // gate's bits).  Up to U groups per round: distinct groups touch distinct
 // entries, so all loads of a round are issued before its stores and their
 // latencies overlap.  Same arithmetic per group as one group at a time.
-template <typename Real, int U>
+template <typename Real, int U, bool BF3 = false>
 __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo,
                                             int hi, int ip, int iq, int ng, int first, int stride, bool track,
                                             Real& lmax) {
@@ -164,12 +206,7 @@ __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16],
       for (int jp = 0; jp < 4; ++jp) {
         Real sr = 0, si = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          sr = fma(Rr[jp * 4 + j], v[u][j].x, sr);
-          sr = fma(-Ri[jp * 4 + j], v[u][j].y, sr);
-          si = fma(Rr[jp * 4 + j], v[u][j].y, si);
-          si = fma(Ri[jp * 4 + j], v[u][j].x, si);
-        }
+        for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[jp * 4 + j], Ri[jp * 4 + j], v[u][j].x, v[u][j].y, sr, si);
         w[jp].x = sr;
         w[jp].y = si;
         if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
@@ -217,7 +254,7 @@ constexpr int chunk_ops() {
 // lazy: the op that ends a column records the largest magnitude it writes,
 // the column end turns it into an exponent P, and the next GATE multiplies
 // its matrix by 2^-P (exact), so no extra pass over the boundary is made.
-template <typename Real, int NT>
+template <typename Real, int NT, bool BF3 = false>
 __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, Op* ops_s, const Op* __restrict__ ops,
                                             int num_ops, const int2* __restrict__ wgates,
                                             const int32_t* __restrict__ factors, const Real* pair_gates, int G,
@@ -236,7 +273,7 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
     for (int i = lane; i < nk; i += NT) {
       const Op op = ops[t0 + i];
       ops_s[i] = op;
-      if ((op.type & OP_TYPE_MASK) == OP_GATE) stage_gate<Real>(pair_gates, G, factors, wgates[op.arg], mats_s + 16 * i);
+      if ((op.type & OP_TYPE_MASK) == OP_GATE) stage_gate<Real, BF3>(pair_gates, G, factors, wgates[op.arg], mats_s + 16 * i);
     }
     group_sync<NT>();
     for (int i = 0; i < nk; ++i) {
@@ -256,7 +293,8 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
-        gate_groups<Real, gate_batch<Real>()>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, NT, track, lmax);
+        gate_groups<Real, BF3 ? 2 : gate_batch<Real>(), BF3>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, NT, track,
+                                                             lmax);
       } else if (type == OP_BELL) {
         const int s = 1 << b;
         for (int k = lane; k < s; k += NT) {

@@ -48,7 +48,7 @@ constexpr size_t wave_slot_bytes() {
   return ((size_t)sizeof(Cplx<Real>) << CAP) + 32 * sizeof(Real);
 }
 
-template <typename Real, int CAP, int WPB>
+template <typename Real, int CAP, int WPB, bool BF3>
 __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int wave = threadIdx.x >> 6;
@@ -134,12 +134,7 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
             v[3] = B[idx + ip + iq];
             Real sr = 0, si = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              sr = fma(Rr[j], v[j].x, sr);
-              sr = fma(-Ri[j], v[j].y, sr);
-              si = fma(Rr[j], v[j].y, si);
-              si = fma(Ri[j], v[j].x, si);
-            }
+            for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[j], Ri[j], v[j].x, v[j].y, sr, si);
             if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
             // the store follows the four loads of every lane (one instruction
             // stream), so no lane overwrites an input another lane still needs
@@ -162,7 +157,8 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
               Ri[k] = ldexp(Ri[k], -pend);
             }
           }
-          gate_groups<Real, gate_batch<Real>()>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, 64, track, lmax);
+          gate_groups<Real, BF3 ? 2 : gate_batch<Real>(), BF3>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, 64,
+                                                               track, lmax);
         }
         expo += pend;
         pend = 0;
@@ -218,27 +214,31 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
   }
 }
 
-template <typename Real, int CAP>
+template <typename Real, int CAP, bool BF3>
 static int launch_wave_t(const SweepArgs& a, hipStream_t s) {
   constexpr int WPB = 4;
   const size_t smem = WPB * wave_slot_bytes<Real, CAP>();
   if (smem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_wave_kernel<Real, CAP, WPB>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_wave_kernel<Real, CAP, WPB, BF3>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();
   }
   const int64_t blocks = (a.num_pairs + WPB - 1) / WPB;
-  hipLaunchKernelGGL((sweep_wave_kernel<Real, CAP, WPB>), dim3((unsigned)blocks), dim3(64 * WPB), smem, s, a);
+  hipLaunchKernelGGL((sweep_wave_kernel<Real, CAP, WPB, BF3>), dim3((unsigned)blocks), dim3(64 * WPB), smem, s, a);
   return check_launch("sweep_wave");
+}
+
+template <int CAP>
+static int launch_wave_cap(const SweepArgs& a, int precision, hipStream_t s) {
+  if (precision == FP_C128) return launch_wave_t<double, CAP, false>(a, s);
+  return a.bf3 ? launch_wave_t<float, CAP, true>(a, s) : launch_wave_t<float, CAP, false>(a, s);
 }
 
 int launch_sweep_wave(const SweepArgs& a, int precision, int cap_bits, hipStream_t s) {
   if (a.num_pairs <= 0) return FP_OK;
   if (!a.wmat) return set_error(FP_EINVAL, "wave sweep needs precomputed gate matrices");
-  if (cap_bits <= 8)
-    return precision == FP_C128 ? launch_wave_t<double, 8>(a, s) : launch_wave_t<float, 8>(a, s);
-  if (cap_bits <= 10)
-    return precision == FP_C128 ? launch_wave_t<double, 10>(a, s) : launch_wave_t<float, 10>(a, s);
+  if (cap_bits <= 8) return launch_wave_cap<8>(a, precision, s);
+  if (cap_bits <= 10) return launch_wave_cap<10>(a, precision, s);
   return set_error(FP_EINVAL, "wave sweep holds at most 2^10 entries per pair");
 }
 

@@ -1,0 +1,71 @@
+"""BF16x3 precision (float32 storage, every real product of the contraction as
+three bf16 products with float32 accumulation) against the float64 oracle on
+the same float32 gates.  Its error is a property of the arithmetic, about
+2^-16 per product; the bounds below are loose enough for that and tight
+enough to fail for an arithmetic slip (a dropped term or a wrong split gives
+errors of order one, a silent fall-back to float32 gives results equal to
+FP_C64)."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dense, estimator, sampler
+
+pytestmark = pytest.mark.gpu
+
+BF16X3 = 2
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2205_09900_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def traces(fp, ens, n, seed, prec):
+    g = fp.sample(ens, n, seed, 0, prec)
+    tr = fp.contract(ens, g, n, prec)
+    torch.cuda.synchronize()
+    return tr.cpu().numpy()
+
+
+def rel_errors(got, want):
+    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
+    floor = np.maximum(np.abs(want), 1e-3 * rms)
+    return np.abs(got - want) / floor
+
+
+@pytest.mark.parametrize("ens,n", [((0, 6, 4), 64), ((0, 8, 6), 32), ((1, 8, 24), 64), ((1, 10, 40), 24),
+                                   ((2, 6, 3), 64), ((2, 5, 6), 32)])
+def test_bf16x3_vs_dense(fp, ens, n):
+    seed = synth.workload_seed(7, ens[2]) + ens[1]
+    got = traces(fp, ens, n, seed, BF16X3)
+    c64 = traces(fp, ens, n, seed, fp.C64)
+    want = dense.traces(sampler.sample_pairs(ens[0], ens[1], ens[2], seed, 0, n, fp32=True))
+    r = rel_errors(got, want)
+    assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (float(np.median(r)), float(r.max()))
+    assert not np.array_equal(got, c64)  # the three-product arithmetic is what ran
+    fg, _ = estimator.frame_potential(got, 2)
+    fw, _ = estimator.frame_potential(want, 2)
+    for k in range(2):
+        assert abs(fg[k] - fw[k]) <= 2e-3 * fw[k], (k, fg[k], fw[k])
+
+
+def test_bf16x3_local_random_n50(fp):
+    """Wide circuits (every sweep class of the local random path) against FP_C64 on
+    the same float32 gates: the float32 result is within about 1e-6 of float64
+    here, far below the BF16x3 error."""
+    ens = (1, 50, 120)
+    n = 300
+    seed = synth.workload_seed(4, 120)
+    g = fp.sample(ens, n, seed, 0, fp.C64)
+    got = fp.contract(ens, g, n, BF16X3).cpu().numpy()
+    ref = fp.contract(ens, g, n, fp.C64).cpu().numpy()
+    r = rel_errors(got, ref)
+    assert np.isfinite(got).all()
+    assert np.median(r) <= 5e-4 and r.max() <= 3e-2, (float(np.median(r)), float(r.max()))

@@ -22,7 +22,7 @@ def _floored(got, want):
     return float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_mixed_groups_vs_dense(fp, prec):
     # HEA of 1..7 layers, brickwork and local random of several depths, ragged group sizes
     ens = [(2, 6, L) for L in range(1, 8)] + [(0, 7, 3), (0, 6, 6), (1, 8, 15)]
@@ -42,7 +42,8 @@ def test_mixed_groups_vs_dense(fp, prec):
     fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
     got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
     want = np.concatenate(want)
-    tol = 1e-12 if prec == 0 else 1e-5
+    # BF16x3: products carry about 2^-16 relative error (reported, not a 1e-5 claim)
+    tol = {0: 1e-12, 1: 1e-5, 2: 5e-3}[prec]
     assert _floored(got, want) <= tol, _floored(got, want)
 
 

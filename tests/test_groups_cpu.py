@@ -23,7 +23,7 @@ def test_groups_validation(fp):
     with pytest.raises(fp.FPError):
         fp.fp_workspace_bytes_groups([(2, 30, 3)], [(1, fp.C64, 0, 10)])       # bad ensemble index
     with pytest.raises(fp.FPError):
-        fp.fp_workspace_bytes_groups([(2, 30, 3)], [(0, fp.BF16X3, 0, 10)])    # precision
+        fp.fp_workspace_bytes_groups([(2, 30, 3)], [(0, 7, 0, 10)])            # unknown precision
     with pytest.raises(fp.FPError):
         fp.fp_workspace_bytes_groups([(2, 30, 3)], [(0, fp.C64, -1, 10)])      # pair range
     with pytest.raises(fp.FPError):
