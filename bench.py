@@ -5,9 +5,10 @@ on a uniformly chosen bond), S steps per circuit, 10^4 (U, V) pairs per
 batch, complex64 with float64 scales and reduction.  One step = the whole
 path over one batch: sample the gates, plan every pair on the device,
 contract Tr(U^dagger V) for every pair, reduce F^(k), k = 1..3 (the reduction
-returns the estimates to the host, which ends the step).  Inputs are
-synthetic and seeded; the gate buffers of a step are resident in HBM before
-the contraction starts.
+returns the estimates to the host, which ends the step).  Two batches are in
+flight on two streams: the next batch is sampled and planned while the
+current one is swept (serial_ms_per_step reports the same steps one at a
+time).  Inputs are synthetic and seeded.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -56,36 +57,53 @@ def parse():
     return ap.parse_args()
 
 
-def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base):
+def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True):
+    """Times `steps` batches.  Pipelined: two streams with their own gate, trace
+    and workspace buffers; batch i+1 is sampled and contracted (its planning
+    waits only for its own plans) before batch i's reduction is awaited, so
+    consecutive batches overlap on the device.  Every batch is sampled,
+    contracted and reduced exactly once inside the timed region."""
     ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
-    gates = fp.alloc_gates(ens, pairs, prec)
-    trace = torch.empty(2 * pairs, dtype=torch.float64, device="cuda")
+    nbuf = 2 if pipeline else 1
+    gates = [fp.alloc_gates(ens, pairs, prec) for _ in range(nbuf)]
+    trace = [torch.empty(2 * pairs, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     wsb = fp.fp_workspace_bytes(ens, pairs, prec)
-    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
+    streams = [torch.cuda.Stream() for _ in range(nbuf)] if pipeline else [torch.cuda.current_stream()]
     seed = seed_base | (depth << 32)
 
-    def step(i):
-        fp.fp_sample_gates(ens, pairs, seed, i * pairs, prec, gates)
-        fp.fp_contract_trace_batch(ens, pairs, prec, gates, trace, ws)
-        return fp.fp_frame_potential(trace, pairs, 3)
+    def launch(i):
+        b = i % nbuf
+        fp.fp_sample_gates(ens, pairs, seed, i * pairs, prec, gates[b], streams[b])
+        fp.fp_contract_trace_batch(ens, pairs, prec, gates[b], trace[b], ws[b], streams[b])
 
-    for i in range(warmup):
-        step(i)
+    def finish(i):
+        b = i % nbuf
+        return fp.fp_frame_potential(trace[b], pairs, 3, streams[b])
+
+    def run(first, count):
+        f = None
+        if pipeline:
+            launch(first)
+            for i in range(first, first + count):
+                if i + 1 < first + count:
+                    launch(i + 1)
+                f = finish(i)
+        else:
+            for i in range(first, first + count):
+                launch(i)
+                f = finish(i)
+        return f
+
+    run(0, warmup)
     torch.cuda.synchronize()
     fp.fp_profile_begin()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record()
-    f = None
-    for i in range(steps):
-        f = step(warmup + i)
-    ev1.record()
+    f = run(warmup, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = fp.fp_profile_end()
-    return {"wall_s": wall, "event_ms": ev0.elapsed_time(ev1), "prof": prof, "F": f[0], "SE": f[1],
-            "ws_bytes": wsb}
+    return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb}
 
 
 def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None):
@@ -237,6 +255,8 @@ def main():
 
     head = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base)
     value = args.pairs * args.steps / head["wall_s"]
+    serial = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, 1, seed_base,
+                          pipeline=False)
     prof = head["prof"]
     # roofline of the sweep kernel with the largest event time (the sweeps
     # hold the method's arithmetic; planning, matrix preparation and sampling
@@ -301,6 +321,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": head["wall_s"] / args.steps * 1e3,
+        "serial_ms_per_step": serial["wall_s"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -308,7 +329,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"local_random_n{args.n}_S{args.depth}", "n_qubits": args.n,
                    "steps_per_circuit": args.depth, "pairs_per_step": args.pairs, "k_max": 3,
-                   "precision": args.precision, "F_k": head["F"], "SE_k": head["SE"]},
+                   "precision": args.precision, "batches_in_flight": 2, "F_k": head["F"], "SE_k": head["SE"]},
         "roofline": roofline,
         "step_kernels_ms": step_kernels,
         "cpu_baseline": cpu,

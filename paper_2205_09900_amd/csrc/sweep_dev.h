@@ -219,10 +219,11 @@ __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16],
   }
 }
 
-// Groups per round of gate_groups: fewer for float64 (register pressure).
+// Groups per round of gate_groups: one (measured: batching several raised the
+// register count and lost more to occupancy than the overlapped loads gained).
 template <typename Real>
 constexpr int gate_batch() {
-  return sizeof(Real) == 4 ? 4 : 2;
+  return 1;
 }
 
 template <typename Real, int NT>
