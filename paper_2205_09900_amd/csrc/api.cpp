@@ -207,7 +207,7 @@ constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
 
 static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
-  int64_t per = ((int64_t)1 << bits) * elem;
+  int64_t per = hbm_slot_bytes(bits, elem);
   int64_t s = POOL_BUDGET / per;
   if (s > 512) s = 512;
   if (s > large_pairs) s = large_pairs;
@@ -239,14 +239,14 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
     }
     if (hp.hdr.peak_bits > 34) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
     int64_t slots = slot_count(hp.hdr.peak_bits, elem, num_pairs);
-    *out = (size_t)(256 + slots * ((int64_t)elem << hp.hdr.peak_bits));
+    *out = (size_t)(256 + slots * hbm_slot_bytes(hp.hdr.peak_bits, elem));
     return FP_OK;
   }
   const int G = e->depth;
   LrLayout l = lr_layout(e->n_qubits, G, precision);
   const int bits = lr_predicted_bits(e->n_qubits, e->depth);
   int64_t pool = 0;
-  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * ((int64_t)elem << bits);
+  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
   *out = (size_t)(lr_fixed_bytes(num_pairs, l) + pool);
   return FP_OK;
 }
@@ -299,7 +299,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   }
   // HBM slots
   const int64_t slots = slot_count(peak, elem, num_pairs);
-  const size_t need = (size_t)(256 + slots * ((int64_t)elem << peak));
+  const size_t need = (size_t)(256 + slots * hbm_slot_bytes(peak, elem));
   if (!ws || ws_bytes < need)
     return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for %d-bit boundaries", need, peak);
   unsigned long long* counter = (unsigned long long*)ws;
@@ -487,7 +487,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   if (count[4] > 0) {
     if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
     // as many slots as the workspace holds (fewer slots only lower the parallelism)
-    const int64_t slot_bytes = (int64_t)c.elem << max_peak;
+    const int64_t slot_bytes = hbm_slot_bytes(max_peak, c.elem);
     int64_t slots = slot_count(max_peak, c.elem, count[4]);
     const int64_t avail = ((int64_t)c.ws_bytes - (int64_t)c.fixed_bytes) / slot_bytes;
     if (avail < 1)

@@ -61,14 +61,158 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
 }
 
 // Large boundaries: one workgroup per pair at a time, boundary in the HBM
-// slot of the workgroup, staging in LDS, pairs taken from a shared counter.
+// slot of the workgroup (2^slot_bits entries), pairs taken from a shared
+// counter.  The interpreter runs the same programs with the same arithmetic
+// as run_program, organised for global-memory latency:
+//   * every lane keeps U groups (GATE), outputs (TRACE) or entries (BELL) in
+//     flight, all loads of a round issued before its stores, so a TRACE needs
+//     two barriers per NT * U outputs;
+//   * op fields are read once per wavefront (scalar), so branching is uniform;
+//   * the realigned matrices come precomputed in program order when the
+//     caller has them (local random), else they are staged from the factors.
+// 512 lanes with 8 (float) or 3 (double) groups each: the most loads in
+// flight without spilling registers.
+constexpr int HBM_NT = 512;
+template <typename Real>
+constexpr int hbm_u() {
+  return sizeof(Real) == 8 ? 3 : 8;
+}
+
+template <typename Real, int NT, int U, bool BF3>
+__device__ __forceinline__ void run_program_hbm(Cplx<Real>* B, Cplx<Real>* mats_s, uint2* ops_s,
+                                                const Op* __restrict__ ops, int num_ops, int num_gate_ops,
+                                                const Real* __restrict__ wmat, const int2* __restrict__ wgates,
+                                                const int32_t* __restrict__ factors, const Real* pair_gates, int G,
+                                                int log2_factor, int lane, Real* red, double* tr_re, double* tr_im) {
+  constexpr int K = 64;  // ops staged per chunk: one per lane of the first wavefront
+  int b = 0;
+  int64_t expo = 0;  // true boundary = stored boundary * 2^expo
+  int pend = 0;      // exponent to remove at the next GATE
+  bool prev_track = false;
+  int gate_base = 0;  // GATE ops before the chunk (first wavefront only)
+  Real lmax = 0;
+  if (lane == 0) {
+    B[0].x = (Real)1;
+    B[0].y = (Real)0;
+  }
+  for (int t0 = 0; t0 < num_ops; t0 += K) {
+    const int nk = num_ops - t0 < K ? num_ops - t0 : K;
+    if (lane < K) {
+      const uint2 w = lane < nk ? reinterpret_cast<const uint2*>(ops)[t0 + lane] : make_uint2(0u, 0u);
+      const bool is_gate = lane < nk && (w.x & OP_TYPE_MASK) == OP_GATE;
+      if (wmat) {
+        const unsigned long long m = __ballot(is_gate);
+        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const int k = gate_base + __popcll(m & below);
+        gate_base += __popcll(m);
+        if (is_gate && k < num_gate_ops) {
+          const Real* src = wmat + 32 * (int64_t)k;
+          Real* dst = reinterpret_cast<Real*>(mats_s + 16 * lane);
+#pragma unroll
+          for (int r = 0; r < 32; ++r) dst[r] = src[r];
+        }
+      } else if (is_gate) {
+        stage_gate<Real, BF3>(pair_gates, G, factors, wgates[(int)w.y], mats_s + 16 * lane);  // y: Op::arg
+      }
+      if (lane < nk) ops_s[lane] = w;
+    }
+    __syncthreads();
+    for (int i = 0; i < nk; ++i) {
+      const unsigned w0 = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i].x);
+      const int type = (int)(w0 & OP_TYPE_MASK);
+      const bool track = (w0 & OP_FLAG_TRACK) != 0;
+      const int p = (int)((w0 >> 8) & 0xff), q = (int)((w0 >> 16) & 0xff);
+      if (type == OP_GATE) {
+        Real Rr[16], Ri[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const Cplx<Real> r = mats_s[16 * i + k];
+          Rr[k] = pend ? ldexp(r.x, -pend) : r.x;
+          Ri[k] = pend ? ldexp(r.y, -pend) : r.y;
+        }
+        expo += pend;
+        pend = 0;
+        const int lo = p < q ? p : q, hi = p < q ? q : p;
+        gate_groups<Real, U, BF3>(B, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, NT, track, lmax);
+      } else if (type == OP_BELL) {
+        const int s = 1 << b;
+        for (int k0 = lane; k0 < s; k0 += NT * U) {
+          Cplx<Real> v[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (k0 + u * NT < s) v[u] = B[k0 + u * NT];
+          Cplx<Real> z;
+          z.x = (Real)0;
+          z.y = (Real)0;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * NT;
+            if (k < s) {
+              B[k + s] = z;
+              B[k + 2 * s] = z;
+              B[k + 3 * s] = v[u];
+            }
+          }
+        }
+        b += 2;
+      } else if (type == OP_TRACE) {
+        // p < q; in place, in chunks of NT * U outputs: every input of a
+        // chunk lies at or above its output, so the chunk reads everything
+        // before anyone writes, and later chunks read above what it wrote
+        const int nout = 1 << (b - 2);
+        const int step = (1 << p) + (1 << q);
+        for (int j0 = 0; j0 < nout; j0 += NT * U) {
+          Cplx<Real> a0[U], a1[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + lane + u * NT;
+            if (j < nout) {
+              const int i0 = insert_zero(insert_zero(j, p), q);
+              a0[u] = B[i0];
+              a1[u] = B[i0 + step];
+            }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int j = j0 + lane + u * NT;
+            if (j < nout) {
+              Cplx<Real> acc;
+              acc.x = a0[u].x + a1[u].x;
+              acc.y = a0[u].y + a1[u].y;
+              if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
+              B[j] = acc;
+            }
+          }
+          if (j0 + NT * U < nout) __syncthreads();  // the last chunk ends at the op's barrier
+        }
+        b -= 2;
+      } else if (prev_track) {  // OP_COLEND after the column's last writing op
+        const Real m = group_max<Real, NT>(lmax, red);
+        lmax = 0;
+        pend = 0;
+        if (m > (Real)0 && isfinite(m)) {
+          int e;
+          frexp(m, &e);
+          pend = e;
+        }
+      }
+      prev_track = track;
+      __syncthreads();
+    }
+  }
+  const Cplx<Real> v = B[0];
+  *tr_re = ldexp((double)v.x, (int)(expo + log2_factor));
+  *tr_im = ldexp((double)v.y, (int)(expo + log2_factor));
+}
+
 template <typename Real, int NT, bool BF3>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter,
                                                        unsigned char* slots, int slot_bits) {
   __shared__ Real red[16];
   __shared__ long long next;
-  __shared__ __align__(16) Cplx<Real> mats[16 * chunk_ops<NT>()];
-  __shared__ Op ops_s[chunk_ops<NT>()];
+  __shared__ __align__(16) Cplx<Real> mats[16 * 64];
+  __shared__ uint2 ops_s[64];
   const int lane = threadIdx.x;
   Cplx<Real>* B = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
   for (;;) {
@@ -89,10 +233,12 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
       continue;
     }
     const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
+    const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
     double re, im;
-    run_program<Real, NT, BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
-                               a.wgates + pidx * a.wg_stride, a.factors + pidx * a.f_stride, pg, a.G,
-                               hdr->log2_factor, lane, red, &re, &im);
+    run_program_hbm<Real, NT, hbm_u<Real>(), BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride,
+                                          hdr->num_ops, hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
+                                          a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red, &re,
+                                          &im);
     if (lane == 0) {
       out[0] = re;
       out[1] = im;
@@ -223,14 +369,14 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
                      int slot_bits, int num_slots, hipStream_t s) {
   if (a.num_pairs <= 0 || num_slots <= 0) return FP_OK;
   if (precision == FP_C128)
-    hipLaunchKernelGGL((sweep_hbm_kernel<double, 512, false>), dim3(num_slots), dim3(512), 0, s, a, counter,
-                       (unsigned char*)slots, slot_bits);
+    hipLaunchKernelGGL((sweep_hbm_kernel<double, HBM_NT, false>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
+                       counter, (unsigned char*)slots, slot_bits);
   else if (a.bf3)
-    hipLaunchKernelGGL((sweep_hbm_kernel<float, 1024, true>), dim3(num_slots), dim3(1024), 0, s, a, counter,
-                       (unsigned char*)slots, slot_bits);
+    hipLaunchKernelGGL((sweep_hbm_kernel<float, HBM_NT, true>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
+                       counter, (unsigned char*)slots, slot_bits);
   else
-    hipLaunchKernelGGL((sweep_hbm_kernel<float, 1024, false>), dim3(num_slots), dim3(1024), 0, s, a, counter,
-                       (unsigned char*)slots, slot_bits);
+    hipLaunchKernelGGL((sweep_hbm_kernel<float, HBM_NT, false>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
+                       counter, (unsigned char*)slots, slot_bits);
   return check_launch("sweep_hbm");
 }
 

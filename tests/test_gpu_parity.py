@@ -142,6 +142,24 @@ def test_brickwork_hbm_path_vs_dense(fp):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_local_random_all_classes_vs_dense(fp, prec):
+    # 8 qubits, 40 steps: peak registers from 2^12 to 2^22 entries, so one
+    # batch runs through both LDS sweeps and the HBM-slot sweep (the last with
+    # the precomputed matrices of the local random path)
+    n, s, npairs, seed = 8, 40, 24, 4242
+    pairs = sampler.sample_pairs(1, n, s, seed, 0, npairs)
+    peaks = []
+    for u, v in pairs:
+        bu = np.array([b for b, _ in u["gates"]], np.int32)
+        bv = np.array([b for b, _ in v["gates"]], np.int32)
+        peaks.append(fp.fp_plan_local_random_host(n, bu, bv)["peak_bits"])
+    assert min(peaks) <= 12 and max(peaks) >= 22, sorted(peaks)
+    got = gpu_traces(fp, (1, n, s), npairs, seed, prec)
+    want = oracle_traces(1, n, s, seed, npairs, prec)
+    assert floored_err(got, want) <= TOL[prec], floored_err(got, want)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_wide_circuits_vs_mpo(fp, prec):
     cases = [(0, 20, 3, 6), (1, 50, 50, 4), (2, 40, 2, 6), (1, 30, 60, 3)]
     for ansatz, n, d, npairs in cases:
