@@ -51,49 +51,212 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
   Op* ops_s = reinterpret_cast<Op*>(mats + 16 * chunk_ops<NT>());
   const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
   double re, im;
+  const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
   run_program<Real, NT, BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
                              a.wgates + pidx * a.wg_stride, a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor,
-                             lane, red, &re, &im);
+                             lane, red, &re, &im, wm, hdr->num_gate_ops);
   if (lane == 0) {
     out[0] = re;
     out[1] = im;
   }
 }
 
-// Large boundaries: one workgroup per pair at a time, boundary in the HBM
-// slot of the workgroup (2^slot_bits entries), pairs taken from a shared
-// counter.  The interpreter runs the same programs with the same arithmetic
-// as run_program, organised for global-memory latency:
+// Large boundaries: one workgroup per pair at a time, pairs taken from a
+// shared counter.  The boundary lives in LDS (2^14 complex64 or 2^13
+// complex128 entries, 128 KiB) while it fits and in the workgroup's HBM slot
+// (2^slot_bits entries) only while it does not: the BELL that grows it past
+// LDS writes its result into the slot, the TRACE that brings it back writes
+// its result into LDS.  In a local random pair at 200 steps on 50 qubits some
+// 390 of 400 ops stay in LDS; the few beyond carry most of the entries.
+// The interpreter runs the same programs with the same arithmetic as
+// run_program, organised for memory latency:
 //   * every lane keeps U groups (GATE), outputs (TRACE) or entries (BELL) in
-//     flight, all loads of a round issued before its stores, so a TRACE needs
-//     two barriers per NT * U outputs;
+//     flight, all loads of a round issued before its stores;
 //   * op fields are read once per wavefront (scalar), so branching is uniform;
 //   * the realigned matrices come precomputed in program order when the
 //     caller has them (local random), else they are staged from the factors.
-// 512 lanes with 8 (float) or 3 (double) groups each: the most loads in
-// flight without spilling registers.
+// 512 lanes with 8 (float), 6 (float, bf16x3 products) or 3 (double) items
+// each: the most loads in flight without spilling registers.
 constexpr int HBM_NT = 512;
-template <typename Real>
+template <typename Real, bool BF3>
 constexpr int hbm_u() {
-  return sizeof(Real) == 8 ? 3 : 8;
+  return sizeof(Real) == 8 ? 3 : BF3 ? 6 : 8;
+}
+template <typename Real>
+constexpr int hbm_lds_bits() {
+  return sizeof(Real) == 8 ? 13 : 14;
+}
+
+// The helpers below work in rounds of NT * U items (groups, outputs,
+// entries; the item counts are powers of two).  Past the end of the range the
+// item index wraps around: every load is valid and issued unconditionally, so
+// all loads of a round are in flight together, and only the owner of an item
+// (index below the count) stores it or counts it in the column maximum.
+// Without wrapping (count a multiple of NT * U) every lane owns its items.
+// The *_any entry points halve U while a round would be larger than the
+// range, and with U = 1 a wavefront that owns no item does nothing.
+
+// GATE: the realigned matrix (Rr, Ri) on the 2^(b-2) groups of four entries
+// (bits lo < hi of the group index are the gate's bits).
+template <typename Real, int NT, int U, bool BF3>
+__device__ __forceinline__ void gate_rounds(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo, int hi,
+                                            int ip, int iq, int ng, int lane, bool track, Real& lmax) {
+  const bool whole = ng % (NT * U) == 0;
+  if (U == 1 && (lane & ~63) >= ng) return;
+  for (int g0 = 0; g0 < ng; g0 += NT * U) {
+    Cplx<Real> v[U][4];
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int g = (g0 + lane + u * NT) & (ng - 1);
+      idx[u] = insert_zero(insert_zero(g, lo), hi);
+      v[u][0] = B[idx[u]];
+      v[u][1] = B[idx[u] + ip];
+      v[u][2] = B[idx[u] + iq];
+      v[u][3] = B[idx[u] + ip + iq];
+    }
+    Cplx<Real> w[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int jp = 0; jp < 4; ++jp) {
+        Real sr = 0, si = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[jp * 4 + j], Ri[jp * 4 + j], v[u][j].x, v[u][j].y, sr, si);
+        w[u][jp].x = sr;
+        w[u][jp].y = si;
+        if (track && (whole || g0 + lane + u * NT < ng)) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (whole || g0 + lane + u * NT < ng) {
+        B[idx[u]] = w[u][0];
+        B[idx[u] + ip] = w[u][1];
+        B[idx[u] + iq] = w[u][2];
+        B[idx[u] + ip + iq] = w[u][3];
+      }
+    }
+  }
 }
 
 template <typename Real, int NT, int U, bool BF3>
-__device__ __forceinline__ void run_program_hbm(Cplx<Real>* B, Cplx<Real>* mats_s, uint2* ops_s,
+__device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo, int hi,
+                                         int ip, int iq, int ng, int lane, bool track, Real& lmax) {
+  if constexpr (U > 1) {
+    if (ng < NT * U) {
+      gate_any<Real, NT, U / 2, BF3>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
+      return;
+    }
+  }
+  gate_rounds<Real, NT, U, BF3>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
+}
+
+// BELL from b to b + 2 bits: dst[k + 3s] = src[k], dst[k + s] = dst[k + 2s] = 0
+// (s = 2^b), and dst[k] = src[k] when the boundary moves (COPY).
+template <typename Real, int NT, int U, bool COPY>
+__device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int s, int lane) {
+  const bool whole = s % (NT * U) == 0;
+  if (U == 1 && (lane & ~63) >= s) return;
+  Cplx<Real> z;
+  z.x = (Real)0;
+  z.y = (Real)0;
+  for (int k0 = 0; k0 < s; k0 += NT * U) {
+    Cplx<Real> v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[(k0 + lane + u * NT) & (s - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = k0 + lane + u * NT;
+      if (whole || k < s) {
+        if (COPY) dst[k] = v[u];
+        dst[k + s] = z;
+        dst[k + 2 * s] = z;
+        dst[k + 3 * s] = v[u];
+      }
+    }
+  }
+}
+
+template <typename Real, int NT, int U, bool COPY>
+__device__ __forceinline__ void bell_op(const Cplx<Real>* src, Cplx<Real>* dst, int b, int lane) {
+  const int s = 1 << b;
+  if constexpr (U > 1) {
+    if (s < NT * U) {
+      bell_op<Real, NT, U / 2, COPY>(src, dst, b, lane);
+      return;
+    }
+  }
+  bell_rounds<Real, NT, U, COPY>(src, dst, s, lane);
+}
+
+// TRACE over bits p < q of a 2^b register: dst[j] = src[i0] + src[i0 + 2^p + 2^q],
+// i0 = j with zeros inserted at p and q.  In place (src == dst) every round
+// reads all its inputs before anyone writes (a barrier between); every input
+// of a round lies at or above its outputs, and later rounds read above what
+// earlier ones wrote.  The barriers are reached by every lane.
+template <typename Real, int NT, int U, bool INPLACE>
+__device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int nout, int p, int q, int lane,
+                                             bool track, Real& lmax) {
+  const int step = (1 << p) + (1 << q);
+  const bool whole = nout % (NT * U) == 0;
+  const bool idle = U == 1 && (lane & ~63) >= nout;  // wavefront-uniform
+  for (int j0 = 0; j0 < nout; j0 += NT * U) {
+    Cplx<Real> acc[U];
+    if (!idle) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i0 = insert_zero(insert_zero((j0 + lane + u * NT) & (nout - 1), p), q);
+        const Cplx<Real> a0 = src[i0], a1 = src[i0 + step];
+        acc[u].x = a0.x + a1.x;
+        acc[u].y = a0.y + a1.y;
+        if (track && (whole || j0 + lane + u * NT < nout))
+          lmax = fmax(lmax, fmax(fabs(acc[u].x), fabs(acc[u].y)));
+      }
+    }
+    if (INPLACE) __syncthreads();
+    if (!idle) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j = j0 + lane + u * NT;
+        if (whole || j < nout) dst[j] = acc[u];
+      }
+    }
+    if (INPLACE && j0 + NT * U < nout) __syncthreads();  // the last round ends at the op's barrier
+  }
+}
+
+template <typename Real, int NT, int U, bool INPLACE>
+__device__ __forceinline__ void trace_op(const Cplx<Real>* src, Cplx<Real>* dst, int b, int p, int q, int lane,
+                                         bool track, Real& lmax) {
+  const int nout = 1 << (b - 2);
+  if constexpr (U > 1) {
+    if (nout < NT * U) {
+      trace_op<Real, NT, U / 2, INPLACE>(src, dst, b, p, q, lane, track, lmax);
+      return;
+    }
+  }
+  trace_rounds<Real, NT, U, INPLACE>(src, dst, nout, p, q, lane, track, lmax);
+}
+
+template <typename Real, int NT, int U, bool BF3>
+__device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cplx<Real>* mats_s, uint2* ops_s,
                                                 const Op* __restrict__ ops, int num_ops, int num_gate_ops,
                                                 const Real* __restrict__ wmat, const int2* __restrict__ wgates,
                                                 const int32_t* __restrict__ factors, const Real* pair_gates, int G,
                                                 int log2_factor, int lane, Real* red, double* tr_re, double* tr_im) {
   constexpr int K = 64;  // ops staged per chunk: one per lane of the first wavefront
+  constexpr int LB = hbm_lds_bits<Real>();
   int b = 0;
+  bool in_lds = true;
   int64_t expo = 0;  // true boundary = stored boundary * 2^expo
   int pend = 0;      // exponent to remove at the next GATE
   bool prev_track = false;
   int gate_base = 0;  // GATE ops before the chunk (first wavefront only)
   Real lmax = 0;
   if (lane == 0) {
-    B[0].x = (Real)1;
-    B[0].y = (Real)0;
+    L[0].x = (Real)1;
+    L[0].y = (Real)0;
   }
   for (int t0 = 0; t0 < num_ops; t0 += K) {
     const int nk = num_ops - t0 < K ? num_ops - t0 : K;
@@ -124,67 +287,38 @@ __device__ __forceinline__ void run_program_hbm(Cplx<Real>* B, Cplx<Real>* mats_
       const int p = (int)((w0 >> 8) & 0xff), q = (int)((w0 >> 16) & 0xff);
       if (type == OP_GATE) {
         Real Rr[16], Ri[16];
+        const int sc = __builtin_amdgcn_readfirstlane(pend);
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
+        for (int k = 0; k < 16; ++k) {  // ldexp by 0 is the identity
           const Cplx<Real> r = mats_s[16 * i + k];
-          Rr[k] = pend ? ldexp(r.x, -pend) : r.x;
-          Ri[k] = pend ? ldexp(r.y, -pend) : r.y;
+          Rr[k] = ldexp(r.x, -sc);
+          Ri[k] = ldexp(r.y, -sc);
         }
         expo += pend;
         pend = 0;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
-        gate_groups<Real, U, BF3>(B, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, NT, track, lmax);
+        if (in_lds)
+          gate_any<Real, NT, U, BF3>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
+        else
+          gate_any<Real, NT, U, BF3>(H, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
       } else if (type == OP_BELL) {
-        const int s = 1 << b;
-        for (int k0 = lane; k0 < s; k0 += NT * U) {
-          Cplx<Real> v[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-            if (k0 + u * NT < s) v[u] = B[k0 + u * NT];
-          Cplx<Real> z;
-          z.x = (Real)0;
-          z.y = (Real)0;
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int k = k0 + u * NT;
-            if (k < s) {
-              B[k + s] = z;
-              B[k + 2 * s] = z;
-              B[k + 3 * s] = v[u];
-            }
-          }
+        if (!in_lds) {
+          bell_op<Real, NT, U, false>(H, H, b, lane);
+        } else if (b + 2 <= LB) {
+          bell_op<Real, NT, U, false>(L, L, b, lane);
+        } else {
+          bell_op<Real, NT, U, true>(L, H, b, lane);
+          in_lds = false;
         }
         b += 2;
-      } else if (type == OP_TRACE) {
-        // p < q; in place, in chunks of NT * U outputs: every input of a
-        // chunk lies at or above its output, so the chunk reads everything
-        // before anyone writes, and later chunks read above what it wrote
-        const int nout = 1 << (b - 2);
-        const int step = (1 << p) + (1 << q);
-        for (int j0 = 0; j0 < nout; j0 += NT * U) {
-          Cplx<Real> a0[U], a1[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int j = j0 + lane + u * NT;
-            if (j < nout) {
-              const int i0 = insert_zero(insert_zero(j, p), q);
-              a0[u] = B[i0];
-              a1[u] = B[i0 + step];
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int j = j0 + lane + u * NT;
-            if (j < nout) {
-              Cplx<Real> acc;
-              acc.x = a0[u].x + a1[u].x;
-              acc.y = a0[u].y + a1[u].y;
-              if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
-              B[j] = acc;
-            }
-          }
-          if (j0 + NT * U < nout) __syncthreads();  // the last chunk ends at the op's barrier
+      } else if (type == OP_TRACE) {  // p < q
+        if (in_lds) {
+          trace_op<Real, NT, U, true>(L, L, b, p, q, lane, track, lmax);
+        } else if (b - 2 > LB) {
+          trace_op<Real, NT, U, true>(H, H, b, p, q, lane, track, lmax);
+        } else {
+          trace_op<Real, NT, U, false>(H, L, b, p, q, lane, track, lmax);
+          in_lds = true;
         }
         b -= 2;
       } else if (prev_track) {  // OP_COLEND after the column's last writing op
@@ -201,20 +335,27 @@ __device__ __forceinline__ void run_program_hbm(Cplx<Real>* B, Cplx<Real>* mats_
       __syncthreads();
     }
   }
-  const Cplx<Real> v = B[0];
+  const Cplx<Real> v = in_lds ? L[0] : H[0];
   *tr_re = ldexp((double)v.x, (int)(expo + log2_factor));
   *tr_im = ldexp((double)v.y, (int)(expo + log2_factor));
+}
+
+template <typename Real>
+constexpr size_t hbm_lds_bytes() {
+  return (size_t)sizeof(Cplx<Real>) << hbm_lds_bits<Real>();
 }
 
 template <typename Real, int NT, bool BF3>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter,
                                                        unsigned char* slots, int slot_bits) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
   __shared__ long long next;
   __shared__ __align__(16) Cplx<Real> mats[16 * 64];
   __shared__ uint2 ops_s[64];
   const int lane = threadIdx.x;
-  Cplx<Real>* B = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
+  Cplx<Real>* L = reinterpret_cast<Cplx<Real>*>(smem_raw);
+  Cplx<Real>* H = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
   for (;;) {
     if (lane == 0) next = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
@@ -235,10 +376,10 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
     const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
     const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
     double re, im;
-    run_program_hbm<Real, NT, hbm_u<Real>(), BF3>(B, mats, ops_s, a.ops + pidx * a.ops_stride,
-                                          hdr->num_ops, hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
-                                          a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red, &re,
-                                          &im);
+    run_program_big<Real, NT, hbm_u<Real, BF3>(), BF3>(L, H, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+                                                  hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
+                                                  a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane,
+                                                  red, &re, &im);
     if (lane == 0) {
       out[0] = re;
       out[1] = im;
@@ -365,18 +506,23 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
   return a.bf3 ? launch_lds_real<float, true>(a, tile, s) : launch_lds_real<float, false>(a, tile, s);
 }
 
+template <typename Real, bool BF3>
+static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, void* slots, int slot_bits, int num_slots,
+                         hipStream_t s) {
+  const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3>;
+  const size_t smem = hbm_lds_bytes<Real>();
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)smem);
+  if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
+  hipLaunchKernelGGL(k, dim3(num_slots), dim3(HBM_NT), smem, s, a, counter, (unsigned char*)slots, slot_bits);
+}
+
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
                      int slot_bits, int num_slots, hipStream_t s) {
   if (a.num_pairs <= 0 || num_slots <= 0) return FP_OK;
-  if (precision == FP_C128)
-    hipLaunchKernelGGL((sweep_hbm_kernel<double, HBM_NT, false>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
-                       counter, (unsigned char*)slots, slot_bits);
-  else if (a.bf3)
-    hipLaunchKernelGGL((sweep_hbm_kernel<float, HBM_NT, true>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
-                       counter, (unsigned char*)slots, slot_bits);
-  else
-    hipLaunchKernelGGL((sweep_hbm_kernel<float, HBM_NT, false>), dim3(num_slots), dim3(HBM_NT), 0, s, a,
-                       counter, (unsigned char*)slots, slot_bits);
+  if (precision == FP_C128) launch_hbm_t<double, false>(a, counter, slots, slot_bits, num_slots, s);
+  else if (a.bf3) launch_hbm_t<float, true>(a, counter, slots, slot_bits, num_slots, s);
+  else launch_hbm_t<float, false>(a, counter, slots, slot_bits, num_slots, s);
   return check_launch("sweep_hbm");
 }
 

@@ -25,8 +25,10 @@ __device__ __forceinline__ void group_sync() {
   }
 }
 
+// x >= 0 with a zero bit inserted at position pos: the bits from pos up move
+// up one place (adding the high part to itself; two instructions)
 __device__ __forceinline__ int insert_zero(int x, int pos) {
-  return ((x >> pos) << (pos + 1)) | (x & ((1 << pos) - 1));
+  return x + (int)((unsigned)x & (~0u << pos));
 }
 
 // BF16x3 products: x = hi + lo with hi = bf16(x) (round to nearest even)
@@ -219,6 +221,53 @@ __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16],
   }
 }
 
+// gate_groups with the op's flags as template arguments, for groups whose op
+// is uniform (one pair per wavefront or more): TRACK records the largest
+// magnitude written, SCALE multiplies the outputs by 2^-scale (the column's
+// pending power of two; exact, the same as scaling the matrix).
+template <typename Real, int U, bool BF3, bool TRACK, bool SCALE>
+__device__ __forceinline__ void gate_groups_u(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo,
+                                              int hi, int ip, int iq, int ng, int first, int stride, int scale,
+                                              Real& lmax) {
+  for (int g0 = first; g0 < ng; g0 += stride * U) {
+    Cplx<Real> v[U][4];
+    int idx[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int g = g0 + u * stride;
+      idx[u] = insert_zero(insert_zero(g, lo), hi);
+      if (g < ng) {
+        v[u][0] = B[idx[u]];
+        v[u][1] = B[idx[u] + ip];
+        v[u][2] = B[idx[u] + iq];
+        v[u][3] = B[idx[u] + ip + iq];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (g0 + u * stride >= ng) break;
+      Cplx<Real> w[4];
+#pragma unroll
+      for (int jp = 0; jp < 4; ++jp) {
+        Real sr = 0, si = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[jp * 4 + j], Ri[jp * 4 + j], v[u][j].x, v[u][j].y, sr, si);
+        if (SCALE) {
+          sr = ldexp(sr, -scale);
+          si = ldexp(si, -scale);
+        }
+        w[jp].x = sr;
+        w[jp].y = si;
+        if (TRACK) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+      }
+      B[idx[u]] = w[0];
+      B[idx[u] + ip] = w[1];
+      B[idx[u] + iq] = w[2];
+      B[idx[u] + ip + iq] = w[3];
+    }
+  }
+}
+
 // Groups per round of gate_groups: one (measured: batching several raised the
 // register count and lost more to occupancy than the overlapped loads gained).
 template <typename Real>
@@ -251,7 +300,8 @@ constexpr int chunk_ops() {
 // Runs one pair's program on boundary B (LDS or global).  The program is
 // processed in chunks of K ops: the group first stages the chunk's op records
 // and the realigned matrices of its GATE ops in LDS (one lane per op, in
-// parallel), then executes the ops from LDS.  The per-column rescale is
+// parallel; the matrices are copied when they come precomputed, else formed
+// from the factors), then executes the ops from LDS.  The per-column rescale is
 // lazy: the op that ends a column records the largest magnitude it writes,
 // the column end turns it into an exponent P, and the next GATE multiplies
 // its matrix by 2^-P (exact), so no extra pass over the boundary is made.
@@ -259,8 +309,13 @@ template <typename Real, int NT, bool BF3 = false>
 __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, Op* ops_s, const Op* __restrict__ ops,
                                             int num_ops, const int2* __restrict__ wgates,
                                             const int32_t* __restrict__ factors, const Real* pair_gates, int G,
-                                            int log2_factor, int lane, Real* red, double* tr_re, double* tr_im) {
+                                            int log2_factor, int lane, Real* red, double* tr_re, double* tr_im,
+                                            const Real* __restrict__ wmat = nullptr, int num_gate_ops = 0) {
   constexpr int K = chunk_ops<NT>();
+  // with the matrices precomputed in program order (wmat), the first
+  // wavefront stages a chunk and numbers its GATEs with a ballot
+  const bool pre = NT >= 64 && wmat != nullptr;
+  int gate_base = 0;  // GATE ops before the chunk (first wavefront only)
   int b = 0;
   int64_t expo = 0;  // true boundary = stored boundary * 2^expo
   int pend = 0;      // exponent to remove at the next GATE
@@ -271,31 +326,76 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
   }
   for (int t0 = 0; t0 < num_ops; t0 += K) {
     const int nk = num_ops - t0 < K ? num_ops - t0 : K;
-    for (int i = lane; i < nk; i += NT) {
-      const Op op = ops[t0 + i];
-      ops_s[i] = op;
-      if ((op.type & OP_TYPE_MASK) == OP_GATE) stage_gate<Real, BF3>(pair_gates, G, factors, wgates[op.arg], mats_s + 16 * i);
+    if (pre) {
+      if (lane < 64) {
+        const bool here = lane < nk;
+        Op op;
+        if (here) op = ops[t0 + lane];
+        const bool is_gate = here && (op.type & OP_TYPE_MASK) == OP_GATE;
+        const unsigned long long m = __ballot(is_gate);
+        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const int k = gate_base + __popcll(m & below);
+        gate_base += __popcll(m);
+        if (here) ops_s[lane] = op;
+        if (is_gate && k < num_gate_ops) {
+          const float4* src = reinterpret_cast<const float4*>(wmat + 32 * (int64_t)k);
+          float4* dst = reinterpret_cast<float4*>(mats_s + 16 * lane);
+#pragma unroll
+          for (int r = 0; r < 8 * (int)sizeof(Real) / 4; ++r) dst[r] = src[r];
+        }
+      }
+    } else {
+      for (int i = lane; i < nk; i += NT) {
+        const Op op = ops[t0 + i];
+        ops_s[i] = op;
+        if ((op.type & OP_TYPE_MASK) == OP_GATE)
+          stage_gate<Real, BF3>(pair_gates, G, factors, wgates[op.arg], mats_s + 16 * i);
+      }
     }
     group_sync<NT>();
     for (int i = 0; i < nk; ++i) {
-      const Op op = ops_s[i];
+      Op op = ops_s[i];
+      if constexpr (NT >= 64) {  // one pair per wavefront or more: the op is uniform
+        const unsigned w0 = (unsigned)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(&op));
+        op.type = (uint8_t)w0;
+        op.p = (uint8_t)(w0 >> 8);
+        op.q = (uint8_t)(w0 >> 16);
+      }
       const int type = op.type & OP_TYPE_MASK;
       const bool track = (op.type & OP_FLAG_TRACK) != 0;
       if (type == OP_GATE) {
-        Real Rr[16], Ri[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const Cplx<Real> r = mats_s[16 * i + k];
-          Rr[k] = pend ? ldexp(r.x, -pend) : r.x;
-          Ri[k] = pend ? ldexp(r.y, -pend) : r.y;
-        }
-        expo += pend;
-        pend = 0;
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
-        gate_groups<Real, BF3 ? 2 : gate_batch<Real>(), BF3>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, NT, track,
-                                                             lmax);
+        constexpr int U = BF3 ? 2 : gate_batch<Real>();
+        Real Rr[16], Ri[16];
+        if constexpr (NT >= 64) {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const Cplx<Real> r = mats_s[16 * i + k];
+            Rr[k] = r.x;
+            Ri[k] = r.y;
+          }
+          const int sc = __builtin_amdgcn_readfirstlane(pend);
+          const int ng = 1 << (b - 2);
+          if (track) {
+            if (sc) gate_groups_u<Real, U, BF3, true, true>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, NT, sc, lmax);
+            else gate_groups_u<Real, U, BF3, true, false>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, NT, 0, lmax);
+          } else {
+            if (sc) gate_groups_u<Real, U, BF3, false, true>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, NT, sc, lmax);
+            else gate_groups_u<Real, U, BF3, false, false>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, NT, 0, lmax);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const Cplx<Real> r = mats_s[16 * i + k];
+            Rr[k] = pend ? ldexp(r.x, -pend) : r.x;
+            Ri[k] = pend ? ldexp(r.y, -pend) : r.y;
+          }
+          gate_groups<Real, U, BF3>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, NT, track, lmax);
+        }
+        expo += pend;
+        pend = 0;
       } else if (type == OP_BELL) {
         const int s = 1 << b;
         for (int k = lane; k < s; k += NT) {

@@ -1,17 +1,21 @@
 // Column sweep with one wavefront per pair, for registers of up to 2^10
 // entries (the bulk of local random pairs).  Same register programs and the
 // same arithmetic as the LDS sweep of sweep_dev.h (Sec. II.A of the paper,
-// trace as a contraction along the qubits; Methods A), organised so that
-// the per-op overhead stays small:
+// trace as a contraction along the qubits; Methods A).  The kernel is bound
+// by vector-instruction issue, so it is organised to spend as few vector
+// instructions per op as it can:
 //   * the op stream is uniform across the wavefront: op records are read 64
 //     at a time into lanes and taken with readlane, so decoding and branching
 //     are scalar;
 //   * the realigned matrices of the GATE ops come precomputed in program
-//     order (written by the planner), prefetched four GATEs ahead by lanes
-//     0..31 and passed through a 32-entry LDS stage;
+//     order, prefetched four GATEs ahead by lanes 0..31 and passed through a
+//     32-entry LDS stage that holds the real parts before the imaginary ones,
+//     so 16-byte LDS reads land in the registers the products use;
 //   * registers of up to 64 entries give each lane one output entry of the
 //     gate (one matrix row, four inputs); larger ones give each lane whole
-//     groups of four entries, several loaded at once.
+//     groups of four entries;
+//   * the ops that record a column's largest magnitude and those that do not
+//     are separate code paths (a scalar branch, not a select per output).
 // The boundary stays in LDS; pairs are independent, so waves never wait for
 // each other.
 #include <hip/hip_runtime.h>
@@ -40,6 +44,92 @@ __device__ __forceinline__ Real wave_max(Real v) {
 }
 
 constexpr int PREFETCH = 4;  // GATE matrices in flight per wavefront
+
+// Registers of up to 64 entries: lane = 4 g + jp computes output jp of group
+// g (g < 2^(b-2)), i.e. row jp of the matrix (stage: real parts at 0..15,
+// imaginary parts at 16..31) against the group's four entries.
+template <typename Real, bool BF3, bool TRACK>
+__device__ __forceinline__ void gate_small(Cplx<Real>* B, const Real* stage, int b, int lo, int hi, int ip, int iq,
+                                           int sp, int sq, int lane, Real& lmax) {
+  const int g = lane >> 2, jp = lane & 3;
+  Real Rr[4], Ri[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    Rr[j] = stage[jp * 4 + j];
+    Ri[j] = stage[16 + jp * 4 + j];
+  }
+  if (g < (1 << (b - 2))) {
+    const int idx = insert_zero(insert_zero(g, lo), hi);
+    Cplx<Real> v[4];
+    v[0] = B[idx];
+    v[1] = B[idx + ip];
+    v[2] = B[idx + iq];
+    v[3] = B[idx + ip + iq];
+    Real sr = 0, si = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[j], Ri[j], v[j].x, v[j].y, sr, si);
+    if (TRACK) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+    // the store follows the four loads of every lane (one instruction
+    // stream), so no lane overwrites an input another lane still needs
+    Cplx<Real> w;
+    w.x = sr;
+    w.y = si;
+    B[idx + ((jp & 1) << sp) + ((jp >> 1) << sq)] = w;
+  }
+}
+
+// Larger registers: each lane applies the whole matrix to groups of four
+// entries, lane, lane + 64, ...
+template <typename Real, bool BF3, bool TRACK>
+__device__ __forceinline__ void gate_big(Cplx<Real>* B, const Real* stage, int b, int lo, int hi, int ip, int iq,
+                                         int lane, Real& lmax) {
+  Real Rr[16], Ri[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    Rr[k] = stage[k];
+    Ri[k] = stage[16 + k];
+  }
+  const int ng = 1 << (b - 2);
+  for (int g = lane; g < ng; g += 64) {
+    const int idx = insert_zero(insert_zero(g, lo), hi);
+    Cplx<Real> v[4];
+    v[0] = B[idx];
+    v[1] = B[idx + ip];
+    v[2] = B[idx + iq];
+    v[3] = B[idx + ip + iq];
+    Cplx<Real> w[4];
+#pragma unroll
+    for (int jp = 0; jp < 4; ++jp) {
+      Real sr = 0, si = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[jp * 4 + j], Ri[jp * 4 + j], v[j].x, v[j].y, sr, si);
+      if (TRACK) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
+      w[jp].x = sr;
+      w[jp].y = si;
+    }
+    B[idx] = w[0];
+    B[idx + ip] = w[1];
+    B[idx + iq] = w[2];
+    B[idx + ip + iq] = w[3];
+  }
+}
+
+// TRACE over bits p < q: entries move down in increasing order, and every
+// read of an iteration precedes its writes, so the compaction is in place.
+template <typename Real, bool TRACK>
+__device__ __forceinline__ void trace_wave(Cplx<Real>* B, int b, int p, int q, int lane, Real& lmax) {
+  const int nout = 1 << (b - 2);
+  const int step = (1 << p) + (1 << q);
+  for (int j = lane; j < nout; j += 64) {
+    const int i0 = insert_zero(insert_zero(j, p), q);
+    const Cplx<Real> a0 = B[i0], a1 = B[i0 + step];
+    Cplx<Real> acc;
+    acc.x = a0.x + a1.x;
+    acc.y = a0.y + a1.y;
+    if (TRACK) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
+    B[j] = acc;
+  }
+}
 
 }  // namespace
 
@@ -75,6 +165,9 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
   Real* stage = reinterpret_cast<Real*>(B + (1 << CAP));
   const uint2* ops = reinterpret_cast<const uint2*>(a.ops + pidx * a.ops_stride);
   const Real* mats = reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride);
+  // lane l < 32 carries real l of a matrix (interleaved re, im) and stages it
+  // de-interleaved
+  Real* my_stage = stage + (lane & 1) * 16 + ((lane & 31) >> 1);
 
   Real pre[PREFETCH];
 #pragma unroll
@@ -85,7 +178,7 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
 
   int b = 0;
   int64_t expo = 0;  // true boundary = stored boundary * 2^expo
-  int pend = 0;      // exponent to remove at the next GATE
+  int pend = 0;      // exponent to remove at the next GATE (uniform)
   bool prev_track = false;
   Real lmax = 0;
   if (lane == 0) {
@@ -101,7 +194,9 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
       const bool track = (w0 & OP_FLAG_TRACK) != 0;
       const int p = (int)((w0 >> 8) & 0xff), q = (int)((w0 >> 16) & 0xff);
       if (type == OP_GATE) {
-        if (lane < 32) stage[lane] = pre[0];
+        // the column's pending power of two is taken out of the matrix here
+        // (exact; ldexp by 0 is the identity)
+        if (lane < 32) *my_stage = ldexp(pre[0], -pend);
 #pragma unroll
         for (int i = 0; i + 1 < PREFETCH; ++i) pre[i] = pre[i + 1];
         pre[PREFETCH - 1] = (lane < 32 && jg < ngate) ? mats[(int64_t)jg * 32 + lane] : (Real)0;
@@ -110,55 +205,11 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
         if (b <= 6) {
-          // one output entry per lane: group g, output jp
-          const int g = lane >> 2, jp = lane & 3;
-          Real Rr[4], Ri[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            Rr[j] = stage[(jp * 4 + j) * 2];
-            Ri[j] = stage[(jp * 4 + j) * 2 + 1];
-          }
-          if (pend) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              Rr[j] = ldexp(Rr[j], -pend);
-              Ri[j] = ldexp(Ri[j], -pend);
-            }
-          }
-          if (g < (1 << (b - 2))) {
-            const int idx = insert_zero(insert_zero(g, lo), hi);
-            Cplx<Real> v[4];
-            v[0] = B[idx];
-            v[1] = B[idx + ip];
-            v[2] = B[idx + iq];
-            v[3] = B[idx + ip + iq];
-            Real sr = 0, si = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) cmac<Real, BF3>(Rr[j], Ri[j], v[j].x, v[j].y, sr, si);
-            if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
-            // the store follows the four loads of every lane (one instruction
-            // stream), so no lane overwrites an input another lane still needs
-            Cplx<Real> w;
-            w.x = sr;
-            w.y = si;
-            B[idx + (jp & 1) * ip + (jp >> 1) * iq] = w;
-          }
+          if (track) gate_small<Real, BF3, true>(B, stage, b, lo, hi, ip, iq, p, q, lane, lmax);
+          else gate_small<Real, BF3, false>(B, stage, b, lo, hi, ip, iq, p, q, lane, lmax);
         } else {
-          Real Rr[16], Ri[16];
-#pragma unroll
-          for (int k = 0; k < 16; ++k) {
-            Rr[k] = stage[2 * k];
-            Ri[k] = stage[2 * k + 1];
-          }
-          if (pend) {
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-              Rr[k] = ldexp(Rr[k], -pend);
-              Ri[k] = ldexp(Ri[k], -pend);
-            }
-          }
-          gate_groups<Real, BF3 ? 2 : gate_batch<Real>(), BF3>(B, Rr, Ri, lo, hi, ip, iq, 1 << (b - 2), lane, 64,
-                                                               track, lmax);
+          if (track) gate_big<Real, BF3, true>(B, stage, b, lo, hi, ip, iq, lane, lmax);
+          else gate_big<Real, BF3, false>(B, stage, b, lo, hi, ip, iq, lane, lmax);
         }
         expo += pend;
         pend = 0;
@@ -175,19 +226,8 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
         }
         b += 2;
       } else if (type == OP_TRACE) {
-        // p < q; entries move down in increasing order, and every read of an
-        // iteration precedes its writes, so the compaction is in place
-        const int nout = 1 << (b - 2);
-        const int step = (1 << p) + (1 << q);
-        for (int j = lane; j < nout; j += 64) {
-          const int i0 = insert_zero(insert_zero(j, p), q);
-          const Cplx<Real> a0 = B[i0], a1 = B[i0 + step];
-          Cplx<Real> acc;
-          acc.x = a0.x + a1.x;
-          acc.y = a0.y + a1.y;
-          if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
-          B[j] = acc;
-        }
+        if (track) trace_wave<Real, true>(B, b, p, q, lane, lmax);
+        else trace_wave<Real, false>(B, b, p, q, lane, lmax);
         b -= 2;
       } else {  // OP_COLEND: the op before it recorded the column's largest magnitude
         if (prev_track) {
@@ -197,7 +237,7 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
           if (m > (Real)0 && isfinite(m)) {
             int e;
             frexp(m, &e);
-            pend = e;
+            pend = __builtin_amdgcn_readfirstlane(e);
           }
         }
       }
