@@ -203,9 +203,13 @@ struct WaveDev {
   __device__ void atomic_add(int32_t* p, int v) const { atomicAdd(p, v); }
 };
 
-// Scratch of the wave planner, in 16-bit entries: 16 arrays of W = 2G entries,
-// one int32 array of W, and per-qubit tables.
-__host__ __device__ inline int64_t plan_wave_scratch_elems(int G) { return 18 * 2 * (int64_t)G + 256; }
+// Scratch of the wave planner, in 16-bit entries: 13 slots of W = 2G entries
+// (arrays whose lifetimes do not overlap share a slot) and per-qubit tables.
+// The bond list may live in slot 11 (it is not read after step 2, and the
+// slot's next array is first written in step 4).
+constexpr int PLAN_SLOTS = 13;
+constexpr int PLAN_BOND_SLOT = 11;
+__host__ __device__ inline int64_t plan_wave_scratch_elems(int G) { return PLAN_SLOTS * 2 * (int64_t)G + 256; }
 
 // Emitted ops are buffered in lanes, 64 at a time (lane j holds op j of the
 // chunk), and stored together; the end of a column marks the op before it
@@ -282,8 +286,9 @@ __host__ __device__ inline void wave_flush(const P& w, WaveEmitter<P>& e) {
 }
 
 // Plan one pair.  bw: bond of each position of W (2G entries: V's gates in
-// time order, then U's gates in reverse order); scratch: plan_wave_scratch_elems(G)
-// entries (4-byte aligned); ops: plan_max_ops(G, n); wgates, factors: 2G each;
+// time order, then U's gates in reverse order; may be slot PLAN_BOND_SLOT of
+// the scratch); scratch: plan_wave_scratch_elems(G) entries (4-byte aligned);
+// ops: plan_max_ops(G, n); wgates, factors: 2G each;
 // gseq (may be null): 2G entries, the merged gate applied by each GATE op in
 // program order.  n <= 64.
 //
@@ -299,31 +304,32 @@ __host__ __device__ inline PlanHeader plan_pair_wave(const P& w, int n, int G, c
                                                      Op* ops, int2* wgates, int32_t* factors, int16_t* gseq) {
   using Lanes = typename P::Lanes;
   const int W = 2 * G;
-  int16_t* prev0 = scratch;  // previous position on the lower / upper qubit of a position
-  int16_t* prev1 = scratch + W;
-  int16_t* gid = scratch + 2 * W;   // merged gate of a position
-  int16_t* root = scratch + 3 * W;  // first position of its merged gate
-  int16_t* mbond = scratch + 4 * W;
-  int16_t* head = scratch + 5 * W;
-  int16_t* tail = scratch + 6 * W;
-  int16_t* dead = scratch + 7 * W;
-  int16_t* nextf = scratch + 8 * W;
-  int16_t* non0 = scratch + 9 * W;
-  int16_t* non1 = scratch + 10 * W;
-  int16_t* pon0 = scratch + 11 * W;
-  int16_t* pon1 = scratch + 12 * W;
-  int16_t* colg = scratch + 13 * W;
-  int16_t* gfl = scratch + 14 * W;
-  int16_t* cnt = scratch + 15 * W;
-  int32_t* cnt32 = reinterpret_cast<int32_t*>(scratch + 16 * W);
-  int16_t* firstpos = scratch + 18 * W;
+  // slots and the steps their arrays live in
+  int16_t* prev0 = scratch;             // 1-4: previous position on the lower qubit of a position
+  int16_t* prev1 = scratch + W;         // 1-4: ... on the upper qubit
+  int16_t* gid = scratch + 2 * W;       // 2-4: merged gate of a position
+  int16_t* root = scratch + 3 * W;      // 2: first position of its merged gate
+  int16_t* mbond = scratch + 4 * W;     // 2-7
+  int16_t* head = scratch + 5 * W;      // 2-6
+  int16_t* tail = scratch + 6 * W;      // 2-4
+  int16_t* dead = scratch + 7 * W;      // 2-6
+  int16_t* nextf = scratch + 8 * W;     // 2-6
+  int32_t* cnt32 = reinterpret_cast<int32_t*>(scratch + 9 * W);  // 2 (slots 9 and 10)
+  int16_t* pon1 = scratch + PLAN_BOND_SLOT * W;                  // 4-7 (the bond list in 1-2)
+  int16_t* cnt = scratch + 12 * W;      // 2-6
+  int16_t* non0 = root;                 // 4-7
+  int16_t* non1 = scratch + 9 * W;      // 4-7
+  int16_t* pon0 = scratch + 10 * W;     // 4-7
+  int16_t* colg = gid;                  // 5-7
+  int16_t* gfl = tail;                  // 7
+  int16_t* firstpos = scratch + PLAN_SLOTS * W;
   int16_t* larr = firstpos + WAVE;
   int32_t* bcnt32 = reinterpret_cast<int32_t*>(larr + WAVE);
-  // walk tables of the columns, once the neighbours are linked
+  // walk tables of the columns (written in 7, read in 8)
   int16_t* wk_g = prev0;
   int16_t* wk_X = prev1;
-  int16_t* wk_Z = root;
-  int16_t* wk_f = gid;
+  int16_t* wk_Z = head;
+  int16_t* wk_f = dead;
 
   PlanHeader h;
   h.num_ops = 0;

@@ -26,7 +26,7 @@ __device__ inline void haar_u4(uint64_t seed, uint64_t pair, uint32_t circuit, u
     const double u2 = u53(x.v[2], x.v[3]);
     const double r = sqrt(-2.0 * log(u1));
     double s, c;
-    sincos(6.283185307179586 * u2, &s, &c);
+    sincospi(2.0 * u2, &s, &c);  // sin and cos of 2 pi u2, without rounding 2 pi u2 first
     z[w >> 2][w & 3].x = r * c;
     z[w >> 2][w & 3].y = r * s;
   }

@@ -397,8 +397,8 @@ __global__ void __launch_bounds__(64) plan_local_random_kernel(PlanJob j) {
   const int64_t pi = blockIdx.x;
   if (pi >= j.num_pairs) return;
   const int G = j.G;
-  int16_t* bw = reinterpret_cast<int16_t*>(smem_raw);
-  int16_t* scratch = bw + ((2 * G + 7) & ~7);
+  int16_t* scratch = reinterpret_cast<int16_t*>(smem_raw);
+  int16_t* bw = scratch + PLAN_BOND_SLOT * 2 * G;  // shares a slot the planner fills only after reading it
   const int32_t* src = reinterpret_cast<const int32_t*>(j.gates + pi * j.gate_stride + j.bonds_off);
   for (int i = threadIdx.x; i < 2 * G; i += 64) {
     const int32_t b = i < G ? src[G + i] : src[2 * G - 1 - i];  // [U bonds][V bonds]
@@ -465,7 +465,7 @@ int launch_order_pairs(const OrderJob& j, hipStream_t s) {
 
 size_t plan_lds_bytes(int G, int n) {
   (void)n;
-  return 2 * (size_t)((2 * G + 7) & ~7) + 2 * (size_t)plan_wave_scratch_elems(G);
+  return 2 * (size_t)plan_wave_scratch_elems(G);
 }
 
 // ---- launchers --------------------------------------------------------------
