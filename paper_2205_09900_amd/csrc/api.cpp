@@ -67,8 +67,9 @@ struct HostPlan {
 static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, HostPlan* out) {
   if (G > PLAN_MAX_GATES) return set_error(FP_EINVAL, "%d gates per circuit exceed %d", G, PLAN_MAX_GATES);
   std::vector<int16_t> scratch((size_t)plan_wave_scratch_elems(G));
-  // bond of each position of W: V's gates in time order, then U's reversed
-  std::vector<int16_t> bw(2 * (size_t)G);
+  // bond of each position of W: V's gates in time order, then U's reversed;
+  // kept in the planner's scratch as the device planner keeps it
+  int16_t* bw = scratch.data() + (size_t)PLAN_BOND_SLOT * 2 * G;
   for (int i = 0; i < 2 * G; ++i) {
     const int32_t b = i < G ? bv[i] : bu[2 * G - 1 - i];
     bw[i] = (b >= 0 && b <= n - 2) ? (int16_t)b : (int16_t)-1;
@@ -77,8 +78,7 @@ static int host_plan_pair(int n, int G, const int32_t* bu, const int32_t* bv, Ho
   out->wg.resize(2 * (size_t)G);
   out->fac.resize(2 * (size_t)G);
   WaveHost wh;
-  out->hdr = plan_pair_wave(wh, n, G, bw.data(), scratch.data(), out->ops.data(), out->wg.data(), out->fac.data(),
-                            nullptr);
+  out->hdr = plan_pair_wave(wh, n, G, bw, scratch.data(), out->ops.data(), out->wg.data(), out->fac.data(), nullptr);
   if (out->hdr.status != PLAN_OK) {
     if (out->hdr.status == PLAN_EWIDE)
       return set_error(FP_ETOOBIG, "boundary wider than %d bits", PLAN_MAX_BITS);
