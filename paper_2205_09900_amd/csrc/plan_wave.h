@@ -114,11 +114,19 @@ struct WaveHost {
 // wavefront's LDS operations complete in order, so a wavefront-scope fence
 // (a compiler barrier) orders them; a workgroup barrier would also wait for
 // the global stores of the emitted ops.
+// v_writelane: x (uniform) into lane q of v.  Clang has no builtin for it,
+// so the LLVM intrinsic is named directly.
+__device__ int lane_write(int x, int q, int v) __asm("llvm.amdgcn.writelane.i32");
+
+// Writes to one lane take a lane index in [0, 64) (writelane uses its low six
+// bits); every caller's index is a qubit, a register position or a chunk slot.
 struct LanesDev {
   int v;
   __device__ static int lane() { return (int)__lane_id(); }
+  // lanes below b, as a ballot mask (b in [0, 64])
+  __device__ static unsigned long long below(int b) { return b >= WAVE ? ~0ull : ((1ull << b) - 1ull); }
   __device__ int get(int q) const { return __builtin_amdgcn_readlane(v, q); }
-  __device__ void set(int q, int x) { v = lane() == q ? x : v; }
+  __device__ void set(int q, int x) { v = lane_write(x, q, v); }
   __device__ void fill(int x) { v = x; }
   template <class F>
   __device__ void fill_by(F f) {
@@ -126,8 +134,8 @@ struct LanesDev {
   }
   __device__ int at(int) const { return v; }
   __device__ void put(int, int x) { v = x; }
-  __device__ void or_at(int q, int x) { v = lane() == q ? (v | x) : v; }
-  __device__ void add_at(int q, int x) { v = lane() == q ? (v + x) : v; }
+  __device__ void or_at(int q, int x) { set(q, get(q) | x); }
+  __device__ void add_at(int q, int x) { set(q, get(q) + x); }
   __device__ double pow2_sum() const {
     double s = (double)v * (double)(1ull << lane());
 #pragma unroll
@@ -135,20 +143,20 @@ struct LanesDev {
     return s;
   }
   __device__ void set2(int q1, int q2, int x) {
-    const int l = lane();
-    v = (l == q1 || l == q2) ? x : v;
+    set(q1, x);
+    set(q2, x);
   }
   __device__ int shfl_at(int q) const { return __shfl(v, q & (WAVE - 1), WAVE); }
   __device__ int find(int t, int b) const {
-    const unsigned long long m = __ballot(v == t && lane() < b);
+    const unsigned long long m = __ballot(v == t) & below(b);
     return m ? __ffsll((long long)m) - 1 : -1;
   }
   __device__ int find_flag(int f, int b) const {
-    const unsigned long long m = __ballot(v >= 0 && (v & f) != 0 && lane() < b);
+    const unsigned long long m = __ballot(v >= 0 && (v & f) != 0) & below(b);
     return m ? __ffsll((long long)m) - 1 : -1;
   }
-  __device__ bool any_flag(int f, int b) const { return __ballot(v >= 0 && (v & f) != 0 && lane() < b) != 0ull; }
-  __device__ int count_nonneg(int lim) const { return __popcll(__ballot(v >= 0 && lane() < lim)); }
+  __device__ bool any_flag(int f, int b) const { return (__ballot(v >= 0 && (v & f) != 0) & below(b)) != 0ull; }
+  __device__ int count_nonneg(int lim) const { return __popcll(__ballot(v >= 0) & below(lim)); }
   __device__ void remove2(int lo, int hi, int b) {
     const int i = lane();
     const int src = i < lo ? i : (i + 1 < hi ? i + 1 : i + 2);

@@ -254,9 +254,12 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
   }
 }
 
+// Waves per workgroup: the LDS slots of 2^10-entry registers (8.3 KB per
+// wavefront) fill a CU's 160 KB best in workgroups of two (18 wavefronts; four
+// per workgroup leave room for only 16).
 template <typename Real, int CAP, bool BF3>
 static int launch_wave_t(const SweepArgs& a, hipStream_t s) {
-  constexpr int WPB = 4;
+  constexpr int WPB = CAP >= 10 ? 2 : 4;
   const size_t smem = WPB * wave_slot_bytes<Real, CAP>();
   if (smem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_wave_kernel<Real, CAP, WPB, BF3>),
