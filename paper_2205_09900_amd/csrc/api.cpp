@@ -203,6 +203,7 @@ static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
 }
 
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
+constexpr int LR_BIG_SLOTS = 32;   // widest pairs of a batch with a slot of their own
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
 
@@ -308,7 +309,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   a.cap_bits = 0;
   a.min_bits = -1;
   profile_launch_begin(KCLASS_HBM, s);
-  rc = launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, s);
+  rc = launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, nullptr, 0, 0, s);
   profile_launch_end(KCLASS_HBM, 8.0 * dp.hdr.macs * (double)num_pairs, s);
   return rc;
 }
@@ -486,13 +487,29 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   };
   if (count[4] > 0) {
     if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
-    // as many slots as the workspace holds (fewer slots only lower the parallelism)
-    const int64_t slot_bytes = hbm_slot_bytes(max_peak, c.elem);
-    int64_t slots = slot_count(max_peak, c.elem, count[4]);
-    const int64_t avail = ((int64_t)c.ws_bytes - (int64_t)c.fixed_bytes) / slot_bytes;
+    // Two sizes of slot: the few widest pairs (at most LR_BIG_SLOTS, the first
+    // of the class) get one slot each of the largest width; the workgroups'
+    // slots only need the width of the rest, so many more of them fit.
+    const int64_t pool_bytes = (int64_t)c.ws_bytes - (int64_t)c.fixed_bytes;
+    int sb = max_peak;
+    for (int t = j.cap_bits + 1; t < max_peak; ++t)
+      if (above[t + 1] <= LR_BIG_SLOTS) {
+        sb = t;
+        break;
+      }
+    int64_t nbig = sb < max_peak ? above[sb + 1] : 0;
+    if (nbig * hbm_slot_bytes(max_peak, c.elem) + hbm_slot_bytes(sb, c.elem) > pool_bytes) {
+      sb = max_peak;  // no room for both sizes: one size, fewer slots
+      nbig = 0;
+    }
+    const int64_t big_bytes = nbig * hbm_slot_bytes(max_peak, c.elem);
+    // as many workgroup slots as the workspace holds (fewer only lower the parallelism)
+    const int64_t slot_bytes = hbm_slot_bytes(sb, c.elem);
+    int64_t slots = slot_count(sb, c.elem, count[4]);  // one per workgroup, also those that take big pairs
+    const int64_t avail = (pool_bytes - big_bytes) / slot_bytes;
     if (avail < 1)
       return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
-                       c.fixed_bytes + (size_t)slot_bytes, max_peak);
+                       c.fixed_bytes + (size_t)(big_bytes + slot_bytes), max_peak);
     if (slots > avail) slots = avail;
     hipStream_t sc = s;
     if (slot_of[4] >= 0) rc = side(slot_of[4], &sc);
@@ -504,7 +521,9 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     ac.order = order + first[4];
     ac.num_pairs = count[4];
     profile_launch_begin(KCLASS_HBM, sc);
-    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, c.w + c.fixed_bytes, max_peak, (int)slots, sc);
+    unsigned char* pool = c.w + c.fixed_bytes;
+    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, pool, sb, (int)slots, pool + slots * slot_bytes, max_peak,
+                          (int)nbig, sc);
     profile_launch_end(KCLASS_HBM, 8.0 * host.macs[4], sc);
     if (rc) return rc;
   }

@@ -80,9 +80,11 @@ struct OrderJob {
 int launch_order_pairs(const OrderJob& j, hipStream_t s);
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
-// Slots of num_slots * hbm_slot_bytes(slot_bits, element bytes): 2^slot_bits entries each.
+// Slots of num_slots * hbm_slot_bytes(slot_bits, element bytes): 2^slot_bits entries each, one per
+// workgroup; the first nbig pairs of the launch (its widest, the pairs being ordered by decreasing
+// width) use big_slots instead, nbig * hbm_slot_bytes(big_bits, element bytes).
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
-                     int slot_bits, int num_slots, hipStream_t s);
+                     int slot_bits, int num_slots, void* big_slots, int big_bits, int nbig, hipStream_t s);
 inline int64_t hbm_slot_bytes(int bits, int elem) { return (int64_t)elem << bits; }
 int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s);
 int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s);

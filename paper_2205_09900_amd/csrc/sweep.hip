@@ -297,10 +297,11 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         expo += pend;
         pend = 0;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
+        const int ng = 1 << (b - 2);
         if (in_lds)
-          gate_any<Real, NT, U, BF3>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
+          gate_any<Real, NT, U, BF3>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
         else
-          gate_any<Real, NT, U, BF3>(H, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
+          gate_any<Real, NT, U, BF3>(H, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
       } else if (type == OP_BELL) {
         if (!in_lds) {
           bell_op<Real, NT, U, false>(H, H, b, lane);
@@ -345,9 +346,13 @@ constexpr size_t hbm_lds_bytes() {
   return (size_t)sizeof(Cplx<Real>) << hbm_lds_bits<Real>();
 }
 
+// Slots: pair ranks below nbig (the widest pairs, which come first) use big
+// slot `rank` of 2^big_bits entries; the others use the workgroup's slot of
+// 2^slot_bits entries.
 template <typename Real, int NT, bool BF3>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter,
-                                                       unsigned char* slots, int slot_bits) {
+                                                       unsigned char* slots, int slot_bits, unsigned char* big_slots,
+                                                       int big_bits, int nbig) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
   __shared__ long long next;
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
   __shared__ uint2 ops_s[64];
   const int lane = threadIdx.x;
   Cplx<Real>* L = reinterpret_cast<Cplx<Real>*>(smem_raw);
-  Cplx<Real>* H = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
+  Cplx<Real>* const own = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
   for (;;) {
     if (lane == 0) next = (long long)atomicAdd(counter, 1ull);
     __syncthreads();
@@ -366,7 +371,9 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
     const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
     if (hdr->status != 0 || hdr->peak_bits <= a.cap_bits) continue;
     double* out = a.trace + 2 * (a.trace_offset + pidx);
-    if (hdr->peak_bits > slot_bits) {
+    const bool big = pi < nbig;
+    Cplx<Real>* H = big ? reinterpret_cast<Cplx<Real>*>(big_slots) + ((int64_t)pi << big_bits) : own;
+    if (hdr->peak_bits > (big ? big_bits : slot_bits)) {
       if (lane == 0) {
         out[0] = __builtin_nan("");
         out[1] = __builtin_nan("");
@@ -508,21 +515,26 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
 
 template <typename Real, bool BF3>
 static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, void* slots, int slot_bits, int num_slots,
-                         hipStream_t s) {
+                         void* big_slots, int big_bits, int nbig, hipStream_t s) {
   const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
-  hipLaunchKernelGGL(k, dim3(num_slots), dim3(HBM_NT), smem, s, a, counter, (unsigned char*)slots, slot_bits);
+  hipLaunchKernelGGL(k, dim3(num_slots), dim3(HBM_NT), smem, s, a, counter, (unsigned char*)slots, slot_bits,
+                     (unsigned char*)big_slots, big_bits, nbig);
 }
 
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
-                     int slot_bits, int num_slots, hipStream_t s) {
+                     int slot_bits, int num_slots, void* big_slots, int big_bits, int nbig, hipStream_t s) {
   if (a.num_pairs <= 0 || num_slots <= 0) return FP_OK;
-  if (precision == FP_C128) launch_hbm_t<double, false>(a, counter, slots, slot_bits, num_slots, s);
-  else if (a.bf3) launch_hbm_t<float, true>(a, counter, slots, slot_bits, num_slots, s);
-  else launch_hbm_t<float, false>(a, counter, slots, slot_bits, num_slots, s);
+  if (nbig > 0 && !big_slots) return set_error(FP_EINVAL, "big slots missing");
+  if (precision == FP_C128)
+    launch_hbm_t<double, false>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
+  else if (a.bf3)
+    launch_hbm_t<float, true>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
+  else
+    launch_hbm_t<float, false>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
   return check_launch("sweep_hbm");
 }
 
