@@ -160,6 +160,25 @@ def test_local_random_all_classes_vs_dense(fp, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_local_random_hbm_slot_sizes_vs_dense(fp, prec):
+    # 96 pairs of 8 qubits, 40 steps: 51 of them need more than 2^14 entries;
+    # the widest 23 (2^18 .. 2^22) get a full-size slot each and the others
+    # share the workgroups' 2^16-entry slots, so both slot sizes are in use
+    n, s, npairs, seed = 8, 40, 96, 4343
+    pairs = sampler.sample_pairs(1, n, s, seed, 0, npairs)
+    peaks = []
+    for u, v in pairs:
+        bu = np.array([b for b, _ in u["gates"]], np.int32)
+        bv = np.array([b for b, _ in v["gates"]], np.int32)
+        peaks.append(fp.fp_plan_local_random_host(n, bu, bv)["peak_bits"])
+    peaks = np.array(peaks)
+    assert (peaks > 14).sum() > 32 and 0 < (peaks > 16).sum() <= 32 and peaks.max() > 18
+    got = gpu_traces(fp, (1, n, s), npairs, seed, prec)
+    want = oracle_traces(1, n, s, seed, npairs, prec)
+    assert floored_err(got, want) <= TOL[prec], floored_err(got, want)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_wide_circuits_vs_mpo(fp, prec):
     cases = [(0, 20, 3, 6), (1, 50, 50, 4), (2, 40, 2, 6), (1, 30, 60, 3)]
     for ansatz, n, d, npairs in cases:
