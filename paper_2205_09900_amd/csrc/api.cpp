@@ -134,16 +134,19 @@ int get_brickwork_plan(int n, int depth, DevPlan* out) {
 }
 
 // ---- auxiliary streams: the sweep classes of one batch touch disjoint pairs
-// and run side by side (all streams at the default priority) --------------------
+// and run side by side (all streams at the default priority).  Each caller
+// stream has its own set, so batches issued on different streams do not queue
+// behind each other's long sweeps. ----------------------------------------------
 static std::mutex g_aux_mu;
-static std::map<int, Aux> g_aux;
+static std::map<std::pair<int, hipStream_t>, Aux> g_aux;
 
-int get_aux(Aux* out) {
+int get_aux(Aux* out, hipStream_t caller) {
   int dev = 0;
   int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
   if (rc) return rc;
   std::lock_guard<std::mutex> lk(g_aux_mu);
-  auto it = g_aux.find(dev);
+  const auto key = std::make_pair(dev, caller);
+  auto it = g_aux.find(key);
   if (it != g_aux.end()) {
     *out = it->second;
     return FP_OK;
@@ -156,7 +159,7 @@ int get_aux(Aux* out) {
   }
   rc = check_hip(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming), "hipEventCreate");
   if (rc) return rc;
-  g_aux[dev] = a;
+  g_aux[key] = a;
   *out = a;
   return FP_OK;
 }
@@ -568,7 +571,7 @@ int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precisi
   for (int i = 0; i < NUM_AUX; ++i) c.used[i] = false;
   if (!ws || ws_bytes < c.fixed_bytes)
     return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", c.fixed_bytes);
-  int rc = get_aux(&c.aux);
+  int rc = get_aux(&c.aux, s);
   if (rc) return rc;
   int64_t chunks = num_pairs / LR_MIN_CHUNK;
   if (chunks < 1) chunks = 1;

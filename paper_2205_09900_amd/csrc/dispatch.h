@@ -16,7 +16,7 @@ struct DevPlan {
   PlanHeader* dhdr = nullptr;
 };
 
-constexpr int NUM_AUX = 3;  // side streams; with the caller's stream within 4 hardware queues
+constexpr int NUM_AUX = 3;  // side streams per caller stream
 struct Aux {
   hipStream_t s[NUM_AUX];
   hipEvent_t fork, join[NUM_AUX];
@@ -25,7 +25,7 @@ struct Aux {
 int check_ensemble(const fp_ensemble_t* e);
 int check_precision(int p);
 int get_brickwork_plan(int n, int depth, DevPlan* out);
-int get_aux(Aux* out);
+int get_aux(Aux* out, hipStream_t caller);  // side streams of the caller's stream
 int lds_bits_max(int precision);
 int tile_pairs(int tile);
 double hea_flops_per_pair(int n, int L);

@@ -229,7 +229,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
   if (!rc) rc = check_hip(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
   if (rc) return rc;
   Aux aux;
-  rc = get_aux(&aux);
+  rc = get_aux(&aux, s);
   if (rc) return rc;
   rc = check_hip(hipEventRecord(aux.fork, s), "fork");
   if (rc) return rc;
