@@ -281,16 +281,17 @@ def main():
                     for c, v in prof.items() if v["launches"]}
 
     per_depth = {}
+    depth_steps = max(4, args.steps)  # batches per depth, two in flight as in the headline
     if args.per_depth:
         for s in [int(x) for x in args.per_depth.split(",") if x]:
-            r = run_workload(fp, torch, args.n, s, args.pairs, prec, max(2, args.steps // 2), 1, seed_base)
+            r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base)
             flops = sum(r["prof"][c]["flops"] for c in SWEEP_CLASSES)
             kms = sum(r["prof"][c]["ms"] for c in SWEEP_CLASSES)
             per_depth[str(s)] = {
-                "contractions_per_s": args.pairs * max(2, args.steps // 2) / r["wall_s"],
+                "contractions_per_s": args.pairs * depth_steps / r["wall_s"],
                 "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
                 "F": r["F"], "SE": r["SE"],
-                "kernel_ms_per_step": {k: v["ms"] / max(2, args.steps // 2) for k, v in r["prof"].items()
+                "kernel_ms_per_step": {k: v["ms"] / depth_steps for k, v in r["prof"].items()
                                        if v["launches"]},
             }
             try:
