@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-suite", action="store_true", help="skip the other ensembles (brickwork n=6, n=20; HEA n=30)")
     ap.add_argument("--suite-pairs", type=int, default=100000)
     ap.add_argument("--cv-surrogate", type=int, default=1000000)
+    ap.add_argument("--serial", action="store_true",
+                    help="time one batch at a time only (the profiling runs use it so that their kernel "
+                         "durations are those the roofline divides by)")
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for PMC runs)")
     return ap.parse_args()
@@ -253,16 +256,20 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    head = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base)
-    value = args.pairs * args.steps / head["wall_s"]
     serial = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, 1, seed_base,
                           pipeline=False)
+    head = serial if args.serial else run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps,
+                                                   args.warmup, seed_base)
+    value = args.pairs * args.steps / head["wall_s"]
     prof = head["prof"]
     # roofline of the sweep kernel with the largest event time (the sweeps
     # hold the method's arithmetic; planning, matrix preparation and sampling
-    # are listed in step_kernels_ms)
-    dom = max(SWEEP_CLASSES, key=lambda c: prof[c]["ms"])
-    d = prof[dom]
+    # are listed in step_kernels_ms), timed in the run with one batch at a
+    # time: with two batches in flight a kernel's events also span the other
+    # batch's work on the GPU (that duration is reported beside it)
+    sprof = serial["prof"]
+    dom = max(SWEEP_CLASSES, key=lambda c: sprof[c]["ms"])
+    d = sprof[dom]
     peak = PEAK_FP32_TFLOPS if prec == fp.C64 else PEAK_FP64_TFLOPS
     achieved = (d["flops"] / d["launches"]) / (d["ms"] / d["launches"] * 1e-3) / 1e12 if d["launches"] else 0.0
     kname = LR_KERNELS[dom].format(r="float" if prec == fp.C64 else "double",
@@ -275,6 +282,8 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic, "kernel": kname, "kernel_class": dom,
                 "kernel_ms_per_launch": d["ms"] / max(1, d["launches"]),
+                "kernel_ms_per_launch_two_in_flight": prof[dom]["ms"] / max(1, prof[dom]["launches"]),
+                "timed_in": "the run with one batch at a time (serial_ms_per_step)",
                 "flops_per_launch": d["flops"] / max(1, d["launches"])}
     step_kernels = {c: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                         "gflop_per_step": v["flops"] / args.steps / 1e9, "gb_per_step": v["bytes"] / args.steps / 1e9}
