@@ -206,9 +206,22 @@ static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
 }
 
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
-constexpr int LR_BIG_SLOTS = 32;   // widest pairs of a batch with a slot of their own
+constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at most
+constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
+constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
-constexpr int64_t POOL_BUDGET = (int64_t)16 << 30;
+constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;
+
+// compute units of the current device (workgroups of one wave of the HBM-slot sweep)
+static int num_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return n;
+}
 
 static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
   int64_t per = hbm_slot_bytes(bits, elem);
@@ -241,7 +254,7 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
       *out = 0;
       return FP_OK;
     }
-    if (hp.hdr.peak_bits > 34) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
+    if (hp.hdr.peak_bits > 31) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
     int64_t slots = slot_count(hp.hdr.peak_bits, elem, num_pairs);
     *out = (size_t)(256 + slots * hbm_slot_bytes(hp.hdr.peak_bits, elem));
     return FP_OK;
@@ -250,7 +263,7 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
   LrLayout l = lr_layout(e->n_qubits, G, precision);
   const int bits = lr_predicted_bits(e->n_qubits, e->depth);
   int64_t pool = 0;
-  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
+  if (bits > LR_SMALL_BITS) pool = HELP_AREA_BYTES + slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
   *out = (size_t)(lr_fixed_bytes(num_pairs, l) + pool);
   return FP_OK;
 }
@@ -301,7 +314,8 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
     profile_launch_end(kc, 8.0 * dp.hdr.macs * (double)num_pairs, s);
     return rc;
   }
-  // HBM slots
+  // HBM slots (32-bit entry indices: registers up to 2^31 entries)
+  if (peak > 31) return set_error(FP_ETOOBIG, "boundary of %d bits", peak);
   const int64_t slots = slot_count(peak, elem, num_pairs);
   const size_t need = (size_t)(256 + slots * hbm_slot_bytes(peak, elem));
   if (!ws || ws_bytes < need)
@@ -312,7 +326,11 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   a.cap_bits = 0;
   a.min_bits = -1;
   profile_launch_begin(KCLASS_HBM, s);
-  rc = launch_sweep_hbm(a, precision, counter, (unsigned char*)ws + 256, peak, (int)slots, nullptr, 0, 0, s);
+  SlotArgs sl;
+  int width[512];
+  for (int k = 0; k < (int)slots; ++k) width[k] = peak;
+  make_slot_args(&sl, (unsigned char*)ws + 256, width, (int)slots, false, elem);
+  rc = launch_sweep_hbm(a, precision, counter, sl, (int)slots, s);
   profile_launch_end(KCLASS_HBM, 8.0 * dp.hdr.macs * (double)num_pairs, s);
   return rc;
 }
@@ -333,6 +351,7 @@ struct LrCtx {
   int64_t num_pairs;     // whole batch
   Aux aux;
   bool used[NUM_AUX];
+  int hbm_slot;  // stream of the HBM class (-2: none yet): all chunks share one slot pool
 };
 
 static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) {
@@ -474,6 +493,11 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
         act[y - 1] = t;
       }
     for (int x = 0; x < na; ++x) slot_of[act[x]] = x < 4 ? x - 1 : slot_of[act[3]];
+    // the HBM launches of all chunks go to one stream, which orders their use of the pool
+    if (count[4] > 0) {
+      if (c.hbm_slot == -2) c.hbm_slot = slot_of[4];
+      slot_of[4] = c.hbm_slot;
+    }
   }
   rc = check_hip(hipEventRecord(c.aux.fork, s), "fork");
   if (rc) return rc;
@@ -489,44 +513,73 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     return FP_OK;
   };
   if (count[4] > 0) {
-    if (max_peak > 34) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
-    // Two sizes of slot: the few widest pairs (at most LR_BIG_SLOTS, the first
-    // of the class) get one slot each of the largest width; the workgroups'
-    // slots only need the width of the rest, so many more of them fit.
-    const int64_t pool_bytes = (int64_t)c.ws_bytes - (int64_t)c.fixed_bytes;
-    int sb = max_peak;
-    for (int t = j.cap_bits + 1; t < max_peak; ++t)
-      if (above[t + 1] <= LR_BIG_SLOTS) {
-        sb = t;
-        break;
-      }
-    int64_t nbig = sb < max_peak ? above[sb + 1] : 0;
-    if (nbig * hbm_slot_bytes(max_peak, c.elem) + hbm_slot_bytes(sb, c.elem) > pool_bytes) {
-      sb = max_peak;  // no room for both sizes: one size, fewer slots
-      nbig = 0;
+    // 32-bit entry indices: registers up to 2^31 entries
+    if (max_peak > 31) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
+    // Slot j has the width of the class's j-th widest pair (see SlotArgs).
+    // As many owners as fit the pool, up to 512; the first HELP_MAX slots
+    // get a second slot for shared TRACE ops when that keeps at least half
+    // of the owners.  Fewer owners than compute units: the rest only help.
+    const int64_t pool_bytes = (int64_t)c.ws_bytes - (int64_t)c.fixed_bytes - HELP_AREA_BYTES;
+    const int wmax = count[4] < LR_MAX_OWNERS ? (int)count[4] : LR_MAX_OWNERS;
+    int width[LR_MAX_OWNERS];
+    for (int r = 0, b = PLAN_HIST - 1; r < wmax; ++r) {
+      const int64_t pos = first[4] + r;  // position in the whole order (decreasing width)
+      while (b > 0 && above[b] <= pos) --b;
+      width[r] = b;
     }
-    const int64_t big_bytes = nbig * hbm_slot_bytes(max_peak, c.elem);
-    // as many workgroup slots as the workspace holds (fewer only lower the parallelism)
-    const int64_t slot_bytes = hbm_slot_bytes(sb, c.elem);
-    int64_t slots = slot_count(sb, c.elem, count[4]);  // one per workgroup, also those that take big pairs
-    const int64_t avail = (pool_bytes - big_bytes) / slot_bytes;
-    if (avail < 1)
+    unsigned char* help_area = c.w + c.fixed_bytes;
+    unsigned char* pool = help_area + HELP_AREA_BYTES;
+    SlotArgs sl;
+    auto fits = [&](int w, bool alt) {
+      make_slot_args(&sl, pool, width, w, alt, c.elem);
+      return slot_args_entries(sl) * c.elem <= pool_bytes;
+    };
+    auto largest = [&](bool alt) {  // most owners that fit (0: none)
+      int lo = 0, hi = wmax;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (fits(mid, alt)) lo = mid;
+        else hi = mid - 1;
+      }
+      return lo;
+    };
+    const int w0 = largest(false);
+    if (w0 < 1) {
+      make_slot_args(&sl, pool, width, 1, false, c.elem);
       return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
-                       c.fixed_bytes + (size_t)(big_bytes + slot_bytes), max_peak);
-    if (slots > avail) slots = avail;
+                       c.fixed_bytes + (size_t)(HELP_AREA_BYTES + slot_args_entries(sl) * c.elem), max_peak);
+    }
+    const int w1 = largest(true);
+    const bool alt = w1 >= 1 && 2 * w1 >= w0;
+    const int owners = alt ? w1 : w0;
+    fits(owners, alt);  // leaves sl at the chosen layout
+    // pairs with a register of 2^LR_HELP_BITS entries or more (the first of the class)
+    int64_t wide_pairs = 0;
+    for (int b = LR_HELP_BITS; b < PLAN_HIST; ++b) wide_pairs += host.hist[b];
+    // helpers-only workgroups where the pool, not the pairs, leaves compute units free
+    int extra = 0;
+    if (wide_pairs > 0 && owners < wmax) {
+      extra = num_cus() - owners;
+      extra = extra < 0 ? 0 : extra > LR_HELPERS ? LR_HELPERS : extra;
+    }
+    const int grid = owners + extra;
     hipStream_t sc = s;
     if (slot_of[4] >= 0) rc = side(slot_of[4], &sc);
     if (!rc) rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, sc), "memset counter");
+    if (!rc && wide_pairs > 0) rc = check_hip(hipMemsetAsync(help_area, 0, HELP_AREA_BYTES, sc), "memset help records");
     if (rc) return rc;
     SweepArgs ac = a;
     ac.min_bits = j.cap_bits;
     ac.cap_bits = j.cap_bits;
     ac.order = order + first[4];
     ac.num_pairs = count[4];
+    HelpArgs help;
+    help.recs = (HelpRec*)help_area;
+    help.finished = (unsigned int*)(help_area + HELP_MAX * (int64_t)sizeof(HelpRec));
+    help.help_bits = LR_HELP_BITS;
+    help.wide_pairs = wide_pairs;
     profile_launch_begin(KCLASS_HBM, sc);
-    unsigned char* pool = c.w + c.fixed_bytes;
-    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, pool, sb, (int)slots, pool + slots * slot_bytes, max_peak,
-                          (int)nbig, sc);
+    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, sl, grid, sc, &help);
     profile_launch_end(KCLASS_HBM, 8.0 * host.macs[4], sc);
     if (rc) return rc;
   }
@@ -569,6 +622,7 @@ int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precisi
   c.fixed_bytes = (size_t)lr_fixed_bytes(num_pairs, c.l);
   c.num_pairs = num_pairs;
   for (int i = 0; i < NUM_AUX; ++i) c.used[i] = false;
+  c.hbm_slot = -2;
   if (!ws || ws_bytes < c.fixed_bytes)
     return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", c.fixed_bytes);
   int rc = get_aux(&c.aux, s);

@@ -80,11 +80,56 @@ struct OrderJob {
 int launch_order_pairs(const OrderJob& j, hipStream_t s);
 
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
-// Slots of num_slots * hbm_slot_bytes(slot_bits, element bytes): 2^slot_bits entries each, one per
-// workgroup; the first nbig pairs of the launch (its widest, the pairs being ordered by decreasing
-// width) use big_slots instead, nbig * hbm_slot_bytes(big_bits, element bytes).
-int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
-                     int slot_bits, int num_slots, void* big_slots, int big_bits, int nbig, hipStream_t s);
+// HBM slots of the large-register sweep.  Owner workgroups (blockIdx below
+// `owners`) take pairs from the launch's list in order; the j-th of them to
+// make its first claim gets slot j, which has 2^b entries for the b with
+// ge[b + 1] <= j < ge[b] (ge[b]: slots of at least 2^b entries, non-increasing
+// in b, ge[32] = 0), at entry offset off[b] + (j - ge[b + 1]) * 2^b of base.
+// The list is ordered by decreasing width and slot j is as wide as its j-th
+// pair, so every pair an owner takes fits its slot.  alt (or null) holds a
+// second slot for each j < min(owners, HELP_MAX), at alt_off[b] + (j - ge[b + 1])
+// * 2^b.  Workgroups from `owners` on only help (needs HelpArgs).
+struct SlotArgs {
+  unsigned char* base;
+  unsigned char* alt;
+  int owners;
+  int ge[33];
+  long long off[33];
+  long long alt_off[33];
+};
+
+// Work sharing: owner slots j < min(owners, HELP_MAX) have a task record.
+// While an owner's boundary is in HBM and an op's register has at least
+// 2^help_bits entries, it publishes the op there in chunks (once workgroups
+// without pairs can exist).  Helpers (the workgroups from `owners` on, and a
+// quarter of the owners once the pairs have run out) take chunks until the
+// launch's first wide_pairs pairs, the only ones with such registers, have
+// finished.
+struct HelpRec {
+  unsigned long long claim;    // task number (bits 40..63), chunks (20..39), next unclaimed chunk (0..19)
+  unsigned long long maxbits;  // largest |entry| the helpers wrote (bits of a non-negative double)
+  unsigned int done;           // chunks finished
+  int type, b, p, q, track, chunk_bits, pad;
+  unsigned long long src, dst;  // device addresses of the boundary before and after the op
+  unsigned long long mat[32];   // realigned GATE matrix, pending scale applied (bits of doubles)
+};
+constexpr int HELP_MAX = 32;  // records per launch
+struct HelpArgs {
+  HelpRec* recs;           // HELP_MAX records, zero at launch
+  unsigned int* finished;  // pairs below wide_pairs that have ended, zero at launch
+  long long wide_pairs;    // pairs of the launch with a register of 2^help_bits entries or more (the first)
+  int help_bits;           // smallest register (log2 entries) of a shared op
+};
+constexpr int64_t HELP_AREA_BYTES = HELP_MAX * (int64_t)sizeof(HelpRec) + 256;
+
+// counter: zero at launch.  grid: workgroups (owners, then helpers).
+int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& slots,
+                     int grid, hipStream_t s, const HelpArgs* help = nullptr);
+// Slot layout for `count` slots of non-increasing widths width[0 .. count)
+// (log2 entries) of elem bytes each, from base; with_alt: the second slots
+// follow.  slot_args_entries: entries of both.
+void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int count, bool with_alt, int elem);
+int64_t slot_args_entries(const SlotArgs& sl);
 inline int64_t hbm_slot_bytes(int bits, int elem) { return (int64_t)elem << bits; }
 int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s);
 int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s);

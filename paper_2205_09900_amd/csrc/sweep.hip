@@ -11,6 +11,7 @@
 // float64 scale.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <string.h>
 
 #include "internal.h"
 #include "layout.h"
@@ -100,7 +101,7 @@ constexpr int hbm_lds_bits() {
 // (bits lo < hi of the group index are the gate's bits).
 template <typename Real, int NT, int U, bool BF3>
 __device__ __forceinline__ void gate_rounds(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo, int hi,
-                                            int ip, int iq, int ng, int lane, bool track, Real& lmax) {
+                                            int ip, int iq, int ng, int lane, bool track, Real& lmax, int base = 0) {
   const bool whole = ng % (NT * U) == 0;
   if (U == 1 && (lane & ~63) >= ng) return;
   for (int g0 = 0; g0 < ng; g0 += NT * U) {
@@ -108,7 +109,7 @@ __device__ __forceinline__ void gate_rounds(Cplx<Real>* B, const Real (&Rr)[16],
     int idx[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int g = (g0 + lane + u * NT) & (ng - 1);
+      const int g = base + ((g0 + lane + u * NT) & (ng - 1));
       idx[u] = insert_zero(insert_zero(g, lo), hi);
       v[u][0] = B[idx[u]];
       v[u][1] = B[idx[u] + ip];
@@ -153,22 +154,23 @@ __device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], co
 }
 
 // BELL from b to b + 2 bits: dst[k + 3s] = src[k], dst[k + s] = dst[k + 2s] = 0
-// (s = 2^b), and dst[k] = src[k] when the boundary moves (COPY).
+// (s = 2^b), and dst[k] = src[k] when the boundary moves (COPY); entries
+// k = base .. base + n - 1.
 template <typename Real, int NT, int U, bool COPY>
-__device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int s, int lane) {
-  const bool whole = s % (NT * U) == 0;
-  if (U == 1 && (lane & ~63) >= s) return;
+__device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int s, int lane, int n, int base) {
+  const bool whole = n % (NT * U) == 0;
+  if (U == 1 && (lane & ~63) >= n) return;
   Cplx<Real> z;
   z.x = (Real)0;
   z.y = (Real)0;
-  for (int k0 = 0; k0 < s; k0 += NT * U) {
+  for (int k0 = 0; k0 < n; k0 += NT * U) {
     Cplx<Real> v[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = src[(k0 + lane + u * NT) & (s - 1)];
+    for (int u = 0; u < U; ++u) v[u] = src[base + ((k0 + lane + u * NT) & (n - 1))];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = k0 + lane + u * NT;
-      if (whole || k < s) {
+      const int k = base + k0 + lane + u * NT;
+      if (whole || k0 + lane + u * NT < n) {
         if (COPY) dst[k] = v[u];
         dst[k + s] = z;
         dst[k + 2 * s] = z;
@@ -187,7 +189,7 @@ __device__ __forceinline__ void bell_op(const Cplx<Real>* src, Cplx<Real>* dst, 
       return;
     }
   }
-  bell_rounds<Real, NT, U, COPY>(src, dst, s, lane);
+  bell_rounds<Real, NT, U, COPY>(src, dst, s, lane, s, 0);
 }
 
 // TRACE over bits p < q of a 2^b register: dst[j] = src[i0] + src[i0 + 2^p + 2^q],
@@ -197,7 +199,7 @@ __device__ __forceinline__ void bell_op(const Cplx<Real>* src, Cplx<Real>* dst, 
 // earlier ones wrote.  The barriers are reached by every lane.
 template <typename Real, int NT, int U, bool INPLACE>
 __device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int nout, int p, int q, int lane,
-                                             bool track, Real& lmax) {
+                                             bool track, Real& lmax, int base = 0) {
   const int step = (1 << p) + (1 << q);
   const bool whole = nout % (NT * U) == 0;
   const bool idle = U == 1 && (lane & ~63) >= nout;  // wavefront-uniform
@@ -206,7 +208,7 @@ __device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* 
     if (!idle) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i0 = insert_zero(insert_zero((j0 + lane + u * NT) & (nout - 1), p), q);
+        const int i0 = insert_zero(insert_zero(base + ((j0 + lane + u * NT) & (nout - 1)), p), q);
         const Cplx<Real> a0 = src[i0], a1 = src[i0 + step];
         acc[u].x = a0.x + a1.x;
         acc[u].y = a0.y + a1.y;
@@ -219,7 +221,7 @@ __device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int j = j0 + lane + u * NT;
-        if (whole || j < nout) dst[j] = acc[u];
+        if (whole || j < nout) dst[base + j] = acc[u];
       }
     }
     if (INPLACE && j0 + NT * U < nout) __syncthreads();  // the last round ends at the op's barrier
@@ -239,14 +241,156 @@ __device__ __forceinline__ void trace_op(const Cplx<Real>* src, Cplx<Real>* dst,
   trace_rounds<Real, NT, U, INPLACE>(src, dst, nout, p, q, lane, track, lmax);
 }
 
+// ---- work sharing among workgroups (widest pairs) ----
+// Publication follows release/acquire at device scope: the owner fences its
+// boundary writes and the record before it opens a task, a helper fences
+// after claiming a chunk (before reading) and after writing it (before
+// counting it done), and the owner fences after the count is complete.  Every
+// wait is bounded: an owner waits only for chunks that running helpers hold,
+// and helpers leave once every pair with a record has finished.
+constexpr int HELP_WAIT_POLLS = 1 << 20;  // owner: polls for its helpers' chunks (each sleeps; about a second)
+constexpr int HELP_IDLE_POLLS = 1 << 21;  // helper: polls that found no open task (a few seconds)
+
+__device__ __forceinline__ unsigned long long claim_word(unsigned seq, unsigned nch) {
+  return ((unsigned long long)seq << 40) | ((unsigned long long)nch << 20);
+}
+__device__ __forceinline__ unsigned claim_next(unsigned long long w) { return (unsigned)(w & 0xFFFFFull); }
+__device__ __forceinline__ unsigned claim_count(unsigned long long w) { return (unsigned)((w >> 20) & 0xFFFFFull); }
+
+template <typename T>
+__device__ __forceinline__ T load_agent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Items base .. base + n - 1 of a shared op (groups of GATE, entries of BELL,
+// outputs of TRACE); BELL stays in place, TRACE goes from src to dst.
+template <typename Real, int NT, int U, bool BF3>
+__device__ __forceinline__ void shared_chunk(int type, int b, int p, int q, bool track, const Real (&Rr)[16],
+                                             const Real (&Ri)[16], Cplx<Real>* src, Cplx<Real>* dst, int base, int n,
+                                             int lane, Real& lmax) {
+  if (type == OP_GATE) {
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    gate_rounds<Real, NT, U, BF3>(src, Rr, Ri, lo, hi, 1 << p, 1 << q, n, lane, track, lmax, base);
+  } else if (type == OP_BELL) {
+    bell_rounds<Real, NT, U, false>(src, src, 1 << b, lane, n, base);
+  } else {
+    trace_rounds<Real, NT, U, false>(src, dst, n, p, q, lane, track, lmax, base);
+  }
+}
+
+// Whether workgroups without a pair may exist: the pair counter (low 32 bits
+// of the claim word) has run out.  Read by one lane and broadcast, so every
+// wavefront takes the same branch.
+__device__ __forceinline__ bool pairs_exhausted(const unsigned long long* counter, long long num_pairs, int lane,
+                                                unsigned long long* sh) {
+  if (lane == 0) sh[1] = (load_agent(counter) & 0xFFFFFFFFull) >= (unsigned long long)num_pairs ? 1ull : 0ull;
+  __syncthreads();
+  const bool r = sh[1] != 0;
+  __syncthreads();
+  return r;
+}
+
+// The owner's side of a shared op, called by every lane of its workgroup.
+// GATE: (Rr, Ri) is the scaled matrix in registers, `mat` the unscaled one in
+// LDS and sc the scale exponent removed from it.  Returns false if the
+// helpers' chunks did not all finish within the wait bound.
+template <typename Real, int NT, int U, bool BF3>
+__device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, int q, bool track,
+                           const Real (&Rr)[16], const Real (&Ri)[16], const Cplx<Real>* mat, int sc,
+                           Cplx<Real>* src, Cplx<Real>* dst, int lane, unsigned long long* sh, Real& lmax) {
+  const int cbits = type == OP_BELL ? b : b - 2;  // log2 of the op's items
+  int chb = cbits - 8;                            // at most 256 chunks of 2^12 .. 2^15 items
+  chb = chb < 12 ? 12 : chb > 15 ? 15 : chb;
+  const unsigned nch = 1u << (cbits - chb);
+  seq = (seq + 1) & 0xFFFFFFu;
+  if (seq == 0) seq = 1;
+  if (type == OP_GATE && lane < 32) {
+    const Cplx<Real> r = mat[lane >> 1];
+    const Real v = ldexp((lane & 1) ? r.y : r.x, -sc);  // the value the owner holds in Rr / Ri
+    rec->mat[lane] = (unsigned long long)__double_as_longlong((double)v);
+  }
+  if (lane == 0) {
+    rec->type = type;
+    rec->b = b;
+    rec->p = p;
+    rec->q = q;
+    rec->track = track ? 1 : 0;
+    rec->chunk_bits = chb;
+    rec->src = (unsigned long long)src;
+    rec->dst = (unsigned long long)dst;
+    rec->maxbits = 0;
+    rec->done = 0;
+  }
+  __threadfence();  // the boundary and the record reach device scope before the task opens
+  __syncthreads();
+  if (lane == 0) __hip_atomic_exchange(&rec->claim, claim_word(seq, nch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned mine = 0;
+  for (;;) {
+    if (lane == 0) sh[0] = atomicAdd(&rec->claim, 1ull);
+    __syncthreads();
+    const unsigned c = claim_next(sh[0]);
+    __syncthreads();
+    if (c >= nch) break;
+    shared_chunk<Real, NT, U, BF3>(type, b, p, q, track, Rr, Ri, src, dst, (int)(c << chb), 1 << chb, lane, lmax);
+    ++mine;
+  }
+  if (lane == 0) {
+    unsigned done = atomicAdd(&rec->done, mine) + mine;
+    for (int polls = 0; done < nch && polls < HELP_WAIT_POLLS; ++polls) {
+      __builtin_amdgcn_s_sleep(2);
+      done = load_agent(&rec->done);
+    }
+    sh[1] = done >= nch ? 1ull : 0ull;
+  }
+  __syncthreads();
+  __threadfence();  // every lane sees the helpers' entries
+  const bool ok = sh[1] != 0;
+  if (track) lmax = fmax(lmax, (Real)__longlong_as_double((long long)load_agent(&rec->maxbits)));
+  __syncthreads();  // sh is reused
+  return ok;
+}
+
+// A helper's chunk of the task in `rec`, claimed with word w.
+template <typename Real, int NT, int U, bool BF3>
+__device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* red, Real* hmat) {
+  __threadfence();  // acquire: the record and the boundary as the owner published them
+  if (lane < 32) hmat[lane] = (Real)__longlong_as_double((long long)load_agent(&rec->mat[lane]));
+  const int type = load_agent(&rec->type), b = load_agent(&rec->b), p = load_agent(&rec->p),
+            q = load_agent(&rec->q), chb = load_agent(&rec->chunk_bits);
+  const bool track = load_agent(&rec->track) != 0;
+  Cplx<Real>* src = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->src));
+  Cplx<Real>* dst = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->dst));
+  __syncthreads();
+  Real Rr[16], Ri[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    Rr[k] = hmat[2 * k];
+    Ri[k] = hmat[2 * k + 1];
+  }
+  Real lmax = 0;
+  shared_chunk<Real, NT, U, BF3>(type, b, p, q, track, Rr, Ri, src, dst, (int)(claim_next(w) << chb), 1 << chb, lane,
+                                 lmax);
+  if (track) {
+    const Real m = group_max<Real, NT>(lmax, red);
+    if (lane == 0) atomicMax(&rec->maxbits, (unsigned long long)__double_as_longlong((double)m));
+  }
+  __threadfence();  // release the chunk's entries before it counts as done
+  __syncthreads();
+  if (lane == 0) atomicAdd(&rec->done, 1u);
+}
+
 template <typename Real, int NT, int U, bool BF3>
 __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cplx<Real>* mats_s, uint2* ops_s,
                                                 const Op* __restrict__ ops, int num_ops, int num_gate_ops,
                                                 const Real* __restrict__ wmat, const int2* __restrict__ wgates,
                                                 const int32_t* __restrict__ factors, const Real* pair_gates, int G,
-                                                int log2_factor, int lane, Real* red, double* tr_re, double* tr_im) {
+                                                int log2_factor, int lane, Real* red, double* tr_re, double* tr_im,
+                                                HelpRec* rec, Cplx<Real>* H2, int help_bits, bool helpers,
+                                                const unsigned long long* counter, long long num_pairs,
+                                                unsigned long long* sh) {
   constexpr int K = 64;  // ops staged per chunk: one per lane of the first wavefront
   constexpr int LB = hbm_lds_bits<Real>();
+  const Real Rr0[16] = {}, Ri0[16] = {};  // matrix argument of shared ops other than GATE (unused)
   int b = 0;
   bool in_lds = true;
   int64_t expo = 0;  // true boundary = stored boundary * 2^expo
@@ -254,6 +398,15 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
   bool prev_track = false;
   int gate_base = 0;  // GATE ops before the chunk (first wavefront only)
   Real lmax = 0;
+  unsigned seq = 0;       // tasks published in rec
+  bool failed = false;    // a shared op was not completed
+  bool exhausted = helpers;  // workgroups that only help exist, or the pair counter has run out
+  // share an op of this pair with idle workgroups (uniform: every input is)
+  auto share = [&](int reg_bits) {
+    if (rec == nullptr || in_lds || reg_bits < help_bits || failed) return false;
+    if (!exhausted) exhausted = pairs_exhausted(counter, num_pairs, lane, sh);
+    return exhausted;
+  };
   if (lane == 0) {
     L[0].x = (Real)1;
     L[0].y = (Real)0;
@@ -300,10 +453,16 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         const int ng = 1 << (b - 2);
         if (in_lds)
           gate_any<Real, NT, U, BF3>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
+        else if (share(b))
+          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_GATE, b, p, q, track, Rr, Ri, mats_s + 16 * i, sc, H,
+                                                  H, lane, sh, lmax);
         else
           gate_any<Real, NT, U, BF3>(H, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
       } else if (type == OP_BELL) {
-        if (!in_lds) {
+        if (!in_lds && share(b + 2)) {
+          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_BELL, b, p, q, false, Rr0, Ri0, mats_s, 0, H, H, lane,
+                                                  sh, lmax);
+        } else if (!in_lds) {
           bell_op<Real, NT, U, false>(H, H, b, lane);
         } else if (b + 2 <= LB) {
           bell_op<Real, NT, U, false>(L, L, b, lane);
@@ -315,6 +474,12 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
       } else if (type == OP_TRACE) {  // p < q
         if (in_lds) {
           trace_op<Real, NT, U, true>(L, L, b, p, q, lane, track, lmax);
+        } else if (b - 2 > LB && H2 != nullptr && share(b)) {  // out of place, into the other buffer
+          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_TRACE, b, p, q, track, Rr0, Ri0, mats_s, 0, H, H2, lane,
+                                                  sh, lmax);
+          Cplx<Real>* t = H;
+          H = H2;
+          H2 = t;
         } else if (b - 2 > LB) {
           trace_op<Real, NT, U, true>(H, H, b, p, q, lane, track, lmax);
         } else {
@@ -337,8 +502,8 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
     }
   }
   const Cplx<Real> v = in_lds ? L[0] : H[0];
-  *tr_re = ldexp((double)v.x, (int)(expo + log2_factor));
-  *tr_im = ldexp((double)v.y, (int)(expo + log2_factor));
+  *tr_re = failed ? __builtin_nan("") : ldexp((double)v.x, (int)(expo + log2_factor));
+  *tr_im = failed ? __builtin_nan("") : ldexp((double)v.y, (int)(expo + log2_factor));
 }
 
 template <typename Real>
@@ -346,52 +511,117 @@ constexpr size_t hbm_lds_bytes() {
   return (size_t)sizeof(Cplx<Real>) << hbm_lds_bits<Real>();
 }
 
-// Slots: pair ranks below nbig (the widest pairs, which come first) use big
-// slot `rank` of 2^big_bits entries; the others use the workgroup's slot of
-// 2^slot_bits entries.
+__device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
+  int b = 31;
+  while (b > 0 && sl.ge[b] <= j) --b;
+  return b;
+}
+
+// Owners take pairs with one atomic on the claim word: the low 32 bits count
+// pairs, the high 32 bits first claims, so the j-th first claim has taken a
+// pair of rank >= j, no wider than slot j.  Every pair below wide_pairs
+// counts in `finished` whatever its path, and helpers leave once all have.
 template <typename Real, int NT, bool BF3>
-__global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter,
-                                                       unsigned char* slots, int slot_bits, unsigned char* big_slots,
-                                                       int big_bits, int nbig) {
+__global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl,
+                                                       HelpArgs h) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
-  __shared__ long long next;
+  __shared__ unsigned long long next;
   __shared__ __align__(16) Cplx<Real> mats[16 * 64];
   __shared__ uint2 ops_s[64];
+  __shared__ unsigned long long sh[2];
+  __shared__ Real hmat[32];
+  constexpr int U = hbm_u<Real, BF3>();
   const int lane = threadIdx.x;
+  const int nrec = h.recs == nullptr ? 0 : sl.owners < HELP_MAX ? sl.owners : HELP_MAX;
+  const bool helpers = nrec > 0 && (int)gridDim.x > sl.owners;  // workgroups that only help
   Cplx<Real>* L = reinterpret_cast<Cplx<Real>*>(smem_raw);
-  Cplx<Real>* const own = reinterpret_cast<Cplx<Real>*>(slots) + ((int64_t)blockIdx.x << slot_bits);
-  for (;;) {
-    if (lane == 0) next = (long long)atomicAdd(counter, 1ull);
-    __syncthreads();
-    const long long pi = next;
-    __syncthreads();
-    if (pi >= a.num_pairs) break;
-    const int64_t pidx = a.order ? (int64_t)a.order[pi] : (int64_t)pi;
-    const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
-    if (hdr->status != 0 || hdr->peak_bits <= a.cap_bits) continue;
-    double* out = a.trace + 2 * (a.trace_offset + pidx);
-    const bool big = pi < nbig;
-    Cplx<Real>* H = big ? reinterpret_cast<Cplx<Real>*>(big_slots) + ((int64_t)pi << big_bits) : own;
-    if (hdr->peak_bits > (big ? big_bits : slot_bits)) {
-      if (lane == 0) {
-        out[0] = __builtin_nan("");
-        out[1] = __builtin_nan("");
+  if ((int)blockIdx.x < sl.owners) {
+    Cplx<Real>* S = nullptr;
+    Cplx<Real>* A = nullptr;
+    HelpRec* rec = nullptr;
+    int sbits = -1;
+    for (;;) {
+      if (lane == 0) next = atomicAdd(counter, sbits < 0 ? (1ull << 32) + 1ull : 1ull);
+      __syncthreads();
+      const unsigned long long w = next;
+      __syncthreads();
+      if (sbits < 0) {  // first claim: this workgroup's slot
+        const int j = (int)(w >> 32);
+        const int b = slot_bits_of(sl, j);
+        const long long k = (long long)(j - sl.ge[b + 1]) << b;
+        sbits = b;
+        S = reinterpret_cast<Cplx<Real>*>(sl.base) + sl.off[b] + k;
+        if (j < nrec) {
+          rec = h.recs + j;
+          if (sl.alt != nullptr) A = reinterpret_cast<Cplx<Real>*>(sl.alt) + sl.alt_off[b] + k;
+        }
       }
+      const long long pi = (long long)(w & 0xFFFFFFFFull);
+      if (pi >= a.num_pairs) break;
+      const int64_t pidx = a.order ? (int64_t)a.order[pi] : (int64_t)pi;
+      const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
+      if (hdr->status == 0 && hdr->peak_bits > a.cap_bits) {
+        double* out = a.trace + 2 * (a.trace_offset + pidx);
+        if (hdr->peak_bits > sbits) {
+          if (lane == 0) {
+            out[0] = __builtin_nan("");
+            out[1] = __builtin_nan("");
+          }
+        } else {
+          const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
+          const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
+          double re, im;
+          run_program_big<Real, NT, U, BF3>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+                                            hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
+                                            a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red,
+                                            &re, &im, rec, A, h.help_bits, helpers, counter, a.num_pairs, sh);
+          if (lane == 0) {
+            out[0] = re;
+            out[1] = im;
+          }
+        }
+      }
+      if (nrec > 0 && pi < h.wide_pairs && lane == 0) atomicAdd(h.finished, 1u);
+      __syncthreads();
+    }
+  }
+  // a quarter of the owners stay to help (with the helpers-only workgroups,
+  // enough to saturate HBM); the others free their compute unit
+  if (nrec == 0 || ((int)blockIdx.x < sl.owners && (blockIdx.x & 3) != 0)) return;
+  // helping: take a chunk of any open task, starting from a record that
+  // depends on the workgroup, until every pair of the launch has finished
+  for (int idle = 0;;) {
+    if (lane < 64) {
+      const unsigned long long cw = lane < nrec ? load_agent(&h.recs[lane].claim) : 0ull;
+      const bool open = (cw >> 40) != 0 && claim_next(cw) < claim_count(cw);
+      const unsigned long long m = __ballot(open);
+      unsigned long long got = 0, flag = 0;  // flag: 1 + record, or 1 << 32 to leave
+      if (m != 0) {
+        const int st = (int)(blockIdx.x % (unsigned)nrec);
+        const unsigned long long from = m & (~0ull << st);
+        const int r = __ffsll((long long)(from != 0 ? from : m)) - 1;
+        if (lane == r) got = atomicAdd(&h.recs[r].claim, 1ull);
+        got = __shfl(got, r, 64);
+        if (claim_next(got) < claim_count(got)) flag = 1 + (unsigned long long)r;
+      } else if (idle >= HELP_IDLE_POLLS || load_agent(h.finished) >= (unsigned long long)h.wide_pairs) {
+        flag = 1ull << 32;
+      }
+      if (lane == 0) {
+        sh[0] = got;
+        sh[1] = flag;
+      }
+    }
+    __syncthreads();
+    const unsigned long long w = sh[0], flag = sh[1];
+    __syncthreads();
+    if (flag >> 32) break;
+    if (flag == 0) {
+      ++idle;
+      __builtin_amdgcn_s_sleep(8);
       continue;
     }
-    const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
-    const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
-    double re, im;
-    run_program_big<Real, NT, hbm_u<Real, BF3>(), BF3>(L, H, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
-                                                  hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
-                                                  a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane,
-                                                  red, &re, &im);
-    if (lane == 0) {
-      out[0] = re;
-      out[1] = im;
-    }
-    __syncthreads();
+    help_chunk<Real, NT, U, BF3>(h.recs + (flag - 1), w, lane, red, hmat);
   }
 }
 
@@ -514,27 +744,60 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
 }
 
 template <typename Real, bool BF3>
-static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, void* slots, int slot_bits, int num_slots,
-                         void* big_slots, int big_bits, int nbig, hipStream_t s) {
+static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, const SlotArgs& sl, int grid,
+                         const HelpArgs& h, hipStream_t s) {
   const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
-  hipLaunchKernelGGL(k, dim3(num_slots), dim3(HBM_NT), smem, s, a, counter, (unsigned char*)slots, slot_bits,
-                     (unsigned char*)big_slots, big_bits, nbig);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(HBM_NT), smem, s, a, counter, sl, h);
 }
 
-int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, void* slots,
-                     int slot_bits, int num_slots, void* big_slots, int big_bits, int nbig, hipStream_t s) {
-  if (a.num_pairs <= 0 || num_slots <= 0) return FP_OK;
-  if (nbig > 0 && !big_slots) return set_error(FP_EINVAL, "big slots missing");
+void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int count, bool with_alt, int elem) {
+  memset(sl, 0, sizeof(*sl));
+  sl->base = base;
+  sl->owners = count;
+  for (int b = 0; b <= 32; ++b) {
+    int c = 0;
+    while (c < count && width[c] >= b) ++c;  // widths do not increase
+    sl->ge[b] = b == 32 ? 0 : c;
+  }
+  const int nalt = with_alt ? (count < HELP_MAX ? count : HELP_MAX) : 0;
+  long long off = 0, aoff = 0;
+  for (int b = 31; b >= 0; --b) {
+    sl->off[b] = off;
+    sl->alt_off[b] = aoff;
+    const int lo = sl->ge[b + 1], hi = sl->ge[b];
+    off += (long long)(hi - lo) << b;
+    const int alo = lo < nalt ? lo : nalt, ahi = hi < nalt ? hi : nalt;
+    aoff += (long long)(ahi - alo) << b;
+  }
+  sl->off[32] = off;       // entries of the slots
+  sl->alt_off[32] = aoff;  // entries of the second slots, which follow them
+  sl->alt = nalt > 0 ? base + off * elem : nullptr;
+}
+
+int64_t slot_args_entries(const SlotArgs& sl) { return sl.off[32] + (sl.alt != nullptr ? sl.alt_off[32] : 0); }
+
+int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl, int grid,
+                     hipStream_t s, const HelpArgs* help) {
+  if (a.num_pairs <= 0 || sl.owners <= 0) return FP_OK;
+  if (a.num_pairs >= (1ll << 31)) return set_error(FP_EINVAL, "too many pairs for one launch");
+  HelpArgs h = {nullptr, nullptr, 0, 0};
+  if (help != nullptr && help->recs != nullptr && help->wide_pairs > 0) {
+    // chunks of at least 2^12 items: GATE and TRACE registers from 2^14 entries, BELL inputs from 2^14
+    if (!help->finished || help->help_bits < 16 || help->wide_pairs > a.num_pairs)
+      return set_error(FP_EINVAL, "bad work-sharing arguments");
+    h = *help;
+  }
+  if (grid < sl.owners || (grid > sl.owners && h.recs == nullptr)) return set_error(FP_EINVAL, "bad HBM grid");
   if (precision == FP_C128)
-    launch_hbm_t<double, false>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
+    launch_hbm_t<double, false>(a, counter, sl, grid, h, s);
   else if (a.bf3)
-    launch_hbm_t<float, true>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
+    launch_hbm_t<float, true>(a, counter, sl, grid, h, s);
   else
-    launch_hbm_t<float, false>(a, counter, slots, slot_bits, num_slots, big_slots, big_bits, nbig, s);
+    launch_hbm_t<float, false>(a, counter, sl, grid, h, s);
   return check_launch("sweep_hbm");
 }
 

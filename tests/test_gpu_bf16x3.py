@@ -69,3 +69,14 @@ def test_bf16x3_local_random_n50(fp):
     r = rel_errors(got, ref)
     assert np.isfinite(got).all()
     assert np.median(r) <= 5e-4 and r.max() <= 3e-2, (float(np.median(r)), float(r.max()))
+
+
+def test_bf16x3_shared_wide_ops_vs_dense(fp):
+    """96 pairs of 8 qubits at 40 steps (the batch of the two-slot-size test):
+    the widest pairs run their ops on registers from 2^18 entries as chunks
+    shared among workgroups, here with the BF16x3 products."""
+    ens, n, seed = (1, 8, 40), 96, 4343
+    got = traces(fp, ens, n, seed, BF16X3)
+    want = dense.traces(sampler.sample_pairs(1, 8, 40, seed, 0, n, fp32=True))
+    r = rel_errors(got, want)
+    assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (float(np.median(r)), float(r.max()))

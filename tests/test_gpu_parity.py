@@ -163,7 +163,9 @@ def test_local_random_all_classes_vs_dense(fp, prec):
 def test_local_random_hbm_slot_sizes_vs_dense(fp, prec):
     # 96 pairs of 8 qubits, 40 steps: 51 of them need more than 2^14 entries;
     # the widest 23 (2^18 .. 2^22) get a full-size slot each and the others
-    # share the workgroups' 2^16-entry slots, so both slot sizes are in use
+    # share the workgroups' 2^16-entry slots, so both slot sizes are in use;
+    # the widest also split their ops on registers from 2^18 entries into
+    # chunks that the workgroups done with their own pairs take over
     n, s, npairs, seed = 8, 40, 96, 4343
     pairs = sampler.sample_pairs(1, n, s, seed, 0, npairs)
     peaks = []
