@@ -44,8 +44,12 @@ def parse():
     ap.add_argument("--pairs", type=int, default=10000)
     ap.add_argument("--n", type=int, default=50)
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--per-depth", default="50,100,150,200",
+    ap.add_argument("--per-depth", default="50,100,150,200,250",
                     help="comma list of step counts measured besides the headline ('' = none)")
+    ap.add_argument("--feasibility", default=",".join(str(x) for x in range(50, 801, 50)),
+                    help="comma list of step counts whose register widths are reported ('' = none)")
+    ap.add_argument("--feasibility-pairs", type=int, default=0,
+                    help="pairs sampled per step count (0: a whole batch up to 400 steps, 2000 beyond)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate experiment (HEA n=40, L=6)")
@@ -186,18 +190,45 @@ def suite(fp, torch, np, synth, pairs):
     return out
 
 
-def bits_stats(fp, np, n, depth, pairs, seed_base, sample=400):
-    """Boundary sizes of a sample of the workload (host planner on the bonds)."""
-    ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
-    g = fp.sample(ens, sample, seed_base | (depth << 32), 0, fp.C64).view(sample, -1).cpu().numpy()
-    off = 2 * depth * 32 * 4
-    peaks = []
-    for p in range(sample):
-        b = np.frombuffer(g[p, off: off + 8 * depth].tobytes(), dtype=np.int32).reshape(2, depth)
-        peaks.append(fp.fp_plan_local_random_host(n, b[0], b[1])["peak_bits"])
-    peaks = np.array(peaks)
-    return {"median_bits": int(np.median(peaks)), "p99_bits": int(np.quantile(peaks, 0.99)),
-            "max_bits": int(peaks.max()), "sample_pairs": sample}
+LR_MAX_BITS = 31  # widest register of the HBM-slot sweep: 2^31 entries (32-bit entry indices)
+
+
+def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
+    """Widest register of each pair in a sample per depth (the product's sampler
+    and host planner on the sampled bonds), and the fraction of pairs beyond
+    what one pair may take: 2^31 entries, and one slot of that width within
+    the workspace the library asks for a batch of `pairs`.  The sample is a
+    whole batch where the tail decides (a batch fits only if its widest pair
+    does), smaller where most pairs are beyond anyway."""
+    elem = 8 if prec == fp.C64 else 16
+    out = {}
+    for s in depths:
+        sample = sample_arg or (pairs if s <= 400 else min(pairs, 2000))
+        ens = fp.Ensemble(fp.LOCAL_RANDOM, n, s)
+        off = 2 * s * 32 * 4  # bonds follow the complex64 gates of U and V
+        peaks = []
+        for first in range(0, sample, 1000):
+            cnt = min(1000, sample - first)
+            g = fp.sample(ens, cnt, seed_base | (s << 32), first, fp.C64).view(cnt, -1)
+            bonds = g[:, off: off + 8 * s].cpu().numpy()
+            del g
+            for p in range(cnt):
+                b = np.frombuffer(bonds[p].tobytes(), dtype=np.int32).reshape(2, s)
+                peaks.append(fp.fp_plan_local_random_host(n, b[0], b[1])["peak_bits"])
+        pk = np.array(peaks)
+        ws = fp.fp_workspace_bytes(ens, pairs, prec)
+        budget = min(LR_MAX_BITS, int(math.floor(math.log2(ws / elem))))
+        over = float(np.mean(pk > budget))
+        top = int(pk.max())
+        out[str(s)] = {
+            "median_bits": int(np.quantile(pk, 0.5)), "p90_bits": int(np.quantile(pk, 0.9)),
+            "p99_bits": int(np.quantile(pk, 0.99)), "max_bits": top, "sample_pairs": sample,
+            "budget_bits": budget, "workspace_gib": ws / 2**30, "over_budget_frac": over,
+            "status": "fits" if over == 0 else
+                      f"infeasible: {over:.1%} of the sample need more than 2^{budget} entries per register "
+                      f"(widest 2^{top} = {elem * 2.0 ** top / 2**30:.3g} GiB)",
+        }
+    return out
 
 
 def _cpu_worker(args):
@@ -303,10 +334,20 @@ def main():
                 "kernel_ms_per_step": {k: v["ms"] / depth_steps for k, v in r["prof"].items()
                                        if v["launches"]},
             }
-            try:
-                per_depth[str(s)].update(bits_stats(fp, np, args.n, s, args.pairs, seed_base, sample=200))
-            except Exception as e:  # statistics only
-                per_depth[str(s)]["bits_error"] = str(e)
+
+    # register widths per depth, and which depths a batch fits: contractions/s
+    # only where measured above, every other depth named with what it needs
+    feas = {}
+    if args.feasibility:
+        feas = feasibility(fp, np, args.n, [int(x) for x in args.feasibility.split(",") if x], args.pairs, prec,
+                           seed_base, args.feasibility_pairs)
+        for k, v in feas.items():
+            if k in per_depth:
+                v["contractions_per_s"] = per_depth[k]["contractions_per_s"]
+                v["status"] = "measured" if v["over_budget_frac"] == 0 else v["status"]
+                per_depth[k].update({q: v[q] for q in ("median_bits", "p99_bits", "max_bits")})
+            elif v["over_budget_frac"] == 0:
+                v["status"] = "fits, not timed"
 
     suite_res = None
     if not args.no_suite:
@@ -344,6 +385,7 @@ def main():
         "step_kernels_ms": step_kernels,
         "cpu_baseline": cpu,
         "per_depth": per_depth,
+        "feasibility": feas,
         "control_variate": cv_res,
         "ensembles": suite_res,
     }
