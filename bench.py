@@ -8,7 +8,10 @@ contract Tr(U^dagger V) for every pair, reduce F^(k), k = 1..3 (the reduction
 returns the estimates to the host, which ends the step).  Two batches are in
 flight on two streams: the next batch is sampled and planned while the
 current one is swept (serial_ms_per_step reports the same steps one at a
-time).  Inputs are synthetic and seeded.
+time).  The headline run has no per-launch HIP events (they cost time of
+their own); kernel durations, the roofline and the step breakdown come from
+runs with events (ms_per_step_with_events, serial_ms_per_step).  Inputs are
+synthetic and seeded.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 """
@@ -43,6 +46,7 @@ def parse():
     ap.add_argument("--depth", type=int, default=100, help="steps per circuit of the headline workload")
     ap.add_argument("--pairs", type=int, default=10000)
     ap.add_argument("--n", type=int, default=50)
+    ap.add_argument("--in-flight", type=int, default=2, help="batches in flight (streams) in the timed runs")
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
     ap.add_argument("--per-depth", default="50,100,150,200,250",
                     help="comma list of step counts measured besides the headline ('' = none)")
@@ -64,19 +68,33 @@ def parse():
     return ap.parse_args()
 
 
-def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True):
-    """Times `steps` batches.  Pipelined: two streams with their own gate, trace
-    and workspace buffers; batch i+1 is sampled and contracted (its planning
-    waits only for its own plans) before batch i's reduction is awaited, so
-    consecutive batches overlap on the device.  Every batch is sampled,
-    contracted and reduced exactly once inside the timed region."""
+_STREAMS = []
+
+
+def bench_streams(torch, k):
+    """The first k of the streams every run uses: created once, so that all
+    runs see the same streams (the library keeps side streams per caller
+    stream, and hardware queues are shared among all streams)."""
+    while len(_STREAMS) < k:
+        _STREAMS.append(torch.cuda.Stream())
+    return _STREAMS[:k]
+
+
+def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True, in_flight=2,
+                 profile=True):
+    """Times `steps` batches.  Pipelined: `in_flight` streams with their own
+    gate, trace and workspace buffers; batches i+1 .. i+in_flight-1 are
+    sampled and contracted (each contraction waits only for its own plans)
+    before batch i's reduction is awaited, so consecutive batches overlap on
+    the device.  Every batch is sampled, contracted and reduced exactly once
+    inside the timed region."""
     ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
-    nbuf = 2 if pipeline else 1
+    nbuf = in_flight if pipeline else 1
     gates = [fp.alloc_gates(ens, pairs, prec) for _ in range(nbuf)]
     trace = [torch.empty(2 * pairs, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     wsb = fp.fp_workspace_bytes(ens, pairs, prec)
     ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda") for _ in range(nbuf)]
-    streams = [torch.cuda.Stream() for _ in range(nbuf)] if pipeline else [torch.cuda.current_stream()]
+    streams = bench_streams(torch, nbuf)
     seed = seed_base | (depth << 32)
 
     def launch(i):
@@ -91,10 +109,11 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     def run(first, count):
         f = None
         if pipeline:
-            launch(first)
+            for i in range(first, min(first + count, first + nbuf - 1)):
+                launch(i)
             for i in range(first, first + count):
-                if i + 1 < first + count:
-                    launch(i + 1)
+                if i + nbuf - 1 < first + count:
+                    launch(i + nbuf - 1)
                 f = finish(i)
         else:
             for i in range(first, first + count):
@@ -104,12 +123,13 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
 
     run(0, warmup)
     torch.cuda.synchronize()
-    fp.fp_profile_begin()
+    if profile:  # HIP events around every launch (they cost time of their own)
+        fp.fp_profile_begin()
     t0 = time.perf_counter()
     f = run(warmup, steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = fp.fp_profile_end()
+    prof = fp.fp_profile_end() if profile else None
     return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb}
 
 
@@ -287,12 +307,20 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # the step with one batch at a time, every launch timed with HIP events
+    # (roofline and step breakdown); the same with batches in flight; and the
+    # headline: batches in flight without events
     serial = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, 1, seed_base,
                           pipeline=False)
-    head = serial if args.serial else run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps,
-                                                   args.warmup, seed_base)
+    if args.serial:
+        head = timed = serial
+    else:
+        timed = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base,
+                             in_flight=args.in_flight)
+        head = run_workload(fp, torch, args.n, args.depth, args.pairs, prec, args.steps, args.warmup, seed_base,
+                            in_flight=args.in_flight, profile=False)
     value = args.pairs * args.steps / head["wall_s"]
-    prof = head["prof"]
+    prof = timed["prof"]
     # roofline of the sweep kernel with the largest event time (the sweeps
     # hold the method's arithmetic; planning, matrix preparation and sampling
     # are listed in step_kernels_ms), timed in the run with one batch at a
@@ -324,11 +352,15 @@ def main():
     depth_steps = max(4, args.steps)  # batches per depth, two in flight as in the headline
     if args.per_depth:
         for s in [int(x) for x in args.per_depth.split(",") if x]:
-            r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base)
+            r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base,
+                             in_flight=args.in_flight)
+            r0 = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base,
+                              in_flight=args.in_flight, profile=False)
             flops = sum(r["prof"][c]["flops"] for c in SWEEP_CLASSES)
             kms = sum(r["prof"][c]["ms"] for c in SWEEP_CLASSES)
             per_depth[str(s)] = {
-                "contractions_per_s": args.pairs * depth_steps / r["wall_s"],
+                "contractions_per_s": args.pairs * depth_steps / r0["wall_s"],
+                "contractions_per_s_with_events": args.pairs * depth_steps / r["wall_s"],
                 "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
                 "F": r["F"], "SE": r["SE"],
                 "kernel_ms_per_step": {k: v["ms"] / depth_steps for k, v in r["prof"].items()
@@ -372,6 +404,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": head["wall_s"] / args.steps * 1e3,
+        "ms_per_step_with_events": timed["wall_s"] / args.steps * 1e3,
         "serial_ms_per_step": serial["wall_s"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -380,7 +413,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"local_random_n{args.n}_S{args.depth}", "n_qubits": args.n,
                    "steps_per_circuit": args.depth, "pairs_per_step": args.pairs, "k_max": 3,
-                   "precision": args.precision, "batches_in_flight": 2, "F_k": head["F"], "SE_k": head["SE"]},
+                   "precision": args.precision, "batches_in_flight": args.in_flight, "F_k": head["F"], "SE_k": head["SE"]},
         "roofline": roofline,
         "step_kernels_ms": step_kernels,
         "cpu_baseline": cpu,

@@ -146,8 +146,19 @@ int fp_workspace_bytes(const fp_ensemble_t* ens, int64_t num_pairs, int precisio
  * j+1 that connect to both neighbouring bonds, and in FP_C64 it is rescaled
  * by a power of two after every column with the exponent kept in float64.
  * d_trace receives 2*num_pairs doubles (re, im of pair i at 2i, 2i+1).
- * Errors: FP_EINVAL, FP_ETOOBIG (workspace too small or a boundary beyond
- * the limits; fp_workspace_bytes reports the size), FP_ENOTIMPL, FP_EDEVICE.
+ * Local random pairs are planned on the device (each pair's network differs)
+ * and the launches that follow are derived there from the plans.  Outside
+ * stream capture the call then waits for the planning of its batch (not for
+ * its sweeps) to size each launch exactly; while
+ * `stream` is being captured it does not wait, and the captured launches
+ * take their pairs from the device's plan whatever their size (sizes from
+ * the last uncaptured call of the same ensemble).  Either way a pair that
+ * cannot be contracted (its plan exceeds the planner's limits, a register
+ * beyond 2^31 entries, or no room in the workspace for it) gets a NaN trace,
+ * which fp_frame_potential reports as FP_ENUMERIC.  No pair is dropped.
+ * Errors: FP_EINVAL, FP_ETOOBIG (workspace too small for the plans, or, for
+ * fixed topologies, a boundary beyond the limits; fp_workspace_bytes reports
+ * the size), FP_ENOTIMPL, FP_EDEVICE.
  */
 int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int precision,
                             const void* d_gates, double* d_trace, void* d_workspace,

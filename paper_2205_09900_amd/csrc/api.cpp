@@ -186,23 +186,26 @@ static LrLayout lr_layout(int n, int G, int precision) {
 }
 
 // Local random workspace: LR_CHUNKS chunk headers of LR_HEAD bytes (zeroed
-// per chunk), then the pair order (int32 per pair), the per-pair plans and
-// the HBM slots.  Chunk header:
+// per chunk up to the set-up), then the pair order (int32 per pair), the
+// per-pair plans, the work-sharing records and the HBM slots.  Chunk header:
 //   +0   int max_peak, num_large, num_failed
 //   +16  double class MACs[5]
 //   +64  uint64 counter of the HBM launch
 //   +128 int hist[PLAN_HIST]   pairs per peak width
 //   +384 int cursor[PLAN_HIST] fill counters of the ordering pass
-constexpr int64_t LR_HEAD = 1024;
+//   +1024 LrDev  launch set-up written on the device
+constexpr int64_t LR_HEAD = 4096;
+constexpr int64_t LR_DEV_OFF = 1024;
+static_assert(LR_DEV_OFF + (int64_t)sizeof(LrDev) <= LR_HEAD, "set-up fits the chunk header");
 constexpr int LR_CHUNKS = 4;
-constexpr int64_t LR_STATS_BYTES = 128 + 4 * PLAN_HIST;
 // Pairs per chunk at least: a chunk must fill the device by itself (planning
 // and the large classes are latency-bound per pair), so only batches far
 // larger than one wave of the device are split.
 constexpr int64_t LR_MIN_CHUNK = 65536;
 
+// ... one work-sharing area of the HBM-slot sweep per chunk, then its slot pool
 static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
-  return LR_CHUNKS * LR_HEAD + pad64(4 * num_pairs) + num_pairs * l.per_pair;
+  return LR_CHUNKS * LR_HEAD + pad64(4 * num_pairs) + num_pairs * l.per_pair + LR_CHUNKS * HELP_AREA_BYTES;
 }
 
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
@@ -211,17 +214,6 @@ constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on re
 constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;
-
-// compute units of the current device (workgroups of one wave of the HBM-slot sweep)
-static int num_cus() {
-  int dev = 0, n = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      n <= 0) {
-    (void)hipGetLastError();
-    return 256;
-  }
-  return n;
-}
 
 static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
   int64_t per = hbm_slot_bytes(bits, elem);
@@ -263,7 +255,7 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
   LrLayout l = lr_layout(e->n_qubits, G, precision);
   const int bits = lr_predicted_bits(e->n_qubits, e->depth);
   int64_t pool = 0;
-  if (bits > LR_SMALL_BITS) pool = HELP_AREA_BYTES + slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
+  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
   *out = (size_t)(lr_fixed_bytes(num_pairs, l) + pool);
   return FP_OK;
 }
@@ -335,9 +327,53 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   return rc;
 }
 
-// One chunk of a local random batch: plan its pairs (on s), order them by
-// peak width, and launch the sweep classes on the side streams, which s does
-// not wait for here, so the next chunk's planning overlaps this chunk's sweep.
+// Launch sizes for local random batches under stream capture: the class
+// sizes of the last eager batch of the same ensemble (per pair of the batch).
+// The captured sweeps take their pairs through counters, so any size is
+// correct; a hint keeps the launches close to the work, which lets the
+// dispatcher interleave the classes as it does with one workgroup per pair.
+struct LrHint {
+  double frac[5];  // class sizes per pair of the batch
+  int hbm_workgroups;
+};
+static std::mutex g_hint_mu;
+static std::map<long long, LrHint> g_hints;
+
+static long long hint_key(const fp_ensemble_t* e, int precision) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return ((long long)dev << 48) | ((long long)e->n_qubits << 32) | ((long long)e->depth << 4) | precision;
+}
+
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // unknown: behave as under capture
+  }
+  return st != hipStreamCaptureStatusNone;
+}
+
+static bool lr_hint(long long key, LrHint* out) {
+  std::lock_guard<std::mutex> lk(g_hint_mu);
+  auto it = g_hints.find(key);
+  if (it == g_hints.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+static void lr_hint_set(long long key, const LrDev& d, int64_t np) {
+  LrHint h;
+  for (int k = 0; k < 5; ++k) h.frac[k] = (double)d.range[k][1] / (double)np;
+  h.hbm_workgroups = d.hbm_workgroups;
+  std::lock_guard<std::mutex> lk(g_hint_mu);
+  g_hints[key] = h;
+}
+
+// One chunk of a local random batch: plan its pairs (on s), derive its
+// launches on the device, order the pairs by peak width, and launch the
+// sweep classes, most on side streams that s does not wait for here, so the
+// next chunk's planning overlaps this chunk's sweep.
 struct LrCtx {
   const fp_ensemble_t* e;
   int precision, elem;
@@ -351,7 +387,8 @@ struct LrCtx {
   int64_t num_pairs;     // whole batch
   Aux aux;
   bool used[NUM_AUX];
-  int hbm_slot;  // stream of the HBM class (-2: none yet): all chunks share one slot pool
+  long long key;  // grid hints
+  int hbm_slot;   // eager: stream of the HBM class (-2: none yet); all chunks share one slot pool
 };
 
 static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) {
@@ -394,7 +431,8 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   j.wmat_stride = l.mat;
   j.bf3 = c.precision == FP_BF16X3 ? 1 : 0;
   static_assert(sizeof(PlanHeader) <= 64, "plan header fits its slot");
-  int rc = check_hip(hipMemsetAsync(hw, 0, LR_HEAD, s), "memset counters");
+  LrDev* dev = (LrDev*)(hw + LR_DEV_OFF);
+  int rc = launch_zero_words(hw, LR_DEV_OFF / 4, s);  // counters, histogram, cursors (the set-up writes dev)
   if (rc) return rc;
   // algorithmic bytes: the planner reads the bond lists and writes the plans;
   // the preparation reads the gate buffer and writes one matrix per GATE op
@@ -407,21 +445,32 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   rc = launch_gate_matrices(j, c.precision, s);
   profile_launch_end(KCLASS_PREP, 0.0, s, gate_bytes + (double)np * (double)l.mat);
   if (rc) return rc;
-  struct {
-    int v[4];
-    double macs[5];
-    unsigned char unused[128 - 56];
-    int hist[PLAN_HIST];
-  } host;
-  static_assert(sizeof(host) == LR_STATS_BYTES, "stats layout");
-  rc = check_hip(hipMemcpyAsync(&host, counters, sizeof(host), hipMemcpyDeviceToHost, s), "copy plan stats");
-  if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
+  // Launches derived on the device from the planner's width histogram.  A
+  // pair that cannot be contracted (a failed plan, a register beyond 2^31
+  // entries, no room in the pool) gets a NaN trace.
+  unsigned char* help_area = c.w + c.fixed_bytes - (LR_CHUNKS - chunk) * HELP_AREA_BYTES;
+  LrSetupJob sj;
+  memset(&sj, 0, sizeof(sj));
+  sj.hist = hist;
+  sj.tiny_bits = j.tiny_bits;
+  sj.small_bits = j.small_bits;
+  sj.mid_bits = j.mid_bits;
+  sj.cap_bits = j.cap_bits;
+  sj.pool = c.w + c.fixed_bytes;
+  sj.pool_bytes = (long long)c.ws_bytes - (long long)c.fixed_bytes;
+  sj.elem_shift = c.elem == 16 ? 4 : 3;
+  sj.max_owners = LR_MAX_OWNERS;
+  sj.max_helpers = LR_HELPERS;
+  sj.num_cus = device_cus();
+  sj.help_bits = LR_HELP_BITS;
+  sj.recs = (HelpRec*)help_area;
+  sj.hbm_counter = hbm_counter;
+  sj.dev = dev;
+  rc = launch_lr_setup(sj, s);
   if (rc) return rc;
-  const int max_peak = host.v[0], num_failed = host.v[2];
-  if (num_failed > 0) return set_error(FP_ETOOBIG, "%d pair(s) could not be planned", num_failed);
   // Order the pairs by decreasing peak width, so that every class below is
-  // one contiguous range of the order and each launch starts with its
-  // costliest pairs.
+  // one contiguous range of the order and each class takes its costliest
+  // pairs first.
   OrderJob oj;
   memset(&oj, 0, sizeof(oj));
   oj.hdr = j.hdr;
@@ -431,19 +480,9 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   oj.order = order;
   oj.trace = c.trace;
   oj.trace_offset = c.trace_offset + p0;
-  int64_t above[PLAN_HIST + 1];  // above[b] = pairs whose peak is >= b
-  above[PLAN_HIST] = 0;
-  for (int b = PLAN_HIST - 1; b >= 0; --b) above[b] = above[b + 1] + host.hist[b];
-  for (int b = 0; b < PLAN_HIST; ++b) oj.first[b] = (int32_t)above[b + 1];
+  oj.first = dev->first;
   rc = launch_order_pairs(oj, s);
   if (rc) return rc;
-  // pairs whose peak lies in (lo, hi]: positions [above[hi + 1], above[lo + 1])
-  auto range_of = [&](int lo, int hi, int64_t* first, int64_t* count) {
-    const int h1 = hi + 1 < PLAN_HIST ? hi + 1 : PLAN_HIST;
-    const int l1 = lo + 1 < 0 ? 0 : (lo + 1 < PLAN_HIST ? lo + 1 : PLAN_HIST);
-    *first = above[h1];
-    *count = above[l1] - above[h1];
-  };
   SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.gates = j.gates;
@@ -462,47 +501,30 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   a.wmat = j.wmat;
   a.wmat_stride = j.wmat_stride;
   a.bf3 = j.bf3;
-  struct Cls {
-    int lo, hi, tile, kclass;
-  };
-  // Classes by the largest boundary of a pair: up to 2^10 entries with one
+  a.order = order;
+  a.num_pairs = np;  // upper bound; each class takes its range from the set-up
+  int64_t dev_first[5] = {0, 0, 0, 0, 0};  // class starts in the order, when read back
+  // Classes by the largest register of a pair: up to 2^10 entries with one
   // wavefront per pair (class 0 stays empty: the VGPRs of the wavefront
   // sweep, not its LDS, bound its occupancy, so one class serves all small
   // registers), up to 2^12 and 2^14 with 256 and 1024 lanes per pair
-  // (boundary in LDS), then HBM slots.  Each class gets its own stream (s or
-  // a side stream), heaviest by planned MACs first.
-  const Cls cls[4] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
+  // (boundary in LDS), then HBM slots, each class on its own stream.
+  struct Cls {
+    int lo, hi, tile, kclass;
+  };
+  const Cls cls[5] = {{-1, j.tiny_bits, TILE_16x16, KCLASS_LDS16},
                       {j.tiny_bits, j.small_bits, TILE_64x4, KCLASS_LDS64},
                       {j.small_bits, j.mid_bits, TILE_256x1, KCLASS_LDS256},
-                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024}};
-  int64_t first[5], count[5];
-  for (int k = 0; k < 4; ++k) {
-    if (cls[k].hi > cls[k].lo) range_of(cls[k].lo, cls[k].hi, &first[k], &count[k]);
-    else first[k] = count[k] = 0;
-  }
-  range_of(j.cap_bits, PLAN_HIST - 1, &first[4], &count[4]);
-  int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
-  {
-    int act[5], na = 0;
-    for (int k = 0; k < 5; ++k)
-      if (count[k] > 0) act[na++] = k;
-    for (int x = 1; x < na; ++x)  // by MACs, heaviest first
-      for (int y = x; y > 0 && host.macs[act[y]] > host.macs[act[y - 1]]; --y) {
-        const int t = act[y];
-        act[y] = act[y - 1];
-        act[y - 1] = t;
-      }
-    for (int x = 0; x < na; ++x) slot_of[act[x]] = x < 4 ? x - 1 : slot_of[act[3]];
-    // the HBM launches of all chunks go to one stream, which orders their use of the pool
-    if (count[4] > 0) {
-      if (c.hbm_slot == -2) c.hbm_slot = slot_of[4];
-      slot_of[4] = c.hbm_slot;
-    }
-  }
+                      {j.mid_bits, j.cap_bits, TILE_1024x1, KCLASS_LDS1024},
+                      {j.cap_bits, PLAN_HIST - 1, 0, KCLASS_HBM}};
   rc = check_hip(hipEventRecord(c.aux.fork, s), "fork");
   if (rc) return rc;
   bool waited[NUM_AUX] = {false, false, false};
   auto side = [&](int ai, hipStream_t* out) -> int {
+    if (ai < 0) {
+      *out = s;
+      return FP_OK;
+    }
     if (!waited[ai]) {
       int r = check_hip(hipStreamWaitEvent(c.aux.s[ai], c.aux.fork, 0), "fork wait");
       if (r) return r;
@@ -512,97 +534,93 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     *out = c.aux.s[ai];
     return FP_OK;
   };
-  if (count[4] > 0) {
-    // 32-bit entry indices: registers up to 2^31 entries
-    if (max_peak > 31) return set_error(FP_ETOOBIG, "a pair needs a %d-bit boundary", max_peak);
-    // Slot j has the width of the class's j-th widest pair (see SlotArgs).
-    // As many owners as fit the pool, up to 512; the first HELP_MAX slots
-    // get a second slot for shared TRACE ops when that keeps at least half
-    // of the owners.  Fewer owners than compute units: the rest only help.
-    const int64_t pool_bytes = (int64_t)c.ws_bytes - (int64_t)c.fixed_bytes - HELP_AREA_BYTES;
-    const int wmax = count[4] < LR_MAX_OWNERS ? (int)count[4] : LR_MAX_OWNERS;
-    int width[LR_MAX_OWNERS];
-    for (int r = 0, b = PLAN_HIST - 1; r < wmax; ++r) {
-      const int64_t pos = first[4] + r;  // position in the whole order (decreasing width)
-      while (b > 0 && above[b] <= pos) --b;
-      width[r] = b;
-    }
-    unsigned char* help_area = c.w + c.fixed_bytes;
-    unsigned char* pool = help_area + HELP_AREA_BYTES;
-    SlotArgs sl;
-    auto fits = [&](int w, bool alt) {
-      make_slot_args(&sl, pool, width, w, alt, c.elem);
-      return slot_args_entries(sl) * c.elem <= pool_bytes;
-    };
-    auto largest = [&](bool alt) {  // most owners that fit (0: none)
-      int lo = 0, hi = wmax;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (fits(mid, alt)) lo = mid;
-        else hi = mid - 1;
-      }
-      return lo;
-    };
-    const int w0 = largest(false);
-    if (w0 < 1) {
-      make_slot_args(&sl, pool, width, 1, false, c.elem);
-      return set_error(FP_ETOOBIG, "workspace of %zu bytes needed (largest boundary %d bits)",
-                       c.fixed_bytes + (size_t)(HELP_AREA_BYTES + slot_args_entries(sl) * c.elem), max_peak);
-    }
-    const int w1 = largest(true);
-    const bool alt = w1 >= 1 && 2 * w1 >= w0;
-    const int owners = alt ? w1 : w0;
-    fits(owners, alt);  // leaves sl at the chosen layout
-    // pairs with a register of 2^LR_HELP_BITS entries or more (the first of the class)
-    int64_t wide_pairs = 0;
-    for (int b = LR_HELP_BITS; b < PLAN_HIST; ++b) wide_pairs += host.hist[b];
-    // helpers-only workgroups where the pool, not the pairs, leaves compute units free
-    int extra = 0;
-    if (wide_pairs > 0 && owners < wmax) {
-      extra = num_cus() - owners;
-      extra = extra < 0 ? 0 : extra > LR_HELPERS ? LR_HELPERS : extra;
-    }
-    const int grid = owners + extra;
-    hipStream_t sc = s;
-    if (slot_of[4] >= 0) rc = side(slot_of[4], &sc);
-    if (!rc) rc = check_hip(hipMemsetAsync(hbm_counter, 0, 8, sc), "memset counter");
-    if (!rc && wide_pairs > 0) rc = check_hip(hipMemsetAsync(help_area, 0, HELP_AREA_BYTES, sc), "memset help records");
-    if (rc) return rc;
-    SweepArgs ac = a;
-    ac.min_bits = j.cap_bits;
-    ac.cap_bits = j.cap_bits;
-    ac.order = order + first[4];
-    ac.num_pairs = count[4];
-    HelpArgs help;
-    help.recs = (HelpRec*)help_area;
-    help.finished = (unsigned int*)(help_area + HELP_MAX * (int64_t)sizeof(HelpRec));
-    help.help_bits = LR_HELP_BITS;
-    help.wide_pairs = wide_pairs;
-    profile_launch_begin(KCLASS_HBM, sc);
-    rc = launch_sweep_hbm(ac, c.precision, hbm_counter, sl, grid, sc, &help);
-    profile_launch_end(KCLASS_HBM, 8.0 * host.macs[4], sc);
-    if (rc) return rc;
-  }
-  for (int k = 3; k >= 0; --k) {
-    if (count[k] <= 0) continue;
-    hipStream_t sx = s;
-    if (slot_of[k] >= 0) {
-      rc = side(slot_of[k], &sx);
-      if (rc) return rc;
-    }
+  auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
+                          double flops) -> int {
+    hipStream_t sx;
+    int r = side(ai, &sx);
+    if (r) return r;
     SweepArgs ax = a;
     ax.min_bits = cls[k].lo;
     ax.cap_bits = cls[k].hi;
-    ax.order = order + first[k];
-    ax.num_pairs = count[k];
+    if (k == 4) {
+      // the HBM sweep contracts the pairs beyond the LDS capacity, and takes
+      // its range (and slots) from the set-up itself: order base, no offset
+      ax.cap_bits = j.cap_bits;
+    } else if (range != nullptr) {  // pairs taken from the device range
+      ax.range = range;
+      ax.claim = &dev->claim[k];
+      ax.grid_pairs = grid_pairs;
+    } else {  // the class's pairs at a known place: one launch slot per pair
+      ax.order = order + dev_first[k];
+      ax.num_pairs = count;
+    }
     profile_launch_begin(cls[k].kclass, sx);
-    // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
-    rc = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
-                         : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
-    profile_launch_end(cls[k].kclass, 8.0 * host.macs[k], sx);
+    if (k == 4)
+      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx);
+    else  // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
+      r = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
+                          : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
+    profile_launch_end(cls[k].kclass, flops, sx);
+    return r;
+  };
+  if (!capturing(s)) {
+    // Eager: read the set-up back (one wait for the plans, as the launch
+    // sizes depend on them), then launch every class at its exact size, the
+    // costliest by planned MACs on s and the HBM class on the same stream in
+    // every chunk (the chunks share its slot pool); launched widest class
+    // first, so their long pairs start first.
+    struct {
+      LrDev d;
+      double macs[5];
+    } h;
+    rc = check_hip(hipMemcpyAsync(&h.d, dev, sizeof(LrDev), hipMemcpyDeviceToHost, s), "copy set-up");
+    if (!rc) rc = check_hip(hipMemcpyAsync(h.macs, j.class_macs, sizeof(h.macs), hipMemcpyDeviceToHost, s), "copy MACs");
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
     if (rc) return rc;
+    lr_hint_set(c.key, h.d, np);
+    for (int k = 0; k < 5; ++k) dev_first[k] = h.d.range[k][0];
+    int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
+    int act[5], na = 0;
+    for (int k = 0; k < 5; ++k)
+      if (h.d.range[k][1] > 0) act[na++] = k;
+    for (int x = 1; x < na; ++x)  // by MACs, heaviest first
+      for (int y = x; y > 0 && h.macs[act[y]] > h.macs[act[y - 1]]; --y) {
+        const int t = act[y];
+        act[y] = act[y - 1];
+        act[y - 1] = t;
+      }
+    for (int x = 0; x < na; ++x) slot_of[act[x]] = x < 4 ? x - 1 : slot_of[act[3]];
+    if (h.d.range[4][1] > 0) {
+      if (c.hbm_slot == -2) c.hbm_slot = slot_of[4];
+      slot_of[4] = c.hbm_slot;
+    }
+    for (int k = 4; k >= 1; --k) {
+      const int64_t count = h.d.range[k][1];
+      if (count <= 0) continue;
+      rc = launch_class(k, slot_of[k], nullptr, count, k == 4 ? h.d.hbm_workgroups : 0, 8.0 * h.macs[k]);
+      if (rc) return rc;
+    }
+    return FP_OK;
   }
-  return FP_OK;
+  // Under stream capture: no waiting.  Every class takes its pairs from the
+  // device range through a counter, so any launch size is correct; the sizes
+  // come from the last eager batch of the ensemble when there was one (else
+  // as many workgroups as stay resident).  The HBM class goes on s, whose
+  // order needs no cross-stream wait, so its long pairs start first.
+  LrHint hint;
+  const bool hinted = lr_hint(c.key, &hint);
+  int grid = LR_MAX_OWNERS + LR_HELPERS;
+  if (hinted) {
+    const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
+    grid = want < grid ? want : grid;
+  }
+  rc = launch_class(4, -1, dev->range[4], 0, grid, 0.0);
+  for (int k = 3; k >= 1 && !rc; --k) {
+    if (cls[k].hi <= cls[k].lo) continue;
+    const int64_t gp = hinted ? (int64_t)(hint.frac[k] * 1.05 * (double)np) + 2 : 0;
+    rc = launch_class(k, k == 1 ? 2 : k - 2, dev->range[k], 0, gp, 0.0);
+  }
+  return rc;
 }
 
 int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
@@ -622,6 +640,7 @@ int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precisi
   c.fixed_bytes = (size_t)lr_fixed_bytes(num_pairs, c.l);
   c.num_pairs = num_pairs;
   for (int i = 0; i < NUM_AUX; ++i) c.used[i] = false;
+  c.key = hint_key(e, precision);
   c.hbm_slot = -2;
   if (!ws || ws_bytes < c.fixed_bytes)
     return set_error(FP_ETOOBIG, "workspace of %zu bytes needed for the plans", c.fixed_bytes);

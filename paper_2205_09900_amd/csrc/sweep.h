@@ -32,6 +32,13 @@ struct SweepArgs {
   const unsigned char* wmat;  // realigned GATE matrices in program order (wave sweep), per pair
   int64_t wmat_stride;        // bytes per pair
   int bf3;                    // float32 storage with BF16x3 products
+  // Pairs given on the device (local random): if range is set, the launch
+  // contracts pairs order[range[0] + i], i < range[1], taken in turn through
+  // the counter *claim (zero at launch) by workgroups (or wavefronts) that
+  // loop until none is left; num_pairs is then only the launch's upper bound.
+  const long long* range;
+  unsigned long long* claim;
+  int64_t grid_pairs;  // with range: pairs the launch is sized for (0: as many workgroups as stay resident)
 };
 
 struct PlanJob {
@@ -75,7 +82,7 @@ struct OrderJob {
   int32_t* order;
   double* trace;
   int64_t trace_offset;
-  int32_t first[PLAN_HIST];
+  const int32_t* first;  // PLAN_HIST first positions (device)
 };
 int launch_order_pairs(const OrderJob& j, hipStream_t s);
 
@@ -125,6 +132,43 @@ constexpr int64_t HELP_AREA_BYTES = HELP_MAX * (int64_t)sizeof(HelpRec) + 256;
 // counter: zero at launch.  grid: workgroups (owners, then helpers).
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& slots,
                      int grid, hipStream_t s, const HelpArgs* help = nullptr);
+
+// Launch set-up of a local random chunk on the device: written by
+// lr_setup_kernel from the planner's statistics and read by the ordering pass
+// and the sweeps, so that the host enqueues the whole chunk without waiting.
+// Classes k = 0..4 as the planner's class MACs: registers up to tiny, small,
+// mid and cap bits, then HBM slots.
+struct LrDev {
+  int32_t first[PLAN_HIST];     // ordering pass: first position of each width
+  long long range[5][2];        // class k: first position in the order and count
+  unsigned long long claim[5];  // class k: pair counter of its sweep (zero after set-up)
+  SlotArgs sl;                  // HBM slots (owners 0: the class's pairs get NaN)
+  HelpArgs help;                // work sharing (recs null: none)
+  int hbm_workgroups;           // owners plus helpers-only workgroups of the HBM launch
+  int status;                   // bit 0: a pair wider than 2^31 entries; bit 1: a pair without room in the pool
+};
+struct LrSetupJob {
+  const int* hist;                 // pairs per peak width (PLAN_HIST)
+  int tiny_bits, small_bits, mid_bits, cap_bits;
+  unsigned char* pool;             // HBM slot pool
+  long long pool_bytes;
+  int elem_shift;                  // log2 of the bytes per complex entry
+  int max_owners, max_helpers, num_cus, help_bits;
+  HelpRec* recs;                   // the chunk's work-sharing area (HELP_AREA_BYTES, cleared here)
+  unsigned long long* hbm_counter; // the chunk's HBM claim word (cleared here)
+  LrDev* dev;
+};
+int launch_lr_setup(const LrSetupJob& j, hipStream_t s);
+// HBM-slot sweep of a local random class set up on the device (launch `grid`
+// workgroups; those beyond dev->hbm_workgroups return at once).
+int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
+                         hipStream_t s);
+// Zero n 32-bit words (a kernel, so that stream capture records no memset node).
+int launch_zero_words(void* p, int64_t n, hipStream_t s);
+// Workgroups of a kernel resident per compute unit (occupancy query, no device work),
+// and the current device's compute units.
+int resident_per_cu(const void* kernel, int block, size_t smem);
+int device_cus();
 // Slot layout for `count` slots of non-increasing widths width[0 .. count)
 // (log2 entries) of elem bytes each, from base; with_alt: the second slots
 // follow.  slot_args_entries: entries of both.

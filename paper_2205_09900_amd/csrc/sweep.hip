@@ -25,15 +25,9 @@ namespace fp {
 // One group of NT lanes per pair, PB pairs per workgroup, boundary in LDS
 // (2^cap_bits complex per pair) next to the staging area of the group.
 // Pairs whose plan needs more are left to the next launch; failed plans give NaN.
-template <typename Real, int NT, int PB, bool BF3>
-__global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ Real red[16];
-  const int slot = threadIdx.x / NT;
-  const int lane = threadIdx.x % NT;
-  const int64_t pi = (int64_t)blockIdx.x * PB + slot;
-  if (pi >= a.num_pairs) return;
-  const int64_t pidx = a.order ? (int64_t)a.order[pi] : pi;
+template <typename Real, int NT, bool BF3>
+__device__ __forceinline__ void lds_pair(const SweepArgs& a, int64_t pidx, int slot, int lane,
+                                         unsigned char* smem_raw, Real* red) {
   const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
   const int status = hdr->status, peak = hdr->peak_bits;
   double* out = a.trace + 2 * (a.trace_offset + pidx);
@@ -59,6 +53,34 @@ __global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
   if (lane == 0) {
     out[0] = re;
     out[1] = im;
+  }
+}
+
+// Pair blockIdx * PB + slot of the launch, or, with a range on the device
+// (one pair per workgroup), pairs taken in turn from its counter until none
+// is left.
+template <typename Real, int NT, int PB, bool BF3>
+__global__ void __launch_bounds__(NT* PB) sweep_lds_kernel(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ Real red[16];
+  __shared__ unsigned long long claimed;
+  const int slot = threadIdx.x / NT;
+  const int lane = threadIdx.x % NT;
+  if (PB > 1 || a.range == nullptr) {
+    const int64_t pi = (int64_t)blockIdx.x * PB + slot;
+    if (pi < a.num_pairs) lds_pair<Real, NT, BF3>(a, a.order ? (int64_t)a.order[pi] : pi, slot, lane, smem_raw, red);
+    return;
+  }
+  const int32_t* order = a.order + a.range[0];
+  const unsigned long long n = (unsigned long long)a.range[1];
+  for (;;) {
+    if (threadIdx.x == 0) claimed = atomicAdd(a.claim, 1ull);
+    __syncthreads();
+    const unsigned long long pi = claimed;
+    __syncthreads();
+    if (pi >= n) break;
+    lds_pair<Real, NT, BF3>(a, (int64_t)order[pi], 0, lane, smem_raw, red);
+    __syncthreads();  // the register and staging area are reused by the next pair
   }
 }
 
@@ -522,8 +544,8 @@ __device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
 // pair of rank >= j, no wider than slot j.  Every pair below wide_pairs
 // counts in `finished` whatever its path, and helpers leave once all have.
 template <typename Real, int NT, bool BF3>
-__global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl,
-                                                       HelpArgs h) {
+__global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl_arg,
+                                                       HelpArgs h_arg, const LrDev* dev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
   __shared__ unsigned long long next;
@@ -533,10 +555,27 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
   __shared__ Real hmat[32];
   constexpr int U = hbm_u<Real, BF3>();
   const int lane = threadIdx.x;
-  const int nrec = h.recs == nullptr ? 0 : sl.owners < HELP_MAX ? sl.owners : HELP_MAX;
-  const bool helpers = nrec > 0 && (int)gridDim.x > sl.owners;  // workgroups that only help
+  // launch arguments, or the set-up the device wrote for this class
+  const SlotArgs& sl = dev != nullptr ? dev->sl : sl_arg;
+  const HelpArgs& h = dev != nullptr ? dev->help : h_arg;
+  const long long np = dev != nullptr ? dev->range[4][1] : a.num_pairs;
+  const int32_t* order = dev != nullptr ? a.order + dev->range[4][0] : a.order;
+  const int wgs = dev != nullptr ? dev->hbm_workgroups : (int)gridDim.x;
+  const int owners = sl.owners;
+  if ((int)blockIdx.x >= wgs) return;
+  if (owners == 0) {  // no slot fits the pool: every pair of the class gets NaN
+    for (long long pi = (long long)blockIdx.x * NT + lane; pi < np; pi += (long long)wgs * NT) {
+      const int64_t pidx = order ? (int64_t)order[pi] : (int64_t)pi;
+      double* out = a.trace + 2 * (a.trace_offset + pidx);
+      out[0] = __builtin_nan("");
+      out[1] = __builtin_nan("");
+    }
+    return;
+  }
+  const int nrec = h.recs == nullptr ? 0 : owners < HELP_MAX ? owners : HELP_MAX;
+  const bool helpers = nrec > 0 && wgs > owners;  // workgroups that only help
   Cplx<Real>* L = reinterpret_cast<Cplx<Real>*>(smem_raw);
-  if ((int)blockIdx.x < sl.owners) {
+  if ((int)blockIdx.x < owners) {
     Cplx<Real>* S = nullptr;
     Cplx<Real>* A = nullptr;
     HelpRec* rec = nullptr;
@@ -558,8 +597,8 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
         }
       }
       const long long pi = (long long)(w & 0xFFFFFFFFull);
-      if (pi >= a.num_pairs) break;
-      const int64_t pidx = a.order ? (int64_t)a.order[pi] : (int64_t)pi;
+      if (pi >= np) break;
+      const int64_t pidx = order ? (int64_t)order[pi] : (int64_t)pi;
       const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
       if (hdr->status == 0 && hdr->peak_bits > a.cap_bits) {
         double* out = a.trace + 2 * (a.trace_offset + pidx);
@@ -575,7 +614,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
           run_program_big<Real, NT, U, BF3>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
                                             hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
                                             a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red,
-                                            &re, &im, rec, A, h.help_bits, helpers, counter, a.num_pairs, sh);
+                                            &re, &im, rec, A, h.help_bits, helpers, counter, np, sh);
           if (lane == 0) {
             out[0] = re;
             out[1] = im;
@@ -588,7 +627,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
   }
   // a quarter of the owners stay to help (with the helpers-only workgroups,
   // enough to saturate HBM); the others free their compute unit
-  if (nrec == 0 || ((int)blockIdx.x < sl.owners && (blockIdx.x & 3) != 0)) return;
+  if (nrec == 0 || ((int)blockIdx.x < owners && (blockIdx.x & 3) != 0)) return;
   // helping: take a chunk of any open task, starting from a record that
   // depends on the workgroup, until every pair of the launch has finished
   for (int idle = 0;;) {
@@ -710,11 +749,19 @@ size_t plan_lds_bytes(int G, int n) {
 template <typename Real, int NT, int PB, bool BF3>
 static int launch_lds_t(const SweepArgs& a, hipStream_t s) {
   const size_t smem = (size_t)PB * ((((size_t)1 << a.cap_bits) * sizeof(Cplx<Real>)) + stage_bytes<Real, NT>());
-  const int64_t blocks = (a.num_pairs + PB - 1) / PB;
+  int64_t blocks = (a.num_pairs + PB - 1) / PB;
   if (smem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_lds_kernel<Real, NT, PB, BF3>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
+  }
+  if (a.range != nullptr) {  // claimed pairs, one per workgroup
+    if (PB > 1) return set_error(FP_EINVAL, "claimed pairs need one pair per workgroup");
+    blocks = a.grid_pairs > 0 ? a.grid_pairs
+                              : (int64_t)resident_per_cu(reinterpret_cast<const void*>(
+                                                             sweep_lds_kernel<Real, NT, PB, BF3>),
+                                                         NT * PB, smem) *
+                                    device_cus();
   }
   hipLaunchKernelGGL((sweep_lds_kernel<Real, NT, PB, BF3>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, a);
   return check_launch("sweep_lds");
@@ -745,13 +792,13 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
 
 template <typename Real, bool BF3>
 static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, const SlotArgs& sl, int grid,
-                         const HelpArgs& h, hipStream_t s) {
+                         const HelpArgs& h, const LrDev* dev, hipStream_t s) {
   const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
-  hipLaunchKernelGGL(k, dim3(grid), dim3(HBM_NT), smem, s, a, counter, sl, h);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(HBM_NT), smem, s, a, counter, sl, h, dev);
 }
 
 void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int count, bool with_alt, int elem) {
@@ -793,12 +840,188 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
   }
   if (grid < sl.owners || (grid > sl.owners && h.recs == nullptr)) return set_error(FP_EINVAL, "bad HBM grid");
   if (precision == FP_C128)
-    launch_hbm_t<double, false>(a, counter, sl, grid, h, s);
+    launch_hbm_t<double, false>(a, counter, sl, grid, h, nullptr, s);
   else if (a.bf3)
-    launch_hbm_t<float, true>(a, counter, sl, grid, h, s);
+    launch_hbm_t<float, true>(a, counter, sl, grid, h, nullptr, s);
   else
-    launch_hbm_t<float, false>(a, counter, sl, grid, h, s);
+    launch_hbm_t<float, false>(a, counter, sl, grid, h, nullptr, s);
   return check_launch("sweep_hbm");
+}
+
+int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
+                         hipStream_t s) {
+  if (grid <= 0) return FP_OK;
+  SlotArgs sl;
+  memset(&sl, 0, sizeof(sl));
+  const HelpArgs h = {nullptr, nullptr, 0, 0};
+  if (precision == FP_C128)
+    launch_hbm_t<double, false>(a, counter, sl, grid, h, dev, s);
+  else if (a.bf3)
+    launch_hbm_t<float, true>(a, counter, sl, grid, h, dev, s);
+  else
+    launch_hbm_t<float, false>(a, counter, sl, grid, h, dev, s);
+  return check_launch("sweep_hbm");
+}
+
+// One wavefront derives a local random chunk's launches from the planner's
+// width histogram: the ordering pass's first positions, the class ranges, and
+// the HBM slots (slot j as wide as the class's j-th widest pair, widths
+// clipped to 2^31 entries; as many owners as the pool holds, up to
+// max_owners; second slots for the first HELP_MAX when that keeps at least
+// half of the owners; helpers-only workgroups where the pool, not the pairs,
+// leaves compute units free).  It also clears the chunk's HBM counter and
+// work-sharing records.  Lane b holds width b; sums over widths are
+// wavefront reductions.
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
+  const int lane = threadIdx.x;
+  LrDev* d = j.dev;
+  // above[b] (lane b): pairs whose peak is at least b, by a suffix scan
+  long long above = j.hist[lane];
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long t = __shfl_down(above, off, 64);
+    if (lane + off < 64) above += t;
+  }
+  auto pos = [&](int b) -> long long {  // above[b], with above[< 0] = all and above[>= 64] = 0
+    const long long v = __shfl(above, b < 0 ? 0 : b > 63 ? 63 : b, 64);
+    return b >= PLAN_HIST ? 0ll : v;
+  };
+  const long long next = __shfl_down(above, 1, 64);
+  d->first[lane] = (int32_t)(lane == 63 ? 0 : next);
+  const int lo[5] = {-1, j.tiny_bits, j.small_bits, j.mid_bits, j.cap_bits};
+  const int hi[5] = {j.tiny_bits, j.small_bits, j.mid_bits, j.cap_bits, PLAN_HIST - 1};
+  long long rf[5], rc[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const bool some = hi[k] > lo[k];
+    const long long a = pos(hi[k] + 1), b = pos(lo[k] + 1);
+    rf[k] = some ? a : 0;
+    rc[k] = some ? b - a : 0;
+  }
+  if (lane < 5) {
+    d->range[lane][0] = rf[lane];
+    d->range[lane][1] = rc[lane];
+    d->claim[lane] = 0;
+  }
+  // the chunk's HBM counter and work-sharing records start at zero
+  for (int i = lane; i < (int)(HELP_AREA_BYTES / 8); i += 64) reinterpret_cast<unsigned long long*>(j.recs)[i] = 0ull;
+  if (lane == 0) *j.hbm_counter = 0ull;
+  // HBM class: lane b < 32 holds ge_all[b], class pairs of clipped width >= b
+  const long long count = rc[4];
+  const int wmax = count < j.max_owners ? (int)count : j.max_owners;
+  const long long pa = pos(lane), pa1 = pos(lane + 1);
+  const long long ge = lane >= 32 ? 0 : lane <= j.cap_bits + 1 ? count : pa;
+  const long long ge1 = lane >= 31 ? 0 : lane + 1 <= j.cap_bits + 1 ? count : pa1;
+  const long long pool_entries = j.pool_bytes > 0 ? j.pool_bytes >> j.elem_shift : 0;
+  // entries of w slots, plus second slots for the first HELP_MAX of them
+  auto entries = [&](int w, bool alt) {
+    const long long na = alt ? (w < HELP_MAX ? w : HELP_MAX) : 0;
+    const long long g0 = ge < w ? ge : w, g1 = ge1 < w ? ge1 : w;
+    const long long a0 = g0 < na ? g0 : na, a1 = g1 < na ? g1 : na;
+    return wave_sum_ll(lane < 32 ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
+  };
+  auto largest = [&](bool alt) {
+    int l = 0, h = wmax;
+    while (l < h) {
+      const int m = (l + h + 1) / 2;
+      if (entries(m, alt) <= pool_entries) l = m;
+      else h = m - 1;
+    }
+    return l;
+  };
+  int owners = 0;
+  bool alt = false;
+  if (count > 0) {
+    const int w0 = largest(false);
+    const int w1 = largest(true);
+    alt = w1 >= 1 && 2 * w1 >= w0;
+    owners = alt ? w1 : w0;
+  }
+  // slot layout: ge, then offsets from the widest down (the sums above b, by a suffix scan)
+  const int g0 = (int)(ge < owners ? ge : owners), g1 = (int)(ge1 < owners ? ge1 : owners);
+  const int nalt = alt ? (owners < HELP_MAX ? owners : HELP_MAX) : 0;
+  long long mine = lane < 32 ? (long long)(g0 - g1) << lane : 0;
+  long long amine = lane < 32 ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
+  long long suf = mine, asuf = amine;  // inclusive sums over widths >= lane
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const long long t = __shfl_down(suf, off, 64), u = __shfl_down(asuf, off, 64);
+    if (lane + off < 64) {
+      suf += t;
+      asuf += u;
+    }
+  }
+  // cross-lane reads first, with every lane active
+  const long long total = __shfl(suf, 0, 64), atotal = __shfl(asuf, 0, 64);
+  const long long wide = count > 0 ? pos(j.help_bits) : 0;
+  const long long beyond = pos(32);  // pairs wider than 2^31 entries
+  SlotArgs& sl = d->sl;
+  if (lane <= 32) {
+    sl.ge[lane] = lane < 32 ? g0 : 0;
+    sl.off[lane] = lane < 32 ? suf - mine : total;  // entries of wider slots; [32]: all
+    sl.alt_off[lane] = lane < 32 ? asuf - amine : atotal;
+  }
+  if (lane == 0) {
+    sl.owners = owners;
+    sl.base = j.pool;
+    sl.alt = nalt > 0 ? j.pool + (total << j.elem_shift) : nullptr;
+    HelpArgs& h = d->help;
+    h.recs = owners > 0 && wide > 0 ? j.recs : nullptr;
+    h.finished = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(j.recs) + HELP_MAX * sizeof(HelpRec));
+    h.wide_pairs = wide;
+    h.help_bits = j.help_bits;
+    int extra = 0;
+    if (h.recs != nullptr && owners < wmax) {
+      extra = j.num_cus - owners;
+      extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
+    }
+    d->hbm_workgroups = owners == 0 ? (count > 0 ? 1 : 0) : owners + extra;
+    d->status = (beyond > 0 ? 1 : 0) | (count > 0 && owners == 0 ? 2 : 0);
+  }
+}
+
+int launch_lr_setup(const LrSetupJob& j, hipStream_t s) {
+  if (j.help_bits < 16 || j.max_owners < 1 || j.elem_shift < 3 || !j.recs || !j.hbm_counter)
+    return set_error(FP_EINVAL, "bad set-up arguments");
+  hipLaunchKernelGGL(lr_setup_kernel, dim3(1), dim3(64), 0, s, j);
+  return check_launch("lr_setup");
+}
+
+__global__ void __launch_bounds__(256) zero_words_kernel(unsigned int* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
+int launch_zero_words(void* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return FP_OK;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_words_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (unsigned int*)p, n);
+  return check_launch("zero_words");
+}
+
+int resident_per_cu(const void* kernel, int block, size_t smem) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, smem) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return n;
+}
+
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return n;
 }
 
 int launch_plan_local_random(const PlanJob& j, int precision, hipStream_t s) {

@@ -138,14 +138,10 @@ constexpr size_t wave_slot_bytes() {
   return ((size_t)sizeof(Cplx<Real>) << CAP) + 32 * sizeof(Real);
 }
 
-template <typename Real, int CAP, int WPB, bool BF3>
-__global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t pi = (int64_t)blockIdx.x * WPB + wave;
-  if (pi >= a.num_pairs) return;
-  const int64_t pidx = a.order ? (int64_t)a.order[pi] : pi;
+// One pair (index pidx) on one wavefront, its register in LDS slot `wave`.
+template <typename Real, int CAP, bool BF3>
+__device__ __forceinline__ void wave_pair(const SweepArgs& a, int64_t pidx, int wave, int lane,
+                                          unsigned char* smem_raw) {
   const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
   const int status = __builtin_amdgcn_readfirstlane(hdr->status);
   const int peak = __builtin_amdgcn_readfirstlane(hdr->peak_bits);
@@ -252,6 +248,31 @@ __global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
     out[0] = ldexp((double)v.x, (int)(expo + log2f));
     out[1] = ldexp((double)v.y, (int)(expo + log2f));
   }
+  wave_fence();  // B is reused by the wavefront's next pair
+}
+
+// One wavefront per pair: pair blockIdx * WPB + wave of the launch, or, with
+// a range on the device, pairs taken in turn from its counter until none is
+// left (each wavefront on its own; no workgroup barrier is involved).
+template <typename Real, int CAP, int WPB, bool BF3>
+__global__ void __launch_bounds__(64 * WPB) sweep_wave_kernel(SweepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  if (a.range == nullptr) {
+    const int64_t pi = (int64_t)blockIdx.x * WPB + wave;
+    if (pi < a.num_pairs) wave_pair<Real, CAP, BF3>(a, a.order ? (int64_t)a.order[pi] : pi, wave, lane, smem_raw);
+    return;
+  }
+  const int32_t* order = a.order + a.range[0];
+  const long long n = a.range[1];
+  for (;;) {
+    unsigned long long c = 0;
+    if (lane == 0) c = atomicAdd(a.claim, 1ull);
+    const long long pi = (long long)__shfl(c, 0, 64);
+    if (pi >= n) break;
+    wave_pair<Real, CAP, BF3>(a, (int64_t)order[pi], wave, lane, smem_raw);
+  }
 }
 
 // Waves per workgroup: the LDS slots of 2^10-entry registers (8.3 KB per
@@ -266,7 +287,14 @@ static int launch_wave_t(const SweepArgs& a, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();
   }
-  const int64_t blocks = (a.num_pairs + WPB - 1) / WPB;
+  int64_t blocks = (a.num_pairs + WPB - 1) / WPB;
+  if (a.range != nullptr) {  // claimed pairs: sized for grid_pairs, or as many workgroups as stay resident
+    blocks = a.grid_pairs > 0 ? (a.grid_pairs + WPB - 1) / WPB
+                              : (int64_t)resident_per_cu(reinterpret_cast<const void*>(
+                                                             sweep_wave_kernel<Real, CAP, WPB, BF3>),
+                                                         64 * WPB, smem) *
+                                    device_cus();
+  }
   hipLaunchKernelGGL((sweep_wave_kernel<Real, CAP, WPB, BF3>), dim3((unsigned)blocks), dim3(64 * WPB), smem, s, a);
   return check_launch("sweep_wave");
 }

@@ -1,0 +1,138 @@
+"""Local random contraction without host waits: the launches after planning
+are derived on the device, so a pair that cannot be contracted is reported
+through its trace (NaN, then FP_ENUMERIC from the reduction) rather than by
+the call, and the sample -> contract sequence can be captured as a graph."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dense, estimator, sampler
+
+pytestmark = pytest.mark.gpu
+
+C64 = 1
+
+
+@pytest.fixture(scope="module")
+def fp():
+    import paper_2205_09900_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def peaks_of(fp, n, s, seed, npairs):
+    out = []
+    for u, v in sampler.sample_pairs(1, n, s, seed, 0, npairs):
+        bu = np.array([b for b, _ in u["gates"]], np.int32)
+        bv = np.array([b for b, _ in v["gates"]], np.int32)
+        out.append(fp.fp_plan_local_random_host(n, bu, bv)["peak_bits"])
+    return np.array(out)
+
+
+def test_no_room_for_wide_pairs_gives_nan(fp):
+    # 96 pairs of 8 qubits at 40 steps, 51 of them beyond the 2^14 entries of
+    # LDS: with a workspace that holds the plans but no HBM slot, exactly those
+    # get NaN, the others their traces, and the reduction flags the batch
+    ens, n, seed = (1, 8, 40), 96, 4343
+    peaks = peaks_of(fp, 8, 40, seed, n)
+    wide = peaks > 14
+    assert 0 < wide.sum() < n
+    g = fp.sample(ens, n, seed, 0, C64)
+    full = fp.fp_workspace_bytes(ens, n, C64)
+    ws = torch.empty(full, dtype=torch.uint8, device="cuda")
+    tr = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    lo, hi = 1, full  # smallest workspace the call accepts: the plans, nothing more
+    while lo < hi:
+        mid = (lo + hi) // 2
+        try:
+            fp.fp_contract_trace_batch(ens, n, C64, g, tr, ws[:mid])
+            hi = mid
+        except fp.FPError as e:
+            assert e.code == fp.FP_ETOOBIG, e
+            lo = mid + 1
+    torch.cuda.synchronize()
+    tr.fill_(0.0)
+    fp.fp_contract_trace_batch(ens, n, C64, g, tr, ws[:lo])
+    torch.cuda.synchronize()
+    got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
+    assert np.isnan(got[wide]).all()
+    assert np.isfinite(got[~wide]).all()
+    want = dense.traces(sampler.sample_pairs(1, 8, 40, seed, 0, n, fp32=True))
+    w = want[~wide]
+    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
+    err = np.abs(got[~wide] - w) / np.maximum(np.abs(w), 1e-3 * rms)
+    assert err.max() <= 1e-5, err.max()
+    with pytest.raises(fp.FPError) as ei:
+        fp.fp_frame_potential(tr, n, 2)
+    assert ei.value.code == fp.FP_ENUMERIC
+
+
+def capture_and_replay(fp, ens, n, seed, eager_first):
+    """Captures sample -> contract of one batch on a side stream and replays it
+    three times, with eager work on the same buffers in between; returns the
+    traces of the first replay after checking that every replay and every
+    eager run agree bit for bit."""
+    g = fp.alloc_gates(ens, n, C64)
+    ws = fp.workspace(ens, n, C64)
+    tr = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    s = torch.cuda.Stream()
+    ref = None
+    if eager_first:
+        with torch.cuda.stream(s):
+            fp.fp_sample_gates(ens, n, seed, 0, C64, g, s)
+            fp.fp_contract_trace_batch(ens, n, C64, g, tr, ws, s)
+        s.synchronize()
+        ref = tr.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        fp.fp_sample_gates(ens, n, seed, 0, C64, g, s)
+        fp.fp_contract_trace_batch(ens, n, C64, g, tr, ws, s)
+    torch.cuda.synchronize()
+    first = None
+    for rep in range(3):
+        tr.fill_(float("nan"))
+        g.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        if first is None:
+            first = tr.clone()
+        assert torch.equal(tr, first), rep
+        if ref is not None:
+            assert torch.equal(tr, ref), rep
+        fp.fp_contract_trace_batch(ens, n, C64, g, tr, ws, s)  # eager, between replays
+        s.synchronize()
+        assert torch.equal(tr, first), rep
+    return torch.view_as_complex(first.view(-1, 2)).cpu().numpy()
+
+
+@pytest.mark.parametrize("eager_first", [True, False])
+def test_graph_replay_wide_pairs_vs_dense(fp, eager_first):
+    # 8 qubits, 40 steps: most pairs need HBM slots (up to 2^22 entries) and
+    # the widest share their ops; captured with or without an earlier eager
+    # batch of the ensemble (launch sizes from it, or as many workgroups as
+    # stay resident), the replays must give the oracle's traces
+    ens, n, seed = (1, 8, 40 if eager_first else 36), 96, 4343
+    peaks = peaks_of(fp, ens[1], ens[2], seed, n)
+    assert (peaks > 14).sum() > n // 5 and (peaks >= 18).any()
+    got = capture_and_replay(fp, ens, n, seed, eager_first)
+    want = dense.traces(sampler.sample_pairs(1, ens[1], ens[2], seed, 0, n, fp32=True))
+    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
+    err = np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)
+    # float32 storage: the floored maximum over a batch can pass 1e-5 on a
+    # pair whose trace nearly cancels; p99 and every F^(k) stay within it
+    assert np.quantile(err, 0.99) <= 1e-5 and err.max() <= 1e-4, (np.quantile(err, 0.99), err.max())
+    fg, _ = estimator.frame_potential(got, 3)
+    fw, _ = estimator.frame_potential(want, 3)
+    for k in range(3):
+        assert abs(fg[k] - fw[k]) <= 1e-5 * fw[k], (k, fg[k], fw[k])
+
+
+def test_local_random_graph_replay(fp):
+    # every class of the local random path (n = 50, 120 steps, 300 pairs) in
+    # one captured graph with its sampling
+    got = capture_and_replay(fp, fp.Ensemble(fp.LOCAL_RANDOM, 50, 120), 300, 777, True)
+    assert np.isfinite(got).all()
