@@ -80,6 +80,11 @@ def bench_streams(torch, k):
     return _STREAMS[:k]
 
 
+def progress(msg):
+    """One line per finished stage on stderr (stdout carries only the JSON line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True, in_flight=2,
                  profile=True):
     """Times `steps` batches.  Pipelined: `in_flight` streams with their own
@@ -130,6 +135,8 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = fp.fp_profile_end() if profile else None
+    progress(f"S={depth}: {steps} batches, {'pipelined' if pipeline else 'one at a time'}"
+             f"{' with events' if profile else ''}: {wall / steps * 1e3:.3f} ms per batch")
     return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb}
 
 
@@ -160,6 +167,7 @@ def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chun
     prof = fp.fp_profile_end()
     kms = sum(prof[c]["ms"] for c in SWEEP_CLASSES)
     flops = sum(prof[c]["flops"] for c in SWEEP_CLASSES)
+    progress(f"ensemble {ansatz}, n={n}, depth {depth}, precision {prec}: {pairs * steps / wall:.4g} pairs/s")
     return {"contractions_per_s": pairs * steps / wall, "F": f[0], "SE": f[1],
             "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
             "kernel_ms_per_step": kms / steps}, trace
@@ -240,13 +248,14 @@ def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
         budget = min(LR_MAX_BITS, int(math.floor(math.log2(ws / elem))))
         over = float(np.mean(pk > budget))
         top = int(pk.max())
+        progress(f"widths at S={s}: {sample} pairs planned, widest 2^{int(pk.max())}")
         out[str(s)] = {
             "median_bits": int(np.quantile(pk, 0.5)), "p90_bits": int(np.quantile(pk, 0.9)),
             "p99_bits": int(np.quantile(pk, 0.99)), "max_bits": top, "sample_pairs": sample,
             "budget_bits": budget, "workspace_gib": ws / 2**30, "over_budget_frac": over,
             "status": "fits" if over == 0 else
-                      f"infeasible: {over:.1%} of the sample need more than 2^{budget} entries per register "
-                      f"(widest 2^{top} = {elem * 2.0 ** top / 2**30:.3g} GiB)",
+                      f"infeasible: {int(round(over * sample))} of {sample} pairs ({over:.2%}) need more than "
+                      f"2^{budget} entries per register (widest 2^{top} = {elem * 2.0 ** top / 2**30:.3g} GiB)",
         }
     return out
 
@@ -384,6 +393,7 @@ def main():
     suite_res = None
     if not args.no_suite:
         suite_res = suite(fp, torch, np, synth, args.suite_pairs)
+        progress("other ensembles done")
 
     cv_res = None
     if not args.no_cv:
@@ -391,10 +401,12 @@ def main():
         cv_res = cv.experiment(n=40, layers=6, k=2, hidden=256, n_train=65536, n_exact=10000,
                                n_surrogate=args.cv_surrogate, epochs=30)
         cv_res.pop("history", None)
+        progress("control-variate experiment done")
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.n, args.depth, args.cpu_seconds, seed_base)
+        progress("CPU baseline done")
 
     out = {
         "metric": METRIC,
