@@ -15,7 +15,7 @@ evaluated on the span of per-qubit permutation labels left by P_e P_o, with
 the Gram correction Tr(Y^m) = Tr(pinv(G_S) G_S M_S^m) so that linearly
 dependent labels (k > d) are handled exactly.
 
-This is an exact (deterministic) value for the ensemble; it is used to judge
+This is an exact (deterministic) value for the ensemble; it is used to check
 Monte Carlo estimates, and is itself pinned by F^(1) = 1, the D = 1 product,
 the paper's analytic bound for k = 2 (Sec. I.A) and the Haar limit.
 """
