@@ -419,7 +419,10 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   j.max_peak = counters;
   j.num_large = counters + 1;
   j.num_failed = counters + 2;
-  j.cap_bits = lds_bits_max(c.precision);
+  // registers up to 2^12 entries: the LDS sweeps; wider: the HBM-slot sweep,
+  // whose interpreter keeps a register in LDS up to 2^14 (c64) entries and
+  // runs such pairs several times faster than 1024 lanes of the LDS sweep
+  j.cap_bits = LR_MID_BITS < lds_bits_max(c.precision) ? LR_MID_BITS : lds_bits_max(c.precision);
   j.small_bits = LR_SMALL_BITS < j.cap_bits ? LR_SMALL_BITS : j.cap_bits;
   j.tiny_bits = -1;  // registers up to 2^10 entries form one class (one wavefront per pair)
   j.mid_bits = LR_MID_BITS < j.cap_bits ? LR_MID_BITS : j.cap_bits;
@@ -456,6 +459,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   sj.small_bits = j.small_bits;
   sj.mid_bits = j.mid_bits;
   sj.cap_bits = j.cap_bits;
+  sj.lds_bits = c.precision == FP_C128 ? 13 : 14;  // registers the HBM-slot sweep keeps in LDS
   sj.pool = c.w + c.fixed_bytes;
   sj.pool_bytes = (long long)c.ws_bytes - (long long)c.fixed_bytes;
   sj.elem_shift = c.elem == 16 ? 4 : 3;

@@ -89,7 +89,7 @@ int launch_order_pairs(const OrderJob& j, hipStream_t s);
 int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s);
 // HBM slots of the large-register sweep.  Owner workgroups (blockIdx below
 // `owners`) take pairs from the launch's list in order; the j-th of them to
-// make its first claim gets slot j, which has 2^b entries for the b with
+// make its first claim gets slot j (width 0 for a pair that stays in LDS), which has 2^b entries for the b with
 // ge[b + 1] <= j < ge[b] (ge[b]: slots of at least 2^b entries, non-increasing
 // in b, ge[32] = 0), at entry offset off[b] + (j - ge[b + 1]) * 2^b of base.
 // The list is ordered by decreasing width and slot j is as wide as its j-th
@@ -153,6 +153,7 @@ struct LrSetupJob {
   unsigned char* pool;             // HBM slot pool
   long long pool_bytes;
   int elem_shift;                  // log2 of the bytes per complex entry
+  int lds_bits;                    // pairs up to 2^lds_bits entries never use their HBM slot
   int max_owners, max_helpers, num_cus, help_bits;
   HelpRec* recs;                   // the chunk's work-sharing area (HELP_AREA_BYTES, cleared here)
   unsigned long long* hbm_counter; // the chunk's HBM claim word (cleared here)

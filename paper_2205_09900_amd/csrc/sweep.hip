@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
       const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
       if (hdr->status == 0 && hdr->peak_bits > a.cap_bits) {
         double* out = a.trace + 2 * (a.trace_offset + pidx);
-        if (hdr->peak_bits > sbits) {
+        if (hdr->peak_bits > sbits && hdr->peak_bits > hbm_lds_bits<Real>()) {  // needs a wider slot
           if (lane == 0) {
             out[0] = __builtin_nan("");
             out[1] = __builtin_nan("");
@@ -916,15 +916,20 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   const long long count = rc[4];
   const int wmax = count < j.max_owners ? (int)count : j.max_owners;
   const long long pa = pos(lane), pa1 = pos(lane + 1);
-  const long long ge = lane >= 32 ? 0 : lane <= j.cap_bits + 1 ? count : pa;
-  const long long ge1 = lane >= 31 ? 0 : lane + 1 <= j.cap_bits + 1 ? count : pa1;
+  // slot widths: a pair's register width, 0 for a pair that stays in LDS
+  // (at most 2^lds_bits entries); ge_all[0] = count, ge_all[b] = pairs wider
+  // than LDS with width >= b otherwise
+  const long long wide_ge = pos(j.lds_bits + 1);
+  const long long ge = lane >= 32 ? 0 : lane == 0 ? count : lane <= j.lds_bits + 1 ? wide_ge : pa;
+  const long long ge1 = lane >= 31 ? 0 : lane + 1 <= j.lds_bits + 1 ? wide_ge : pa1;
   const long long pool_entries = j.pool_bytes > 0 ? j.pool_bytes >> j.elem_shift : 0;
   // entries of w slots, plus second slots for the first HELP_MAX of them
+  // (slots of width 0 take none)
   auto entries = [&](int w, bool alt) {
     const long long na = alt ? (w < HELP_MAX ? w : HELP_MAX) : 0;
     const long long g0 = ge < w ? ge : w, g1 = ge1 < w ? ge1 : w;
     const long long a0 = g0 < na ? g0 : na, a1 = g1 < na ? g1 : na;
-    return wave_sum_ll(lane < 32 ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
+    return wave_sum_ll(lane >= 1 && lane < 32 ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
   };
   auto largest = [&](bool alt) {
     int l = 0, h = wmax;
@@ -936,18 +941,24 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     return l;
   };
   int owners = 0;
-  bool alt = false;
+  bool alt = false, none = false;
   if (count > 0) {
     const int w0 = largest(false);
     const int w1 = largest(true);
     alt = w1 >= 1 && 2 * w1 >= w0;
     owners = alt ? w1 : w0;
+    if (owners == 0) {  // no room for the widest pair's slot: all slots of width 0, pairs
+      owners = wmax;    // that stay in LDS still run and the others get NaN
+      none = true;
+    }
   }
   // slot layout: ge, then offsets from the widest down (the sums above b, by a suffix scan)
-  const int g0 = (int)(ge < owners ? ge : owners), g1 = (int)(ge1 < owners ? ge1 : owners);
+  const int g0 = none ? (lane == 0 ? owners : 0) : (int)(ge < owners ? ge : owners);
+  const int g1 = none ? 0 : (int)(ge1 < owners ? ge1 : owners);
   const int nalt = alt ? (owners < HELP_MAX ? owners : HELP_MAX) : 0;
-  long long mine = lane < 32 ? (long long)(g0 - g1) << lane : 0;
-  long long amine = lane < 32 ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
+  long long mine = lane >= 1 && lane < 32 ? (long long)(g0 - g1) << lane : 0;
+  long long amine =
+      lane >= 1 && lane < 32 ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
   long long suf = mine, asuf = amine;  // inclusive sums over widths >= lane
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -972,7 +983,7 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     sl.base = j.pool;
     sl.alt = nalt > 0 ? j.pool + (total << j.elem_shift) : nullptr;
     HelpArgs& h = d->help;
-    h.recs = owners > 0 && wide > 0 ? j.recs : nullptr;
+    h.recs = owners > 0 && wide > 0 && !none ? j.recs : nullptr;
     h.finished = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(j.recs) + HELP_MAX * sizeof(HelpRec));
     h.wide_pairs = wide;
     h.help_bits = j.help_bits;
@@ -982,12 +993,12 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
       extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
     }
     d->hbm_workgroups = owners == 0 ? (count > 0 ? 1 : 0) : owners + extra;
-    d->status = (beyond > 0 ? 1 : 0) | (count > 0 && owners == 0 ? 2 : 0);
+    d->status = (beyond > 0 ? 1 : 0) | (none ? 2 : 0);
   }
 }
 
 int launch_lr_setup(const LrSetupJob& j, hipStream_t s) {
-  if (j.help_bits < 16 || j.max_owners < 1 || j.elem_shift < 3 || !j.recs || !j.hbm_counter)
+  if (j.help_bits < 16 || j.max_owners < 1 || j.elem_shift < 3 || !j.recs || !j.hbm_counter || j.lds_bits < j.cap_bits)
     return set_error(FP_EINVAL, "bad set-up arguments");
   hipLaunchKernelGGL(lr_setup_kernel, dim3(1), dim3(64), 0, s, j);
   return check_launch("lr_setup");
