@@ -136,3 +136,67 @@ def test_local_random_graph_replay(fp):
     # one captured graph with its sampling
     got = capture_and_replay(fp, fp.Ensemble(fp.LOCAL_RANDOM, 50, 120), 300, 777, True)
     assert np.isfinite(got).all()
+
+
+def read_setup(buf):
+    """The launch set-up the device wrote into a chunk header (layout of LrDev)."""
+    import struct
+    o = 0
+    first = struct.unpack_from("<64i", buf, o); o += 256
+    rng = struct.unpack_from("<10q", buf, o); o += 80
+    o += 40  # claim counters
+    base, alt, owners = struct.unpack_from("<QQi", buf, o); o += 20
+    ge = struct.unpack_from("<33i", buf, o); o += 132
+    off = struct.unpack_from("<33q", buf, o); o += 264
+    alt_off = struct.unpack_from("<33q", buf, o); o += 264
+    recs, finished, wide, help_bits = struct.unpack_from("<QQqi", buf, o); o += 32
+    wgs, status = struct.unpack_from("<ii", buf, o)
+    return dict(first=first, range=[(rng[2 * k], rng[2 * k + 1]) for k in range(5)], base=base, alt=alt,
+                owners=owners, ge=ge, off=off, alt_off=alt_off, recs=recs, wide=wide, help_bits=help_bits,
+                wgs=wgs, status=status)
+
+
+def test_device_setup_matches_host_plans(fp):
+    # the set-up the device derives from its plans (class ranges, ordering
+    # offsets, graded HBM slots, work sharing) against the host planner's
+    # widths of the same pairs
+    ens, n, seed = (1, 8, 40), 96, 4343
+    peaks = peaks_of(fp, 8, 40, seed, n)
+    g = fp.sample(ens, n, seed, 0, C64)
+    ws = fp.workspace(ens, n, C64)
+    fp.contract(ens, g, n, C64, ws)
+    torch.cuda.synchronize()
+    d = read_setup(ws[1024:1024 + 1200].cpu().numpy().tobytes())
+    for b in range(64):
+        assert d["first"][b] == int((peaks > b).sum()), b
+    bounds = [(-1, -1), (-1, 10), (10, 12), (12, 12), (12, 63)]
+    for k, (lo, hi) in enumerate(bounds):
+        cnt = int(((peaks > lo) & (peaks <= hi)).sum()) if hi > lo else 0
+        assert d["range"][k][1] == cnt, (k, d["range"][k], cnt)
+        if cnt:
+            assert d["range"][k][0] == int((peaks > hi).sum()), k
+    hbm = np.sort(peaks[peaks > 12])[::-1]  # the class in launch order
+    owners = d["owners"]
+    assert 1 <= owners <= min(len(hbm), 512)
+    ge = d["ge"]
+
+    def width(j):
+        b = 31
+        while b > 0 and ge[b] <= j:
+            b -= 1
+        return b
+
+    regions = []
+    for j in range(owners):
+        w = width(j)
+        assert w >= (hbm[j] if hbm[j] > 14 else 0), (j, w, hbm[j])  # 0: stays in LDS
+        if w > 0:
+            regions.append((d["off"][w] + ((j - ge[w + 1]) << w), 1 << w))
+    regions.sort()
+    for (a0, n0), (a1, _) in zip(regions, regions[1:]):
+        assert a0 + n0 <= a1
+    ws_end = ws.data_ptr() + ws.numel()
+    if regions:
+        assert d["base"] + 8 * (regions[-1][0] + regions[-1][1]) <= ws_end
+    assert d["wide"] == int((peaks >= d["help_bits"]).sum())
+    assert d["status"] == 0 and d["wgs"] >= owners
