@@ -5,10 +5,10 @@ on a uniformly chosen bond), S steps per circuit, 10^4 (U, V) pairs per
 batch, complex64 with float64 scales and reduction.  One step = the whole
 path over one batch: sample the gates, plan every pair on the device,
 contract Tr(U^dagger V) for every pair, reduce F^(k), k = 1..3 (the reduction
-returns the estimates to the host, which ends the step).  Two batches are in
-flight on two streams: the next batch is sampled and planned while the
-current one is swept (serial_ms_per_step reports the same steps one at a
-time).  The headline run has no per-launch HIP events (they cost time of
+returns the estimates to the host, which ends the step).  Three batches are
+in flight on three streams: sampling runs two batches ahead, and a batch is
+planned while the previous one is swept (serial_ms_per_step reports the same
+steps one at a time).  The headline run has no per-launch HIP events (they cost time of
 their own); kernel durations, the roofline and the step breakdown come from
 runs with events (ms_per_step_with_events, serial_ms_per_step).  Inputs are
 synthetic and seeded.
@@ -41,13 +41,14 @@ LR_KERNELS = {
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=50, help="batches timed in each headline run")
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--depth", type=int, default=100, help="steps per circuit of the headline workload")
     ap.add_argument("--pairs", type=int, default=10000)
     ap.add_argument("--n", type=int, default=50)
-    ap.add_argument("--in-flight", type=int, default=2, help="batches in flight (streams) in the timed runs")
+    ap.add_argument("--in-flight", type=int, default=3, help="batches in flight (buffers and streams) in the timed runs")
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--depth-steps", type=int, default=6, help="batches timed per step count of --per-depth")
     ap.add_argument("--per-depth", default="50,100,150,200,250",
                     help="comma list of step counts measured besides the headline ('' = none)")
     ap.add_argument("--feasibility", default=",".join(str(x) for x in range(50, 801, 50)),
@@ -87,12 +88,14 @@ def progress(msg):
 
 def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True, in_flight=2,
                  profile=True):
-    """Times `steps` batches.  Pipelined: `in_flight` streams with their own
-    gate, trace and workspace buffers; batches i+1 .. i+in_flight-1 are
-    sampled and contracted (each contraction waits only for its own plans)
-    before batch i's reduction is awaited, so consecutive batches overlap on
-    the device.  Every batch is sampled, contracted and reduced exactly once
-    inside the timed region."""
+    """Times `steps` batches.  Pipelined: `in_flight` buffers (gates, traces,
+    workspace) on streams of their own.  Sampling runs in_flight - 1 batches
+    ahead of contraction: batch i + in_flight - 1 is sampled as soon as batch
+    i - 1's reduction has returned (its buffer is then free), so that while
+    the host waits for batch i's plans (the contraction reads the planner's
+    register widths back), the device runs batch i - 1's sweeps, batch i's
+    planner and the next samplers side by side.  Every batch is sampled,
+    contracted and reduced exactly once inside the timed region."""
     ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
     nbuf = in_flight if pipeline else 1
     gates = [fp.alloc_gates(ens, pairs, prec) for _ in range(nbuf)]
@@ -102,9 +105,12 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     streams = bench_streams(torch, nbuf)
     seed = seed_base | (depth << 32)
 
-    def launch(i):
+    def sample(i):
         b = i % nbuf
         fp.fp_sample_gates(ens, pairs, seed, i * pairs, prec, gates[b], streams[b])
+
+    def contract(i):
+        b = i % nbuf
         fp.fp_contract_trace_batch(ens, pairs, prec, gates[b], trace[b], ws[b], streams[b])
 
     def finish(i):
@@ -113,16 +119,23 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
 
     def run(first, count):
         f = None
-        if pipeline:
-            for i in range(first, min(first + count, first + nbuf - 1)):
-                launch(i)
-            for i in range(first, first + count):
-                if i + nbuf - 1 < first + count:
-                    launch(i + nbuf - 1)
-                f = finish(i)
+        end = first + count
+        if count <= 0:
+            return f
+        if pipeline and nbuf > 1:
+            for i in range(first, min(end, first + nbuf - 1)):
+                sample(i)
+            for i in range(first, end):
+                contract(i)
+                if i > first:
+                    f = finish(i - 1)
+                if i + nbuf - 1 < end:
+                    sample(i + nbuf - 1)
+            f = finish(end - 1)
         else:
-            for i in range(first, first + count):
-                launch(i)
+            for i in range(first, end):
+                sample(i)
+                contract(i)
                 f = finish(i)
         return f
 
@@ -308,6 +321,7 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    bench_streams(torch, max(1, args.in_flight))  # created together, before the library adds its side streams
     prec = fp.C64 if args.precision == "c64" else fp.C128
     seed_base = synth.workload_seed(4, 0)
     if args.with_copy:
@@ -333,8 +347,8 @@ def main():
     # roofline of the sweep kernel with the largest event time (the sweeps
     # hold the method's arithmetic; planning, matrix preparation and sampling
     # are listed in step_kernels_ms), timed in the run with one batch at a
-    # time: with two batches in flight a kernel's events also span the other
-    # batch's work on the GPU (that duration is reported beside it)
+    # time: with batches in flight a kernel's events also span the other
+    # batches' work on the GPU (that duration is reported beside it)
     sprof = serial["prof"]
     dom = max(SWEEP_CLASSES, key=lambda c: sprof[c]["ms"])
     d = sprof[dom]
@@ -350,7 +364,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": traffic, "kernel": kname, "kernel_class": dom,
                 "kernel_ms_per_launch": d["ms"] / max(1, d["launches"]),
-                "kernel_ms_per_launch_two_in_flight": prof[dom]["ms"] / max(1, prof[dom]["launches"]),
+                "kernel_ms_per_launch_in_flight": prof[dom]["ms"] / max(1, prof[dom]["launches"]),
                 "timed_in": "the run with one batch at a time (serial_ms_per_step)",
                 "flops_per_launch": d["flops"] / max(1, d["launches"])}
     step_kernels = {c: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
@@ -358,7 +372,7 @@ def main():
                     for c, v in prof.items() if v["launches"]}
 
     per_depth = {}
-    depth_steps = max(4, args.steps)  # batches per depth, two in flight as in the headline
+    depth_steps = max(args.in_flight + 1, args.depth_steps)  # batches per depth, in flight as in the headline
     if args.per_depth:
         for s in [int(x) for x in args.per_depth.split(",") if x]:
             r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base,
