@@ -73,11 +73,18 @@ _STREAMS = []
 
 
 def bench_streams(torch, k):
-    """The first k of the streams every run uses: created once, so that all
-    runs see the same streams (the library keeps side streams per caller
-    stream, and hardware queues are shared among all streams)."""
+    """The first k of the streams every run uses: created once, together and
+    before the library creates its side streams, straight through the HIP
+    runtime (torch's stream pool hands out streams that already share the
+    process's four hardware queues), so that each batch in flight has a
+    hardware queue of its own."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime torch has loaded
     while len(_STREAMS) < k:
-        _STREAMS.append(torch.cuda.Stream())
+        h = ctypes.c_void_p()
+        if hip.hipStreamCreateWithFlags(ctypes.byref(h), 1) != 0:  # hipStreamNonBlocking
+            raise RuntimeError("hipStreamCreateWithFlags failed")
+        _STREAMS.append(torch.cuda.ExternalStream(h.value))
     return _STREAMS[:k]
 
 
@@ -324,10 +331,11 @@ def main():
     bench_streams(torch, max(1, args.in_flight))  # created together, before the library adds its side streams
     prec = fp.C64 if args.precision == "c64" else fp.C128
     seed_base = synth.workload_seed(4, 0)
-    if args.with_copy:
-        a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        b.copy_(a)
+    if args.with_copy:  # on a bench stream: the null stream takes no hardware queue of its own
+        with torch.cuda.stream(bench_streams(torch, 1)[0]):
+            a = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+            b = torch.empty_like(a)
+            b.copy_(a)
         torch.cuda.synchronize()
 
     # the step with one batch at a time, every launch timed with HIP events

@@ -134,33 +134,73 @@ int get_brickwork_plan(int n, int depth, DevPlan* out) {
 }
 
 // ---- auxiliary streams: the sweep classes of one batch touch disjoint pairs
-// and run side by side (all streams at the default priority).  Each caller
-// stream has its own set, so batches issued on different streams do not queue
-// behind each other's long sweeps. ----------------------------------------------
+// and run side by side (all streams at the default priority).  Eager calls on
+// a device share one set of side streams: with the four hardware queues a
+// process gets, few streams keep each caller stream on a queue of its own, so
+// that a caller's wait for its side streams stalls no other caller's work
+// (the sweeps of batches issued one after another on different streams seldom
+// overlap, so sharing costs little).  A call under stream capture takes side
+// streams of its caller's own, so that a capture never draws in another
+// caller's work.  Fork and join events always belong to the caller stream. ---
+struct CallerAux {
+  Aux a;              // the caller's events (a.s: filled per call)
+  bool own = false;   // own side streams created (capture)
+  hipStream_t own_s[NUM_AUX];
+};
 static std::mutex g_aux_mu;
-static std::map<std::pair<int, hipStream_t>, Aux> g_aux;
+static std::map<std::pair<int, hipStream_t>, CallerAux> g_aux;
+static std::map<int, Aux> g_shared;  // device -> shared side streams (s only)
+
+static int create_streams(hipStream_t* out) {
+  for (int i = 0; i < NUM_AUX; ++i) {
+    int rc = check_hip(hipStreamCreateWithFlags(&out[i], hipStreamNonBlocking), "hipStreamCreate");
+    if (rc) return rc;
+  }
+  return FP_OK;
+}
 
 int get_aux(Aux* out, hipStream_t caller) {
   int dev = 0;
   int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
   if (rc) return rc;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  bool capture = true;  // unknown: as under capture
+  if (hipStreamIsCapturing(caller, &cs) == hipSuccess)
+    capture = cs != hipStreamCaptureStatusNone;
+  else
+    (void)hipGetLastError();
   std::lock_guard<std::mutex> lk(g_aux_mu);
   const auto key = std::make_pair(dev, caller);
   auto it = g_aux.find(key);
-  if (it != g_aux.end()) {
-    *out = it->second;
-    return FP_OK;
-  }
-  Aux a;
-  for (int i = 0; i < NUM_AUX; ++i) {
-    rc = check_hip(hipStreamCreateWithFlags(&a.s[i], hipStreamNonBlocking), "hipStreamCreate");
-    if (!rc) rc = check_hip(hipEventCreateWithFlags(&a.join[i], hipEventDisableTiming), "hipEventCreate");
+  if (it == g_aux.end()) {
+    CallerAux c;
+    for (int i = 0; i < NUM_AUX; ++i) {
+      rc = check_hip(hipEventCreateWithFlags(&c.a.join[i], hipEventDisableTiming), "hipEventCreate");
+      if (rc) return rc;
+    }
+    rc = check_hip(hipEventCreateWithFlags(&c.a.fork, hipEventDisableTiming), "hipEventCreate");
     if (rc) return rc;
+    it = g_aux.emplace(key, c).first;
   }
-  rc = check_hip(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming), "hipEventCreate");
-  if (rc) return rc;
-  g_aux[key] = a;
-  *out = a;
+  CallerAux& c = it->second;
+  if (capture) {
+    if (!c.own) {
+      rc = create_streams(c.own_s);
+      if (rc) return rc;
+      c.own = true;
+    }
+    for (int i = 0; i < NUM_AUX; ++i) c.a.s[i] = c.own_s[i];
+  } else {
+    auto sh = g_shared.find(dev);
+    if (sh == g_shared.end()) {
+      Aux a;
+      rc = create_streams(a.s);
+      if (rc) return rc;
+      sh = g_shared.emplace(dev, a).first;
+    }
+    for (int i = 0; i < NUM_AUX; ++i) c.a.s[i] = sh->second.s[i];
+  }
+  *out = c.a;
   return FP_OK;
 }
 

@@ -25,7 +25,7 @@ struct Aux {
 int check_ensemble(const fp_ensemble_t* e);
 int check_precision(int p);
 int get_brickwork_plan(int n, int depth, DevPlan* out);
-int get_aux(Aux* out, hipStream_t caller);  // side streams of the caller's stream
+int get_aux(Aux* out, hipStream_t caller);  // side streams for a call on caller (shared per device unless capturing)
 int lds_bits_max(int precision);
 int tile_pairs(int tile);
 double hea_flops_per_pair(int n, int L);
