@@ -1079,8 +1079,65 @@ __global__ void __launch_bounds__(256) gate_matrices_kernel(PlanJob j) {
   store_matrix(m, reinterpret_cast<Real*>(j.wmat + pi * j.wmat_stride) + 32 * (int64_t)jj);
 }
 
+// The same matrices with one workgroup per pair: the pair's gate block
+// (2G gates, contiguous) is first copied to LDS with coalesced 16-byte
+// loads, and every thread then multiplies its merged gate's factors from LDS
+// (the per-thread form reads each 128-byte gate in eight strided pieces).
+constexpr int PREP_NT = 256;
+template <typename Real, bool BF3>
+__global__ void __launch_bounds__(PREP_NT) gate_matrices_lds_kernel(PlanJob j) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t pi = blockIdx.x;
+  const PlanHeader* h = j.hdr + pi;
+  const int ng = h->status != 0 ? 0 : h->num_gate_ops;  // uniform over the workgroup
+  if (ng <= 0) return;
+  const int n16 = (int)(2 * (int64_t)j.G * 32 * (int64_t)sizeof(Real) / 16);
+  const float4* src = reinterpret_cast<const float4*>(j.gates + pi * j.gate_stride);
+  float4* lds = reinterpret_cast<float4*>(smem_raw);
+  for (int i = threadIdx.x; i < n16; i += PREP_NT) lds[i] = src[i];
+  __syncthreads();
+  const Real* pg = reinterpret_cast<const Real*>(smem_raw);
+  Real* out = reinterpret_cast<Real*>(j.wmat + pi * j.wmat_stride);
+  if (ng > PREP_NT) {  // several matrices per thread: stored as they are made
+    for (int jj = threadIdx.x; jj < ng; jj += PREP_NT) {
+      const int k = j.gseq[pi * j.gseq_stride + jj];
+      Cplx<Real> m[16];
+      stage_gate<Real, BF3>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], m);
+      store_matrix(m, out + 32 * (int64_t)jj);
+    }
+    return;
+  }
+  // one matrix per thread: the matrices replace the gate block in LDS (ng <=
+  // 2G blocks of the same size) once every thread has read its factors, and
+  // leave with coalesced stores
+  const int jj = threadIdx.x;
+  Cplx<Real> m[16];
+  if (jj < ng) {
+    const int k = j.gseq[pi * j.gseq_stride + jj];
+    stage_gate<Real, BF3>(pg, j.G, j.factors + pi * j.f_stride, j.wgates[pi * j.wg_stride + k], m);
+  }
+  __syncthreads();
+  if (jj < ng) store_matrix(m, reinterpret_cast<Real*>(smem_raw) + 32 * jj);
+  __syncthreads();
+  const int o16 = (int)((int64_t)ng * 32 * (int64_t)sizeof(Real) / 16);
+  float4* dst = reinterpret_cast<float4*>(out);
+  for (int i = threadIdx.x; i < o16; i += PREP_NT) dst[i] = lds[i];
+}
+
 int launch_gate_matrices(const PlanJob& j, int precision, hipStream_t s) {
   if (j.num_pairs <= 0) return FP_OK;
+  const size_t elem = precision == FP_C128 ? sizeof(double) : sizeof(float);
+  const size_t smem = 2 * (size_t)j.G * 32 * elem;  // the pair's gate block
+  if (smem <= 64 * 1024) {
+    const dim3 grid((unsigned)j.num_pairs);
+    if (precision == FP_C128)
+      hipLaunchKernelGGL((gate_matrices_lds_kernel<double, false>), grid, dim3(PREP_NT), smem, s, j);
+    else if (j.bf3)
+      hipLaunchKernelGGL((gate_matrices_lds_kernel<float, true>), grid, dim3(PREP_NT), smem, s, j);
+    else
+      hipLaunchKernelGGL((gate_matrices_lds_kernel<float, false>), grid, dim3(PREP_NT), smem, s, j);
+    return check_launch("gate_matrices");
+  }
   const int64_t threads = j.num_pairs * 2 * (int64_t)j.G;
   const int64_t blocks = (threads + 255) / 256;
   if (precision == FP_C128)
