@@ -181,6 +181,42 @@ def test_local_random_hbm_slot_sizes_vs_dense(fp, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_long_circuits_one_bond_vs_dense(fp, prec):
+    # 2 qubits, 140 steps: every gate sits on the one bond, so each pair is a
+    # single merged gate of 280 factors; in complex128 the pair's gate block
+    # (70 KiB) exceeds the LDS copy of the matrix preparation, which then
+    # multiplies the factors straight from global memory
+    n, s, npairs, seed = 2, 140, 8, 4848
+    got = gpu_traces(fp, (1, n, s), npairs, seed, prec)
+    want = oracle_traces(1, n, s, seed, npairs, prec)
+    assert floored_err(got, want) <= TOL[prec], floored_err(got, want)
+
+
+def test_preparation_paths_agree_at_200_steps(fp):
+    # 50 qubits, 200 steps: 246 to 280 GATE ops per pair, so the LDS matrix
+    # preparation (complex64, 50 KiB gate block) makes one matrix per thread
+    # for some pairs and several for the others, while complex128 (100 KiB)
+    # takes the global-memory preparation; the two precisions must agree to
+    # complex64 accuracy
+    ens, npairs, seed = (1, 50, 200), 12, 4747
+    pairs = sampler.sample_pairs(1, 50, 200, seed, 0, npairs)
+    ngate = []
+    for u, v in pairs:
+        bu = np.array([b for b, _ in u["gates"]], np.int32)
+        bv = np.array([b for b, _ in v["gates"]], np.int32)
+        ops, _, _, _ = fp.fp_plan_program_host(50, bu, bv)
+        ngate.append(sum(1 for o in ops if (int(o["type"]) & 3) == 0))
+    assert min(ngate) <= 256 < max(ngate), ngate
+    t64 = gpu_traces(fp, ens, npairs, seed, 1)
+    t128 = gpu_traces(fp, ens, npairs, seed, 0)
+    assert np.all(np.isfinite(t128)) and np.all(np.isfinite(t64))
+    assert floored_err(t64, t128) <= 1e-4, floored_err(t64, t128)
+    f64 = np.mean(np.abs(t64) ** 2)
+    f128 = np.mean(np.abs(t128) ** 2)
+    assert abs(f64 - f128) <= 1e-5 * f128
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_wide_circuits_vs_mpo(fp, prec):
     cases = [(0, 20, 3, 6), (1, 50, 50, 4), (2, 40, 2, 6), (1, 30, 60, 3)]
     for ansatz, n, d, npairs in cases:
