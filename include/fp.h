@@ -149,10 +149,12 @@ int fp_workspace_bytes(const fp_ensemble_t* ens, int64_t num_pairs, int precisio
  * Local random pairs are planned on the device (each pair's network differs)
  * and the launches that follow are derived there from the plans.  Outside
  * stream capture the call then waits for the planning of its batch (not for
- * its sweeps) to size each launch exactly; while
- * `stream` is being captured it does not wait, and the captured launches
- * take their pairs from the device's plan whatever their size (sizes from
- * the last uncaptured call of the same ensemble).  Either way a pair that
+ * its sweeps) to size each launch exactly, unless the last call that waited
+ * for the same ensemble and precision found more than a fifth of its pairs
+ * beyond 2^12 register entries; in that case, and while `stream` is being
+ * captured, it does not wait, and the launches take their pairs from the
+ * device's plan whatever their size (sizes from the last call that waited
+ * for the same ensemble and precision).  Either way a pair that
  * cannot be contracted (its plan exceeds the planner's limits, a register
  * beyond 2^31 entries, or no room in the workspace for it) gets a NaN trace,
  * which fp_frame_potential reports as FP_ENUMERIC.  No pair is dropped.
