@@ -79,9 +79,15 @@ def bench_streams(torch, k):
     process's four hardware queues), so that each batch in flight has a
     hardware queue of its own."""
     import ctypes
-    hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime torch has loaded
+    try:
+        hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime torch has loaded
+    except OSError:
+        hip = None  # another runtime name: torch's own streams (slower queue layout)
     while len(_STREAMS) < k:
         h = ctypes.c_void_p()
+        if hip is None:
+            _STREAMS.append(torch.cuda.Stream())
+            continue
         if hip.hipStreamCreateWithFlags(ctypes.byref(h), 1) != 0:  # hipStreamNonBlocking
             raise RuntimeError("hipStreamCreateWithFlags failed")
         _STREAMS.append(torch.cuda.ExternalStream(h.value))
