@@ -181,6 +181,21 @@ int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int pre
 int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max,
                        double* h_F, double* h_stderr, void* stream);
 
+/*
+ * fp_set_launch_mode -- how later fp_contract_trace_batch calls of local
+ * random ensembles launch their sweeps outside stream capture (a captured
+ * call never waits, whatever the mode):
+ *   FP_LAUNCH_AUTO      as described at fp_contract_trace_batch (default);
+ *   FP_LAUNCH_WAIT      always read the planning's set-up back first and
+ *                       launch every class at its exact size;
+ *   FP_LAUNCH_WAIT_FREE never wait: the launches take their pairs from the
+ *                       device's set-up through counters.
+ * Both modes give identical traces.  Process-wide; takes effect at the next
+ * call.  Errors: FP_EINVAL (unknown mode).
+ */
+enum { FP_LAUNCH_AUTO = 0, FP_LAUNCH_WAIT = 1, FP_LAUNCH_WAIT_FREE = 2 };
+int fp_set_launch_mode(int mode);
+
 /* ---- uneven batches ------------------------------------------------------- */
 /*
  * fp_contract_trace_groups -- contract several groups of pairs with different

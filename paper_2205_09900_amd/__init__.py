@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libfp.so")
 FP_OK, FP_EINVAL, FP_ETOOBIG, FP_EDEVICE, FP_ENOTIMPL, FP_ENUMERIC = 0, -1, -2, -3, -4, -5
 BRICKWORK, LOCAL_RANDOM, HEA = 0, 1, 2
 C128, C64, BF16X3 = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_WAIT, LAUNCH_WAIT_FREE = 0, 1, 2
 
 ERROR_NAMES = {FP_EINVAL: "FP_EINVAL", FP_ETOOBIG: "FP_ETOOBIG", FP_EDEVICE: "FP_EDEVICE",
                FP_ENOTIMPL: "FP_ENOTIMPL", FP_ENUMERIC: "FP_ENUMERIC"}
@@ -31,7 +32,7 @@ EXPORTS = [
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
     "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient", "fp_log_moments",
     "fp_mlp_log_targets", "fp_mlp_link",
-    "fp_frame_potential_cv", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
+    "fp_frame_potential_cv", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
 
@@ -94,6 +95,7 @@ def _load():
         "fp_mlp_log_targets": (I, [P, I64, D, D, D, P, P]),
         "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
+        "fp_set_launch_mode": (I, [I]),
         "fp_profile_begin": (I, []),
         "fp_profile_end": (I, [P, P, P, P]),
         "fp_last_error": (ctypes.c_char_p, []),
@@ -164,6 +166,10 @@ def fp_contract_trace_batch(ens, num_pairs, precision, d_gates, d_trace, d_works
     return _check(lib.fp_contract_trace_batch(ctypes.byref(_ens(ens)), int(num_pairs), int(precision),
                                               _ptr(d_gates), _ptr(d_trace), _ptr(d_workspace), wsb,
                                               _stream(stream)))
+
+
+def fp_set_launch_mode(mode):
+    _check(lib.fp_set_launch_mode(int(mode)))
 
 
 def fp_frame_potential(d_trace, num_pairs, k_max, stream=None):

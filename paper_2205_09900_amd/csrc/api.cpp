@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -395,8 +396,31 @@ static bool capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
+static std::atomic<int> g_launch_mode{FP_LAUNCH_AUTO};
+
+static LrHint hint_of(const LrDev& d, int64_t np) {
+  LrHint h;
+  for (int k = 0; k < 5; ++k) h.frac[k] = (double)d.range[k][1] / (double)np;
+  h.hbm_workgroups = d.hbm_workgroups;
+  return h;
+}
+
+// A set-up read back without waiting: a pinned copy and the event after it.
+struct PendingHint {
+  LrDev* host = nullptr;
+  hipEvent_t done = nullptr;
+  int64_t np = 0;
+  bool pending = false;
+};
+static std::map<long long, PendingHint> g_pending;
+
 static bool lr_hint(long long key, LrHint* out) {
   std::lock_guard<std::mutex> lk(g_hint_mu);
+  auto p = g_pending.find(key);
+  if (p != g_pending.end() && p->second.pending && hipEventQuery(p->second.done) == hipSuccess) {
+    g_hints[key] = hint_of(*p->second.host, p->second.np);
+    p->second.pending = false;
+  }
   auto it = g_hints.find(key);
   if (it == g_hints.end()) return false;
   *out = it->second;
@@ -404,11 +428,40 @@ static bool lr_hint(long long key, LrHint* out) {
 }
 
 static void lr_hint_set(long long key, const LrDev& d, int64_t np) {
-  LrHint h;
-  for (int k = 0; k < 5; ++k) h.frac[k] = (double)d.range[k][1] / (double)np;
-  h.hbm_workgroups = d.hbm_workgroups;
   std::lock_guard<std::mutex> lk(g_hint_mu);
-  g_hints[key] = h;
+  g_hints[key] = hint_of(d, np);
+  auto p = g_pending.find(key);
+  if (p != g_pending.end()) p->second.pending = false;  // superseded
+}
+
+// Queue the copy of a batch's set-up on s; the next lr_hint of the key takes
+// it up once it has landed.  A copy still in flight from an earlier batch
+// is left to finish and this one is skipped.
+static int lr_hint_post(long long key, const LrDev* dev, int64_t np, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_hint_mu);
+  PendingHint& p = g_pending[key];
+  if (!p.host) {
+    if (hipHostMalloc((void**)&p.host, sizeof(LrDev), hipHostMallocDefault) != hipSuccess) {
+      p.host = nullptr;
+      (void)hipGetLastError();
+      return FP_OK;  // no refresh; the hint stays as it was
+    }
+    if (hipEventCreateWithFlags(&p.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(p.host);
+      p.host = nullptr;
+      return FP_OK;
+    }
+  }
+  if (p.pending && hipEventQuery(p.done) != hipSuccess) {
+    (void)hipGetLastError();
+    return FP_OK;
+  }
+  int rc = check_hip(hipMemcpyAsync(p.host, dev, sizeof(LrDev), hipMemcpyDeviceToHost, s), "copy set-up (hint)");
+  if (!rc) rc = check_hip(hipEventRecord(p.done, s), "hint event");
+  p.np = np;
+  p.pending = rc == FP_OK;
+  return rc;
 }
 
 // One chunk of a local random batch: plan its pairs (on s), derive its
@@ -579,6 +632,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     *out = c.aux.s[ai];
     return FP_OK;
   };
+  // flops < 0: the class's MAC count is read from the device afterwards
   auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
                           double flops) -> int {
     hipStream_t sx;
@@ -605,7 +659,10 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     else  // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
       r = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
                           : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
-    profile_launch_end(cls[k].kclass, flops, sx);
+    if (flops < 0.0)
+      profile_launch_end_dev(cls[k].kclass, j.class_macs + k, sx);
+    else
+      profile_launch_end(cls[k].kclass, flops, sx);
     return r;
   };
   // An eager batch also goes without waiting when the previous eager batch
@@ -615,7 +672,10 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // contractions/s; at S = 100 waiting is faster, 1.19 against 1.36 ms).
   LrHint hint;
   const bool hinted = lr_hint(c.key, &hint);
-  const bool wait_free = capturing(s) || (hinted && hint.frac[4] > LR_WAIT_FREE_HBM_FRAC);
+  const bool captured = capturing(s);
+  const int mode = g_launch_mode.load();
+  const bool wait_free = captured || mode == FP_LAUNCH_WAIT_FREE ||
+                         (mode == FP_LAUNCH_AUTO && hinted && hint.frac[4] > LR_WAIT_FREE_HBM_FRAC);
   if (!wait_free) {
     // Eager: read the set-up back (one wait for the plans, as the launch
     // sizes depend on them), then launch every class at its exact size, the
@@ -665,12 +725,15 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
     grid = want < grid ? want : grid;
   }
-  rc = launch_class(4, -1, dev->range[4], 0, grid, 0.0);
+  rc = launch_class(4, -1, dev->range[4], 0, grid, -1.0);
   for (int k = 3; k >= 1 && !rc; --k) {
     if (cls[k].hi <= cls[k].lo) continue;
     const int64_t gp = hinted ? (int64_t)(hint.frac[k] * 1.05 * (double)np) + 2 : 0;
-    rc = launch_class(k, k == 1 ? 2 : k - 2, dev->range[k], 0, gp, 0.0);
+    rc = launch_class(k, k == 1 ? 2 : k - 2, dev->range[k], 0, gp, -1.0);
   }
+  // An uncaptured batch refreshes the hint from its own set-up, read back
+  // without a wait and taken up by the next batch of the ensemble.
+  if (!rc && !captured) rc = lr_hint_post(c.key, dev, np, s);
   return rc;
 }
 
@@ -808,6 +871,13 @@ int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int pre
   if (!d_gates || !d_trace) return set_error(FP_EINVAL, "NULL gates or trace buffer");
   return contract_dispatch(ens, num_pairs, precision, d_gates, d_trace, d_workspace, workspace_bytes,
                            (hipStream_t)stream, 0, -1);
+}
+
+int fp_set_launch_mode(int mode) {
+  if (mode != FP_LAUNCH_AUTO && mode != FP_LAUNCH_WAIT && mode != FP_LAUNCH_WAIT_FREE)
+    return set_error(FP_EINVAL, "unknown launch mode %d", mode);
+  g_launch_mode.store(mode);
+  return FP_OK;
 }
 
 int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max, double* h_F, double* h_stderr,

@@ -16,7 +16,14 @@ struct Rec {
   int kclass;
   hipEvent_t a, b;
   double flops, bytes;
+  int deferred;  // index into g_pinned of a MAC count copied from the device, or -1
 };
+
+// Pinned host slots that receive MAC counts known only on the device (the
+// launches that do not wait for their plans); read at fp_profile_end.
+constexpr int PINNED_SLOTS = 1 << 14;
+static double* g_pinned = nullptr;
+static int g_pinned_used = 0;
 
 static std::mutex g_mu;
 static bool g_on = false;
@@ -32,6 +39,7 @@ void profile_launch_begin(int kclass, hipStream_t s) {
   g_open.kclass = kclass;
   g_open.flops = 0.0;
   g_open.bytes = 0.0;
+  g_open.deferred = -1;
   (void)hipEventCreate(&g_open.a);
   (void)hipEventCreate(&g_open.b);
   (void)hipEventRecord(g_open.a, s);
@@ -49,6 +57,22 @@ void profile_launch_end(int kclass, double flops, hipStream_t s, double bytes) {
   g_has_open = false;
 }
 
+void profile_launch_end_dev(int kclass, const double* d_macs, hipStream_t s) {
+  if (!g_on) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_has_open || g_open.kclass != kclass) return;
+  (void)hipEventRecord(g_open.b, s);
+  g_open.flops = 0.0;
+  g_open.bytes = 0.0;
+  g_open.deferred = -1;
+  if (!g_pinned) (void)hipHostMalloc((void**)&g_pinned, sizeof(double) * PINNED_SLOTS, hipHostMallocDefault);
+  if (g_pinned && g_pinned_used < PINNED_SLOTS &&
+      hipMemcpyAsync(g_pinned + g_pinned_used, d_macs, sizeof(double), hipMemcpyDeviceToHost, s) == hipSuccess)
+    g_open.deferred = g_pinned_used++;
+  g_recs.push_back(g_open);
+  g_has_open = false;
+}
+
 }  // namespace fp
 
 using namespace fp;
@@ -62,6 +86,7 @@ int fp_profile_begin(void) {
     (void)hipEventDestroy(r.b);
   }
   g_recs.clear();
+  g_pinned_used = 0;
   g_on = true;
   return FP_OK;
 }
@@ -76,13 +101,18 @@ int fp_profile_end(double* kernel_ms, int64_t* launches, double* flops, double* 
     if (bytes) bytes[c] = 0.0;
   }
   int rc = FP_OK;
+  if (g_pinned_used > 0) {  // the deferred counts are copied after their launches' end events
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = check_hip(e, "profile sync (deferred counts)");
+  }
   for (Rec& r : g_recs) {
     hipError_t e = hipEventSynchronize(r.b);
     if (e != hipSuccess && !rc) rc = check_hip(e, "profile sync");
     float ms = 0.f;
     e = hipEventElapsedTime(&ms, r.a, r.b);
     if (e != hipSuccess && !rc) rc = check_hip(e, "profile elapsed");
-    const double f = r.flops;
+    // 8 real flops per complex MAC
+    const double f = r.deferred >= 0 ? 8.0 * g_pinned[r.deferred] : r.flops;
     if (kernel_ms) kernel_ms[r.kclass] += ms;
     if (launches) launches[r.kclass] += 1;
     if (flops) flops[r.kclass] += f;
@@ -91,6 +121,7 @@ int fp_profile_end(double* kernel_ms, int64_t* launches, double* flops, double* 
     (void)hipEventDestroy(r.b);
   }
   g_recs.clear();
+  g_pinned_used = 0;
   return rc;
 }
 

@@ -188,6 +188,9 @@ enum { KCLASS_LDS16 = 0, KCLASS_LDS64 = 1, KCLASS_LDS256 = 2, KCLASS_LDS1024 = 3
 bool profiling();
 void profile_launch_begin(int kclass, hipStream_t s);
 void profile_launch_end(int kclass, double flops, hipStream_t s, double bytes = 0.0);
+// As profile_launch_end, with the launch's complex MAC count read from device
+// memory once the launch's stream reaches this point (flops = 8 x MACs).
+void profile_launch_end_dev(int kclass, const double* d_macs, hipStream_t s);
 
 // HEA (diagonal CZ ladders -> Walsh-Hadamard column transfer)
 struct HeaArgs {
