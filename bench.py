@@ -212,6 +212,30 @@ def precision_error(np, t32, t64, f32, f64):
             "rel_err_F_k": [abs(x - y) / abs(y) for x, y in zip(f32, f64)]}
 
 
+def same_gate_precision(fp, torch, np, ens, gates_per_circuit, pairs, seed):
+    """Contraction error of complex64 and BF16x3 against complex128 on the
+    same gates: float32 gates are sampled once, and the complex128 run takes
+    them widened to float64 (exactly), so only the contraction's rounding
+    differs.  Haar ensembles only (the buffer holds 2 x gates_per_circuit
+    4x4 complex gates per pair, then padding)."""
+    e = fp.Ensemble(*ens)
+    g32 = fp.sample(e, pairs, seed, 0, fp.C64)
+    nb32, nb64 = fp.fp_gate_bytes_per_pair(e, fp.C64), fp.fp_gate_bytes_per_pair(e, fp.C128)
+    nreal = 2 * gates_per_circuit * 32
+    g64 = torch.zeros(pairs * nb64, dtype=torch.uint8, device="cuda")
+    src = g32.view(pairs, nb32)[:, : 4 * nreal].contiguous().view(torch.float32)
+    g64.view(pairs, nb64)[:, : 8 * nreal].view(torch.float64).copy_(src.to(torch.float64))
+    out = {}
+    for prec, buf in ((fp.C64, g32), (fp.C128, g64), (fp.BF16X3, g32)):
+        out[prec] = fp.contract(e, buf, pairs, prec)
+    f = {p: fp.frame_potential(out[p], 3)[0] for p in out}
+    return {"pairs": pairs,
+            "c64_vs_c128": precision_error(np, torch.view_as_real(out[fp.C64]), torch.view_as_real(out[fp.C128]),
+                                           f[fp.C64], f[fp.C128]),
+            "bf16x3_vs_c128": precision_error(np, torch.view_as_real(out[fp.BF16X3]),
+                                              torch.view_as_real(out[fp.C128]), f[fp.BF16X3], f[fp.C128])}
+
+
 def suite(fp, torch, np, synth, pairs):
     out = {}
     # brickwork n = 6, depths 1..6, 2000 pairs, complex128
@@ -234,8 +258,9 @@ def suite(fp, torch, np, synth, pairs):
         r32["pairs"] = np_
         r32["c128_contractions_per_s"] = r64["contractions_per_s"]
         r32["bf16x3_contractions_per_s"] = rb3["contractions_per_s"]
-        r32["c64_vs_c128"] = precision_error(np, t32, t64, r32["F"], r64["F"])
-        r32["bf16x3_vs_c128"] = precision_error(np, tb3, t64, rb3["F"], r64["F"])
+        ngates = d // 2 * 9 + (d + 1) // 2 * 10  # 10 gates on odd layers, 9 on even ones (n = 20)
+        r32["precision_same_gates"] = same_gate_precision(fp, torch, np, (fp.BRICKWORK, 20, d), ngates,
+                                                          min(np_, 20000), seed)
         r[str(d)] = r32
     out["brickwork_n20"] = r
     # HEA n = 30, layers 1..8, complex64

@@ -414,10 +414,12 @@ struct PendingHint {
 };
 static std::map<long long, PendingHint> g_pending;
 
-static bool lr_hint(long long key, LrHint* out) {
+// take_pending: take up a pending read-back (never under stream capture,
+// where querying an event would invalidate the capture).
+static bool lr_hint(long long key, LrHint* out, bool take_pending) {
   std::lock_guard<std::mutex> lk(g_hint_mu);
   auto p = g_pending.find(key);
-  if (p != g_pending.end() && p->second.pending && hipEventQuery(p->second.done) == hipSuccess) {
+  if (take_pending && p != g_pending.end() && p->second.pending && hipEventQuery(p->second.done) == hipSuccess) {
     g_hints[key] = hint_of(*p->second.host, p->second.np);
     p->second.pending = false;
   }
@@ -671,8 +673,8 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // batch's planner run beside them (S = 200: 1.9 -> 2.4 x 10^5
   // contractions/s; at S = 100 waiting is faster, 1.19 against 1.36 ms).
   LrHint hint;
-  const bool hinted = lr_hint(c.key, &hint);
   const bool captured = capturing(s);
+  const bool hinted = lr_hint(c.key, &hint, !captured);
   const int mode = g_launch_mode.load();
   const bool wait_free = captured || mode == FP_LAUNCH_WAIT_FREE ||
                          (mode == FP_LAUNCH_AUTO && hinted && hint.frac[4] > LR_WAIT_FREE_HBM_FRAC);

@@ -10,6 +10,7 @@ import pytest
 import torch
 
 from oracle import dense, estimator, sampler
+from tolerance import floored
 
 pytestmark = pytest.mark.gpu
 
@@ -62,8 +63,7 @@ def test_no_room_for_wide_pairs_gives_nan(fp):
     assert np.isfinite(got[~wide]).all()
     want = dense.traces(sampler.sample_pairs(1, 8, 40, seed, 0, n, fp32=True))
     w = want[~wide]
-    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
-    err = np.abs(got[~wide] - w) / np.maximum(np.abs(w), 1e-3 * rms)
+    err = floored(got[~wide], w, 1)
     assert err.max() <= 1e-5, err.max()
     with pytest.raises(fp.FPError) as ei:
         fp.fp_frame_potential(tr, n, 2)
@@ -120,11 +120,9 @@ def test_graph_replay_wide_pairs_vs_dense(fp, eager_first):
     assert (peaks > 14).sum() > n // 5 and (peaks >= 18).any()
     got = capture_and_replay(fp, ens, n, seed, eager_first)
     want = dense.traces(sampler.sample_pairs(1, ens[1], ens[2], seed, 0, n, fp32=True))
-    rms = math.sqrt(float(np.mean(np.abs(want) ** 2)))
-    err = np.abs(got - want) / np.maximum(np.abs(want), 1e-3 * rms)
-    # float32 storage: the floored maximum over a batch can pass 1e-5 on a
-    # pair whose trace nearly cancels; p99 and every F^(k) stay within it
-    assert np.quantile(err, 0.99) <= 1e-5 and err.max() <= 1e-4, (np.quantile(err, 0.99), err.max())
+    err = floored(got, want, 1)
+    worst = int(np.argmax(err))
+    assert err.max() <= 1e-5, (worst, err.max(), got[worst], want[worst])
     fg, _ = estimator.frame_potential(got, 3)
     fw, _ = estimator.frame_potential(want, 3)
     for k in range(3):
