@@ -55,7 +55,7 @@ def parse():
                     help="comma list of step counts whose register widths are reported ('' = none)")
     ap.add_argument("--feasibility-pairs", type=int, default=0,
                     help="pairs sampled per step count (0: a whole batch up to 400 steps, 2000 beyond)")
-    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="length of each of the three oracle runs")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="length of each of the three oracle windows")
     ap.add_argument("--out", default="", help="also write the full record (per step count, ensembles, "
                                              "control variate) to this JSON file")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -313,29 +313,33 @@ def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
     return out
 
 
-def _cpu_worker(args):
-    depth, n, seed, first, count, deadline = args
+def _cpu_import(_):
+    import oracle.mpo  # noqa: F401
+    import oracle.sampler  # noqa: F401
+    return 0
+
+
+def _cpu_pair(args):
+    depth, n, seed, pair = args
     try:
         from threadpoolctl import threadpool_limits
         threadpool_limits(1)
     except Exception:
         pass
     from oracle import mpo, sampler
-    done = 0
-    for i in range(count):
-        if time.time() > deadline:
-            break
-        pr = sampler.sample_pairs(sampler.LOCAL_RANDOM, n, depth, seed, first + i, 1, fp32=False)
-        mpo.trace_pair(pr[0][0], pr[0][1])
-        done += 1
-    return done
+    pr = sampler.sample_pairs(sampler.LOCAL_RANDOM, n, depth, seed, pair, 1, fp32=False)
+    mpo.trace_pair(pr[0][0], pr[0][1])
+    return 1
 
 
-def cpu_baseline(n, depth, seconds, seed_base, runs=3):
-    """The oracle (MPO-zip, complex128, with its own sampler) on a time-bounded
-    sample: `runs` runs of `seconds` each, one process per core the bench may
-    use (at most 16: a GPU machine allots 16 CPUs to its one GPU), the median
-    run reported."""
+def cpu_baseline(n, depth, seed_base, seconds=8.0, runs=3):
+    """The oracle (MPO-zip, complex128, with its own sampler) on a bounded
+    sample: `runs` windows of `seconds` each over fresh pairs of the
+    workload, handed out one at a time to one process per core the bench may
+    use (at most 16: a GPU machine allots 16 CPUs to its one GPU).  Pairs still
+    running at the end of a window are dropped with their processes (so the
+    window's rate counts completed pairs only); the median window is
+    reported."""
     import multiprocessing as mp
     try:
         avail = len(os.sched_getaffinity(0))
@@ -343,23 +347,35 @@ def cpu_baseline(n, depth, seconds, seed_base, runs=3):
         avail = os.cpu_count() or 1
     workers = max(1, min(16, avail))
     seed = seed_base | (depth << 32)
-    rates, counts, walls = [], [], []
-    with mp.get_context("spawn").Pool(workers) as pool:
-        pool.map(_cpu_worker, [(depth, n, seed, 0, 0, 0.0)] * workers)  # start-up outside the timing
-        for r in range(runs):
-            deadline = time.time() + seconds
-            jobs = [(depth, n, seed, (r * workers + w) * 100000, 100000, deadline) for w in range(workers)]
+    rates, counts = [], []
+    ctx = mp.get_context("spawn")
+    for r in range(runs):
+        pool = ctx.Pool(workers)
+        try:
+            pool.map(_cpu_import, range(workers), chunksize=1)  # start-up outside the window
+            jobs = [(depth, n, seed, r * 100000 + i) for i in range(100000)]
+            it = pool.imap_unordered(_cpu_pair, jobs, chunksize=1)
             t0 = time.perf_counter()
-            done = pool.map(_cpu_worker, jobs)
+            done = 0
+            while True:
+                left = seconds - (time.perf_counter() - t0)
+                if left <= 0:
+                    break
+                try:
+                    done += it.next(timeout=left)
+                except mp.TimeoutError:
+                    break
             el = time.perf_counter() - t0
-            rates.append(sum(done) / el)
-            counts.append(int(sum(done)))
-            walls.append(el)
+        finally:
+            pool.terminate()
+            pool.join()
+        rates.append(done / el)
+        counts.append(done)
     i = sorted(range(runs), key=lambda x: rates[x])[runs // 2]
     return {"value": rates[i], "unit": "contractions/s", "cores": workers, "nproc": os.cpu_count(),
             "cpus_available": avail, "kind": "oracle", "runs": [round(x, 4) for x in rates],
-            "sample": f"median of {runs} runs of {seconds:g} s: {counts[i]} pairs of local random n={n} S={depth} "
-                      f"(own Philox sampler + MPO-zip, complex128) in {walls[i]:.1f} s, "
+            "sample": f"median of {runs} windows of {seconds:g} s over fresh pairs of local random n={n} S={depth} "
+                      f"(own Philox sampler + MPO-zip, complex128): {counts[i]} pairs completed, "
                       f"{workers} processes x 1 thread"}
 
 
@@ -475,7 +491,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.n, args.depth, args.cpu_seconds, seed_base)
+        cpu = cpu_baseline(args.n, args.depth, seed_base, args.cpu_seconds)
         progress("CPU baseline done")
 
     config = {"workload": f"local_random_n{args.n}_S{args.depth}", "n_qubits": args.n,
