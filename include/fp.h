@@ -196,6 +196,22 @@ int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max,
 enum { FP_LAUNCH_AUTO = 0, FP_LAUNCH_WAIT = 1, FP_LAUNCH_WAIT_FREE = 2 };
 int fp_set_launch_mode(int mode);
 
+/*
+ * fp_frame_potential_noalloc -- fp_frame_potential for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same reduction, kernels and result
+ * bit for bit, with its partial results in a static scratch array of the
+ * library (128 KiB per device, held until the process ends) instead of
+ * memory allocated per call.  It calls no allocating routine.  Every call on
+ * a device shares that device's array, so calls that overlap on one device
+ * (on different streams or host threads) race and must be serialised by the
+ * caller.  The reduction needs at most about 107 KiB for any num_pairs; a
+ * larger need would fail with FP_ETOOBIG.  Synchronises `stream`.
+ * Errors: as fp_frame_potential, FP_ETOOBIG.
+ */
+int fp_frame_potential_noalloc(const double* d_trace, int64_t num_pairs, int k_max,
+                               double* h_F, double* h_stderr, void* stream);
+
 /* ---- uneven batches ------------------------------------------------------- */
 /*
  * fp_contract_trace_groups -- contract several groups of pairs with different

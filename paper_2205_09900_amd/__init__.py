@@ -32,7 +32,7 @@ EXPORTS = [
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
     "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient", "fp_log_moments",
     "fp_mlp_log_targets", "fp_mlp_link",
-    "fp_frame_potential_cv", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
+    "fp_frame_potential_cv", "fp_frame_potential_noalloc", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
 
@@ -96,6 +96,7 @@ def _load():
         "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_set_launch_mode": (I, [I]),
+        "fp_frame_potential_noalloc": (I, [P, I64, I, P, P, P]),
         "fp_profile_begin": (I, []),
         "fp_profile_end": (I, [P, P, P, P]),
         "fp_last_error": (ctypes.c_char_p, []),
@@ -176,6 +177,13 @@ def fp_frame_potential(d_trace, num_pairs, k_max, stream=None):
     f = (ctypes.c_double * k_max)()
     se = (ctypes.c_double * k_max)()
     _check(lib.fp_frame_potential(_ptr(d_trace), int(num_pairs), int(k_max), f, se, _stream(stream)))
+    return list(f), list(se)
+
+
+def fp_frame_potential_noalloc(d_trace, num_pairs, k_max, stream=None):
+    f = (ctypes.c_double * k_max)()
+    se = (ctypes.c_double * k_max)()
+    _check(lib.fp_frame_potential_noalloc(_ptr(d_trace), int(num_pairs), int(k_max), f, se, _stream(stream)))
     return list(f), list(se)
 
 

@@ -890,6 +890,14 @@ int fp_frame_potential(const double* d_trace, int64_t num_pairs, int k_max, doub
   return run_frame_potential(d_trace, num_pairs, k_max, h_F, h_stderr, (hipStream_t)stream);
 }
 
+int fp_frame_potential_noalloc(const double* d_trace, int64_t num_pairs, int k_max, double* h_F, double* h_stderr,
+                               void* stream) {
+  if (!d_trace || !h_F) return set_error(FP_EINVAL, "NULL trace or output");
+  if (num_pairs < 1) return set_error(FP_EINVAL, "num_pairs must be >= 1");
+  if (k_max < 1 || k_max > 8) return set_error(FP_EINVAL, "k_max %d outside 1..8", k_max);
+  return run_frame_potential_noalloc(d_trace, num_pairs, k_max, h_F, h_stderr, (hipStream_t)stream);
+}
+
 int fp_frame_potential_cv(const double* d_trace_B, const float* d_g_B, int64_t nB, const float* d_g_C, int64_t nC,
                           int k, double c, double* h_F, double* h_stderr, void* stream) {
   if (!d_trace_B || !d_g_B || !h_F) return set_error(FP_EINVAL, "NULL argument");

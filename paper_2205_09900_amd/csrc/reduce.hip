@@ -10,6 +10,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace fp {
@@ -159,13 +161,15 @@ static int red_blocks(int64_t n) {
   return (int)b;
 }
 
-int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
-                        hipStream_t s) {
+static size_t red_scratch_bytes(int nb) {
+  return sizeof(double) * (2 * (size_t)nb + 2 + 2 * KMAX + 1) + sizeof(Welford) * nb * KMAX;
+}
+
+// The reduction on a scratch area of red_scratch_bytes(red_blocks(n)) bytes
+// (no allocation; every partial is written before it is read).
+static int frame_potential_on(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se, void* ws,
+                              hipStream_t s, bool free_ws) {
   const int nb = red_blocks(n);
-  const size_t bytes = sizeof(double) * (2 * (size_t)nb + 2 + 2 * KMAX + 1) + sizeof(Welford) * nb * KMAX;
-  void* ws = nullptr;
-  int rc = check_hip(hipMallocAsync(&ws, bytes, s), "hipMallocAsync(reduce)");
-  if (rc) return rc;
   double* part = (double*)ws;
   double* scale = part + 2 * nb;
   double* out = scale + 2;
@@ -174,10 +178,10 @@ int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F,
   hipLaunchKernelGGL(red_max_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scale);
   hipLaunchKernelGGL(red_moments_kernel, dim3(nb), dim3(RED_THREADS), 0, s, d_trace, n, kmax, scale, wpart);
   hipLaunchKernelGGL(red_moments_final, dim3(1), dim3(64), 0, s, wpart, nb, kmax, scale, out);
-  rc = check_launch("frame_potential");
+  int rc = check_launch("frame_potential");
   double host[2 * KMAX + 1];
   if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy F");
-  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(reduce)");
+  int rc2 = free_ws ? check_hip(hipFreeAsync(ws, s), "hipFreeAsync(reduce)") : FP_OK;
   int rc3 = check_hip(hipStreamSynchronize(s), "sync(reduce)");
   if (rc) return rc;
   if (rc2) return rc2;
@@ -189,6 +193,56 @@ int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F,
     if (h_se) h_se[k] = host[2 * k + 1];
   }
   return FP_OK;
+}
+
+int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
+                        hipStream_t s) {
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, red_scratch_bytes(red_blocks(n)), s), "hipMallocAsync(reduce)");
+  if (rc) return rc;
+  return frame_potential_on(d_trace, n, kmax, h_F, h_se, ws, s, true);
+}
+
+// ---- the reduction without allocation -------------------------------------------
+// One file-scope scratch array per device for callers that cannot allocate.
+// The largest reduction needs red_scratch_bytes(RED_MAX_BLOCKS) bytes (about
+// 107 KiB) whatever the number of traces.  Host code never passes the
+// array's name to a kernel: each device's address of it is taken once with
+// hipGetSymbolAddress, with that device current, and kept per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+static int scratch_of_current_device(void** out) {
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_error(FP_EDEVICE, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    if (!p) return set_error(FP_EDEVICE, "no address for the scratch array on device %d", dev);
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FP_OK;
+}
+
+int run_frame_potential_noalloc(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
+                                hipStream_t s) {
+  const size_t need = red_scratch_bytes(red_blocks(n));
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return set_error(FP_ETOOBIG, "reduction needs %zu bytes of scratch, the static array holds %zu", need,
+                     NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  int rc = scratch_of_current_device(&ws);
+  if (rc) return rc;
+  return frame_potential_on(d_trace, n, kmax, h_F, h_se, ws, s, false);
 }
 
 // ---- control variate ----------------------------------------------------------

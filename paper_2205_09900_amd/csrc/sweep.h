@@ -207,6 +207,10 @@ int hea_bits(int L);
 
 int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
                         hipStream_t s);
+// As run_frame_potential, on the library's static scratch array of the
+// current device (no allocation).
+int run_frame_potential_noalloc(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
+                                hipStream_t s);
 int run_log_moments(const double* tr, int64_t n, double eps, double* mu, double* sigma, hipStream_t s);
 int run_log_targets(const double* tr, int64_t n, double eps, double mu, double sigma, float* t, hipStream_t s);
 int run_link(const float* y, int64_t n, int k, double mu, double sigma, double shift, float* g, hipStream_t s);
