@@ -268,6 +268,55 @@ def suite(fp, torch, np, synth, pairs):
     for L in range(1, 9):
         r[str(L)], _ = fixed_topology(fp, torch, fp.HEA, 30, L, pairs, fp.C64, synth.workload_seed(3, L))
     out["hea_n30"] = r
+    out["hea_n30_mixed_launch"] = hea_mixed(fp, torch, pairs)
+    return out
+
+
+def hea_mixed(fp, torch, pairs, steps=3):
+    """The uneven-depth workload: HEA n = 30, L = 1..8, `pairs` pairs per L,
+    in one fp_contract_trace_groups launch -- with the library's default
+    launch choices, then with choices from fp_autotune -- against one
+    fp_contract_trace_batch call per L on the same gates.  Contraction only
+    (the gates are sampled beforehand); F^(1), F^(2) per L from the tuned
+    launch."""
+    import synth
+    ens = [fp.Ensemble(fp.HEA, 30, L) for L in range(1, 9)]
+    bufs = [fp.sample(e, pairs, synth.workload_seed(3, e.depth), 0, fp.C64) for e in ens]
+    groups = [(i, fp.C64, 0, pairs) for i in range(len(ens))]
+    tr = torch.empty(2 * pairs * len(ens), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(256, fp.fp_workspace_bytes_groups(ens, groups)), dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return pairs * len(ens) * steps / (time.perf_counter() - t0)
+
+    def mixed():
+        fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
+
+    def per_l():
+        for i, e in enumerate(ens):
+            fp.fp_contract_trace_batch(e, pairs, fp.C64, bufs[i], tr[2 * i * pairs: 2 * (i + 1) * pairs])
+
+    out = {"pairs_per_L": pairs, "default_mixed_launch_pairs_per_s": timed(mixed)}
+    t0 = time.perf_counter()
+    choices = {}
+    for e in ens:
+        c = fp.fp_autotune(e, fp.C64)
+        choices[str(e.depth)] = [fp.AUTOTUNE_CLASSES[c // 3], fp.AUTOTUNE_TASK_FLOPS[c % 3]]
+    out["autotune_s"] = time.perf_counter() - t0
+    out["choices"] = choices
+    out["tuned_mixed_launch_pairs_per_s"] = timed(mixed)
+    out["per_L_calls_pairs_per_s"] = timed(per_l)
+    mixed()
+    out["F_per_L"] = {str(e.depth): fp.fp_frame_potential(tr[2 * i * pairs: 2 * (i + 1) * pairs], pairs, 2)[0]
+                      for i, e in enumerate(ens)}
+    progress(f"HEA n=30 L=1..8 mixed: default {out['default_mixed_launch_pairs_per_s']:.4g}, tuned "
+             f"{out['tuned_mixed_launch_pairs_per_s']:.4g}, per-L calls {out['per_L_calls_pairs_per_s']:.4g} pairs/s")
     return out
 
 

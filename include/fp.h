@@ -231,14 +231,25 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
                              void* d_ws, size_t ws_bytes, void* stream);
 
 /*
- * fp_autotune -- time the candidate tile shapes of the persistent sweep for
- * this ensemble and precision on the current device with synthetic gates
- * drawn by fp_sample_gates, keep the fastest in the library's tuning table,
- * and write its id to *out_choice.  Synchronous.  Uses d_ws (ws_bytes) as
- * scratch, which must hold fp_autotune_workspace_bytes bytes.
- * fp_autotune_table writes the table as text (one line per tuned key) into
- * buf (capacity cap, NUL-terminated) and fp_autotune_load reads such text.
- * Errors: FP_EINVAL, FP_EDEVICE.
+ * fp_autotune -- time the launch choices of the persistent sweep of
+ * fp_contract_trace_groups for one fixed-topology ensemble (brickwork or
+ * HEA whose register fits LDS) and precision on the current device, with
+ * synthetic gates drawn by fp_sample_gates, keep the fastest in the
+ * library's tuning table, and write its index to *out_choice:
+ *   choice = 3 * lane_class + task_size,
+ *   lane_class 0: 64 lanes per pair, 4 pairs per workgroup (registers up to
+ *                 2^10 entries, 2^9 in FP_C128); 1: one workgroup per pair;
+ *   task_size 0, 1, 2: about 5e6, 2e7, 8e7 algorithmic flops per task taken
+ *                 from the launch's counter.
+ * fp_contract_trace_groups uses the table's entry of every group's ensemble
+ * and precision (else class 0 where the register fits and 2e7 flops per
+ * task).  Synchronous.  Uses d_ws (ws_bytes) as scratch, which must hold
+ * fp_autotune_workspace_bytes bytes (0 for an ensemble it cannot tune).
+ * fp_autotune_table writes the table as text, one line per tuned key,
+ *   "<arch> <ansatz> <n> <depth> <precision> small|large <task flops> <ms>",
+ * into buf (capacity cap, NUL-terminated); fp_autotune_load reads such text.
+ * Errors: FP_EINVAL, FP_ETOOBIG (workspace), FP_ENOTIMPL (local random or
+ * a boundary beyond LDS), FP_EDEVICE.
  */
 size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision);
 int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_bytes,

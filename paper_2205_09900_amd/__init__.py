@@ -329,7 +329,9 @@ def fp_autotune(ens, precision, d_ws=None, stream=None):
     return choice.value
 
 
-TILE_NAMES = ("16x16", "64x4", "64x1", "256x1", "512x1", "1024x1")
+# fp_autotune's choices: 3 * lane class + task size
+AUTOTUNE_CLASSES = ("small", "large")
+AUTOTUNE_TASK_FLOPS = (5e6, 2e7, 8e7)
 
 
 def fp_autotune_table():

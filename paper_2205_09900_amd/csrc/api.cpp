@@ -312,8 +312,7 @@ static int choose_lds_tile(int bits) {
 int tile_pairs(int tile) { return tile == TILE_16x16 ? 16 : tile == TILE_64x4 ? 4 : 1; }
 
 int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates,
-                              double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset,
-                              int tile_override) {
+                              double* trace, void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
   DevPlan dp;
   int rc = get_brickwork_plan(e->n_qubits, e->depth, &dp);
   if (rc) return rc;
@@ -333,7 +332,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   const int peak = dp.hdr.peak_bits;
   const int elem = sweep_elem_bytes(precision);
   if (peak <= lds_bits_max(precision)) {
-    int tile = tile_override >= 0 ? tile_override : tune_lookup(e, precision, choose_lds_tile(peak));
+    int tile = choose_lds_tile(peak);
     int cap = peak < 2 ? 2 : peak;
     if ((int64_t)tile_pairs(tile) * ((int64_t)elem << cap) > 160 * 1024) tile = choose_lds_tile(peak);
     a.cap_bits = cap;
@@ -792,7 +791,7 @@ double hea_flops_per_pair(int n, int L) {
 }
 
 int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
-                        hipStream_t s, int64_t trace_offset, int tile_override) {
+                        hipStream_t s, int64_t trace_offset) {
   HeaArgs a;
   a.gates = (const unsigned char*)gates;
   a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
@@ -804,10 +803,7 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
   a.bf3 = precision == FP_BF16X3 ? 1 : 0;
   const int m = hea_bits(e->depth);
   if (m > lds_bits_max(precision)) return set_error(FP_ETOOBIG, "HEA boundary of %d bits exceeds LDS", m);
-  int def = m <= 6 ? TILE_16x16 : m <= 10 ? TILE_64x4 : m <= 12 ? TILE_256x1 : TILE_1024x1;
-  int tile = tile_override >= 0 ? tile_override : tune_lookup(e, precision, def);
-  const size_t elem = precision == FP_C128 ? 16 : 8;
-  if ((size_t)tile_pairs(tile) * (elem << m) > 140 * 1024) tile = def;
+  const int tile = m <= 6 ? TILE_16x16 : m <= 10 ? TILE_64x4 : m <= 12 ? TILE_256x1 : TILE_1024x1;
   profile_launch_begin(KCLASS_HEA, s);
   int rc = launch_hea(a, precision, tile, s);
   profile_launch_end(KCLASS_HEA, hea_flops_per_pair(e->n_qubits, e->depth) * (double)num_pairs, s);
@@ -815,12 +811,12 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
 }
 
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
-                      void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset, int tile_override) {
+                      void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
   if (e->ansatz == FP_BRICKWORK_HAAR)
-    return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset, tile_override);
+    return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset);
   if (e->ansatz == FP_LOCAL_RANDOM_HAAR)
     return contract_local_random(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset);
-  return contract_hea(e, num_pairs, precision, gates, trace, s, trace_offset, tile_override);
+  return contract_hea(e, num_pairs, precision, gates, trace, s, trace_offset);
 }
 
 }  // namespace fp
@@ -872,7 +868,7 @@ int fp_contract_trace_batch(const fp_ensemble_t* ens, int64_t num_pairs, int pre
   if (num_pairs == 0) return FP_OK;
   if (!d_gates || !d_trace) return set_error(FP_EINVAL, "NULL gates or trace buffer");
   return contract_dispatch(ens, num_pairs, precision, d_gates, d_trace, d_workspace, workspace_bytes,
-                           (hipStream_t)stream, 0, -1);
+                           (hipStream_t)stream, 0);
 }
 
 int fp_set_launch_mode(int mode) {

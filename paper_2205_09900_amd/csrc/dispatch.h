@@ -31,10 +31,10 @@ int tile_pairs(int tile);
 double hea_flops_per_pair(int n, int L);
 int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precision, size_t* out);
 int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
-                       void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset, int tile_override);
+                       void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset);
 int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
                           void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset);
 int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
-                 hipStream_t s, int64_t trace_offset, int tile_override);
+                 hipStream_t s, int64_t trace_offset);
 
 }  // namespace fp

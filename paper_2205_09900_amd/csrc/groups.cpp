@@ -25,32 +25,49 @@ struct GroupPlan {
   int cls;           // PCLASS_* for the persistent route
   int bits;          // LDS boundary bits
   double pair_cost;  // algorithmic flops of one pair
+  double task_flops; // algorithmic flops per task
   int per_task;      // pairs per task
   int64_t ntasks;
   size_t sep_ws;     // workspace of the separate route
   DevPlan plan;      // brickwork
 };
 
-// Pairs per task: about 2e7 flops of work per task, between 1 and 256 pairs.
-int pairs_per_task(double cost) {
-  double c = 2e7 / (cost > 1.0 ? cost : 1.0);
+constexpr double DEFAULT_TASK_FLOPS = 2e7;
+
+// Pairs per task: about task_flops of work per task, between 1 and 256 pairs.
+int pairs_per_task(double cost, double task_flops) {
+  double c = task_flops / (cost > 1.0 ? cost : 1.0);
   if (c < 1.0) c = 1.0;
   if (c > 256.0) c = 256.0;
   return (int)c;
 }
 
-int plan_group(const fp_ensemble_t* e, const fp_group_t* g, bool upload_plan, GroupPlan* gp) {
+// Lane class and task size of a persistent group: `force` if given, else the
+// tuning table's entry, else 64 lanes for registers up to 2^small_bits
+// entries and a whole workgroup beyond, with DEFAULT_TASK_FLOPS per task.
+void choose_launch(const fp_ensemble_t* e, int prec, int bits, const GroupLaunch* force, GroupPlan* gp) {
+  const int small_bits = prec == FP_C128 ? 9 : 10;  // 64 lanes x 4 pairs per workgroup
+  GroupLaunch c{bits <= small_bits ? PCLASS_SMALL : PCLASS_LARGE, DEFAULT_TASK_FLOPS};
+  GroupLaunch t;
+  if (force)
+    c = *force;
+  else if (tune_group_lookup(e, prec, &t))
+    c = t;
+  if (c.cls == PCLASS_SMALL && bits > small_bits) c.cls = PCLASS_LARGE;  // the register must fit 4 per workgroup
+  gp->cls = c.cls;
+  gp->task_flops = c.task_flops > 0.0 ? c.task_flops : DEFAULT_TASK_FLOPS;
+}
+
+int plan_group(const fp_ensemble_t* e, const fp_group_t* g, bool upload_plan, const GroupLaunch* force,
+               GroupPlan* gp) {
   memset(gp, 0, sizeof(*gp));
   const int prec = g->precision;
-  const int small_bits = prec == FP_C128 ? 9 : 10;  // 64 lanes x 4 pairs per workgroup
   if (e->ansatz == FP_HEA_RYRZ_CZ) {
     gp->bits = hea_bits(e->depth);
     gp->pair_cost = hea_flops_per_pair(e->n_qubits, e->depth);
     if (gp->bits > lds_bits_max(prec)) return set_error(FP_ETOOBIG, "HEA boundary of %d bits exceeds LDS", gp->bits);
     gp->route = ROUTE_PERSISTENT;
-    const int def = gp->bits <= small_bits ? PCLASS_SMALL : PCLASS_LARGE;
-    const int tile = tune_lookup(e, prec, -1);
-    gp->cls = tile < 0 ? def : (tile_pairs(tile) > 1 && gp->bits <= small_bits ? PCLASS_SMALL : PCLASS_LARGE);
+    choose_launch(e, prec, gp->bits, force, gp);
   } else if (e->ansatz == FP_BRICKWORK_HAAR) {
     int rc = 0;
     if (upload_plan) {
@@ -68,7 +85,7 @@ int plan_group(const fp_ensemble_t* e, const fp_group_t* g, bool upload_plan, Gr
     }
     if (gp->bits <= lds_bits_max(prec)) {
       gp->route = ROUTE_PERSISTENT;
-      gp->cls = gp->bits <= small_bits ? PCLASS_SMALL : PCLASS_LARGE;
+      choose_launch(e, prec, gp->bits < 2 ? 2 : gp->bits, force, gp);
     } else {
       gp->route = ROUTE_SEPARATE;
     }
@@ -82,7 +99,7 @@ int plan_group(const fp_ensemble_t* e, const fp_group_t* g, bool upload_plan, Gr
     if (rc) return rc;
     gp->sep_ws = (b + 255) & ~(size_t)255;
   } else {
-    gp->per_task = pairs_per_task(gp->pair_cost);
+    gp->per_task = pairs_per_task(gp->pair_cost, gp->task_flops);
     gp->ntasks = (g->num_pairs + gp->per_task - 1) / gp->per_task;
   }
   return FP_OK;
@@ -118,15 +135,15 @@ int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_grou
   if (!out_bytes) return set_error(FP_EINVAL, "out_bytes is NULL");
   size_t total = 256 + (size_t)n_groups * sizeof(GroupDesc);
   total = (total + 255) & ~(size_t)255;
-  int64_t ntasks = 0;
+  int64_t ntasks = 0;  // at most one task per pair, whatever the launch choice
   for (int g = 0; g < n_groups; ++g) {
     GroupPlan gp;
-    rc = plan_group(&ens[groups[g].ensemble_index], &groups[g], false, &gp);
+    rc = plan_group(&ens[groups[g].ensemble_index], &groups[g], false, nullptr, &gp);
     if (rc) return rc;
     if (gp.route == ROUTE_SEPARATE)
       total += gp.sep_ws;
     else
-      ntasks += gp.ntasks;
+      ntasks += groups[g].num_pairs;
   }
   total += (size_t)ntasks * sizeof(Task) + 6 * 256;
   *out_bytes = total;
@@ -135,11 +152,21 @@ int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_grou
 
 int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups, int n_groups,
                              const void* const* d_gates, double* d_trace, void* d_ws, size_t ws_bytes, void* stream) {
+  return contract_groups(ens, n_ens, groups, n_groups, d_gates, d_trace, d_ws, ws_bytes, (hipStream_t)stream,
+                         nullptr);
+}
+
+}  // extern "C"
+
+namespace fp {
+
+int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups, int n_groups,
+                    const void* const* d_gates, double* d_trace, void* d_ws, size_t ws_bytes, hipStream_t s,
+                    const GroupLaunch* force) {
   int rc = check_groups(ens, n_ens, groups, n_groups);
   if (rc) return rc;
   if (n_groups == 0) return FP_OK;
   if (!d_gates || !d_trace) return set_error(FP_EINVAL, "NULL gates or trace");
-  hipStream_t s = (hipStream_t)stream;
   size_t need = 0;
   rc = fp_workspace_bytes_groups(ens, n_ens, groups, n_groups, &need);
   if (rc) return rc;
@@ -156,7 +183,7 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
     const fp_group_t& gr = groups[g];
     if (gr.num_pairs > 0 && !d_gates[g]) return set_error(FP_EINVAL, "group %d: NULL gate buffer", g);
     GroupPlan& gp = gps[g];
-    rc = plan_group(e, &gr, true, &gp);
+    rc = plan_group(e, &gr, true, force, &gp);
     if (rc) return rc;
     GroupDesc& d = descs[g];
     memset(&d, 0, sizeof(d));
@@ -272,10 +299,10 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
                                  descs[g].trace_offset);
     else
       rc = contract_brickwork(e, groups[g].num_pairs, groups[g].precision, gg, d_trace, w + off, gps[g].sep_ws, s,
-                              descs[g].trace_offset, -1);
+                              descs[g].trace_offset);
     off += gps[g].sep_ws;
   }
   return rc;
 }
 
-}  // extern "C"
+}  // namespace fp

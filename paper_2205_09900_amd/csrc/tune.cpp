@@ -1,8 +1,15 @@
-// Autotuner of the sweep tile (lanes per pair x pairs per workgroup).
-// Candidates are timed on the device with HIP events on synthetic gates
-// drawn by fp_sample_gates; the fastest is kept in a table keyed by the
-// device architecture, the ensemble and the precision.  The table can be
-// written out and read back as text.
+// Autotuner of the persistent sweep over groups (fp_contract_trace_groups).
+//
+// For one ensemble and precision it times the candidate launch choices of a
+// group on the device -- the lane class (64 lanes with four pairs per
+// workgroup, or a whole workgroup per pair; the first only while the
+// register fits four times in LDS) and the work per task the persistent
+// workgroups take from their counter -- on synthetic pairs drawn by
+// fp_sample_gates, and keeps the fastest in a table keyed by the device
+// architecture, the ensemble and the precision.  fp_contract_trace_groups
+// reads the table for every group it launches.  The table can be written
+// out and read back as text.  Every candidate runs the same kernels, with the
+// same shapes, as untuned launches of some register width.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
@@ -17,6 +24,7 @@
 #include "dispatch.h"
 #include "internal.h"
 #include "layout.h"
+#include "sched.h"
 #include "sweep.h"
 #include "tune.h"
 
@@ -26,11 +34,17 @@ namespace {
 
 using Key = std::tuple<std::string, int, int, int, int>;  // arch, ansatz, n, depth, precision
 struct Entry {
-  int tile;
+  GroupLaunch launch;
   double ms;
 };
 std::mutex g_mu;
 std::map<Key, Entry> g_table;
+
+// Candidates: choice = 3 * class + task size index.
+constexpr double TASK_FLOPS[3] = {5e6, 2e7, 8e7};
+constexpr int NUM_CHOICES = 6;
+
+GroupLaunch choice_launch(int c) { return GroupLaunch{c / 3, TASK_FLOPS[c % 3]}; }
 
 std::string arch_name() {
   int dev = 0;
@@ -48,30 +62,7 @@ std::string arch_name() {
   return c == std::string::npos ? a : a.substr(0, c);
 }
 
-const char* tile_name(int t) {
-  static const char* names[NUM_TILES] = {"16x16", "64x4", "64x1", "256x1", "512x1", "1024x1"};
-  return t >= 0 && t < NUM_TILES ? names[t] : "?";
-}
-
-int lanes_of(int t) { return t == TILE_16x16 ? 16 : (t == TILE_64x4 || t == TILE_64x1) ? 64 : t == TILE_256x1 ? 256 : t == TILE_512x1 ? 512 : 1024; }
-
-// LDS bytes of one workgroup for a tile and a boundary of `bits` bits.
-size_t tile_lds(int ansatz, int t, int bits, int precision) {
-  const size_t rb = precision == FP_C128 ? 8 : 4;
-  const int nt = lanes_of(t);
-  const int k = nt <= 16 ? 16 : nt <= 64 ? 32 : 64;
-  size_t per;
-  if (ansatz == FP_HEA_RYRZ_CZ) {
-    const int h = bits / 2;
-    per = bits == 0 ? (size_t)nt * 16
-                    : (((size_t)1 << bits) + ((size_t)1 << (h + 1)) + ((size_t)1 << (bits - h + 1))) * 2 * rb +
-                          (size_t)bits * 64 + 16;
-  } else {
-    per = ((2 * rb) << bits) + (size_t)k * (32 * rb + 8);
-  }
-  return per * tile_pairs(t);
-}
-
+// Register width and algorithmic flops of one pair of a fixed-topology ensemble.
 int ensemble_bits(const fp_ensemble_t* e, int* bits, double* cost) {
   if (e->ansatz == FP_HEA_RYRZ_CZ) {
     *bits = hea_bits(e->depth);
@@ -81,25 +72,32 @@ int ensemble_bits(const fp_ensemble_t* e, int* bits, double* cost) {
   int32_t peak = 0;
   double macs = 0.0;
   int rc = fp_plan_info(e, nullptr, &peak, &macs, nullptr);
-  *bits = peak;
+  *bits = peak < 2 ? 2 : peak;
   *cost = 8.0 * macs;
   return rc;
 }
 
+// Pairs timed per candidate: about 4e9 flops of work, 2^12 .. 2^16 pairs.
 int64_t tune_pairs(double cost) {
   double p = 4e9 / (cost > 1.0 ? cost : 1.0);
-  if (p < 512) p = 512;
+  if (p < 4096) p = 4096;
   if (p > 65536) p = 65536;
   return (int64_t)p;
 }
 
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+const char* class_name(int c) { return c == PCLASS_SMALL ? "small" : "large"; }
+
 }  // namespace
 
-int tune_lookup(const fp_ensemble_t* e, int precision, int fallback) {
+bool tune_group_lookup(const fp_ensemble_t* e, int precision, GroupLaunch* out) {
   std::lock_guard<std::mutex> lk(g_mu);
-  if (g_table.empty()) return fallback;
+  if (g_table.empty()) return false;
   auto it = g_table.find(Key(arch_name(), e->ansatz, e->n_qubits, e->depth, precision));
-  return it == g_table.end() ? fallback : it->second.tile;
+  if (it == g_table.end()) return false;
+  *out = it->second.launch;
+  return true;
 }
 
 }  // namespace fp
@@ -114,57 +112,58 @@ size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision) {
   double cost = 0.0;
   if (ensemble_bits(ens, &bits, &cost)) return 0;
   const int64_t np = tune_pairs(cost);
+  fp_group_t g{0, precision, 0, np};
   size_t ws = 0;
-  if (workspace_bytes_impl(ens, np, precision, &ws)) return 0;
-  return (size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision) + 16 * (size_t)np +
-         ((ws + 255) & ~(size_t)255) + 512;
+  if (fp_workspace_bytes_groups(ens, 1, &g, 1, &ws)) return 0;
+  return round256((size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision)) +
+         round256(16 * (size_t)np) + round256(ws);
 }
-
-// The device timing loop below is switched off: its first run on the GPU
-// stopped responding and the cause has not been found.  Tables written
-// elsewhere can still be loaded with fp_autotune_load and are used by the
-// dispatch.
-static const bool kTimingEnabled = false;
 
 int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_bytes, int* out_choice, void* stream) {
   int rc = check_ensemble(ens);
   if (rc) return rc;
-  if (!kTimingEnabled) return set_error(FP_ENOTIMPL, "device timing of the autotuner is switched off in this build");
   if ((rc = check_precision(precision))) return rc;
-  if (precision == FP_BF16X3) return set_error(FP_ENOTIMPL, "no tiles to tune for BF16x3");
   if (ens->ansatz == FP_LOCAL_RANDOM_HAAR)
-    return set_error(FP_ENOTIMPL, "local random pairs choose their tile by boundary size");
+    return set_error(FP_ENOTIMPL, "local random pairs are planned per pair and launched by register width");
   if (!out_choice) return set_error(FP_EINVAL, "out_choice is NULL");
-  const size_t need = fp_autotune_workspace_bytes(ens, precision);
-  if (!d_ws || ws_bytes < need) return set_error(FP_ETOOBIG, "autotune needs %zu bytes of workspace", need);
   int bits = 0;
   double cost = 0.0;
   if ((rc = ensemble_bits(ens, &bits, &cost))) return rc;
-  if (bits > lds_bits_max(precision)) return set_error(FP_ENOTIMPL, "boundaries beyond LDS have one kernel shape");
+  if (bits > lds_bits_max(precision))
+    return set_error(FP_ENOTIMPL, "boundaries beyond LDS do not run in the persistent sweep");
+  const size_t need = fp_autotune_workspace_bytes(ens, precision);
+  if (need == 0) return set_error(FP_EINVAL, "no workspace size for this ensemble");
+  if (!d_ws || ws_bytes < need) return set_error(FP_ETOOBIG, "autotune needs %zu bytes of workspace", need);
   hipStream_t s = (hipStream_t)stream;
   const int64_t np = tune_pairs(cost);
   unsigned char* w = (unsigned char*)d_ws;
   const size_t gbytes = (size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
   void* gates = w;
-  double* trace = (double*)(w + ((gbytes + 255) & ~(size_t)255));
-  unsigned char* cws = (unsigned char*)trace + ((16 * (size_t)np + 255) & ~(size_t)255);
-  const size_t cws_bytes = ws_bytes - (size_t)(cws - w);
+  double* trace = (double*)(w + round256(gbytes));
+  unsigned char* gws = (unsigned char*)trace + round256(16 * (size_t)np);
+  const size_t gws_bytes = ws_bytes - (size_t)(gws - w);
   rc = fp_sample_gates(ens, np, 0x7E57ull, 0, precision, gates, gbytes, stream);
   if (rc) return rc;
+  const fp_group_t grp{0, precision, 0, np};
+  const void* gptr[1] = {gates};
+  const int small_bits = precision == FP_C128 ? 9 : 10;
   hipEvent_t a, b;
   if ((rc = check_hip(hipEventCreate(&a), "event"))) return rc;
-  if ((rc = check_hip(hipEventCreate(&b), "event"))) return rc;
+  if ((rc = check_hip(hipEventCreate(&b), "event"))) {
+    (void)hipEventDestroy(a);
+    return rc;
+  }
   int best = -1;
   double best_ms = 1e300;
-  for (int t = 0; t < NUM_TILES && !rc; ++t) {
-    if (tile_lds(ens->ansatz, t, bits < 2 ? 2 : bits, precision) > 150 * 1024) continue;
-    if (lanes_of(t) > 64 * 16) continue;
+  for (int c = 0; c < NUM_CHOICES && !rc; ++c) {
+    const GroupLaunch gl = choice_launch(c);
+    if (gl.cls == PCLASS_SMALL && bits > small_bits) continue;  // four registers must fit one workgroup's LDS
     // warm-up, then the median of three timed runs
-    rc = contract_dispatch(ens, np, precision, gates, trace, cws, cws_bytes, s, 0, t);
+    rc = contract_groups(ens, 1, &grp, 1, gptr, trace, gws, gws_bytes, s, &gl);
     std::vector<double> ms;
     for (int r = 0; r < 3 && !rc; ++r) {
       rc = check_hip(hipEventRecord(a, s), "record");
-      if (!rc) rc = contract_dispatch(ens, np, precision, gates, trace, cws, cws_bytes, s, 0, t);
+      if (!rc) rc = contract_groups(ens, 1, &grp, 1, gptr, trace, gws, gws_bytes, s, &gl);
       if (!rc) rc = check_hip(hipEventRecord(b, s), "record");
       if (!rc) rc = check_hip(hipEventSynchronize(b), "sync");
       float el = 0.f;
@@ -175,16 +174,16 @@ int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_b
     std::sort(ms.begin(), ms.end());
     if (ms[1] < best_ms) {
       best_ms = ms[1];
-      best = t;
+      best = c;
     }
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   if (rc) return rc;
-  if (best < 0) return set_error(FP_ENOTIMPL, "no tile fits");
+  if (best < 0) return set_error(FP_ENOTIMPL, "no launch choice fits");
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_table[Key(arch_name(), ens->ansatz, ens->n_qubits, ens->depth, precision)] = Entry{best, best_ms};
+    g_table[Key(arch_name(), ens->ansatz, ens->n_qubits, ens->depth, precision)] = Entry{choice_launch(best), best_ms};
   }
   *out_choice = best;
   return FP_OK;
@@ -197,9 +196,9 @@ int fp_autotune_table(char* buf, size_t cap) {
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto& kv : g_table) {
       char line[256];
-      snprintf(line, sizeof(line), "%s %d %d %d %d %s %.6f\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
-               std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first), tile_name(kv.second.tile),
-               kv.second.ms);
+      snprintf(line, sizeof(line), "%s %d %d %d %d %s %.0f %.6f\n", std::get<0>(kv.first).c_str(),
+               std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
+               class_name(kv.second.launch.cls), kv.second.launch.task_flops, kv.second.ms);
       out += line;
     }
   }
@@ -217,16 +216,17 @@ int fp_autotune_load(const char* text) {
     std::string line = e ? std::string(p, e - p) : std::string(p);
     p = e ? e + 1 : p + line.size();
     if (line.empty() || line[0] == '#') continue;
-    char arch[64], tname[16];
+    char arch[64], cname[16];
     int an, n, d, pr;
-    double ms;
-    if (sscanf(line.c_str(), "%63s %d %d %d %d %15s %lf", arch, &an, &n, &d, &pr, tname, &ms) != 7)
+    double tf, ms;
+    if (sscanf(line.c_str(), "%63s %d %d %d %d %15s %lf %lf", arch, &an, &n, &d, &pr, cname, &tf, &ms) != 8)
       return set_error(FP_EINVAL, "bad tuning line: %s", line.c_str());
-    int t = -1;
-    for (int i = 0; i < NUM_TILES; ++i)
-      if (strcmp(tname, tile_name(i)) == 0) t = i;
-    if (t < 0) return set_error(FP_EINVAL, "unknown tile %s", tname);
-    add[Key(arch, an, n, d, pr)] = Entry{t, ms};
+    int c = -1;
+    if (strcmp(cname, "small") == 0) c = PCLASS_SMALL;
+    if (strcmp(cname, "large") == 0) c = PCLASS_LARGE;
+    if (c < 0) return set_error(FP_EINVAL, "unknown lane class %s", cname);
+    if (!(tf >= 1.0 && tf <= 1e12)) return set_error(FP_EINVAL, "task flops %g outside 1 .. 1e12", tf);
+    add[Key(arch, an, n, d, pr)] = Entry{GroupLaunch{c, tf}, ms};
   }
   std::lock_guard<std::mutex> lk(g_mu);
   for (const auto& kv : add) g_table[kv.first] = kv.second;

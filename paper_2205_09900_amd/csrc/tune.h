@@ -1,10 +1,29 @@
-// Tile-shape tuning table of the persistent sweep (host side).
+// Launch tuning of the persistent sweep over groups (host side).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include "../../include/fp.h"
 
 namespace fp {
-// Tuned tile for (ensemble, precision) on the current device, or `fallback`.
-int tune_lookup(const fp_ensemble_t* e, int precision, int fallback);
+
+// Launch choice of one group of the persistent sweep: its lane class
+// (PCLASS_SMALL: 64 lanes, 4 pairs per workgroup; PCLASS_LARGE: a whole
+// workgroup per pair) and the algorithmic flops of work per task.
+struct GroupLaunch {
+  int cls;
+  double task_flops;
+};
+
+// Tuned choice for (ensemble, precision) on the current device; false if none.
+bool tune_group_lookup(const fp_ensemble_t* e, int precision, GroupLaunch* out);
+
+// The persistent sweep over groups; `force` (may be NULL) overrides the
+// launch choice of every group.
+int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* groups, int n_groups,
+                    const void* const* d_gates, double* d_trace, void* d_ws, size_t ws_bytes, hipStream_t s,
+                    const GroupLaunch* force);
+
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
-                      void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset, int tile_override);
+                      void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset);
+
 }  // namespace fp

@@ -49,29 +49,34 @@ def test_mixed_groups_vs_dense(fp, prec):
     assert _floored(got, want, prec) <= tol, _floored(got, want, prec)
 
 
-def test_groups_match_single_calls_at_scale(fp):
-    # HEA n = 30, L = 1..8 mixed (the uneven-depth workload at reduced size)
-    ens = [(2, 30, L) for L in range(1, 9)]
-    n = 500
-    bufs = [fp.sample(e, n, synth.workload_seed(3, e[2]), 0, fp.C64) for e in ens]
+def _group_traces(fp, ens, bufs, n):
     groups = [(i, fp.C64, 0, n) for i in range(len(ens))]
     tr = torch.empty(2 * n * len(ens), dtype=torch.float64, device="cuda")
-    ws = torch.empty(fp.fp_workspace_bytes_groups(ens, groups), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(256, fp.fp_workspace_bytes_groups(ens, groups)), dtype=torch.uint8, device="cuda")
     fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
-    got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
-    for i, e in enumerate(ens):
-        one = fp.contract(e, bufs[i], n, fp.C64).cpu().numpy()
-        assert _floored(got[i * n:(i + 1) * n], one) <= 1e-5, e
+    return torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
 
 
-@pytest.mark.skip(reason="the autotuner's device timing stopped responding on its first GPU run; cause not "
-                         "found, the timing path is switched off (fp_autotune returns FP_ENOTIMPL)")
-def test_autotune_choice_is_valid_and_correct(fp):
-    for ens in [(2, 12, 4), (0, 8, 4)]:
-        t = fp.fp_autotune(ens, fp.C64)
-        assert 0 <= t < 6
-        assert f" {fp.TILE_NAMES[t]} " in fp.fp_autotune_table()
-        seed = 555
-        got = fp.contract(ens, fp.sample(ens, 40, seed, 0, fp.C64), 40, fp.C64).cpu().numpy()
-        want = dense.traces(sampler.sample_pairs(ens[0], ens[1], ens[2], seed, 0, 40, fp32=True))
-        assert _floored(got, want) <= 1e-5
+def test_autotune_choices_and_tuned_launches_vs_oracle(fp):
+    """fp_autotune picks a valid launch choice and records it; every launch
+    choice (loaded into the table one at a time) gives the oracle's traces."""
+    import oracle_pool
+    cases = [(2, 30, 3), (2, 30, 7), (0, 12, 5)]  # 4, 12 and 8 boundary bits
+    for ens in cases:
+        c = fp.fp_autotune(ens, fp.C64)
+        assert 0 <= c < 6
+        key = [str(x) for x in ens] + ["1"]
+        lines = [l.split() for l in fp.fp_autotune_table().splitlines() if l.split()[1:5] == key]
+        assert len(lines) == 1 and lines[0][5] == fp.AUTOTUNE_CLASSES[c // 3]
+        assert float(lines[0][6]) == fp.AUTOTUNE_TASK_FLOPS[c % 3]
+    n, pick = 300, [0, 1, 77, 150, 299]
+    for ens in cases:
+        seed = synth.workload_seed(40, ens[2]) + ens[1]
+        buf = fp.sample(ens, n, seed, 0, fp.C64)
+        want = np.array(oracle_pool.traces(ens[0], ens[1], ens[2], seed, pick, fp32=True))
+        for cls in fp.AUTOTUNE_CLASSES:
+            for tf in fp.AUTOTUNE_TASK_FLOPS:
+                fp.fp_autotune_load(f"gfx950 {ens[0]} {ens[1]} {ens[2]} 1 {cls} {tf:.0f} 0\n")
+                got = _group_traces(fp, [ens], [buf], n)
+                assert np.isfinite(got).all()
+                assert _floored(got[pick], want, 1) <= 1e-5, (ens, cls, tf)

@@ -31,18 +31,22 @@ def test_groups_validation(fp):
 
 
 def test_autotune_table_round_trip(fp):
-    fp.fp_autotune_load("# comment\ngfx950 2 30 6 1 64x4 0.125000\ngfx950 0 20 8 1 1024x1 2.500000\n")
+    fp.fp_autotune_load("# comment\ngfx950 2 30 6 1 small 20000000 0.125000\ngfx950 0 20 8 1 large 5000000 2.500000\n")
     text = fp.fp_autotune_table()
-    assert "gfx950 2 30 6 1 64x4" in text and "gfx950 0 20 8 1 1024x1" in text
+    assert "gfx950 2 30 6 1 small 20000000" in text and "gfx950 0 20 8 1 large 5000000" in text
     with pytest.raises(fp.FPError):
-        fp.fp_autotune_load("gfx950 2 30 6 1 7x7 0.1\n")
+        fp.fp_autotune_load("gfx950 2 30 6 1 medium 2e7 0.1\n")
+    with pytest.raises(fp.FPError):
+        fp.fp_autotune_load("gfx950 2 30 6 1 small 0 0.1\n")
     with pytest.raises(fp.FPError):
         fp.fp_autotune_load("garbage line\n")
 
 
-def test_autotune_timing_switched_off(fp):
+def test_autotune_rejects_what_it_cannot_tune(fp):
     import ctypes
-    ens = fp.Ensemble(2, 12, 4)
     choice = ctypes.c_int(-1)
-    rc = fp.lib.fp_autotune(ctypes.byref(ens), fp.C64, ctypes.c_void_p(256), 1 << 30, ctypes.byref(choice), None)
-    assert rc == fp.FP_ENOTIMPL
+    for ens in [fp.Ensemble(1, 50, 100), fp.Ensemble(0, 20, 10)]:  # per-pair plans; a boundary beyond LDS
+        rc = fp.lib.fp_autotune(ctypes.byref(ens), fp.C64, ctypes.c_void_p(256), 1 << 30, ctypes.byref(choice), None)
+        assert rc == fp.FP_ENOTIMPL
+    assert fp.fp_autotune_workspace_bytes((1, 50, 100), fp.C64) == 0
+    assert fp.fp_autotune_workspace_bytes((2, 30, 4), fp.C64) > 0
