@@ -367,6 +367,42 @@ int fp_mlp_link(const float* d_y, int64_t n, int k, double mean, double std_dev,
                 void* stream);
 
 /*
+ * fp_cv_holdout -- statistics of a hold-out set for the control variate,
+ * f_i = |Tr_i|^{2k} against surrogate values g_i (float64, fixed reduction
+ * order), into h_stats[6]: c = Cov(f, g)/Var(g) (0 for constant g), the
+ * correlation rho (0 if f or g is constant), mean and sample variance of f,
+ * mean and sample variance of g.  Synchronises `stream`.
+ * fp_moments_f32 -- mean and sample variance (float64) of a float array on
+ *   the device (n >= 2).  Synchronises `stream`.
+ * Errors: FP_EINVAL, FP_ENUMERIC (non-finite statistics), FP_EDEVICE.
+ */
+int fp_cv_holdout(const double* d_trace, const float* d_g, int64_t num_pairs, int k, double* h_stats,
+                  void* stream);
+int fp_moments_f32(const float* d_x, int64_t n, double* h_mean, double* h_var, void* stream);
+/*
+ * fp_cv_choose -- the rule that keeps the control variate or falls back to
+ * the plain estimator, decided before the estimation pairs are drawn (so it
+ * cannot bias the estimate): with correlation rho between f and g and costs
+ * of sec_per_exact per exact pair and sec_per_surrogate per surrogate draw,
+ * the best split of a time budget gives a variance proportional to
+ *   (sqrt((1 - rho^2) sec_per_exact) + |rho| sqrt(sec_per_surrogate))^2,
+ * against sec_per_exact for the plain mean.  *time_ratio (may be NULL)
+ * receives the ratio of the two; *use_cv = 1 when it is below 1.  Host only.
+ * fp_cv_time_to_rel_se -- wall time to reach a relative standard error
+ * rel_se on F, from stats_B (fp_cv_holdout of the exact pairs against their
+ * surrogate values; F = their mean of f), the coefficient c in use and the
+ * variance var_g_C of the surrogate draws: plain var_f / (rel_se F)^2 x
+ * sec_per_exact; control variate (sqrt(var_r sec_per_exact) +
+ * |c| sqrt(var_g_C sec_per_surrogate))^2 / (rel_se F)^2, with
+ * var_r = var_f - 2 c Cov(f, g) + c^2 var_g the variance of f - c g.
+ * Host only.
+ * Errors: FP_EINVAL.
+ */
+int fp_cv_choose(double rho, double sec_per_exact, double sec_per_surrogate, int* use_cv, double* time_ratio);
+int fp_cv_time_to_rel_se(const double* stats_B, double c, double var_g_C, double rel_se, double sec_per_exact,
+                         double sec_per_surrogate, double* t_plain, double* t_cv);
+
+/*
  * fp_frame_potential_cv -- control-variate estimate of F^(k):
  *   F_CV = mean_B(f - c g) + c mean_C(g),  f_i = |Tr_i|^{2k}
  * over nB exact traces d_trace_B with surrogate values d_g_B, and nC fresh

@@ -32,7 +32,8 @@ EXPORTS = [
     "fp_plan_info", "fp_plan_local_random_host", "fp_plan_program_host", "fp_mlp_param_count", "fp_mlp_act_floats",
     "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient", "fp_log_moments",
     "fp_mlp_log_targets", "fp_mlp_link",
-    "fp_frame_potential_cv", "fp_frame_potential_noalloc", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
+    "fp_frame_potential_cv", "fp_frame_potential_noalloc", "fp_cv_holdout", "fp_moments_f32", "fp_cv_choose",
+    "fp_cv_time_to_rel_se", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
 
@@ -96,6 +97,10 @@ def _load():
         "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_set_launch_mode": (I, [I]),
+        "fp_cv_holdout": (I, [P, P, I64, I, P, P]),
+        "fp_moments_f32": (I, [P, I64, P, P, P]),
+        "fp_cv_choose": (I, [D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "fp_cv_time_to_rel_se": (I, [ctypes.POINTER(D), D, D, D, D, D, ctypes.POINTER(D), ctypes.POINTER(D)]),
         "fp_frame_potential_noalloc": (I, [P, I64, I, P, P, P]),
         "fp_profile_begin": (I, []),
         "fp_profile_end": (I, [P, P, P, P]),
@@ -272,6 +277,35 @@ def fp_cv_coefficient(d_trace, d_g, num_pairs, k, stream=None):
     _check(lib.fp_cv_coefficient(_ptr(d_trace), _ptr(d_g), int(num_pairs), int(k), ctypes.byref(c),
                                  _stream(stream)))
     return c.value
+
+
+def fp_cv_holdout(d_trace, d_g, num_pairs, k, stream=None):
+    """dict with c, rho, mean_f, var_f, mean_g, var_g of a hold-out set."""
+    out = (ctypes.c_double * 6)()
+    _check(lib.fp_cv_holdout(_ptr(d_trace), _ptr(d_g), int(num_pairs), int(k), out, _stream(stream)))
+    return dict(zip(("c", "rho", "mean_f", "var_f", "mean_g", "var_g"), list(out)))
+
+
+def fp_moments_f32(d_x, n, stream=None):
+    m, v = ctypes.c_double(), ctypes.c_double()
+    _check(lib.fp_moments_f32(_ptr(d_x), int(n), ctypes.byref(m), ctypes.byref(v), _stream(stream)))
+    return m.value, v.value
+
+
+def fp_cv_choose(rho, sec_per_exact, sec_per_surrogate):
+    use, ratio = ctypes.c_int(), ctypes.c_double()
+    _check(lib.fp_cv_choose(float(rho), float(sec_per_exact), float(sec_per_surrogate), ctypes.byref(use),
+                            ctypes.byref(ratio)))
+    return bool(use.value), ratio.value
+
+
+def fp_cv_time_to_rel_se(stats_B, c, var_g_C, rel_se, sec_per_exact, sec_per_surrogate):
+    """stats_B: the dict of fp_cv_holdout on the exact pairs; returns (t_plain, t_cv)."""
+    st = (ctypes.c_double * 6)(*[stats_B[k] for k in ("c", "rho", "mean_f", "var_f", "mean_g", "var_g")])
+    tp, tc = ctypes.c_double(), ctypes.c_double()
+    _check(lib.fp_cv_time_to_rel_se(st, float(c), float(var_g_C), float(rel_se), float(sec_per_exact),
+                                    float(sec_per_surrogate), ctypes.byref(tp), ctypes.byref(tc)))
+    return tp.value, tc.value
 
 
 def fp_log_moments(d_trace, num_pairs, eps=1e-30, stream=None):

@@ -346,19 +346,21 @@ __global__ void __launch_bounds__(256) targets_kernel(const double* __restrict__
   t[i] = (float)(scale * f);
 }
 
+// Co-moments of (f, g): count, means, and the sums of products of deviations.
 struct Co {
-  double n, mf, mg, cfg, m2g;
+  double n, mf, mg, cfg, m2g, m2f;
 };
 
 __device__ __forceinline__ Co co_merge(Co a, Co b) {
   Co r;
   r.n = a.n + b.n;
-  if (r.n == 0.0) return Co{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (r.n == 0.0) return Co{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   const double df = b.mf - a.mf, dg = b.mg - a.mg, w = a.n * b.n / r.n;
   r.mf = a.mf + df * (b.n / r.n);
   r.mg = a.mg + dg * (b.n / r.n);
   r.cfg = a.cfg + b.cfg + df * dg * w;
   r.m2g = a.m2g + b.m2g + dg * dg * w;
+  r.m2f = a.m2f + b.m2f + df * df * w;
   return r;
 }
 
@@ -366,7 +368,7 @@ __device__ __forceinline__ Co co_merge(Co a, Co b) {
 __global__ void __launch_bounds__(RED_THREADS) cvcoef_kernel(const double* __restrict__ tr, const float* __restrict__ g,
                                                              int64_t n, int k, Co* __restrict__ part) {
   __shared__ Co sh[RED_THREADS];
-  Co c{0.0, 0.0, 0.0, 0.0, 0.0};
+  Co c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS) {
     const double a = tr[2 * i] * tr[2 * i] + tr[2 * i + 1] * tr[2 * i + 1];
     double f = 1.0;
@@ -378,6 +380,7 @@ __global__ void __launch_bounds__(RED_THREADS) cvcoef_kernel(const double* __res
     c.mg += dg / c.n;
     c.cfg += df * (gv - c.mg);
     c.m2g += dg * (gv - c.mg);
+    c.m2f += df * (f - c.mf);
   }
   sh[threadIdx.x] = c;
   __syncthreads();
@@ -388,13 +391,18 @@ __global__ void __launch_bounds__(RED_THREADS) cvcoef_kernel(const double* __res
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// out: c = Cov(f, g) / Var(g) (0 for constant g), the correlation rho (0
+// when either is constant), mean and sample variance of f, then of g.
 __global__ void cvcoef_final(const Co* __restrict__ part, int nb, double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  Co a{0.0, 0.0, 0.0, 0.0, 0.0};
+  Co a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int b = 0; b < nb; ++b) a = co_merge(a, part[b]);
   out[0] = a.m2g > 0.0 ? a.cfg / a.m2g : 0.0;
-  out[1] = a.mf;
-  out[2] = a.mg;
+  out[1] = a.m2g > 0.0 && a.m2f > 0.0 ? a.cfg / sqrt(a.m2f * a.m2g) : 0.0;
+  out[2] = a.mf;
+  out[3] = a.n > 1.0 ? a.m2f / (a.n - 1.0) : 0.0;
+  out[4] = a.mg;
+  out[5] = a.n > 1.0 ? a.m2g / (a.n - 1.0) : 0.0;
 }
 
 int run_targets(const double* tr, int64_t n, int k, double scale, float* t, hipStream_t s) {
@@ -402,24 +410,82 @@ int run_targets(const double* tr, int64_t n, int k, double scale, float* t, hipS
   return check_launch("targets");
 }
 
-int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, double* c_out, hipStream_t s) {
+int run_cv_holdout(const double* tr, const float* g, int64_t n, int k, double* out6, hipStream_t s) {
   const int nb = red_blocks(n);
   void* ws = nullptr;
-  int rc = check_hip(hipMallocAsync(&ws, sizeof(Co) * nb + 4 * sizeof(double), s), "hipMallocAsync(cvcoef)");
+  int rc = check_hip(hipMallocAsync(&ws, sizeof(Co) * nb + 8 * sizeof(double), s), "hipMallocAsync(cvcoef)");
   if (rc) return rc;
   Co* part = (Co*)ws;
   double* out = (double*)(part + nb);
   hipLaunchKernelGGL(cvcoef_kernel, dim3(nb), dim3(RED_THREADS), 0, s, tr, g, n, k, part);
   hipLaunchKernelGGL(cvcoef_final, dim3(1), dim3(64), 0, s, part, nb, out);
   rc = check_launch("cv_coefficient");
-  double host[3] = {0.0, 0.0, 0.0};
+  double host[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy c");
   int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(cvcoef)");
   int rc3 = check_hip(hipStreamSynchronize(s), "sync(cvcoef)");
   if (rc) return rc;
   if (rc2) return rc2;
   if (rc3) return rc3;
-  *c_out = host[0];
+  for (int i = 0; i < 6; ++i) {
+    if (!isfinite(host[i])) return set_error(FP_ENUMERIC, "non-finite hold-out statistic %d", i);
+    out6[i] = host[i];
+  }
+  return FP_OK;
+}
+
+int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, double* c_out, hipStream_t s) {
+  double st[6];
+  int rc = run_cv_holdout(tr, g, n, k, st, s);
+  if (rc) return rc;
+  *c_out = st[0];
+  return FP_OK;
+}
+
+// Mean and sample variance of a float array (Welford in float64, fixed order).
+__global__ void __launch_bounds__(RED_THREADS) mom32_kernel(const float* __restrict__ x, int64_t n,
+                                                            Welford* __restrict__ part) {
+  __shared__ Welford sw[RED_THREADS];
+  Welford w{0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * RED_THREADS)
+    welford_add(w, (double)x[i]);
+  sw[threadIdx.x] = w;
+  __syncthreads();
+  for (int s2 = RED_THREADS / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) sw[threadIdx.x] = chan_merge(sw[threadIdx.x], sw[threadIdx.x + s2]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sw[0];
+}
+
+__global__ void mom32_final(const Welford* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Welford a{0.0, 0.0, 0.0};
+  for (int b = 0; b < nb; ++b) a = chan_merge(a, part[b]);
+  out[0] = a.mean;
+  out[1] = a.n > 1.0 ? a.m2 / (a.n - 1.0) : 0.0;
+}
+
+int run_moments_f32(const float* x, int64_t n, double* mean, double* var, hipStream_t s) {
+  const int nb = red_blocks(n);
+  void* ws = nullptr;
+  int rc = check_hip(hipMallocAsync(&ws, sizeof(Welford) * nb + 2 * sizeof(double), s), "hipMallocAsync(mom32)");
+  if (rc) return rc;
+  Welford* part = (Welford*)ws;
+  double* out = (double*)(part + nb);
+  hipLaunchKernelGGL(mom32_kernel, dim3(nb), dim3(RED_THREADS), 0, s, x, n, part);
+  hipLaunchKernelGGL(mom32_final, dim3(1), dim3(64), 0, s, part, nb, out);
+  rc = check_launch("moments_f32");
+  double host[2] = {0.0, 0.0};
+  if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy moments");
+  int rc2 = check_hip(hipFreeAsync(ws, s), "hipFreeAsync(mom32)");
+  int rc3 = check_hip(hipStreamSynchronize(s), "sync(mom32)");
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (rc3) return rc3;
+  if (!isfinite(host[0]) || !isfinite(host[1])) return set_error(FP_ENUMERIC, "non-finite values");
+  *mean = host[0];
+  *var = host[1];
   return FP_OK;
 }
 

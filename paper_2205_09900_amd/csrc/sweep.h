@@ -216,6 +216,8 @@ int run_log_targets(const double* tr, int64_t n, double eps, double mu, double s
 int run_link(const float* y, int64_t n, int k, double mu, double sigma, double shift, float* g, hipStream_t s);
 int run_targets(const double* tr, int64_t n, int k, double scale, float* t, hipStream_t s);
 int run_cv_coefficient(const double* tr, const float* g, int64_t n, int k, double* c_out, hipStream_t s);
+int run_cv_holdout(const double* tr, const float* g, int64_t n, int k, double* out6, hipStream_t s);
+int run_moments_f32(const float* x, int64_t n, double* mean, double* var, hipStream_t s);
 int run_frame_potential_cv(const double* trB, const float* gB, int64_t nB, const float* gC, int64_t nC,
                            int k, double c, double* h_F, double* h_se, hipStream_t s);
 

@@ -24,10 +24,10 @@ import time
 import numpy as np
 import torch
 
-from . import (C64, HEA, Ensemble, fp_contract_trace_batch, fp_cv_coefficient, fp_frame_potential,
-               fp_frame_potential_cv, fp_log_moments, fp_mlp_act_floats, fp_mlp_adam_step, fp_mlp_backward,
-               fp_mlp_features, fp_mlp_forward, fp_mlp_init, fp_mlp_link, fp_mlp_log_targets, fp_mlp_param_count,
-               fp_mlp_targets, fp_sample_gates, alloc_gates, workspace)
+from . import (C64, HEA, Ensemble, fp_contract_trace_batch, fp_cv_choose, fp_cv_holdout, fp_cv_time_to_rel_se,
+               fp_frame_potential, fp_frame_potential_cv, fp_log_moments, fp_mlp_act_floats, fp_mlp_adam_step,
+               fp_mlp_backward, fp_mlp_features, fp_mlp_forward, fp_mlp_init, fp_mlp_link, fp_mlp_log_targets,
+               fp_mlp_param_count, fp_mlp_targets, fp_moments_f32, fp_sample_gates, alloc_gates, workspace)
 
 LOG_EPS = 1e-30
 
@@ -146,13 +146,10 @@ def train_surrogate(ens, k=2, hidden=256, n_train=65536, holdout_frac=0.1, batch
     t_train = time.perf_counter() - t1
     model = {"target": target, "k": k, "log_mean": log_mean, "log_std": log_std,
              "log_shift": math.log(f_mean[k - 1])}
-    # c on the hold-out
+    # c and the correlation on the hold-out
     g_hold = link(model, predict(n_in, hidden, best_p, x[n_fit:]))
-    c = fp_cv_coefficient(tr[2 * n_fit:], g_hold, n_hold, k)
-    # correlation on the hold-out (diagnostic)
-    f_hold = torch.empty(n_hold, dtype=torch.float32, device="cuda")
-    fp_mlp_targets(tr[2 * n_fit:], n_hold, k, scale, f_hold)   # f / F_train, same units as g
-    rho = float(torch.corrcoef(torch.stack([f_hold.double(), g_hold.double()]))[0, 1])
+    st = fp_cv_holdout(tr[2 * n_fit:], g_hold, n_hold, k)
+    c, rho = st["c"], st["rho"]
     model.update({"params": best_p, "n_in": n_in, "hidden": hidden, "scale": scale, "c": c, "rho_holdout": rho,
             "holdout_mse": best, "epochs_run": len(history), "history": history,
             "t_data_s": t_data, "t_train_s": t_train, "n_train": n_train})
@@ -175,31 +172,22 @@ def estimate(ens, model, k=2, n_exact=10000, n_surrogate=1000000, seed_exact=0xB
     f_cv, se_cv = fp_frame_potential_cv(tr, g_b, n_exact, g_c, n_surrogate, k, c)
     f_pl, se_pl = fp_frame_potential(tr, n_exact, k)
     f_pl, se_pl = f_pl[k - 1], se_pl[k - 1]
-    # Fallback rule, decided from the hold-out only (so it cannot bias the estimate):
-    # with correlation rho and unit costs tau_e (exact) and tau_s (surrogate), the best
-    # allocation needs time proportional to (sqrt((1-rho^2) tau_e) + |rho| sqrt(tau_s))^2
-    # against tau_e for the plain mean; use the control variate only if that is smaller.
-    rho = model["rho_holdout"]
-    rho = 0.0 if rho != rho else rho
-    tau_e0, tau_s0 = t_exact / n_exact, t_surr / n_surrogate
-    predicted_ratio = (math.sqrt(max(1.0 - rho * rho, 0.0) * tau_e0) + abs(rho) * math.sqrt(tau_s0)) ** 2 / tau_e0
-    use_cv = predicted_ratio < 1.0
+    tau_e, tau_s = t_exact / n_exact, t_surr / n_surrogate
+    # The fallback rule, decided from the hold-out's correlation and the unit
+    # costs only (it cannot bias the estimate).
+    use_cv, predicted_ratio = fp_cv_choose(model["rho_holdout"], tau_e, tau_s)
     f_used, se_used = (f_cv, se_cv) if use_cv else (f_pl, se_pl)
-    # variance components (diagnostics for the time-to-precision extrapolation)
-    var_g = float(g_c.double().var())
-    var_r = max(se_cv ** 2 - c * c * var_g / n_surrogate, 0.0) * n_exact
-    var_f = se_pl ** 2 * n_exact
-    tau_e = t_exact / n_exact
-    tau_s = t_surr / n_surrogate
-    target = (0.01 * f_pl) ** 2
-    t_plain_1pct = var_f / target * tau_e
-    t_cv_1pct = (math.sqrt(var_r * tau_e) + abs(c) * math.sqrt(var_g * tau_s)) ** 2 / target
+    # time to 1 % relative standard error, from the exact pairs' statistics
+    st_b = fp_cv_holdout(tr, g_b, n_exact, k)
+    _, var_g = fp_moments_f32(g_c, n_surrogate)
+    t_plain_1pct, t_cv_1pct = fp_cv_time_to_rel_se(st_b, c, var_g, 0.01, tau_e, tau_s)
+    var_f = st_b["var_f"]
     return {"F": f_used, "SE": se_used, "used_control_variate": use_cv,
             "predicted_time_ratio_from_holdout": predicted_ratio,
             "F_cv": f_cv, "SE_cv": se_cv, "F_plain": f_pl, "SE_plain": se_pl, "c": c,
             "t_exact_s": t_exact, "t_surrogate_s": t_surr, "n_exact": n_exact, "n_surrogate": n_surrogate,
             "sec_per_exact_pair": tau_e, "sec_per_surrogate": tau_s,
-            "var_f": var_f, "var_residual": var_r, "var_g": var_g,
+            "var_f": var_f, "var_g": var_g, "rho_exact_pairs": st_b["rho"], "stats_exact_pairs": st_b,
             "rel_se_cv": se_cv / f_cv if f_cv else None, "rel_se_plain": se_pl / f_pl if f_pl else None,
             "time_to_1pct_plain_s": t_plain_1pct, "time_to_1pct_cv_s": t_cv_1pct,
             "variance_reduction_per_time": t_plain_1pct / t_cv_1pct if t_cv_1pct > 0 else None,
