@@ -7,7 +7,8 @@ the other; both take seeded raw inputs from ``synth``.
 
 Modules (each cites the passage of the paper it follows):
   philox        Philox4x32-10 counter generator (published definition)
-  sampler       the three ensembles: brickwork, local random, HEA
+  sampler       the ensembles: brickwork, local random, HEA (RY RZ + CZ), and
+                the paper's HEA (RY(pi/4) wall, Pauli rotations, CNOT or CZ walls)
   dense         Tr(U^dagger V) from dense 2^n x 2^n unitaries (n <= 12)
   ancilla       the paper's single-amplitude construction (n <= 10)
   mpo           MPO-zip contraction for wide, shallow circuits (n up to 50)

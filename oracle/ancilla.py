@@ -17,7 +17,7 @@ indexed [ancilla basis, target basis].
 import numpy as np
 
 from .dense import apply_1q, apply_2q
-from .sampler import HEA, hea_gate_list, CZ
+from .sampler import HEA, PAULI_HEA, hea_gate_list, pauli_gate_list, CZ
 
 H = np.array([[1.0, 1.0], [1.0, -1.0]], dtype=np.complex128) / np.sqrt(2.0)
 
@@ -42,7 +42,9 @@ def _apply_circuit_to_targets(psi, circ, dagger):
     """Apply the circuit (or its inverse) to the target register (axis 1)."""
     n = circ["n"]
     st = psi.T.copy()           # (target, ancilla): gates act on axis 0
-    if circ["ansatz"] == HEA:
+    if circ["ansatz"] in PAULI_HEA:
+        seq = list(pauli_gate_list(circ))
+    elif circ["ansatz"] == HEA:
         ops = hea_gate_list(circ)
         seq = [(op[0], op[1], op[2] if op[0] == "1q" else CZ) for op in ops]
     else:

@@ -12,6 +12,13 @@ the two circuit unitaries (frame-potential definition, Sec. I.A):
   * Hardware-efficient ansatz, one layer (the CZ ladders cancel inside the
     trace): Tr = prod_q 2 cos(dphi_q / 2) cos(dtheta_q / 2), and with
     uniform angles F^(k) = (C(2k, k)^2 / 4^k)^n.
+  * The paper's Pauli-rotation ansatz, one layer: the RY(pi/4) walls and the
+    entangling walls cancel inside the trace, leaving prod_q Tr(R_q^U^dagger
+    R_q^V) with R = exp(-i theta P / 2): 2 cos((theta_V - theta_U) / 2) for
+    equal axes and 2 cos(theta_U / 2) cos(theta_V / 2) for different ones
+    (Tr(P Q) = 0).  With uniform axes and angles, per qubit
+    E |Tr|^{2k} = C(2k, k) / 3 + (2/3) C(2k, k)^2 / 4^k, so
+    F^(1) = (4/3)^n and F^(2) = (7/2)^n.
 """
 
 import math
@@ -50,3 +57,20 @@ def hea_one_layer_trace(cu, cv):
 
 def hea_one_layer_frame_potential(n, k):
     return (math.comb(2 * k, k) ** 2 / 4.0 ** k) ** n
+
+
+def pauli_one_layer_trace(cu, cv):
+    tu, tv = cu["theta"][0], cv["theta"][0]
+    au, av = cu["axis"][0], cv["axis"][0]
+    t = 1.0 + 0.0j
+    for q in range(len(tu)):
+        if au[q] == av[q]:
+            t *= 2.0 * math.cos((tv[q] - tu[q]) / 2.0)
+        else:
+            t *= 2.0 * math.cos(tu[q] / 2.0) * math.cos(tv[q] / 2.0)
+    return t
+
+
+def pauli_one_layer_frame_potential(n, k):
+    c = math.comb(2 * k, k)
+    return (c / 3.0 + 2.0 * c * c / (3.0 * 4.0 ** k)) ** n

@@ -13,7 +13,7 @@ rows = outputs and columns = inputs.  Cost O(#gates 4^n): n <= 12.
 
 import numpy as np
 
-from .sampler import HEA, hea_gate_list, CZ
+from .sampler import HEA, PAULI_HEA, hea_gate_list, pauli_gate_list, CZ
 
 
 def apply_2q(mat, gate, q, n):
@@ -29,9 +29,13 @@ def apply_1q(mat, gate, q, n):
     return np.einsum("ij,ajbc->aibc", gate, m).reshape(2 ** n, cols)
 
 
-def circuit_unitary(circ):
+def circuit_unitary(circ, wall=True):
     n = circ["n"]
     u = np.eye(2 ** n, dtype=np.complex128)
+    if circ["ansatz"] in PAULI_HEA:
+        for kind, q, g in pauli_gate_list(circ, wall):
+            u = apply_1q(u, g, q, n) if kind == "1q" else apply_2q(u, g, q, n)
+        return u
     if circ["ansatz"] == HEA:
         for op in hea_gate_list(circ):
             if op[0] == "1q":
@@ -44,10 +48,10 @@ def circuit_unitary(circ):
     return u
 
 
-def trace_pair(cu, cv):
+def trace_pair(cu, cv, wall=True):
     """Tr(U^dagger V) for one sampled pair (complex128)."""
-    u = circuit_unitary(cu)
-    v = circuit_unitary(cv)
+    u = circuit_unitary(cu, wall)
+    v = circuit_unitary(cv, wall)
     return complex(np.sum(np.conj(u) * v))
 
 

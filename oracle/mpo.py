@@ -10,7 +10,8 @@ are never merged.  Each circuit becomes a matrix product operator by the exact
 block split of every two-qubit gate,
     G = sum_{p,q} |p><q| (on qubit j)  (x)  G^{(pq)} (on qubit j+1),
     G^{(pq)}[a, b] = G[2p + a, 2q + b],
-(CZ uses its exact rank-2 split |p><p| (x) Z^p), so qubit j carries the
+(CZ uses its exact rank-2 split |p><p| (x) Z^p, CNOT with control j its split
+|p><p| (x) X^p), so qubit j carries the
 time-ordered product of its factors, indexed by one bond index per gate on
 its left and right.  Then
     Tr(U^dagger V) = sum over bond indices of prod_j Tr(A^U_j^dagger A^V_j),
@@ -20,7 +21,7 @@ All arithmetic is complex128.
 
 import numpy as np
 
-from .sampler import HEA, hea_gate_list
+from .sampler import CNOT, HEA, PAULI_CNOT, PAULI_HEA, hea_gate_list, pauli_gate_list
 
 _PQ = np.zeros((4, 2, 2), dtype=np.complex128)
 for _p in range(2):
@@ -30,11 +31,17 @@ _PP = np.zeros((2, 2, 2), dtype=np.complex128)
 _PP[0, 0, 0] = 1.0
 _PP[1, 1, 1] = 1.0
 _ZP = np.array([np.eye(2), np.diag([1.0, -1.0])], dtype=np.complex128)
+_XP = np.array([np.eye(2), [[0.0, 1.0], [1.0, 0.0]]], dtype=np.complex128)
 
 
 def _events(circ):
     """Time-ordered events: ('1q', q, M) or ('2q', bond, left_stack, right_stack)."""
     ev = []
+    if circ["ansatz"] in PAULI_HEA:
+        right = _XP if circ["ansatz"] == PAULI_CNOT else _ZP
+        for kind, q, g in pauli_gate_list(circ):
+            ev.append(("1q", q, g) if kind == "1q" else ("2q", q, _PP, right))
+        return ev
     if circ["ansatz"] == HEA:
         for op in hea_gate_list(circ):
             if op[0] == "1q":

@@ -9,6 +9,13 @@ Ensembles (Results, Fig. 2 of the paper; 1D open chain, q = 2):
     uniformly among the n-1 neighbouring pairs.
   * hardware-efficient ansatz: each layer is RY(theta) then RZ(phi) on every
     qubit, then CZ on every bond, with theta, phi ~ U[0, 2pi).
+  * the paper's hardware-efficient ansatz (Fig. 2c; Sec. II.C): a wall of
+    RY(pi/4) rotations, then per layer a random Pauli rotation
+    R_P(theta) = exp(-i theta P / 2) on every qubit (P uniform in {X, Y, Z},
+    theta ~ U[0, 2pi)) and two walls of entangling gates, first on the bonds
+    (q, q+1) with q even, then with q odd -- each layer has two walls of
+    two-qubit gates (Sec. II.C) -- CNOT with control q and target q+1, or
+    CZ.
 
 Haar U(4) is drawn as complex Gaussian -> QR -> multiply column a of Q by
 R[a,a]/|R[a,a]| (Mezzadri 2007), which is the unique QR factor with a
@@ -26,6 +33,10 @@ Random draws follow one counter stream (Philox4x32-10, see philox.py):
       outputs in order, first x < 2^32 - (2^32 mod (n-1)) gives bond x mod (n-1).
   HEA angles of (layer l, qubit q): item = l*n + q, word 0:
       theta = 2 pi U53(x0,x1), phi = 2 pi U53(x2,x3).
+  Pauli-rotation HEA, (layer l, qubit q): item = l*n + q, word 0: the axis
+      is x mod 3 for the first x of (x0, x1) below 2^32 - 1 (0 if neither
+      is; 2^32 - 1 = 3 * 1431655765, so x mod 3 is uniform), 0 = X, 1 = Y,
+      2 = Z; theta = 2 pi U53(x2, x3).
   U53(a, b) = ((a >> 5) * 2^26 + (b >> 6) + 1) * 2^-53, exact in float64 and
       in (0, 1], so the logarithm of Box-Muller is always finite.
 Gates are computed in float64 and then stored in the precision's type.
@@ -35,7 +46,8 @@ import numpy as np
 
 from .philox import philox4x32_10, key_from_seed, make_counter
 
-BRICKWORK, LOCAL_RANDOM, HEA = 0, 1, 2
+BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ = 0, 1, 2, 3, 4
+PAULI_HEA = (PAULI_CNOT, PAULI_CZ)
 
 
 def u53(a, b):
@@ -113,6 +125,22 @@ def hea_angles(seed, n, layers, pairs, circuit):
     return theta, phi
 
 
+def pauli_params(seed, n, layers, pairs, circuit):
+    """theta (float64) and axis (int, 0 = X, 1 = Y, 2 = Z) of shape
+    (num_pairs, layers, n) for the Pauli-rotation HEA."""
+    pairs = np.asarray(pairs, dtype=np.uint64)
+    l = np.arange(layers, dtype=np.uint64)[:, None]
+    q = np.arange(n, dtype=np.uint64)[None, :]
+    item = l * np.uint64(n) + q
+    ctr = make_counter(0, item[None], pairs[:, None, None], circuit)
+    x = philox4x32_10(ctr, key_from_seed(seed))
+    top = np.uint64(0xFFFFFFFF)
+    x0, x1 = x[..., 0].astype(np.uint64), x[..., 1].astype(np.uint64)
+    axis = np.where(x0 < top, x0 % np.uint64(3), np.where(x1 < top, x1 % np.uint64(3), np.uint64(0)))
+    theta = 2.0 * np.pi * u53(x[..., 2], x[..., 3])
+    return theta, axis.astype(np.int64)
+
+
 def _store(a, precision_is_fp32):
     if precision_is_fp32:
         return a.astype(np.complex64).astype(np.complex128) if np.iscomplexobj(a) \
@@ -125,12 +153,19 @@ def sample_pairs(ansatz, n, depth, seed, first_pair, num_pairs, fp32=False):
 
     Each circuit is a dict with 'ansatz', 'n' and either
       'gates': list of (bond, 4x4 complex128) in time order, or
-      'theta', 'phi': (layers, n) float64 arrays (HEA).
+      'theta', 'phi': (layers, n) float64 arrays (HEA), or
+      'theta' (float64), 'axis' (int): (layers, n) arrays (Pauli-rotation HEA).
     With fp32=True, stored values are rounded to float32 exactly as the
     library stores them and then widened back to float64 exactly.
     """
     pairs = np.arange(first_pair, first_pair + num_pairs, dtype=np.uint64)
     out = []
+    if ansatz in PAULI_HEA:
+        par = [pauli_params(seed, n, depth, pairs, c) for c in (0, 1)]
+        for i in range(num_pairs):
+            out.append(tuple({"ansatz": ansatz, "n": n, "theta": _store(par[c][0][i], fp32),
+                              "axis": par[c][1][i].copy()} for c in (0, 1)))
+        return out
     if ansatz == HEA:
         ang = [hea_angles(seed, n, depth, pairs, c) for c in (0, 1)]
         for i in range(num_pairs):
@@ -185,3 +220,37 @@ def rz(p):
 
 
 CZ = np.diag([1.0, 1.0, 1.0, -1.0]).astype(np.complex128)
+
+
+def pauli_rotation(axis, theta):
+    """R_P(theta) = exp(-i theta P / 2) = cos(theta/2) I - i sin(theta/2) P."""
+    c, s_ = np.cos(theta / 2.0), np.sin(theta / 2.0)
+    p = (PAULI_X, PAULI_Y, PAULI_Z)[int(axis)]
+    return c * np.eye(2, dtype=np.complex128) - 1j * s_ * p
+
+
+PAULI_X = np.array([[0.0, 1.0], [1.0, 0.0]], dtype=np.complex128)
+PAULI_Y = np.array([[0.0, -1.0j], [1.0j, 0.0]], dtype=np.complex128)
+PAULI_Z = np.array([[1.0, 0.0], [0.0, -1.0]], dtype=np.complex128)
+# control = qubit b (the more significant bit of the composite index), target b + 1
+CNOT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], dtype=np.complex128)
+
+
+def pauli_gate_list(circ, wall=True):
+    """Pauli-rotation HEA as a time-ordered list of ('1q', q, 2x2) and
+    ('2q', bond, 4x4): the RY(pi/4) wall (omitted with wall=False), then per
+    layer the rotations, the entangling wall on even bonds, then on odd bonds."""
+    n = circ["n"]
+    theta, axis = circ["theta"], circ["axis"]
+    ent = CNOT if circ["ansatz"] == PAULI_CNOT else CZ
+    ops = []
+    if wall:
+        for q in range(n):
+            ops.append(("1q", q, ry(np.pi / 4.0)))
+    for l in range(theta.shape[0]):
+        for q in range(n):
+            ops.append(("1q", q, pauli_rotation(axis[l, q], theta[l, q])))
+        for first in (0, 1):
+            for b in range(first, n - 1, 2):
+                ops.append(("2q", b, ent))
+    return ops
