@@ -269,6 +269,13 @@ def suite(fp, torch, np, synth, pairs):
         r[str(L)], _ = fixed_topology(fp, torch, fp.HEA, 30, L, pairs, fp.C64, synth.workload_seed(3, L))
     out["hea_n30"] = r
     out["hea_n30_mixed_launch"] = hea_mixed(fp, torch, pairs)
+    # the paper's hardware-efficient ansatz, CNOT walls against CZ walls,
+    # n = 30, L = 1..7, complex64 (F^(k) falls toward k! faster with CNOT)
+    for name, ans in (("pauli_cnot_n30", fp.PAULI_CNOT), ("pauli_cz_n30", fp.PAULI_CZ)):
+        r = {}
+        for L in range(1, 8):
+            r[str(L)], _ = fixed_topology(fp, torch, ans, 30, L, pairs, fp.C64, synth.workload_seed(7 + ans, L))
+        out[name] = r
     return out
 
 

@@ -55,9 +55,16 @@ enum {
                                on bonds b = t-1 (mod 2); Haar U(4) gates          */
   FP_LOCAL_RANDOM_HAAR = 1, /* "local random unitaries": depth = steps; each step is
                                one Haar U(4) gate on a uniformly chosen bond      */
-  FP_HEA_RYRZ_CZ = 2        /* hardware-efficient ansatz: depth = layers; a layer is
+  FP_HEA_RYRZ_CZ = 2,       /* hardware-efficient ansatz: depth = layers; a layer is
                                RY(theta) then RZ(phi) on every qubit, then CZ on
                                every bond; theta, phi ~ U(0, 2 pi]                */
+  FP_HEA_PAULI_CNOT = 3,    /* the paper's hardware-efficient ansatz (Fig. 2c;
+                               Sec. II.C): a wall of RY(pi/4), then per layer a
+                               rotation exp(-i theta P / 2) on every qubit (P
+                               uniform in {X, Y, Z}, theta ~ U(0, 2 pi]) and two
+                               walls of CNOT (control q, target q+1), first on
+                               the bonds q even, then q odd; depth = layers     */
+  FP_HEA_PAULI_CZ = 4       /* the same with CZ walls                            */
 };
 
 /* ---- precisions ------------------------------------------------------------ */
@@ -76,7 +83,7 @@ enum {
 };
 
 typedef struct {
-  int32_t ansatz;    /* FP_BRICKWORK_HAAR, FP_LOCAL_RANDOM_HAAR, FP_HEA_RYRZ_CZ */
+  int32_t ansatz;    /* FP_BRICKWORK_HAAR ... FP_HEA_PAULI_CZ                    */
   int32_t n_qubits;  /* 2..64                                                    */
   int32_t depth;     /* layers (brickwork, HEA) or steps (local random), >= 1    */
   int32_t reserved;  /* must be 0                                                */
@@ -98,6 +105,9 @@ typedef struct {
  *   local random: followed by [U bonds][V bonds], one int32 per step.
  *   HEA: [U angles][V angles], per layer l and qubit q the pair (theta, phi)
  *     as Real, index ((l * n) + q) * 2.
+ *   Pauli-rotation HEA: the same with the pair (theta, axis), axis 0, 1, 2
+ *     for X, Y, Z stored as Real (the fixed RY(pi/4) wall is not stored; it
+ *     cancels inside the trace).
  * The total is padded to a multiple of 64 bytes.  Returns 0 for an invalid
  * ensemble or precision.
  */
@@ -118,6 +128,9 @@ size_t fp_gate_bytes_per_pair(const fp_ensemble_t* ens, int precision);
  *     x < 2^32 - (2^32 mod (n-1)) gives the bond x mod (n-1).
  *   HEA layer l, qubit q: item l*n + q, word 0: theta = 2 pi U53(x0, x1),
  *     phi = 2 pi U53(x2, x3).
+ *   Pauli-rotation HEA layer l, qubit q: item l*n + q, word 0: axis = x mod 3
+ *     for the first x of (x0, x1) below 2^32 - 1 (0 if neither is),
+ *     theta = 2 pi U53(x2, x3).
  *   U53(a, b) = ((a >> 5) * 2^26 + (b >> 6) + 1) * 2^-53.
  * Values are computed in float64 and stored as the precision's Real.
  * gates_bytes must be >= num_pairs * fp_gate_bytes_per_pair(ens, precision).

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfp.so")
 
 FP_OK, FP_EINVAL, FP_ETOOBIG, FP_EDEVICE, FP_ENOTIMPL, FP_ENUMERIC = 0, -1, -2, -3, -4, -5
-BRICKWORK, LOCAL_RANDOM, HEA = 0, 1, 2
+BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ = 0, 1, 2, 3, 4
 C128, C64, BF16X3 = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_WAIT, LAUNCH_WAIT_FREE = 0, 1, 2
 

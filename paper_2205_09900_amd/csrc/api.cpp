@@ -40,14 +40,15 @@ int check_launch(const char* what) { return check_hip(hipGetLastError(), what); 
 
 int check_ensemble(const fp_ensemble_t* e) {
   if (!e) return set_error(FP_EINVAL, "ensemble is NULL");
-  if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_HEA_RYRZ_CZ)
+  if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_HEA_PAULI_CZ)
     return set_error(FP_EINVAL, "unknown ansatz %d", e->ansatz);
   if (e->n_qubits < 2 || e->n_qubits > 64) return set_error(FP_EINVAL, "n_qubits %d outside 2..64", e->n_qubits);
   if (e->depth < 1) return set_error(FP_EINVAL, "depth %d < 1", e->depth);
   if (e->reserved != 0) return set_error(FP_EINVAL, "reserved field must be 0");
-  if (e->ansatz != FP_HEA_RYRZ_CZ && gates_per_circuit(e->ansatz, e->n_qubits, e->depth) > PLAN_MAX_GATES)
+  const bool hea = e->ansatz == FP_HEA_RYRZ_CZ || is_pauli_hea(e->ansatz);
+  if (!hea && gates_per_circuit(e->ansatz, e->n_qubits, e->depth) > PLAN_MAX_GATES)
     return set_error(FP_EINVAL, "more than %d gates per circuit", PLAN_MAX_GATES);
-  if (e->ansatz == FP_HEA_RYRZ_CZ && e->depth > 64) return set_error(FP_EINVAL, "depth %d too large", e->depth);
+  if (hea && e->depth > 64) return set_error(FP_EINVAL, "depth %d too large", e->depth);
   return FP_OK;
 }
 
@@ -274,6 +275,12 @@ static int lr_predicted_bits(int n, int S) {
 int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precision, size_t* out) {
   const int elem = sweep_elem_bytes(precision);
   if (e->ansatz == FP_HEA_RYRZ_CZ) {
+    *out = 0;
+    return FP_OK;
+  }
+  if (is_pauli_hea(e->ansatz)) {
+    if (pauli_bits(e->depth) + 1 > lds_bits_max(precision))
+      return set_error(FP_ETOOBIG, "Pauli HEA of %d layers: its register exceeds LDS", e->depth);
     *out = 0;
     return FP_OK;
   }
@@ -810,8 +817,29 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
   return rc;
 }
 
+int contract_pauli_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+                       hipStream_t s, int64_t trace_offset) {
+  size_t ws = 0;
+  int rc = workspace_bytes_impl(e, num_pairs, precision, &ws);
+  if (rc) return rc;
+  HeaArgs a;
+  a.gates = (const unsigned char*)gates;
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.n = e->n_qubits;
+  a.L = e->depth;
+  a.trace = trace;
+  a.trace_offset = trace_offset;
+  a.num_pairs = num_pairs;
+  a.bf3 = precision == FP_BF16X3 ? 1 : 0;
+  profile_launch_begin(KCLASS_HEA, s);
+  rc = launch_pauli_hea(a, precision, e->ansatz == FP_HEA_PAULI_CNOT ? 1 : 0, s);
+  profile_launch_end(KCLASS_HEA, pauli_flops_per_pair(e->n_qubits, e->depth) * (double)num_pairs, s);
+  return rc;
+}
+
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
                       void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
+  if (is_pauli_hea(e->ansatz)) return contract_pauli_hea(e, num_pairs, precision, gates, trace, s, trace_offset);
   if (e->ansatz == FP_BRICKWORK_HAAR)
     return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset);
   if (e->ansatz == FP_LOCAL_RANDOM_HAAR)
@@ -943,6 +971,16 @@ int fp_plan_info(const fp_ensemble_t* ens, int32_t* out_bits, int32_t* peak_bits
   const int n = ens->n_qubits;
   if (ens->ansatz == FP_LOCAL_RANDOM_HAAR)
     return set_error(FP_ENOTIMPL, "local random ensembles are planned per pair");
+  if (is_pauli_hea(ens->ansatz)) {
+    const int m = pauli_bits(ens->depth);
+    if (out_bits)
+      for (int j = 0; j < n - 1; ++j) out_bits[j] = m;
+    if (peak_bits) *peak_bits = m == 0 ? 0 : m + 1;  // the register adds the wire's bit
+    // complex multiply-adds of the rotations (two per register entry and slot)
+    if (macs) *macs = m == 0 ? (double)n : (double)n * m * 2.0 * (double)(2ull << m);
+    if (ops) *ops = (int64_t)n * m;
+    return FP_OK;
+  }
   if (ens->ansatz == FP_HEA_RYRZ_CZ) {
     const int m = hea_bits(ens->depth);
     if (out_bits)

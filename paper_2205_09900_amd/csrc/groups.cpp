@@ -294,12 +294,8 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
     const fp_ensemble_t* e = &ens[groups[g].ensemble_index];
     const unsigned char* gg = (const unsigned char*)d_gates[g] +
                               groups[g].first_pair * pair_bytes(e->ansatz, e->n_qubits, e->depth, groups[g].precision);
-    if (e->ansatz == FP_LOCAL_RANDOM_HAAR)
-      rc = contract_local_random(e, groups[g].num_pairs, groups[g].precision, gg, d_trace, w + off, gps[g].sep_ws, s,
-                                 descs[g].trace_offset);
-    else
-      rc = contract_brickwork(e, groups[g].num_pairs, groups[g].precision, gg, d_trace, w + off, gps[g].sep_ws, s,
-                              descs[g].trace_offset);
+    rc = contract_dispatch(e, groups[g].num_pairs, groups[g].precision, gg, d_trace, w + off, gps[g].sep_ws, s,
+                           descs[g].trace_offset);
     off += gps[g].sep_ws;
   }
   return rc;

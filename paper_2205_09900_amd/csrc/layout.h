@@ -9,6 +9,11 @@ namespace fp {
 
 __host__ __device__ inline int real_bytes(int precision) { return precision == FP_C128 ? 8 : 4; }
 
+// The paper's hardware-efficient ansatz (Pauli rotations, CNOT or CZ walls).
+__host__ __device__ inline bool is_pauli_hea(int ansatz) {
+  return ansatz == FP_HEA_PAULI_CNOT || ansatz == FP_HEA_PAULI_CZ;
+}
+
 // Two-qubit gates per circuit (Haar ensembles).
 __host__ __device__ inline int64_t gates_per_circuit(int ansatz, int n, int depth) {
   if (ansatz == FP_LOCAL_RANDOM_HAAR) return depth;
@@ -31,7 +36,7 @@ __host__ __device__ inline int64_t pad64(int64_t x) { return (x + 63) & ~(int64_
 
 __host__ __device__ inline int64_t pair_bytes(int ansatz, int n, int depth, int precision) {
   const int64_t rb = real_bytes(precision);
-  if (ansatz == FP_HEA_RYRZ_CZ) return pad64(2 * (int64_t)depth * n * 2 * rb);
+  if (ansatz == FP_HEA_RYRZ_CZ || is_pauli_hea(ansatz)) return pad64(2 * (int64_t)depth * n * 2 * rb);
   const int64_t G = gates_per_circuit(ansatz, n, depth);
   int64_t b = 2 * G * 32 * rb;
   if (ansatz == FP_LOCAL_RANDOM_HAAR) b += 2 * G * 4;

@@ -117,11 +117,45 @@ __global__ void __launch_bounds__(256) sample_hea_kernel(Real* __restrict__ gate
   dst[1] = (Real)phi;
 }
 
+// Pauli-rotation HEA: one thread per (pair, circuit, layer, qubit) writes
+// (theta, axis); the axis comes from the first of x0, x1 below 2^32 - 1
+// (2^32 - 1 is a multiple of 3, so x mod 3 is uniform), theta from x2, x3.
+template <typename Real>
+__global__ void __launch_bounds__(256) sample_pauli_kernel(Real* __restrict__ gates, int64_t num_pairs,
+                                                           uint64_t seed, uint64_t first_pair, int n,
+                                                           int layers, int64_t stride_bytes) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_circ = (int64_t)layers * n;
+  if (tid >= num_pairs * 2 * per_circ) return;
+  const int64_t p = tid / (2 * per_circ);
+  const int rem = (int)(tid % (2 * per_circ));
+  const uint32_t circuit = (uint32_t)(rem / per_circ);
+  const uint32_t item = (uint32_t)(rem % per_circ);  // l * n + q
+  const uint64_t pair = first_pair + (uint64_t)p;
+  u32x4 x = draw(seed, 0u, item, pair, circuit);
+  const uint32_t top = 0xFFFFFFFFu;
+  const uint32_t axis = x.v[0] < top ? x.v[0] % 3u : x.v[1] < top ? x.v[1] % 3u : 0u;
+  const double theta = 6.283185307179586 * u53(x.v[2], x.v[3]);
+  Real* dst = reinterpret_cast<Real*>(reinterpret_cast<char*>(gates) + p * stride_bytes) +
+              ((int64_t)circuit * per_circ + item) * 2;
+  dst[0] = (Real)theta;
+  dst[1] = (Real)axis;
+}
+
 int launch_sample(const fp_ensemble_t* e, int64_t num_pairs, uint64_t seed, uint64_t first_pair,
                   int precision, void* d_gates, hipStream_t stream) {
   const int64_t stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
   const int threads = 256;
-  if (e->ansatz == FP_HEA_RYRZ_CZ) {
+  if (is_pauli_hea(e->ansatz)) {
+    const int64_t work = num_pairs * 2 * (int64_t)e->depth * e->n_qubits;
+    const int64_t blocks = (work + threads - 1) / threads;
+    if (precision == FP_C128)
+      hipLaunchKernelGGL(sample_pauli_kernel<double>, dim3((unsigned)blocks), dim3(threads), 0, stream,
+                         (double*)d_gates, num_pairs, seed, first_pair, e->n_qubits, e->depth, stride);
+    else
+      hipLaunchKernelGGL(sample_pauli_kernel<float>, dim3((unsigned)blocks), dim3(threads), 0, stream,
+                         (float*)d_gates, num_pairs, seed, first_pair, e->n_qubits, e->depth, stride);
+  } else if (e->ansatz == FP_HEA_RYRZ_CZ) {
     const int64_t work = num_pairs * 2 * (int64_t)e->depth * e->n_qubits;
     const int64_t blocks = (work + threads - 1) / threads;
     if (precision == FP_C128)

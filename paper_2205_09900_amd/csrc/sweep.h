@@ -204,6 +204,11 @@ struct HeaArgs {
 };
 int launch_hea(const HeaArgs& a, int precision, int tile, hipStream_t s);
 int hea_bits(int L);
+// The paper's hardware-efficient ansatz (Pauli rotations; cnot = 1: CNOT
+// walls, 0: CZ walls): boundary of 2L-2 labels, register of one more bit.
+int launch_pauli_hea(const HeaArgs& a, int precision, int cnot, hipStream_t s);
+int pauli_bits(int L);
+double pauli_flops_per_pair(int n, int L);
 
 int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,
                         hipStream_t s);
