@@ -13,6 +13,8 @@ Modules (each cites the passage of the paper it follows):
   ancilla       the paper's single-amplitude construction (n <= 10)
   mpo           MPO-zip contraction for wide, shallow circuits (n up to 50)
   estimator     Monte Carlo F^(k), standard error, bootstrap, control variate
+  statistics    Philox bootstrap, quantiles, fit region, layers to epsilon,
+                sample-size rule
   haar_moments  F_Haar^(k) for U(d) by counting permutations
   weingarten    exact brickwork F^(k) by the permutation transfer
   closed_forms  special-case traces and frame potentials
