@@ -168,6 +168,27 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb}
 
 
+def layer_scaling(fp, torch, traces_by_depth, n, k_max=3, resamples=300, epsilon=0.1):
+    """The paper's uncertainty analysis and fit on the device: bootstrap of
+    F^(k) at every depth (300 resamples), then per resample the exponential
+    fit over the depths with (F - F_Haar)/F_Haar < 5 and the layers to an
+    epsilon-approximate k-design; median and failed resamples per k."""
+    depths = sorted(traces_by_depth)
+    samples = torch.empty(len(depths), k_max, resamples, dtype=torch.float64, device="cuda")
+    boot = {}
+    for j, d in enumerate(depths):
+        tr = traces_by_depth[d]
+        med, lo, hi = fp.fp_bootstrap(tr, tr.numel() // 2, k_max, resamples, 0xB0075 + d, samples[j])
+        boot[str(d)] = {"median": med, "lo95": lo, "hi95": hi}
+    out = {"depths": depths, "bootstrap": boot, "layers_to_epsilon": {}}
+    for k in range(1, k_max + 1):
+        fk = samples[:, k - 1, :].contiguous()
+        med, failed = fp.fp_layers_to_epsilon(fk, depths, resamples, fp.fp_haar_frame_potential(k, 2.0 ** n),
+                                              epsilon, n, 2, k)
+        out["layers_to_epsilon"][str(k)] = {"median": med, "failed_resamples": failed}
+    return out
+
+
 def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None):
     """Throughput of sample + contract + reduce for one fixed-topology ensemble; traces of the
     last step are returned for the precision comparison."""
@@ -245,6 +266,7 @@ def suite(fp, torch, np, synth, pairs):
     out["brickwork_n6_c128"] = r
     # brickwork n = 20, depths 2..10, complex64 and BF16x3 against complex128 on the same seeds
     r = {}
+    keep = {}
     for d in range(2, 11):
         np_ = pairs if d <= 8 else max(1000, pairs // 20)
         seed = synth.workload_seed(2, d)
@@ -262,7 +284,11 @@ def suite(fp, torch, np, synth, pairs):
         r32["precision_same_gates"] = same_gate_precision(fp, torch, np, (fp.BRICKWORK, 20, d), ngates,
                                                           min(np_, 20000), seed)
         r[str(d)] = r32
+        keep[d] = t32
     out["brickwork_n20"] = r
+    out["brickwork_n20_layer_scaling"] = layer_scaling(fp, torch, keep, 20)
+    progress(f"brickwork n=20 layers to epsilon = 0.1: "
+             f"{ {k: round(v['median'], 2) for k, v in out['brickwork_n20_layer_scaling']['layers_to_epsilon'].items()} }")
     # HEA n = 30, layers 1..8, complex64
     r = {}
     for L in range(1, 9):

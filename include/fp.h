@@ -225,6 +225,80 @@ int fp_set_launch_mode(int mode);
 int fp_frame_potential_noalloc(const double* d_trace, int64_t num_pairs, int k_max,
                                double* h_F, double* h_stderr, void* stream);
 
+/* ---- statistics of the estimates ------------------------------------------ */
+/*
+ * fp_haar_frame_potential -- F_Haar^(k) of U(dim): the number of
+ * permutations of k elements whose longest increasing subsequence is at most
+ * dim, which is k! for dim >= k (the paper's Haar value, Sec. I.A; exact for
+ * every dim by the count).  k in 1..10.  Host only.  Errors: FP_EINVAL.
+ */
+int fp_haar_frame_potential(int k, double dim, double* out);
+
+/*
+ * fp_bootstrap -- bootstrap distribution of F^(k), k = 1..k_max
+ * (Supplementary Methods, bootstrapping for uncertainty quantification; the
+ * paper uses 300 resamples): resample r draws num_pairs traces with
+ * replacement, draw i taking index floor(u N / 2^64) of the 64-bit word u of
+ * Philox4x32-10 block i >> 1 (x0 + 2^32 x1 for even i, x2 + 2^32 x3 for odd
+ * i) with counter (block low 32, block high 32, r, 0xB0075A3B) and key
+ * seed, and F_r^(k) is the mean of |Tr|^{2k} over the draws (float64, terms
+ * scaled by a batch power of two, fixed order).
+ * d_samples (k_max x resamples doubles on the device, F_r^(k) at
+ * (k-1) * resamples + r, in resample order) may be NULL.  h_median, h_lo,
+ * h_hi (k_max doubles each, may be NULL) receive the median and the
+ * (1 -/+ coverage)/2 quantiles (linear interpolation between order
+ * statistics at q (R-1)).  resamples in 2..1024.  Synchronises `stream`.
+ * Errors: FP_EINVAL, FP_ENUMERIC (a non-finite trace), FP_EDEVICE.
+ */
+int fp_bootstrap(const double* d_trace, int64_t num_pairs, int k_max, int resamples, uint64_t seed,
+                 double* d_samples, double* h_median, double* h_lo, double* h_hi, double coverage,
+                 void* stream);
+
+/*
+ * fp_layers_to_epsilon -- layers needed for an epsilon-approximate k-design
+ * from estimates at several depths (main text: F - F_Haar = A^2 exp(-2l/C)
+ * gives l = C (k n log q + log A + log(1/epsilon)); Supplementary Methods,
+ * choice of curve fitting region: only depths with
+ * 0 < (F - F_Haar)/F_Haar < rel_dev_max, the paper's 5).  d_F holds
+ * n_layers x resamples doubles on the device (F of depth h_layers[j] in
+ * sample r at j * resamples + r; bootstrap samples of each depth, or one
+ * estimate per depth with resamples = 1); h_layers are the depths (host).
+ * Per sample, a least-squares line through (l, log(F - F_Haar)) over the
+ * qualifying depths; a sample with fewer than two of them, or a line that
+ * does not decay, has no value (NaN in d_out, counted in *h_failed).
+ * d_out (resamples doubles, device) may be NULL; *h_median is the median of
+ * the samples that have a value (NaN if none).  Synchronises `stream`.
+ * Errors: FP_EINVAL, FP_EDEVICE.
+ */
+int fp_layers_to_epsilon(const double* d_F, const int32_t* h_layers, int n_layers, int resamples, double F_haar,
+                         double epsilon, int n_qubits, int q, int k, double rel_dev_max, double* d_out,
+                         double* h_median, int* h_failed, void* stream);
+
+/*
+ * fp_sample_size_decision -- the adaptive sample-size rule (Supplementary
+ * Methods, determination of sample sizes): FP_STOP_BUDGET once n_done >=
+ * n_max or seconds >= max_seconds; else FP_CONTINUE while the estimate is
+ * unphysical (F < F_haar, or F above the estimate at one layer less,
+ * F_lower, when F_lower > 0); else FP_STOP_RESOLVED once F - F_haar > z se;
+ * else FP_CONTINUE.  Host only.  Errors: FP_EINVAL.
+ * fp_frame_potential_adaptive -- sample, contract and reduce batches of
+ * batch_pairs pairs (global pairs 0, 1, ... of `seed`, as fp_sample_gates
+ * numbers them) into d_trace (2 * max_pairs doubles) until the rule, applied
+ * to F^(k_rule) of all pairs so far after every batch, stops; writes F^(k)
+ * and its standard error, k = 1..k_max (h_stderr may be NULL), the pairs
+ * used and the reason.  d_gates and d_ws hold one batch (fp_gate_bytes_per_pair
+ * and fp_workspace_bytes for batch_pairs).  Synchronous.
+ * Errors: as fp_contract_trace_batch and fp_frame_potential.
+ */
+enum { FP_CONTINUE = 0, FP_STOP_RESOLVED = 1, FP_STOP_BUDGET = 2 };
+int fp_sample_size_decision(double F, double se, double F_haar, double F_lower, double z, int64_t n_done,
+                            int64_t n_max, double seconds, double max_seconds, int* decision);
+int fp_frame_potential_adaptive(const fp_ensemble_t* ens, int precision, int k_max, int k_rule, uint64_t seed,
+                                int64_t batch_pairs, int64_t max_pairs, double max_seconds, double z, double F_haar,
+                                double F_lower, void* d_gates, size_t gates_bytes, void* d_ws, size_t ws_bytes,
+                                double* d_trace, double* h_F, double* h_stderr, int64_t* h_pairs_used,
+                                int* h_reason, void* stream);
+
 /* ---- uneven batches ------------------------------------------------------- */
 /*
  * fp_contract_trace_groups -- contract several groups of pairs with different

@@ -20,6 +20,7 @@ FP_OK, FP_EINVAL, FP_ETOOBIG, FP_EDEVICE, FP_ENOTIMPL, FP_ENUMERIC = 0, -1, -2, 
 BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ = 0, 1, 2, 3, 4
 C128, C64, BF16X3 = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_WAIT, LAUNCH_WAIT_FREE = 0, 1, 2
+CONTINUE, STOP_RESOLVED, STOP_BUDGET = 0, 1, 2
 
 ERROR_NAMES = {FP_EINVAL: "FP_EINVAL", FP_ETOOBIG: "FP_ETOOBIG", FP_EDEVICE: "FP_EDEVICE",
                FP_ENOTIMPL: "FP_ENOTIMPL", FP_ENUMERIC: "FP_ENUMERIC"}
@@ -33,7 +34,8 @@ EXPORTS = [
     "fp_mlp_init", "fp_mlp_features", "fp_mlp_forward", "fp_mlp_backward", "fp_mlp_adam_step", "fp_mlp_gemm", "fp_mlp_targets", "fp_cv_coefficient", "fp_log_moments",
     "fp_mlp_log_targets", "fp_mlp_link",
     "fp_frame_potential_cv", "fp_frame_potential_noalloc", "fp_cv_holdout", "fp_moments_f32", "fp_cv_choose",
-    "fp_cv_time_to_rel_se", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
+    "fp_cv_time_to_rel_se", "fp_haar_frame_potential", "fp_bootstrap", "fp_layers_to_epsilon",
+    "fp_sample_size_decision", "fp_frame_potential_adaptive", "fp_set_launch_mode", "fp_profile_begin", "fp_profile_end", "fp_last_error", "fp_version",
 ]
 
 
@@ -97,6 +99,12 @@ def _load():
         "fp_mlp_link": (I, [P, I64, I, D, D, D, P, P]),
         "fp_frame_potential_cv": (I, [P, P, I64, P, I64, I, D, P, P, P]),
         "fp_set_launch_mode": (I, [I]),
+        "fp_haar_frame_potential": (I, [I, D, ctypes.POINTER(D)]),
+        "fp_bootstrap": (I, [P, I64, I, I, U64, P, P, P, P, D, P]),
+        "fp_layers_to_epsilon": (I, [P, P, I, I, D, D, I, I, I, D, P, ctypes.POINTER(D), ctypes.POINTER(I), P]),
+        "fp_sample_size_decision": (I, [D, D, D, D, D, I64, I64, D, D, ctypes.POINTER(I)]),
+        "fp_frame_potential_adaptive": (I, [E, I, I, I, U64, I64, I64, D, D, D, D, P, SZ, P, SZ, P, P, P,
+                                            ctypes.POINTER(I64), ctypes.POINTER(I), P]),
         "fp_cv_holdout": (I, [P, P, I64, I, P, P]),
         "fp_moments_f32": (I, [P, I64, P, P, P]),
         "fp_cv_choose": (I, [D, D, D, ctypes.POINTER(I), ctypes.POINTER(D)]),
@@ -306,6 +314,60 @@ def fp_cv_time_to_rel_se(stats_B, c, var_g_C, rel_se, sec_per_exact, sec_per_sur
     _check(lib.fp_cv_time_to_rel_se(st, float(c), float(var_g_C), float(rel_se), float(sec_per_exact),
                                     float(sec_per_surrogate), ctypes.byref(tp), ctypes.byref(tc)))
     return tp.value, tc.value
+
+
+def fp_haar_frame_potential(k, dim):
+    out = ctypes.c_double()
+    _check(lib.fp_haar_frame_potential(int(k), float(dim), ctypes.byref(out)))
+    return out.value
+
+
+def fp_bootstrap(d_trace, num_pairs, k_max, resamples=300, seed=0, d_samples=None, coverage=0.95, stream=None):
+    """Bootstrap of F^(k): (median, lo, hi) lists of k_max values; d_samples (optional device
+    tensor of k_max * resamples doubles) receives F^(k) of every resample."""
+    med, lo, hi = ((ctypes.c_double * k_max)() for _ in range(3))
+    _check(lib.fp_bootstrap(_ptr(d_trace), int(num_pairs), int(k_max), int(resamples), ctypes.c_uint64(seed),
+                            _ptr(d_samples), med, lo, hi, float(coverage), _stream(stream)))
+    return list(med), list(lo), list(hi)
+
+
+def fp_layers_to_epsilon(d_F, layers, resamples, F_haar, epsilon, n_qubits, q, k, rel_dev_max=5.0, d_out=None,
+                         stream=None):
+    """(median layers, failed samples) of the exponential fit over the fit region."""
+    lay = (ctypes.c_int32 * len(layers))(*[int(x) for x in layers])
+    med, failed = ctypes.c_double(), ctypes.c_int()
+    _check(lib.fp_layers_to_epsilon(_ptr(d_F), lay, len(layers), int(resamples), float(F_haar), float(epsilon),
+                                    int(n_qubits), int(q), int(k), float(rel_dev_max), _ptr(d_out),
+                                    ctypes.byref(med), ctypes.byref(failed), _stream(stream)))
+    return med.value, failed.value
+
+
+def fp_sample_size_decision(F, se, F_haar, F_lower, z, n_done, n_max, seconds, max_seconds):
+    d = ctypes.c_int()
+    _check(lib.fp_sample_size_decision(float(F), float(se), float(F_haar), float(F_lower), float(z), int(n_done),
+                                       int(n_max), float(seconds), float(max_seconds), ctypes.byref(d)))
+    return d.value
+
+
+def fp_frame_potential_adaptive(ens, precision, k_max, k_rule, seed, batch_pairs, max_pairs, max_seconds, z,
+                                F_haar, F_lower=-1.0, d_gates=None, d_ws=None, d_trace=None, stream=None):
+    """Adaptive estimate: returns (F, SE, pairs used, reason, d_trace)."""
+    ens = _ens(ens)
+    if d_gates is None:
+        d_gates = alloc_gates(ens, batch_pairs, precision)
+    if d_ws is None:
+        d_ws = workspace(ens, batch_pairs, precision)
+    if d_trace is None:
+        d_trace = torch.empty(2 * int(max_pairs), dtype=torch.float64, device="cuda")
+    f = (ctypes.c_double * k_max)()
+    se = (ctypes.c_double * k_max)()
+    used, reason = ctypes.c_int64(), ctypes.c_int()
+    _check(lib.fp_frame_potential_adaptive(ctypes.byref(ens), int(precision), int(k_max), int(k_rule),
+                                           ctypes.c_uint64(seed), int(batch_pairs), int(max_pairs),
+                                           float(max_seconds), float(z), float(F_haar), float(F_lower), _ptr(d_gates),
+                                           d_gates.numel(), _ptr(d_ws), d_ws.numel(), _ptr(d_trace), f, se,
+                                           ctypes.byref(used), ctypes.byref(reason), _stream(stream)))
+    return list(f), list(se), used.value, reason.value, d_trace
 
 
 def fp_log_moments(d_trace, num_pairs, eps=1e-30, stream=None):

@@ -201,11 +201,14 @@ def test_haar_two_qubit_validation(fp):
         fp.fp_sample_gates(ens, chunk, seed, o, fp.C128, g)
         fp.fp_contract_trace_batch(ens, chunk, fp.C128, g, tr[2 * o: 2 * (o + chunk)], ws)
     f, se = fp.fp_frame_potential(tr, total, 6)
+    # the paper's uncertainty analysis: 300 bootstrap resamples (99.9 % interval)
+    med, lo, hi = fp.fp_bootstrap(tr, total, 6, 300, seed, coverage=0.999)
     want = [haar_frame_potential(k, 4) for k in range(1, 7)]
     assert want == [1, 2, 6, 24, 119, 694]
     for k in range(6):
-        print(f"k={k + 1}: F={f[k]:.5g} +- {se[k]:.2g} (exact {want[k]})")
+        print(f"k={k + 1}: F={f[k]:.5g} +- {se[k]:.2g}, bootstrap [{lo[k]:.5g}, {hi[k]:.5g}] (exact {want[k]})")
         assert abs(f[k] - want[k]) <= 5 * se[k], (k + 1, f[k], se[k], want[k])
+        assert lo[k] <= want[k] <= hi[k], (k + 1, lo[k], hi[k], want[k])
         assert se[k] <= 0.02 * want[k]
 
 
@@ -224,3 +227,5 @@ def test_brickwork_n20_first_moment_is_one(fp, depth):
         fp.fp_contract_trace_batch(ens, chunk, fp.C64, g, tr[2 * o: 2 * (o + chunk)], ws)
     f, se = fp.fp_frame_potential(tr, npairs, 1)
     assert abs(f[0] - 1.0) <= 5 * se[0], (depth, f[0], se[0])
+    med, lo, hi = fp.fp_bootstrap(tr, npairs, 1, 300, seed, coverage=0.999)
+    assert lo[0] <= 1.0 <= hi[0], (depth, lo[0], hi[0])

@@ -147,3 +147,23 @@ def test_local_random_plan_edge_cases(fp):
         fp.fp_plan_local_random_host(5, [0, 4], [1, 1])   # bond 4 does not exist for n = 5
     with pytest.raises(ValueError):
         fp.fp_plan_local_random_host(5, [0, 1], [1])      # both circuits need the same step count
+
+
+def test_haar_frame_potential_matches_the_oracle_count():
+    import paper_2205_09900_amd as fp
+    from oracle.haar_moments import haar_frame_potential
+    for k in range(1, 9):
+        for d in range(1, 10):
+            assert fp.fp_haar_frame_potential(k, d) == haar_frame_potential(k, d), (k, d)
+
+
+def test_sample_size_decision_matches_the_oracle_rule():
+    import itertools
+    import paper_2205_09900_amd as fp
+    from oracle import statistics as st
+    cases = itertools.product([1.5, 2.0, 2.2, 2.6, 3.5], [0.01, 0.1, 0.4], [None, 2.4, 4.0], [100, 1000],
+                              [1.0, 20.0])
+    for f, se, lower, n_done, secs in cases:
+        want = st.adaptive_decision(f, se, 2.0, lower, 3.0, n_done, 1000, secs, 10.0)
+        got = fp.fp_sample_size_decision(f, se, 2.0, -1.0 if lower is None else lower, 3.0, n_done, 1000, secs, 10.0)
+        assert got == want, (f, se, lower, n_done, secs)
