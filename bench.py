@@ -181,7 +181,7 @@ def layer_scaling(fp, torch, traces_by_depth, n, k_max=3, resamples=300, epsilon
         med, lo, hi = fp.fp_bootstrap(tr, tr.numel() // 2, k_max, resamples, 0xB0075 + d, samples[j])
         boot[str(d)] = {"median": med, "lo95": lo, "hi95": hi}
     out = {"depths": depths, "bootstrap": boot, "layers_to_epsilon": {}}
-    for k in range(1, k_max + 1):
+    for k in range(2, k_max + 1):  # F^(1) equals its Haar value exactly for these ensembles: nothing to fit
         fk = samples[:, k - 1, :].contiguous()
         med, failed = fp.fp_layers_to_epsilon(fk, depths, resamples, fp.fp_haar_frame_potential(k, 2.0 ** n),
                                               epsilon, n, 2, k)

@@ -255,20 +255,23 @@ constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at
 constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
 constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
-constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;
+constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;        // registers predicted up to 2^31 entries
+constexpr int64_t POOL_BUDGET_DEEP = (int64_t)192 << 30;  // beyond: most of the device's 288 GB
 
-static int64_t slot_count(int bits, int elem, int64_t large_pairs) {
+static int64_t slot_count(int bits, int elem, int64_t large_pairs, int64_t budget = POOL_BUDGET) {
   int64_t per = hbm_slot_bytes(bits, elem);
-  int64_t s = POOL_BUDGET / per;
+  int64_t s = budget / per;
   if (s > 512) s = 512;
   if (s > large_pairs) s = large_pairs;
   if (s < 1) s = 1;
   return s;
 }
 
-// predicted largest boundary of a local random batch (bits)
+// predicted largest boundary of a local random batch (bits), unclipped
+static int lr_predicted_bits_raw(int n, int S) { return (int)(4.0 * S / (n - 1)) + 10; }
+// the same, clipped to the slot width the workspace is sized in
 static int lr_predicted_bits(int n, int S) {
-  int b = (int)(4.0 * S / (n - 1)) + 10;
+  const int b = lr_predicted_bits_raw(n, S);
   return b > 30 ? 30 : b;
 }
 
@@ -294,7 +297,7 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
       *out = 0;
       return FP_OK;
     }
-    if (hp.hdr.peak_bits > 31) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
+    if (hp.hdr.peak_bits > SLOT_BITS) return set_error(FP_ETOOBIG, "boundary of %d bits", hp.hdr.peak_bits);
     int64_t slots = slot_count(hp.hdr.peak_bits, elem, num_pairs);
     *out = (size_t)(256 + slots * hbm_slot_bytes(hp.hdr.peak_bits, elem));
     return FP_OK;
@@ -302,8 +305,12 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
   const int G = e->depth;
   LrLayout l = lr_layout(e->n_qubits, G, precision);
   const int bits = lr_predicted_bits(e->n_qubits, e->depth);
+  // the deep pool where registers beyond 2^31 entries are expected: wide
+  // circuits (the prediction is made for them; narrow ones stay far below it)
+  const bool deep = e->n_qubits >= 32 && lr_predicted_bits_raw(e->n_qubits, e->depth) > 31;
+  const int64_t budget = deep ? POOL_BUDGET_DEEP : POOL_BUDGET;
   int64_t pool = 0;
-  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs) * hbm_slot_bytes(bits, elem);
+  if (bits > LR_SMALL_BITS) pool = slot_count(bits, elem, num_pairs, budget) * hbm_slot_bytes(bits, elem);
   *out = (size_t)(lr_fixed_bytes(num_pairs, l) + pool);
   return FP_OK;
 }
@@ -353,8 +360,8 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
     profile_launch_end(kc, 8.0 * dp.hdr.macs * (double)num_pairs, s);
     return rc;
   }
-  // HBM slots (32-bit entry indices: registers up to 2^31 entries)
-  if (peak > 31) return set_error(FP_ETOOBIG, "boundary of %d bits", peak);
+  // HBM slots (registers up to 2^SLOT_BITS entries)
+  if (peak > SLOT_BITS) return set_error(FP_ETOOBIG, "boundary of %d bits", peak);
   const int64_t slots = slot_count(peak, elem, num_pairs);
   const size_t need = (size_t)(256 + slots * hbm_slot_bytes(peak, elem));
   if (!ws || ws_bytes < need)
@@ -382,6 +389,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
 struct LrHint {
   double frac[5];  // class sizes per pair of the batch
   int hbm_workgroups;
+  int max_bits;    // widest register of the batch (log2 entries)
 };
 constexpr double LR_WAIT_FREE_HBM_FRAC = 0.2;  // HBM-slot share of the pairs beyond which eager batches do not wait
 static std::mutex g_hint_mu;
@@ -408,6 +416,7 @@ static LrHint hint_of(const LrDev& d, int64_t np) {
   LrHint h;
   for (int k = 0; k < 5; ++k) h.frac[k] = (double)d.range[k][1] / (double)np;
   h.hbm_workgroups = d.hbm_workgroups;
+  h.max_bits = d.max_bits;
   return h;
 }
 
@@ -640,6 +649,10 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     *out = c.aux.s[ai];
     return FP_OK;
   };
+  // The HBM-slot sweep runs with 64-bit entry indices when a register may
+  // exceed 2^31 entries: known exactly once the set-up is read back, else
+  // from the last batch of the ensemble or, for the first, from the depth.
+  bool wide_hbm = n >= 32 && lr_predicted_bits_raw(n, G) > 27;
   // flops < 0: the class's MAC count is read from the device afterwards
   auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
                           double flops) -> int {
@@ -663,7 +676,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     }
     profile_launch_begin(cls[k].kclass, sx);
     if (k == 4)
-      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx);
+      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx, wide_hbm);
     else  // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
       r = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
                           : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
@@ -699,6 +712,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
     if (rc) return rc;
     lr_hint_set(c.key, h.d, np);
+    wide_hbm = h.d.max_bits > 31;
     for (int k = 0; k < 5; ++k) dev_first[k] = h.d.range[k][0];
     int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
     int act[5], na = 0;
@@ -729,6 +743,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // as many workgroups as stay resident).  The HBM class goes on s, whose
   // order needs no cross-stream wait, so its long pairs start first.
   int grid = LR_MAX_OWNERS + LR_HELPERS;
+  if (hinted) wide_hbm = hint.max_bits > 31 || wide_hbm;
   if (hinted) {
     const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
     grid = want < grid ? want : grid;

@@ -96,13 +96,18 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
 // pair, so every pair an owner takes fits its slot.  alt (or null) holds a
 // second slot for each j < min(owners, HELP_MAX), at alt_off[b] + (j - ge[b + 1])
 // * 2^b.  Workgroups from `owners` on only help (needs HelpArgs).
+// Widest HBM slot: 2^SLOT_BITS entries (registers beyond 2^31 entries run
+// with 64-bit entry indices).  Slot arrays are indexed by width 0..SLOT_BITS
+// with one more entry (SLOT_TOP) for the totals.
+constexpr int SLOT_BITS = 36;
+constexpr int SLOT_TOP = SLOT_BITS + 1;
 struct SlotArgs {
   unsigned char* base;
   unsigned char* alt;
   int owners;
-  int ge[33];
-  long long off[33];
-  long long alt_off[33];
+  int ge[SLOT_TOP + 1];
+  long long off[SLOT_TOP + 1];
+  long long alt_off[SLOT_TOP + 1];
 };
 
 // Work sharing: owner slots j < min(owners, HELP_MAX) have a task record.
@@ -130,6 +135,7 @@ struct HelpArgs {
 constexpr int64_t HELP_AREA_BYTES = HELP_MAX * (int64_t)sizeof(HelpRec) + 256;
 
 // counter: zero at launch.  grid: workgroups (owners, then helpers).
+int slot_bits_host(const SlotArgs& sl);
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& slots,
                      int grid, hipStream_t s, const HelpArgs* help = nullptr);
 
@@ -145,7 +151,8 @@ struct LrDev {
   SlotArgs sl;                  // HBM slots (owners 0: the class's pairs get NaN)
   HelpArgs help;                // work sharing (recs null: none)
   int hbm_workgroups;           // owners plus helpers-only workgroups of the HBM launch
-  int status;                   // bit 0: a pair wider than 2^31 entries; bit 1: a pair without room in the pool
+  int max_bits;                 // widest register of the chunk's pairs (log2 entries)
+  int status;                   // bit 0: a pair wider than 2^SLOT_BITS entries; bit 1: a pair without room in the pool
 };
 struct LrSetupJob {
   const int* hist;                 // pairs per peak width (PLAN_HIST)
@@ -163,7 +170,7 @@ int launch_lr_setup(const LrSetupJob& j, hipStream_t s);
 // HBM-slot sweep of a local random class set up on the device (launch `grid`
 // workgroups; those beyond dev->hbm_workgroups return at once).
 int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s);
+                         hipStream_t s, bool wide);
 // Zero n 32-bit words (a kernel, so that stream capture records no memset node).
 int launch_zero_words(void* p, int64_t n, hipStream_t s);
 // Workgroups of a kernel resident per compute unit (occupancy query, no device work),

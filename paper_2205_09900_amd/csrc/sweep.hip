@@ -121,17 +121,18 @@ constexpr int hbm_lds_bits() {
 
 // GATE: the realigned matrix (Rr, Ri) on the 2^(b-2) groups of four entries
 // (bits lo < hi of the group index are the gate's bits).
-template <typename Real, int NT, int U, bool BF3>
+// I: the index type of the register, int up to 2^31 entries, int64_t beyond.
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ __forceinline__ void gate_rounds(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo, int hi,
-                                            int ip, int iq, int ng, int lane, bool track, Real& lmax, int base = 0) {
+                                            I ip, I iq, I ng, int lane, bool track, Real& lmax, I base = 0) {
   const bool whole = ng % (NT * U) == 0;
-  if (U == 1 && (lane & ~63) >= ng) return;
-  for (int g0 = 0; g0 < ng; g0 += NT * U) {
+  if (U == 1 && (I)(lane & ~63) >= ng) return;
+  for (I g0 = 0; g0 < ng; g0 += NT * U) {
     Cplx<Real> v[U][4];
-    int idx[U];
+    I idx[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int g = base + ((g0 + lane + u * NT) & (ng - 1));
+      const I g = base + ((g0 + lane + u * NT) & (ng - 1));
       idx[u] = insert_zero(insert_zero(g, lo), hi);
       v[u][0] = B[idx[u]];
       v[u][1] = B[idx[u] + ip];
@@ -163,35 +164,35 @@ __device__ __forceinline__ void gate_rounds(Cplx<Real>* B, const Real (&Rr)[16],
   }
 }
 
-template <typename Real, int NT, int U, bool BF3>
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo, int hi,
-                                         int ip, int iq, int ng, int lane, bool track, Real& lmax) {
+                                         I ip, I iq, I ng, int lane, bool track, Real& lmax) {
   if constexpr (U > 1) {
     if (ng < NT * U) {
-      gate_any<Real, NT, U / 2, BF3>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
+      gate_any<Real, NT, U / 2, BF3, I>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
       return;
     }
   }
-  gate_rounds<Real, NT, U, BF3>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
+  gate_rounds<Real, NT, U, BF3, I>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
 }
 
 // BELL from b to b + 2 bits: dst[k + 3s] = src[k], dst[k + s] = dst[k + 2s] = 0
 // (s = 2^b), and dst[k] = src[k] when the boundary moves (COPY); entries
 // k = base .. base + n - 1.
-template <typename Real, int NT, int U, bool COPY>
-__device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int s, int lane, int n, int base) {
+template <typename Real, int NT, int U, bool COPY, typename I>
+__device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* dst, I s, int lane, I n, I base) {
   const bool whole = n % (NT * U) == 0;
-  if (U == 1 && (lane & ~63) >= n) return;
+  if (U == 1 && (I)(lane & ~63) >= n) return;
   Cplx<Real> z;
   z.x = (Real)0;
   z.y = (Real)0;
-  for (int k0 = 0; k0 < n; k0 += NT * U) {
+  for (I k0 = 0; k0 < n; k0 += NT * U) {
     Cplx<Real> v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = src[base + ((k0 + lane + u * NT) & (n - 1))];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int k = base + k0 + lane + u * NT;
+      const I k = base + k0 + lane + u * NT;
       if (whole || k0 + lane + u * NT < n) {
         if (COPY) dst[k] = v[u];
         dst[k + s] = z;
@@ -202,16 +203,16 @@ __device__ __forceinline__ void bell_rounds(const Cplx<Real>* src, Cplx<Real>* d
   }
 }
 
-template <typename Real, int NT, int U, bool COPY>
+template <typename Real, int NT, int U, bool COPY, typename I>
 __device__ __forceinline__ void bell_op(const Cplx<Real>* src, Cplx<Real>* dst, int b, int lane) {
-  const int s = 1 << b;
+  const I s = (I)1 << b;
   if constexpr (U > 1) {
     if (s < NT * U) {
-      bell_op<Real, NT, U / 2, COPY>(src, dst, b, lane);
+      bell_op<Real, NT, U / 2, COPY, I>(src, dst, b, lane);
       return;
     }
   }
-  bell_rounds<Real, NT, U, COPY>(src, dst, s, lane, s, 0);
+  bell_rounds<Real, NT, U, COPY, I>(src, dst, s, lane, s, (I)0);
 }
 
 // TRACE over bits p < q of a 2^b register: dst[j] = src[i0] + src[i0 + 2^p + 2^q],
@@ -219,18 +220,18 @@ __device__ __forceinline__ void bell_op(const Cplx<Real>* src, Cplx<Real>* dst, 
 // reads all its inputs before anyone writes (a barrier between); every input
 // of a round lies at or above its outputs, and later rounds read above what
 // earlier ones wrote.  The barriers are reached by every lane.
-template <typename Real, int NT, int U, bool INPLACE>
-__device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* dst, int nout, int p, int q, int lane,
-                                             bool track, Real& lmax, int base = 0) {
-  const int step = (1 << p) + (1 << q);
+template <typename Real, int NT, int U, bool INPLACE, typename I>
+__device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* dst, I nout, int p, int q, int lane,
+                                             bool track, Real& lmax, I base = 0) {
+  const I step = ((I)1 << p) + ((I)1 << q);
   const bool whole = nout % (NT * U) == 0;
-  const bool idle = U == 1 && (lane & ~63) >= nout;  // wavefront-uniform
-  for (int j0 = 0; j0 < nout; j0 += NT * U) {
+  const bool idle = U == 1 && (I)(lane & ~63) >= nout;  // wavefront-uniform
+  for (I j0 = 0; j0 < nout; j0 += NT * U) {
     Cplx<Real> acc[U];
     if (!idle) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int i0 = insert_zero(insert_zero(base + ((j0 + lane + u * NT) & (nout - 1)), p), q);
+        const I i0 = insert_zero(insert_zero(base + ((j0 + lane + u * NT) & (nout - 1)), p), q);
         const Cplx<Real> a0 = src[i0], a1 = src[i0 + step];
         acc[u].x = a0.x + a1.x;
         acc[u].y = a0.y + a1.y;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* 
     if (!idle) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int j = j0 + lane + u * NT;
+        const I j = j0 + lane + u * NT;
         if (whole || j < nout) dst[base + j] = acc[u];
       }
     }
@@ -250,17 +251,17 @@ __device__ __forceinline__ void trace_rounds(const Cplx<Real>* src, Cplx<Real>* 
   }
 }
 
-template <typename Real, int NT, int U, bool INPLACE>
+template <typename Real, int NT, int U, bool INPLACE, typename I>
 __device__ __forceinline__ void trace_op(const Cplx<Real>* src, Cplx<Real>* dst, int b, int p, int q, int lane,
                                          bool track, Real& lmax) {
-  const int nout = 1 << (b - 2);
+  const I nout = (I)1 << (b - 2);
   if constexpr (U > 1) {
     if (nout < NT * U) {
-      trace_op<Real, NT, U / 2, INPLACE>(src, dst, b, p, q, lane, track, lmax);
+      trace_op<Real, NT, U / 2, INPLACE, I>(src, dst, b, p, q, lane, track, lmax);
       return;
     }
   }
-  trace_rounds<Real, NT, U, INPLACE>(src, dst, nout, p, q, lane, track, lmax);
+  trace_rounds<Real, NT, U, INPLACE, I>(src, dst, nout, p, q, lane, track, lmax);
 }
 
 // ---- work sharing among workgroups (widest pairs) ----
@@ -286,17 +287,17 @@ __device__ __forceinline__ T load_agent(const T* p) {
 
 // Items base .. base + n - 1 of a shared op (groups of GATE, entries of BELL,
 // outputs of TRACE); BELL stays in place, TRACE goes from src to dst.
-template <typename Real, int NT, int U, bool BF3>
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ __forceinline__ void shared_chunk(int type, int b, int p, int q, bool track, const Real (&Rr)[16],
-                                             const Real (&Ri)[16], Cplx<Real>* src, Cplx<Real>* dst, int base, int n,
+                                             const Real (&Ri)[16], Cplx<Real>* src, Cplx<Real>* dst, I base, I n,
                                              int lane, Real& lmax) {
   if (type == OP_GATE) {
     const int lo = p < q ? p : q, hi = p < q ? q : p;
-    gate_rounds<Real, NT, U, BF3>(src, Rr, Ri, lo, hi, 1 << p, 1 << q, n, lane, track, lmax, base);
+    gate_rounds<Real, NT, U, BF3, I>(src, Rr, Ri, lo, hi, (I)1 << p, (I)1 << q, n, lane, track, lmax, base);
   } else if (type == OP_BELL) {
-    bell_rounds<Real, NT, U, false>(src, src, 1 << b, lane, n, base);
+    bell_rounds<Real, NT, U, false, I>(src, src, (I)1 << b, lane, n, base);
   } else {
-    trace_rounds<Real, NT, U, false>(src, dst, n, p, q, lane, track, lmax, base);
+    trace_rounds<Real, NT, U, false, I>(src, dst, n, p, q, lane, track, lmax, base);
   }
 }
 
@@ -316,13 +317,14 @@ __device__ __forceinline__ bool pairs_exhausted(const unsigned long long* counte
 // GATE: (Rr, Ri) is the scaled matrix in registers, `mat` the unscaled one in
 // LDS and sc the scale exponent removed from it.  Returns false if the
 // helpers' chunks did not all finish within the wait bound.
-template <typename Real, int NT, int U, bool BF3>
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, int q, bool track,
                            const Real (&Rr)[16], const Real (&Ri)[16], const Cplx<Real>* mat, int sc,
                            Cplx<Real>* src, Cplx<Real>* dst, int lane, unsigned long long* sh, Real& lmax) {
   const int cbits = type == OP_BELL ? b : b - 2;  // log2 of the op's items
-  int chb = cbits - 8;                            // at most 256 chunks of 2^12 .. 2^15 items
-  chb = chb < 12 ? 12 : chb > 15 ? 15 : chb;
+  int chb = cbits - 8;                            // at most 256 chunks of 2^12 .. 2^15 items,
+  chb = chb < 12 ? 12 : chb > 15 ? 15 : chb;      // more for the widest registers
+  if (cbits - chb > 19) chb = cbits - 19;         // (the claim word counts up to 2^20 chunks)
   const unsigned nch = 1u << (cbits - chb);
   seq = (seq + 1) & 0xFFFFFFu;
   if (seq == 0) seq = 1;
@@ -353,7 +355,7 @@ __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, 
     const unsigned c = claim_next(sh[0]);
     __syncthreads();
     if (c >= nch) break;
-    shared_chunk<Real, NT, U, BF3>(type, b, p, q, track, Rr, Ri, src, dst, (int)(c << chb), 1 << chb, lane, lmax);
+    shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, (I)c << chb, (I)1 << chb, lane, lmax);
     ++mine;
   }
   if (lane == 0) {
@@ -373,7 +375,7 @@ __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, 
 }
 
 // A helper's chunk of the task in `rec`, claimed with word w.
-template <typename Real, int NT, int U, bool BF3>
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* red, Real* hmat) {
   __threadfence();  // acquire: the record and the boundary as the owner published them
   if (lane < 32) hmat[lane] = (Real)__longlong_as_double((long long)load_agent(&rec->mat[lane]));
@@ -390,8 +392,8 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
     Ri[k] = hmat[2 * k + 1];
   }
   Real lmax = 0;
-  shared_chunk<Real, NT, U, BF3>(type, b, p, q, track, Rr, Ri, src, dst, (int)(claim_next(w) << chb), 1 << chb, lane,
-                                 lmax);
+  shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, (I)claim_next(w) << chb, (I)1 << chb,
+                                    lane, lmax);
   if (track) {
     const Real m = group_max<Real, NT>(lmax, red);
     if (lane == 0) atomicMax(&rec->maxbits, (unsigned long long)__double_as_longlong((double)m));
@@ -401,7 +403,7 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
   if (lane == 0) atomicAdd(&rec->done, 1u);
 }
 
-template <typename Real, int NT, int U, bool BF3>
+template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cplx<Real>* mats_s, uint2* ops_s,
                                                 const Op* __restrict__ ops, int num_ops, int num_gate_ops,
                                                 const Real* __restrict__ wmat, const int2* __restrict__ wgates,
@@ -472,40 +474,39 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         expo += pend;
         pend = 0;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
-        const int ng = 1 << (b - 2);
         if (in_lds)
-          gate_any<Real, NT, U, BF3>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
+          gate_any<Real, NT, U, BF3, int>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
         else if (share(b))
-          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_GATE, b, p, q, track, Rr, Ri, mats_s + 16 * i, sc, H,
-                                                  H, lane, sh, lmax);
+          failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_GATE, b, p, q, track, Rr, Ri, mats_s + 16 * i, sc, H,
+                                                     H, lane, sh, lmax);
         else
-          gate_any<Real, NT, U, BF3>(H, Rr, Ri, lo, hi, 1 << p, 1 << q, ng, lane, track, lmax);
+          gate_any<Real, NT, U, BF3, I>(H, Rr, Ri, lo, hi, (I)1 << p, (I)1 << q, (I)1 << (b - 2), lane, track, lmax);
       } else if (type == OP_BELL) {
         if (!in_lds && share(b + 2)) {
-          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_BELL, b, p, q, false, Rr0, Ri0, mats_s, 0, H, H, lane,
-                                                  sh, lmax);
+          failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_BELL, b, p, q, false, Rr0, Ri0, mats_s, 0, H, H,
+                                                     lane, sh, lmax);
         } else if (!in_lds) {
-          bell_op<Real, NT, U, false>(H, H, b, lane);
+          bell_op<Real, NT, U, false, I>(H, H, b, lane);
         } else if (b + 2 <= LB) {
-          bell_op<Real, NT, U, false>(L, L, b, lane);
+          bell_op<Real, NT, U, false, int>(L, L, b, lane);
         } else {
-          bell_op<Real, NT, U, true>(L, H, b, lane);
+          bell_op<Real, NT, U, true, int>(L, H, b, lane);
           in_lds = false;
         }
         b += 2;
       } else if (type == OP_TRACE) {  // p < q
         if (in_lds) {
-          trace_op<Real, NT, U, true>(L, L, b, p, q, lane, track, lmax);
+          trace_op<Real, NT, U, true, int>(L, L, b, p, q, lane, track, lmax);
         } else if (b - 2 > LB && H2 != nullptr && share(b)) {  // out of place, into the other buffer
-          failed |= !run_shared<Real, NT, U, BF3>(rec, seq, OP_TRACE, b, p, q, track, Rr0, Ri0, mats_s, 0, H, H2, lane,
-                                                  sh, lmax);
+          failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_TRACE, b, p, q, track, Rr0, Ri0, mats_s, 0, H, H2,
+                                                     lane, sh, lmax);
           Cplx<Real>* t = H;
           H = H2;
           H2 = t;
         } else if (b - 2 > LB) {
-          trace_op<Real, NT, U, true>(H, H, b, p, q, lane, track, lmax);
+          trace_op<Real, NT, U, true, I>(H, H, b, p, q, lane, track, lmax);
         } else {
-          trace_op<Real, NT, U, false>(H, L, b, p, q, lane, track, lmax);
+          trace_op<Real, NT, U, false, int>(H, L, b, p, q, lane, track, lmax);
           in_lds = true;
         }
         b -= 2;
@@ -534,7 +535,7 @@ constexpr size_t hbm_lds_bytes() {
 }
 
 __device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
-  int b = 31;
+  int b = SLOT_BITS;
   while (b > 0 && sl.ge[b] <= j) --b;
   return b;
 }
@@ -543,7 +544,7 @@ __device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
 // pairs, the high 32 bits first claims, so the j-th first claim has taken a
 // pair of rank >= j, no wider than slot j.  Every pair below wide_pairs
 // counts in `finished` whatever its path, and helpers leave once all have.
-template <typename Real, int NT, bool BF3>
+template <typename Real, int NT, bool BF3, typename I>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl_arg,
                                                        HelpArgs h_arg, const LrDev* dev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -580,6 +581,10 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
     Cplx<Real>* A = nullptr;
     HelpRec* rec = nullptr;
     int sbits = -1;
+    // Once a shared op of this owner's pair did not complete, a helper may
+    // still write into its slot: the slot is not used again, and the owner's
+    // later pairs that would need it get NaN.
+    bool poisoned = false;
     for (;;) {
       if (lane == 0) next = atomicAdd(counter, sbits < 0 ? (1ull << 32) + 1ull : 1ull);
       __syncthreads();
@@ -602,7 +607,10 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
       const PlanHeader* hdr = a.hdr + pidx * a.hdr_stride;
       if (hdr->status == 0 && hdr->peak_bits > a.cap_bits) {
         double* out = a.trace + 2 * (a.trace_offset + pidx);
-        if (hdr->peak_bits > sbits && hdr->peak_bits > hbm_lds_bits<Real>()) {  // needs a wider slot
+        const bool uses_slot = hdr->peak_bits > hbm_lds_bits<Real>();
+        const bool fits_index = sizeof(I) == 8 || hdr->peak_bits <= 31;  // 32-bit indices: up to 2^31 entries
+        if (uses_slot && (hdr->peak_bits > sbits || poisoned || !fits_index)) {  // a wider slot or wider indices needed,
+                                                                                  // or a slot it may not use
           if (lane == 0) {
             out[0] = __builtin_nan("");
             out[1] = __builtin_nan("");
@@ -611,10 +619,11 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
           const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
           const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
           double re, im;
-          run_program_big<Real, NT, U, BF3>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
-                                            hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
-                                            a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red,
-                                            &re, &im, rec, A, h.help_bits, helpers, counter, np, sh);
+          run_program_big<Real, NT, U, BF3, I>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+                                               hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
+                                               a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red,
+                                               &re, &im, rec, A, h.help_bits, helpers, counter, np, sh);
+          if (re != re) poisoned = true;  // uniform: every lane holds the same result
           if (lane == 0) {
             out[0] = re;
             out[1] = im;
@@ -660,7 +669,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
       __builtin_amdgcn_s_sleep(8);
       continue;
     }
-    help_chunk<Real, NT, U, BF3>(h.recs + (flag - 1), w, lane, red, hmat);
+    help_chunk<Real, NT, U, BF3, I>(h.recs + (flag - 1), w, lane, red, hmat);
   }
 }
 
@@ -790,10 +799,10 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
   return a.bf3 ? launch_lds_real<float, true>(a, tile, s) : launch_lds_real<float, false>(a, tile, s);
 }
 
-template <typename Real, bool BF3>
+template <typename Real, bool BF3, typename I>
 static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, const SlotArgs& sl, int grid,
                          const HelpArgs& h, const LrDev* dev, hipStream_t s) {
-  const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3>;
+  const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3, I>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
@@ -805,14 +814,14 @@ void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int cou
   memset(sl, 0, sizeof(*sl));
   sl->base = base;
   sl->owners = count;
-  for (int b = 0; b <= 32; ++b) {
+  for (int b = 0; b <= SLOT_TOP; ++b) {
     int c = 0;
     while (c < count && width[c] >= b) ++c;  // widths do not increase
-    sl->ge[b] = b == 32 ? 0 : c;
+    sl->ge[b] = b == SLOT_TOP ? 0 : c;
   }
   const int nalt = with_alt ? (count < HELP_MAX ? count : HELP_MAX) : 0;
   long long off = 0, aoff = 0;
-  for (int b = 31; b >= 0; --b) {
+  for (int b = SLOT_BITS; b >= 0; --b) {
     sl->off[b] = off;
     sl->alt_off[b] = aoff;
     const int lo = sl->ge[b + 1], hi = sl->ge[b];
@@ -820,12 +829,32 @@ void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int cou
     const int alo = lo < nalt ? lo : nalt, ahi = hi < nalt ? hi : nalt;
     aoff += (long long)(ahi - alo) << b;
   }
-  sl->off[32] = off;       // entries of the slots
-  sl->alt_off[32] = aoff;  // entries of the second slots, which follow them
+  sl->off[SLOT_TOP] = off;       // entries of the slots
+  sl->alt_off[SLOT_TOP] = aoff;  // entries of the second slots, which follow them
   sl->alt = nalt > 0 ? base + off * elem : nullptr;
 }
 
-int64_t slot_args_entries(const SlotArgs& sl) { return sl.off[32] + (sl.alt != nullptr ? sl.alt_off[32] : 0); }
+int64_t slot_args_entries(const SlotArgs& sl) {
+  return sl.off[SLOT_TOP] + (sl.alt != nullptr ? sl.alt_off[SLOT_TOP] : 0);
+}
+
+// Width of the widest slot (0 without slots).
+int slot_bits_host(const SlotArgs& sl) {
+  int b = SLOT_BITS;
+  while (b > 0 && sl.ge[b] == 0) --b;
+  return b;
+}
+
+template <typename I>
+static void launch_hbm_prec(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl,
+                            int grid, const HelpArgs& h, const LrDev* dev, hipStream_t s) {
+  if (precision == FP_C128)
+    launch_hbm_t<double, false, I>(a, counter, sl, grid, h, dev, s);
+  else if (a.bf3)
+    launch_hbm_t<float, true, I>(a, counter, sl, grid, h, dev, s);
+  else
+    launch_hbm_t<float, false, I>(a, counter, sl, grid, h, dev, s);
+}
 
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl, int grid,
                      hipStream_t s, const HelpArgs* help) {
@@ -839,34 +868,30 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
     h = *help;
   }
   if (grid < sl.owners || (grid > sl.owners && h.recs == nullptr)) return set_error(FP_EINVAL, "bad HBM grid");
-  if (precision == FP_C128)
-    launch_hbm_t<double, false>(a, counter, sl, grid, h, nullptr, s);
-  else if (a.bf3)
-    launch_hbm_t<float, true>(a, counter, sl, grid, h, nullptr, s);
+  if (slot_bits_host(sl) > 31)
+    launch_hbm_prec<int64_t>(a, precision, counter, sl, grid, h, nullptr, s);
   else
-    launch_hbm_t<float, false>(a, counter, sl, grid, h, nullptr, s);
+    launch_hbm_prec<int>(a, precision, counter, sl, grid, h, nullptr, s);
   return check_launch("sweep_hbm");
 }
 
 int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s) {
+                         hipStream_t s, bool wide) {
   if (grid <= 0) return FP_OK;
   SlotArgs sl;
   memset(&sl, 0, sizeof(sl));
   const HelpArgs h = {nullptr, nullptr, 0, 0};
-  if (precision == FP_C128)
-    launch_hbm_t<double, false>(a, counter, sl, grid, h, dev, s);
-  else if (a.bf3)
-    launch_hbm_t<float, true>(a, counter, sl, grid, h, dev, s);
+  if (wide)
+    launch_hbm_prec<int64_t>(a, precision, counter, sl, grid, h, dev, s);
   else
-    launch_hbm_t<float, false>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int>(a, precision, counter, sl, grid, h, dev, s);
   return check_launch("sweep_hbm");
 }
 
 // One wavefront derives a local random chunk's launches from the planner's
 // width histogram: the ordering pass's first positions, the class ranges, and
 // the HBM slots (slot j as wide as the class's j-th widest pair, widths
-// clipped to 2^31 entries; as many owners as the pool holds, up to
+// clipped to 2^SLOT_BITS entries; as many owners as the pool holds, up to
 // max_owners; second slots for the first HELP_MAX when that keeps at least
 // half of the owners; helpers-only workgroups where the pool, not the pairs,
 // leaves compute units free).  It also clears the chunk's HBM counter and
@@ -912,7 +937,7 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   // the chunk's HBM counter and work-sharing records start at zero
   for (int i = lane; i < (int)(HELP_AREA_BYTES / 8); i += 64) reinterpret_cast<unsigned long long*>(j.recs)[i] = 0ull;
   if (lane == 0) *j.hbm_counter = 0ull;
-  // HBM class: lane b < 32 holds ge_all[b], class pairs of clipped width >= b
+  // HBM class: lane b <= SLOT_BITS holds ge_all[b], class pairs of clipped width >= b
   const long long count = rc[4];
   const int wmax = count < j.max_owners ? (int)count : j.max_owners;
   const long long pa = pos(lane), pa1 = pos(lane + 1);
@@ -920,8 +945,8 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   // (at most 2^lds_bits entries); ge_all[0] = count, ge_all[b] = pairs wider
   // than LDS with width >= b otherwise
   const long long wide_ge = pos(j.lds_bits + 1);
-  const long long ge = lane >= 32 ? 0 : lane == 0 ? count : lane <= j.lds_bits + 1 ? wide_ge : pa;
-  const long long ge1 = lane >= 31 ? 0 : lane + 1 <= j.lds_bits + 1 ? wide_ge : pa1;
+  const long long ge = lane > SLOT_BITS ? 0 : lane == 0 ? count : lane <= j.lds_bits + 1 ? wide_ge : pa;
+  const long long ge1 = lane >= SLOT_BITS ? 0 : lane + 1 <= j.lds_bits + 1 ? wide_ge : pa1;
   const long long pool_entries = j.pool_bytes > 0 ? j.pool_bytes >> j.elem_shift : 0;
   // entries of w slots, plus second slots for the first HELP_MAX of them
   // (slots of width 0 take none)
@@ -929,7 +954,7 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     const long long na = alt ? (w < HELP_MAX ? w : HELP_MAX) : 0;
     const long long g0 = ge < w ? ge : w, g1 = ge1 < w ? ge1 : w;
     const long long a0 = g0 < na ? g0 : na, a1 = g1 < na ? g1 : na;
-    return wave_sum_ll(lane >= 1 && lane < 32 ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
+    return wave_sum_ll(lane >= 1 && lane <= SLOT_BITS ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
   };
   auto largest = [&](bool alt) {
     int l = 0, h = wmax;
@@ -956,9 +981,9 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   const int g0 = none ? (lane == 0 ? owners : 0) : (int)(ge < owners ? ge : owners);
   const int g1 = none ? 0 : (int)(ge1 < owners ? ge1 : owners);
   const int nalt = alt ? (owners < HELP_MAX ? owners : HELP_MAX) : 0;
-  long long mine = lane >= 1 && lane < 32 ? (long long)(g0 - g1) << lane : 0;
+  long long mine = lane >= 1 && lane <= SLOT_BITS ? (long long)(g0 - g1) << lane : 0;
   long long amine =
-      lane >= 1 && lane < 32 ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
+      lane >= 1 && lane <= SLOT_BITS ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
   long long suf = mine, asuf = amine;  // inclusive sums over widths >= lane
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1) {
@@ -971,12 +996,12 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   // cross-lane reads first, with every lane active
   const long long total = __shfl(suf, 0, 64), atotal = __shfl(asuf, 0, 64);
   const long long wide = count > 0 ? pos(j.help_bits) : 0;
-  const long long beyond = pos(32);  // pairs wider than 2^31 entries
+  const long long beyond = pos(SLOT_BITS + 1);  // pairs wider than the widest slot
   SlotArgs& sl = d->sl;
-  if (lane <= 32) {
-    sl.ge[lane] = lane < 32 ? g0 : 0;
-    sl.off[lane] = lane < 32 ? suf - mine : total;  // entries of wider slots; [32]: all
-    sl.alt_off[lane] = lane < 32 ? asuf - amine : atotal;
+  if (lane <= SLOT_TOP) {
+    sl.ge[lane] = lane < SLOT_TOP ? g0 : 0;
+    sl.off[lane] = lane < SLOT_TOP ? suf - mine : total;  // entries of wider slots; [SLOT_TOP]: all
+    sl.alt_off[lane] = lane < SLOT_TOP ? asuf - amine : atotal;
   }
   if (lane == 0) {
     sl.owners = owners;
@@ -994,6 +1019,10 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     }
     d->hbm_workgroups = owners == 0 ? (count > 0 ? 1 : 0) : owners + extra;
     d->status = (beyond > 0 ? 1 : 0) | (none ? 2 : 0);
+  }
+  {  // widest register: the highest width with pairs
+    const unsigned long long m = __ballot(lane < PLAN_HIST && j.hist[lane] > 0);
+    if (lane == 0) d->max_bits = m == 0 ? 0 : 63 - __clzll((long long)m);
   }
 }
 

@@ -30,6 +30,9 @@ __device__ __forceinline__ void group_sync() {
 __device__ __forceinline__ int insert_zero(int x, int pos) {
   return x + (int)((unsigned)x & (~0u << pos));
 }
+__device__ __forceinline__ int64_t insert_zero(int64_t x, int pos) {
+  return x + (int64_t)((uint64_t)x & (~0ull << pos));
+}
 
 // BF16x3 products: x = hi + lo with hi = bf16(x) (round to nearest even)
 // and lo = bf16(x - hi); a*b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b.

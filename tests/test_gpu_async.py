@@ -136,22 +136,32 @@ def test_local_random_graph_replay(fp):
     assert np.isfinite(got).all()
 
 
+SLOT_TOP = 37  # slot arrays are indexed by register width 0..36, plus one entry for the totals
+
+
 def read_setup(buf):
     """The launch set-up the device wrote into a chunk header (layout of LrDev)."""
-    import struct
-    o = 0
-    first = struct.unpack_from("<64i", buf, o); o += 256
-    rng = struct.unpack_from("<10q", buf, o); o += 80
-    o += 40  # claim counters
-    base, alt, owners = struct.unpack_from("<QQi", buf, o); o += 20
-    ge = struct.unpack_from("<33i", buf, o); o += 132
-    off = struct.unpack_from("<33q", buf, o); o += 264
-    alt_off = struct.unpack_from("<33q", buf, o); o += 264
-    recs, finished, wide, help_bits = struct.unpack_from("<QQqi", buf, o); o += 32
-    wgs, status = struct.unpack_from("<ii", buf, o)
-    return dict(first=first, range=[(rng[2 * k], rng[2 * k + 1]) for k in range(5)], base=base, alt=alt,
-                owners=owners, ge=ge, off=off, alt_off=alt_off, recs=recs, wide=wide, help_bits=help_bits,
-                wgs=wgs, status=status)
+    import ctypes
+
+    class Slot(ctypes.Structure):
+        _fields_ = [("base", ctypes.c_uint64), ("alt", ctypes.c_uint64), ("owners", ctypes.c_int32),
+                    ("ge", ctypes.c_int32 * (SLOT_TOP + 1)), ("off", ctypes.c_int64 * (SLOT_TOP + 1)),
+                    ("alt_off", ctypes.c_int64 * (SLOT_TOP + 1))]
+
+    class Help(ctypes.Structure):
+        _fields_ = [("recs", ctypes.c_uint64), ("finished", ctypes.c_uint64), ("wide", ctypes.c_int64),
+                    ("help_bits", ctypes.c_int32)]
+
+    class Dev(ctypes.Structure):
+        _fields_ = [("first", ctypes.c_int32 * 64), ("range", ctypes.c_int64 * 10), ("claim", ctypes.c_uint64 * 5),
+                    ("sl", Slot), ("help", Help), ("wgs", ctypes.c_int32), ("max_bits", ctypes.c_int32),
+                    ("status", ctypes.c_int32)]
+
+    d = Dev.from_buffer_copy(bytes(buf[: ctypes.sizeof(Dev)]))
+    return dict(first=list(d.first), range=[(d.range[2 * k], d.range[2 * k + 1]) for k in range(5)],
+                base=d.sl.base, alt=d.sl.alt, owners=d.sl.owners, ge=list(d.sl.ge), off=list(d.sl.off),
+                alt_off=list(d.sl.alt_off), recs=d.help.recs, wide=d.help.wide, help_bits=d.help.help_bits,
+                wgs=d.wgs, max_bits=d.max_bits, status=d.status)
 
 
 def test_device_setup_matches_host_plans(fp):
@@ -164,7 +174,7 @@ def test_device_setup_matches_host_plans(fp):
     ws = fp.workspace(ens, n, C64)
     fp.contract(ens, g, n, C64, ws)
     torch.cuda.synchronize()
-    d = read_setup(ws[1024:1024 + 1200].cpu().numpy().tobytes())
+    d = read_setup(ws[1024:1024 + 2048].cpu().numpy().tobytes())
     for b in range(64):
         assert d["first"][b] == int((peaks > b).sum()), b
     bounds = [(-1, -1), (-1, 10), (10, 12), (12, 12), (12, 63)]
@@ -178,8 +188,10 @@ def test_device_setup_matches_host_plans(fp):
     assert 1 <= owners <= min(len(hbm), 512)
     ge = d["ge"]
 
+    assert d["max_bits"] == int(peaks.max())
+
     def width(j):
-        b = 31
+        b = SLOT_TOP - 1
         while b > 0 and ge[b] <= j:
             b -= 1
         return b
