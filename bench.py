@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--in-flight", type=int, default=3, help="batches in flight (buffers and streams) in the timed runs")
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
     ap.add_argument("--depth-steps", type=int, default=6, help="batches timed per step count of --per-depth")
-    ap.add_argument("--per-depth", default="50,100,150,200,250",
+    ap.add_argument("--per-depth", default="50,100,150,200,250,300",
                     help="comma list of step counts measured besides the headline ('' = none)")
     ap.add_argument("--feasibility", default=",".join(str(x) for x in range(50, 801, 50)),
                     help="comma list of step counts whose register widths are reported ('' = none)")
@@ -353,13 +353,13 @@ def hea_mixed(fp, torch, pairs, steps=3):
     return out
 
 
-LR_MAX_BITS = 31  # widest register of the HBM-slot sweep: 2^31 entries (32-bit entry indices)
+LR_MAX_BITS = 36  # widest slot of the HBM-slot sweep: 2^36 entries (64-bit entry indices beyond 2^31)
 
 
 def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
     """Widest register of each pair in a sample per depth (the product's sampler
     and host planner on the sampled bonds), and the fraction of pairs beyond
-    what one pair may take: 2^31 entries, and one slot of that width within
+    what one pair may take: 2^36 entries, and one slot of that width within
     the workspace the library asks for a batch of `pairs`.  The sample is a
     whole batch where the tail decides (a batch fits only if its widest pair
     does), smaller where most pairs are beyond anyway."""
@@ -526,20 +526,25 @@ def main():
                     for c, v in prof.items() if v["launches"]}
 
     per_depth = {}
-    depth_steps = max(args.in_flight + 1, args.depth_steps)  # batches per depth, in flight as in the headline
     if args.per_depth:
         for s in [int(x) for x in args.per_depth.split(",") if x]:
-            r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base,
-                             in_flight=args.in_flight)
-            r0 = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1, seed_base,
-                              in_flight=args.in_flight, profile=False)
+            # step counts whose workspace takes most of the device (registers
+            # beyond 2^31 entries) run one batch at a time, two batches
+            deep = fp.fp_workspace_bytes(fp.Ensemble(fp.LOCAL_RANDOM, args.n, s), args.pairs, prec) > (64 << 30)
+            fl = 1 if deep else args.in_flight
+            depth_steps = 2 if deep else max(args.in_flight + 1, args.depth_steps)
+            torch.cuda.empty_cache()
+            r = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1 if not deep else 0, seed_base,
+                             in_flight=fl, pipeline=not deep)
+            r0 = run_workload(fp, torch, args.n, s, args.pairs, prec, depth_steps, 1 if not deep else 0, seed_base,
+                              in_flight=fl, pipeline=not deep, profile=False)
             flops = sum(r["prof"][c]["flops"] for c in SWEEP_CLASSES)
             kms = sum(r["prof"][c]["ms"] for c in SWEEP_CLASSES)
             per_depth[str(s)] = {
                 "contractions_per_s": args.pairs * depth_steps / r0["wall_s"],
                 "contractions_per_s_with_events": args.pairs * depth_steps / r["wall_s"],
                 "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
-                "F": r["F"], "SE": r["SE"],
+                "F": r["F"], "SE": r["SE"], "batches": depth_steps, "batches_in_flight": fl,
                 "kernel_ms_per_step": {k: v["ms"] / depth_steps for k, v in r["prof"].items()
                                        if v["launches"]},
             }
