@@ -19,6 +19,7 @@ Modules (each cites the passage of the paper it follows):
   weingarten    exact brickwork F^(k) by the permutation transfer
   closed_forms  special-case traces and frame potentials
   mlp           float64 reference forward/backward of the surrogate network
+  qudit         brickwork of Haar U(q^2) gates on qudits: sampler, dense, MPO-zip
 
 Parity status: every module is pinned by the tests in tests/test_oracle_*.py
 against published values, closed forms, brute force or an independent
