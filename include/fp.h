@@ -64,7 +64,18 @@ enum {
                                uniform in {X, Y, Z}, theta ~ U(0, 2 pi]) and two
                                walls of CNOT (control q, target q+1), first on
                                the bonds q even, then q odd; depth = layers     */
-  FP_HEA_PAULI_CZ = 4       /* the same with CZ walls                            */
+  FP_HEA_PAULI_CZ = 4,      /* the same with CZ walls                            */
+  FP_BRICKWORK_QUDIT = 5    /* brickwork of qudits (Sec. II.A, the generalisation
+                               to local dimension q > 2): n_qubits counts the
+                               qudits, local_dim holds q (3, 4 or 5); layer
+                               t = 1..depth acts on bonds b = t-1 (mod 2); Haar
+                               U(q^2) gates, composite index q x_b + x_{b+1}.
+                               Contracted in LDS, one pair per workgroup: the
+                               boundary of q^(2(depth-1)) entries must fit
+                               160 KiB with the gate tables (q = 3: depth <= 5;
+                               q = 4: depth <= 4; q = 5: depth <= 4 in FP_C64
+                               and FP_BF16X3, <= 3 in FP_C128); deeper ones
+                               fail with FP_ETOOBIG                          */
 };
 
 /* ---- precisions ------------------------------------------------------------ */
@@ -83,10 +94,10 @@ enum {
 };
 
 typedef struct {
-  int32_t ansatz;    /* FP_BRICKWORK_HAAR ... FP_HEA_PAULI_CZ                    */
-  int32_t n_qubits;  /* 2..64                                                    */
+  int32_t ansatz;    /* FP_BRICKWORK_HAAR ... FP_BRICKWORK_QUDIT                 */
+  int32_t n_qubits;  /* 2..64 (qubits, or qudits for FP_BRICKWORK_QUDIT)         */
   int32_t depth;     /* layers (brickwork, HEA) or steps (local random), >= 1    */
-  int32_t reserved;  /* must be 0                                                */
+  int32_t local_dim; /* FP_BRICKWORK_QUDIT: q in 3..5; every other ansatz: 0     */
 } fp_ensemble_t;
 
 typedef struct {
@@ -108,6 +119,8 @@ typedef struct {
  *   Pauli-rotation HEA: the same with the pair (theta, axis), axis 0, 1, 2
  *     for X, Y, Z stored as Real (the fixed RY(pi/4) wall is not stored; it
  *     cancels inside the trace).
+ *   qudit brickwork: [U gates][V gates], each gate q^2 x q^2 complex, row
+ *     major, in the brickwork order of the qubit case.
  * The total is padded to a multiple of 64 bytes.  Returns 0 for an invalid
  * ensemble or precision.
  */
@@ -124,6 +137,7 @@ size_t fp_gate_bytes_per_pair(const fp_ensemble_t* ens, int precision);
  *   Haar gate g: item g, words 0..15 -> complex Gaussian entry (w/4, w%4) by
  *     Box-Muller of U53(x0, x1), U53(x2, x3); the gate is the Q factor of the
  *     QR decomposition with a positive real diagonal in R (Mezzadri 2007).
+ *     Qudit gates the same with words 0..q^4-1 -> entry (w / q^2, w % q^2).
  *   local-random step s: item s, words 16, 17, ...: first 32-bit output x with
  *     x < 2^32 - (2^32 mod (n-1)) gives the bond x mod (n-1).
  *   HEA layer l, qubit q: item l*n + q, word 0: theta = 2 pi U53(x0, x1),

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfp.so")
 
 FP_OK, FP_EINVAL, FP_ETOOBIG, FP_EDEVICE, FP_ENOTIMPL, FP_ENUMERIC = 0, -1, -2, -3, -4, -5
-BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ = 0, 1, 2, 3, 4
+BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ, BRICKWORK_QUDIT = 0, 1, 2, 3, 4, 5
 C128, C64, BF16X3 = 0, 1, 2
 LAUNCH_AUTO, LAUNCH_WAIT, LAUNCH_WAIT_FREE = 0, 1, 2
 CONTINUE, STOP_RESOLVED, STOP_BUDGET = 0, 1, 2
@@ -47,13 +47,14 @@ class FPError(RuntimeError):
 
 class Ensemble(ctypes.Structure):
     _fields_ = [("ansatz", ctypes.c_int32), ("n_qubits", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("depth", ctypes.c_int32), ("local_dim", ctypes.c_int32)]
 
-    def __init__(self, ansatz, n_qubits, depth):
-        super().__init__(int(ansatz), int(n_qubits), int(depth), 0)
+    def __init__(self, ansatz, n_qubits, depth, local_dim=0):
+        super().__init__(int(ansatz), int(n_qubits), int(depth), int(local_dim))
 
     def __repr__(self):
-        return f"Ensemble(ansatz={self.ansatz}, n={self.n_qubits}, depth={self.depth})"
+        q = f", q={self.local_dim}" if self.local_dim else ""
+        return f"Ensemble(ansatz={self.ansatz}, n={self.n_qubits}, depth={self.depth}{q})"
 
 
 class Group(ctypes.Structure):

@@ -40,11 +40,16 @@ int check_launch(const char* what) { return check_hip(hipGetLastError(), what); 
 
 int check_ensemble(const fp_ensemble_t* e) {
   if (!e) return set_error(FP_EINVAL, "ensemble is NULL");
-  if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_HEA_PAULI_CZ)
+  if (e->ansatz < FP_BRICKWORK_HAAR || e->ansatz > FP_BRICKWORK_QUDIT)
     return set_error(FP_EINVAL, "unknown ansatz %d", e->ansatz);
   if (e->n_qubits < 2 || e->n_qubits > 64) return set_error(FP_EINVAL, "n_qubits %d outside 2..64", e->n_qubits);
   if (e->depth < 1) return set_error(FP_EINVAL, "depth %d < 1", e->depth);
-  if (e->reserved != 0) return set_error(FP_EINVAL, "reserved field must be 0");
+  if (e->ansatz == FP_BRICKWORK_QUDIT) {
+    if (e->local_dim < 3 || e->local_dim > 5)
+      return set_error(FP_EINVAL, "local_dim %d outside 3..5", e->local_dim);
+  } else if (e->local_dim != 0) {
+    return set_error(FP_EINVAL, "local_dim must be 0 for qubit ensembles");
+  }
   const bool hea = e->ansatz == FP_HEA_RYRZ_CZ || is_pauli_hea(e->ansatz);
   if (!hea && gates_per_circuit(e->ansatz, e->n_qubits, e->depth) > PLAN_MAX_GATES)
     return set_error(FP_EINVAL, "more than %d gates per circuit", PLAN_MAX_GATES);
@@ -287,6 +292,16 @@ int workspace_bytes_impl(const fp_ensemble_t* e, int64_t num_pairs, int precisio
     *out = 0;
     return FP_OK;
   }
+  if (e->ansatz == FP_BRICKWORK_QUDIT) {
+    HostPlan hp;
+    int rc = host_plan_brickwork(e->n_qubits, e->depth, &hp);
+    if (rc) return rc;
+    if (qudit_lds_bytes(e->local_dim, hp.hdr.peak_bits, precision) > 160 * 1024)
+      return set_error(FP_ETOOBIG, "qudit boundary of %d digits (q = %d) exceeds LDS", hp.hdr.peak_bits,
+                       e->local_dim);
+    *out = 0;
+    return FP_OK;
+  }
   if (e->ansatz == FP_BRICKWORK_HAAR) {
     DevPlan dp;
     HostPlan hp;
@@ -333,7 +348,7 @@ int contract_brickwork(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   SweepArgs a;
   memset(&a, 0, sizeof(a));
   a.gates = (const unsigned char*)gates;
-  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
   a.G = (int)gates_per_circuit(e->ansatz, e->n_qubits, e->depth);
   a.ops = dp.ops;
   a.wgates = dp.wg;
@@ -768,7 +783,7 @@ int contract_local_random(const fp_ensemble_t* e, int64_t num_pairs, int precisi
   c.elem = sweep_elem_bytes(precision);
   c.l = lr_layout(e->n_qubits, e->depth, precision);
   c.gates = (const unsigned char*)gates;
-  c.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  c.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
   c.bonds_off = bonds_offset(e->n_qubits, e->depth, precision);
   c.trace = trace;
   c.trace_offset = trace_offset;
@@ -816,7 +831,7 @@ int contract_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision, const
                         hipStream_t s, int64_t trace_offset) {
   HeaArgs a;
   a.gates = (const unsigned char*)gates;
-  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
   a.n = e->n_qubits;
   a.L = e->depth;
   a.trace = trace;
@@ -839,7 +854,7 @@ int contract_pauli_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   if (rc) return rc;
   HeaArgs a;
   a.gates = (const unsigned char*)gates;
-  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  a.gate_stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
   a.n = e->n_qubits;
   a.L = e->depth;
   a.trace = trace;
@@ -852,8 +867,35 @@ int contract_pauli_hea(const fp_ensemble_t* e, int64_t num_pairs, int precision,
   return rc;
 }
 
+// Complex multiply-adds of the GATE ops of a qudit brickwork pair: a GATE on a
+// register of b digits updates q^(b-2) groups with a q^2 x q^2 matrix.
+static double qudit_macs(const HostPlan& hp, int q) {
+  double m = 0.0;
+  for (const Op& o : hp.ops)
+    if ((o.type & OP_TYPE_MASK) == OP_GATE) m += pow((double)q, (double)o.bits + 2.0);
+  return m;
+}
+
+int contract_qudit(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+                   hipStream_t s, int64_t trace_offset) {
+  DevPlan dp;
+  int rc = get_brickwork_plan(e->n_qubits, e->depth, &dp);
+  if (rc) return rc;
+  double macs = 0.0;
+  if (profiling()) {
+    HostPlan hp;
+    if ((rc = host_plan_brickwork(e->n_qubits, e->depth, &hp))) return rc;
+    macs = qudit_macs(hp, e->local_dim);
+  }
+  profile_launch_begin(KCLASS_LDS256, s);
+  rc = launch_qudit(e, num_pairs, precision, gates, trace, dp, s, trace_offset);
+  profile_launch_end(KCLASS_LDS256, 8.0 * macs * (double)num_pairs, s);
+  return rc;
+}
+
 int contract_dispatch(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
                       void* ws, size_t ws_bytes, hipStream_t s, int64_t trace_offset) {
+  if (e->ansatz == FP_BRICKWORK_QUDIT) return contract_qudit(e, num_pairs, precision, gates, trace, s, trace_offset);
   if (is_pauli_hea(e->ansatz)) return contract_pauli_hea(e, num_pairs, precision, gates, trace, s, trace_offset);
   if (e->ansatz == FP_BRICKWORK_HAAR)
     return contract_brickwork(e, num_pairs, precision, gates, trace, ws, ws_bytes, s, trace_offset);
@@ -873,7 +915,7 @@ int fp_version(void) { return 1; }
 
 size_t fp_gate_bytes_per_pair(const fp_ensemble_t* ens, int precision) {
   if (check_ensemble(ens) || check_precision(precision)) return 0;
-  return (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+  return (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision, ens->local_dim);
 }
 
 int fp_sample_gates(const fp_ensemble_t* ens, int64_t num_pairs, uint64_t seed, uint64_t first_pair, int precision,
@@ -884,7 +926,7 @@ int fp_sample_gates(const fp_ensemble_t* ens, int64_t num_pairs, uint64_t seed, 
   if (num_pairs < 0) return set_error(FP_EINVAL, "num_pairs < 0");
   if (num_pairs == 0) return FP_OK;
   if (!d_gates) return set_error(FP_EINVAL, "d_gates is NULL");
-  const int64_t need = num_pairs * pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+  const int64_t need = num_pairs * pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision, ens->local_dim);
   if ((int64_t)gates_bytes < need) return set_error(FP_EINVAL, "gates_bytes %zu < %lld", gates_bytes, (long long)need);
   if (first_pair + (uint64_t)num_pairs > (1ull << 62)) return set_error(FP_EINVAL, "pair index beyond 2^62");
   profile_launch_begin(KCLASS_SAMPLE, (hipStream_t)stream);
@@ -1012,7 +1054,7 @@ int fp_plan_info(const fp_ensemble_t* ens, int32_t* out_bits, int32_t* peak_bits
   if (out_bits)
     for (int j = 0; j < n - 1 && j < (int)hp.bits.size(); ++j) out_bits[j] = hp.bits[j];
   if (peak_bits) *peak_bits = hp.hdr.peak_bits;
-  if (macs) *macs = hp.hdr.macs;
+  if (macs) *macs = ens->ansatz == FP_BRICKWORK_QUDIT ? qudit_macs(hp, ens->local_dim) : hp.hdr.macs;
   if (ops) *ops = hp.hdr.num_ops;
   return FP_OK;
 }

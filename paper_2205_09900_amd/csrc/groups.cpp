@@ -192,7 +192,7 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
     d.G = (int)gates_per_circuit(e->ansatz, e->n_qubits, e->depth);
     d.m = gp.bits < 2 && e->ansatz != FP_HEA_RYRZ_CZ ? 2 : gp.bits;
     d.gates = (const unsigned char*)d_gates[g];
-    d.stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, gr.precision);
+    d.stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, gr.precision, e->local_dim);
     d.gate_first = gr.first_pair;
     d.trace_offset = offset;
     d.bf3 = gr.precision == FP_BF16X3 ? 1 : 0;
@@ -293,7 +293,7 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
     if (gps[g].route != ROUTE_SEPARATE || groups[g].num_pairs == 0) continue;
     const fp_ensemble_t* e = &ens[groups[g].ensemble_index];
     const unsigned char* gg = (const unsigned char*)d_gates[g] +
-                              groups[g].first_pair * pair_bytes(e->ansatz, e->n_qubits, e->depth, groups[g].precision);
+                              groups[g].first_pair * pair_bytes(e->ansatz, e->n_qubits, e->depth, groups[g].precision, e->local_dim);
     rc = contract_dispatch(e, groups[g].num_pairs, groups[g].precision, gg, d_trace, w + off, gps[g].sep_ws, s,
                            descs[g].trace_offset);
     off += gps[g].sep_ws;

@@ -15,5 +15,8 @@ int check_hip(hipError_t e, const char* what);
 
 int launch_sample(const fp_ensemble_t* e, int64_t num_pairs, uint64_t seed, uint64_t first_pair,
                   int precision, void* d_gates, hipStream_t stream);
+// Haar U(q^2) gates of a qudit brickwork (qudit.hip)
+int launch_sample_qudit(const fp_ensemble_t* e, int64_t num_pairs, uint64_t seed, uint64_t first_pair, int precision,
+                        void* d_gates, hipStream_t s);
 
 }  // namespace fp

@@ -17,7 +17,7 @@ __host__ __device__ inline bool is_pauli_hea(int ansatz) {
 // Two-qubit gates per circuit (Haar ensembles).
 __host__ __device__ inline int64_t gates_per_circuit(int ansatz, int n, int depth) {
   if (ansatz == FP_LOCAL_RANDOM_HAAR) return depth;
-  if (ansatz == FP_BRICKWORK_HAAR) {
+  if (ansatz == FP_BRICKWORK_HAAR || ansatz == FP_BRICKWORK_QUDIT) {
     int64_t even = n / 2, odd = (n - 1) / 2;  // bonds 0,2,.. and 1,3,..
     return even * ((depth + 1) / 2) + odd * (depth / 2);
   }
@@ -34,8 +34,13 @@ __host__ __device__ inline int brickwork_bond(int n, int g) {
 
 __host__ __device__ inline int64_t pad64(int64_t x) { return (x + 63) & ~(int64_t)63; }
 
-__host__ __device__ inline int64_t pair_bytes(int ansatz, int n, int depth, int precision) {
+// local_dim: q of a qudit brickwork (ignored otherwise)
+__host__ __device__ inline int64_t pair_bytes(int ansatz, int n, int depth, int precision, int local_dim = 0) {
   const int64_t rb = real_bytes(precision);
+  if (ansatz == FP_BRICKWORK_QUDIT) {
+    const int64_t d2 = (int64_t)local_dim * local_dim;
+    return pad64(2 * gates_per_circuit(ansatz, n, depth) * d2 * d2 * 2 * rb);
+  }
   if (ansatz == FP_HEA_RYRZ_CZ || is_pauli_hea(ansatz)) return pad64(2 * (int64_t)depth * n * 2 * rb);
   const int64_t G = gates_per_circuit(ansatz, n, depth);
   int64_t b = 2 * G * 32 * rb;

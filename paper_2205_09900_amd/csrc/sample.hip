@@ -144,7 +144,8 @@ __global__ void __launch_bounds__(256) sample_pauli_kernel(Real* __restrict__ ga
 
 int launch_sample(const fp_ensemble_t* e, int64_t num_pairs, uint64_t seed, uint64_t first_pair,
                   int precision, void* d_gates, hipStream_t stream) {
-  const int64_t stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision);
+  if (e->ansatz == FP_BRICKWORK_QUDIT) return launch_sample_qudit(e, num_pairs, seed, first_pair, precision, d_gates, stream);
+  const int64_t stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
   const int threads = 256;
   if (is_pauli_hea(e->ansatz)) {
     const int64_t work = num_pairs * 2 * (int64_t)e->depth * e->n_qubits;

@@ -115,7 +115,7 @@ int fp_frame_potential_adaptive(const fp_ensemble_t* ens, int precision, int k_m
   if (!d_gates || !d_trace || !h_F || !h_pairs_used || !h_reason) return set_error(FP_EINVAL, "NULL argument");
   if (k_max < 1 || k_max > 8 || k_rule < 1 || k_rule > k_max) return set_error(FP_EINVAL, "bad k");
   if (batch_pairs < 2 || max_pairs < batch_pairs) return set_error(FP_EINVAL, "bad batch or budget");
-  const int64_t stride = pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+  const int64_t stride = pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision, ens->local_dim);
   if ((int64_t)gates_bytes < batch_pairs * stride) return set_error(FP_EINVAL, "gate buffer below one batch");
   size_t need = 0;
   if ((rc = workspace_bytes_impl(ens, batch_pairs, precision, &need))) return rc;

@@ -215,6 +215,13 @@ int hea_bits(int L);
 // walls, 0: CZ walls): boundary of 2L-2 labels, register of one more bit.
 int launch_pauli_hea(const HeaArgs& a, int precision, int cnot, hipStream_t s);
 int pauli_bits(int L);
+
+// Qudit brickwork (qudit.hip): sampler, LDS budget and the column sweep on
+// the brickwork program with base-q digits.
+struct DevPlan;
+size_t qudit_lds_bytes(int q, int peak, int precision);
+int launch_qudit(const fp_ensemble_t* e, int64_t num_pairs, int precision, const void* gates, double* trace,
+                 const DevPlan& dp, hipStream_t s, int64_t trace_offset);
 double pauli_flops_per_pair(int n, int L);
 
 int run_frame_potential(const double* d_trace, int64_t n, int kmax, double* h_F, double* h_se,

@@ -107,7 +107,9 @@ using namespace fp;
 extern "C" {
 
 size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision) {
-  if (check_ensemble(ens) || check_precision(precision) || ens->ansatz == FP_LOCAL_RANDOM_HAAR) return 0;
+  if (check_ensemble(ens) || check_precision(precision) || ens->ansatz == FP_LOCAL_RANDOM_HAAR ||
+      ens->ansatz == FP_BRICKWORK_QUDIT)
+    return 0;
   int bits = 0;
   double cost = 0.0;
   if (ensemble_bits(ens, &bits, &cost)) return 0;
@@ -115,7 +117,7 @@ size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision) {
   fp_group_t g{0, precision, 0, np};
   size_t ws = 0;
   if (fp_workspace_bytes_groups(ens, 1, &g, 1, &ws)) return 0;
-  return round256((size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision)) +
+  return round256((size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision, ens->local_dim)) +
          round256(16 * (size_t)np) + round256(ws);
 }
 
@@ -125,6 +127,8 @@ int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_b
   if ((rc = check_precision(precision))) return rc;
   if (ens->ansatz == FP_LOCAL_RANDOM_HAAR)
     return set_error(FP_ENOTIMPL, "local random pairs are planned per pair and launched by register width");
+  if (ens->ansatz == FP_BRICKWORK_QUDIT)
+    return set_error(FP_ENOTIMPL, "qudit brickworks have one launch shape (one pair per workgroup)");
   if (!out_choice) return set_error(FP_EINVAL, "out_choice is NULL");
   int bits = 0;
   double cost = 0.0;
@@ -137,7 +141,7 @@ int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_b
   hipStream_t s = (hipStream_t)stream;
   const int64_t np = tune_pairs(cost);
   unsigned char* w = (unsigned char*)d_ws;
-  const size_t gbytes = (size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision);
+  const size_t gbytes = (size_t)np * (size_t)pair_bytes(ens->ansatz, ens->n_qubits, ens->depth, precision, ens->local_dim);
   void* gates = w;
   double* trace = (double*)(w + round256(gbytes));
   unsigned char* gws = (unsigned char*)trace + round256(16 * (size_t)np);

@@ -11,7 +11,7 @@ network batches).
 
 import numpy as np
 
-BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ = 0, 1, 2, 3, 4
+BRICKWORK, LOCAL_RANDOM, HEA, PAULI_CNOT, PAULI_CZ, BRICKWORK_QUDIT = 0, 1, 2, 3, 4, 5
 C128, C64, BF16X3 = 0, 1, 2
 
 

@@ -78,6 +78,32 @@ def test_validation_errors(fp):
     assert rc == fp.FP_EINVAL           # c != 0 without surrogate values
 
 
+def test_qudit_ensemble_checks(fp):
+    """Qudit brickworks: q in 3..5 in local_dim, 0 there for qubit ensembles;
+    q^4 complex entries per gate; the register (q^(2(D-1)) entries at depth
+    D, the qubit brickwork's program with digits) must fit LDS."""
+    d2 = 9 * 9
+    G = 3 + 2 + 3  # n = 6, D = 3
+    assert fp.fp_gate_bytes_per_pair((5, 6, 3, 3), fp.C128) == -(-2 * G * d2 * 16 // 64) * 64
+    assert fp.fp_gate_bytes_per_pair((5, 6, 3, 5), fp.C64) == -(-2 * G * 625 * 8 // 64) * 64
+    for bad in [(5, 6, 3, 2), (5, 6, 3, 6), (5, 6, 3, 0), (0, 6, 3, 3)]:
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_workspace_bytes(bad, 10, fp.C64)
+        assert e.value.code == fp.FP_EINVAL, bad
+        assert fp.fp_gate_bytes_per_pair(bad, fp.C64) == 0
+    assert fp.fp_workspace_bytes((5, 6, 5, 3), 10, fp.C128) == 0   # 3^8 entries
+    assert fp.fp_workspace_bytes((5, 6, 4, 5), 10, fp.C64) == 0    # 5^6 entries, complex64
+    for ens, prec in [((5, 6, 6, 3), fp.C64), ((5, 6, 5, 4), fp.C64), ((5, 6, 4, 5), fp.C128)]:
+        with pytest.raises(fp.FPError) as e:
+            fp.fp_workspace_bytes(ens, 10, prec)
+        assert e.value.code == fp.FP_ETOOBIG, (ens, prec)
+    info = fp.fp_plan_info((5, 8, 4, 3))
+    assert info["peak_bits"] == 6 and info["bits"] == fp.fp_plan_info((0, 8, 4))["bits"]
+    # GATE ops on b digits cost q^(b+2) multiply-adds: the qubit count at q = 2
+    # is the plan's own, so the digit count is checked against it
+    assert info["macs"] > fp.fp_plan_info((0, 8, 4))["macs"] * 1.5 ** 6
+
+
 def test_brickwork_plan_sizes(fp):
     for n in (4, 6, 7, 20):
         for d in range(2, 8):
