@@ -189,10 +189,10 @@ def layer_scaling(fp, torch, traces_by_depth, n, k_max=3, resamples=300, epsilon
     return out
 
 
-def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None):
+def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None, local_dim=0):
     """Throughput of sample + contract + reduce for one fixed-topology ensemble; traces of the
     last step are returned for the precision comparison."""
-    ens = fp.Ensemble(ansatz, n, depth)
+    ens = fp.Ensemble(ansatz, n, depth, local_dim)
     chunk = chunk or pairs
     gates = fp.alloc_gates(ens, chunk, prec)
     trace = torch.empty(2 * pairs, dtype=torch.float64, device="cuda")
@@ -302,6 +302,14 @@ def suite(fp, torch, np, synth, pairs):
         for L in range(1, 8):
             r[str(L)], _ = fixed_topology(fp, torch, ans, 30, L, pairs, fp.C64, synth.workload_seed(7 + ans, L))
         out[name] = r
+    # qudit brickworks, n = 20, local dimension 3, 4, 5, every depth whose
+    # register fits LDS, complex64 (F^(k) against k!, reached once q^n >= k)
+    for q, dmax in ((3, 5), (4, 4), (5, 4)):
+        r = {}
+        for d in range(1, dmax + 1):
+            r[str(d)], _ = fixed_topology(fp, torch, fp.BRICKWORK_QUDIT, 20, d, min(pairs, 20000), fp.C64,
+                                          synth.workload_seed(10 + q, d), local_dim=q)
+        out[f"qudit_q{q}_n20"] = r
     return out
 
 
