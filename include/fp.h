@@ -349,8 +349,8 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
  * fp_autotune_table writes the table as text, one line per tuned key,
  *   "<arch> <ansatz> <n> <depth> <precision> small|large <task flops> <ms>",
  * into buf (capacity cap, NUL-terminated); fp_autotune_load reads such text.
- * Errors: FP_EINVAL, FP_ETOOBIG (workspace), FP_ENOTIMPL (local random or
- * a boundary beyond LDS), FP_EDEVICE.
+ * Errors: FP_EINVAL, FP_ETOOBIG (workspace), FP_ENOTIMPL (local random,
+ * qudit brickworks, or a boundary beyond LDS), FP_EDEVICE.
  */
 size_t fp_autotune_workspace_bytes(const fp_ensemble_t* ens, int precision);
 int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_bytes,

@@ -13,8 +13,8 @@
 // The register lives in LDS (one pair per workgroup); after every column it
 // is rescaled by a power of two with the exponent kept in float64.
 //
-// Sampling: one wavefront per gate, lane r holding row r of a Q^2 x Q^2
-// complex Gaussian matrix (Philox4x32-10 block (w, gate, pair, circuit) for
+// Sampling: one segment of 16 or 32 lanes per gate, lane r holding row r of a
+// Q^2 x Q^2 complex Gaussian matrix (Philox4x32-10 block (w, gate, pair, circuit) for
 // entry w = r Q^2 + c, Box-Muller in float64), made unitary by Gram-Schmidt
 // over the columns (two projection passes per column), which gives the Q
 // factor of the QR decomposition with a positive real R diagonal (Mezzadri
@@ -34,44 +34,65 @@ namespace fp {
 
 namespace {
 
+// Sum over the W lanes of a W-lane segment of the wavefront (W a power of two).
 template <int W>
-__device__ __forceinline__ double wsum(double v) {
+__device__ __forceinline__ double seg_sum(double v) {
 #pragma unroll
-  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, W);
   return v;
 }
 
 }  // namespace
 
+// Lanes per gate (a power of two holding the Q^2 rows), gates per wavefront
+// and wavefronts per workgroup of the sampler.
+template <int Q>
+struct QuditSampleShape {
+  static constexpr int D = Q * Q;
+  static constexpr int L = D <= 16 ? 16 : 32;
+  static constexpr int S = 64 / L;
+  static constexpr int WAVES = D <= 9 ? 4 : 2;  // static LDS within 64 KiB
+};
+
 // Gate buffer of one pair: [U gates][V gates], each gate Q^4 complex (row-major).
+// Each L-lane segment of a wavefront draws one gate: lane r holds row r in
+// LDS and every reduction over the rows is a segment shuffle.
 template <typename Real, int Q>
-__global__ void __launch_bounds__(256) sample_qudit_kernel(Real* __restrict__ gates, int64_t num_pairs, uint64_t seed,
-                                                           uint64_t first_pair, int G, int64_t stride_bytes) {
-  constexpr int D = Q * Q;
-  __shared__ double mre[4][D][D + 1], mim[4][D][D + 1];  // per wavefront, [row][col]
+__global__ void __launch_bounds__(64 * QuditSampleShape<Q>::WAVES)
+    sample_qudit_kernel(Real* __restrict__ gates, int64_t num_pairs, uint64_t seed, uint64_t first_pair, int G,
+                        int64_t stride_bytes) {
+  using Sh = QuditSampleShape<Q>;
+  constexpr int D = Sh::D, L = Sh::L, S = Sh::S;
+  __shared__ double mre[Sh::WAVES * S][D][D + 1], mim[Sh::WAVES * S][D][D + 1];  // per gate, [row][col]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t gid = (int64_t)blockIdx.x * 4 + wave;  // (pair, circuit, gate)
-  if (gid >= num_pairs * 2 * G) return;
+  const int seg = lane / L, r = lane % L;
+  const int64_t total = num_pairs * 2 * G;
+  const int64_t gid0 = ((int64_t)blockIdx.x * Sh::WAVES + wave) * S + seg;  // (pair, circuit, gate)
+  // a segment past the end repeats the last gate and stores nothing, so that
+  // every lane of the wavefront takes part in the shuffles
+  const bool valid = gid0 < total;
+  const int64_t gid = valid ? gid0 : total - 1;
   const int64_t p = gid / (2 * G);
   const int rem = (int)(gid % (2 * G));
   const uint32_t circuit = (uint32_t)(rem / G), g = (uint32_t)(rem % G);
   const uint64_t pair = first_pair + (uint64_t)p;
-  double(*Ar)[D + 1] = mre[wave];
-  double(*Ai)[D + 1] = mim[wave];
-  const int r = lane;
+  double(*Ar)[D + 1] = mre[wave * S + seg];
+  double(*Ai)[D + 1] = mim[wave * S + seg];
   if (r < D) {
     for (int c = 0; c < D; ++c) {
       const u32x4 x = draw(seed, (uint32_t)(r * D + c), g, pair, circuit);
       const double u1 = u53(x.v[0], x.v[1]), u2 = u53(x.v[2], x.v[3]);
       const double rad = sqrt(-2.0 * log(u1));
-      double s, co;
-      sincospi(2.0 * u2, &s, &co);
+      double sn, co;
+      sincospi(2.0 * u2, &sn, &co);
       Ar[r][c] = rad * co;
-      Ai[r][c] = rad * s;
+      Ai[r][c] = rad * sn;
     }
   }
   __builtin_amdgcn_wave_barrier();
-  // classical Gram-Schmidt, twice, column by column (lane r: row r)
+  // Gram-Schmidt column by column, two projection passes per column (lane r:
+  // row r; a lane reads and writes only its own row, the column sums are
+  // segment shuffles)
   for (int j = 0; j < D; ++j) {
     for (int pass = 0; pass < 2; ++pass) {
       for (int k = 0; k < j; ++k) {
@@ -81,25 +102,24 @@ __global__ void __launch_bounds__(256) sample_qudit_kernel(Real* __restrict__ ga
           cr = Ar[r][k] * Ar[r][j] + Ai[r][k] * Ai[r][j];
           ci = Ar[r][k] * Ai[r][j] - Ai[r][k] * Ar[r][j];
         }
-        cr = wsum<64>(cr);
-        ci = wsum<64>(ci);
+        cr = seg_sum<L>(cr);
+        ci = seg_sum<L>(ci);
         if (r < D) {
           const double qr = Ar[r][k], qi = Ai[r][k];
           Ar[r][j] -= cr * qr - ci * qi;
           Ai[r][j] -= cr * qi + ci * qr;
         }
-        __builtin_amdgcn_wave_barrier();
       }
     }
     double nn = r < D ? Ar[r][j] * Ar[r][j] + Ai[r][j] * Ai[r][j] : 0.0;
-    nn = wsum<64>(nn);
+    nn = seg_sum<L>(nn);
     const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     if (r < D) {
       Ar[r][j] *= inv;
       Ai[r][j] *= inv;
     }
-    __builtin_amdgcn_wave_barrier();
   }
+  if (!valid) return;
   Real* dst = reinterpret_cast<Real*>(reinterpret_cast<char*>(gates) + p * stride_bytes) +
               ((int64_t)circuit * G + g) * 2 * D * D;
   if (r < D)
@@ -114,15 +134,18 @@ int launch_sample_qudit(const fp_ensemble_t* e, int64_t num_pairs, uint64_t seed
   const int q = e->local_dim;
   const int G = (int)gates_per_circuit(FP_BRICKWORK_HAAR, e->n_qubits, e->depth);
   const int64_t stride = pair_bytes(e->ansatz, e->n_qubits, e->depth, precision, e->local_dim);
-  const int64_t waves = num_pairs * 2 * G;
-  const dim3 grid((unsigned)((waves + 3) / 4)), block(256);
+  const int64_t total = num_pairs * 2 * G;
 #define FP_QS(QV)                                                                                                   \
-  if (precision == FP_C128)                                                                                         \
-    hipLaunchKernelGGL((sample_qudit_kernel<double, QV>), grid, block, 0, s, (double*)d_gates, num_pairs, seed,     \
-                       first_pair, G, stride);                                                                      \
-  else                                                                                                              \
-    hipLaunchKernelGGL((sample_qudit_kernel<float, QV>), grid, block, 0, s, (float*)d_gates, num_pairs, seed,       \
-                       first_pair, G, stride);
+  {                                                                                                                 \
+    using Sh = QuditSampleShape<QV>;                                                                                \
+    const dim3 grid((unsigned)((total + Sh::WAVES * Sh::S - 1) / (Sh::WAVES * Sh::S))), block(64 * Sh::WAVES);      \
+    if (precision == FP_C128)                                                                                       \
+      hipLaunchKernelGGL((sample_qudit_kernel<double, QV>), grid, block, 0, s, (double*)d_gates, num_pairs, seed,   \
+                         first_pair, G, stride);                                                                    \
+    else                                                                                                            \
+      hipLaunchKernelGGL((sample_qudit_kernel<float, QV>), grid, block, 0, s, (float*)d_gates, num_pairs, seed,     \
+                         first_pair, G, stride);                                                                    \
+  }
   if (q == 3) {
     FP_QS(3)
   } else if (q == 4) {

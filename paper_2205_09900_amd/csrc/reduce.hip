@@ -138,20 +138,34 @@ __global__ void __launch_bounds__(RED_THREADS) red_moments_kernel(const double* 
   }
 }
 
-// Pass 4 (one thread): merge workgroup partials in index order.
-__global__ void red_moments_final(const Welford* __restrict__ part, int nb, int kmax,
-                                  const double* __restrict__ scale, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int e = (int)scale[0];
-  for (int k = 0; k < kmax; ++k) {
-    Welford acc{0.0, 0.0, 0.0};
-    for (int b = 0; b < nb; ++b) acc = chan_merge(acc, part[(int64_t)b * KMAX + k]);
-    const double f = ldexp(acc.mean, e * (k + 1));
-    const double se = acc.n > 1.0 ? ldexp(sqrt(acc.m2 / (acc.n - 1.0) / acc.n), e * (k + 1)) : 0.0;
-    out[2 * k] = f;
-    out[2 * k + 1] = se;
+// Pass 4 (one workgroup of 256): merge the workgroup partials.  Thirty-two
+// threads per k: thread j merges partials [j nb/32, (j+1) nb/32) in index
+// order, then a fixed tree (j with j + s, s = 16, 8, .., 1) merges the 32
+// results, so the order of the merges, and the result, never change.
+constexpr int FINAL_THREADS = 256;
+__global__ void __launch_bounds__(FINAL_THREADS) red_moments_final(const Welford* __restrict__ part, int nb, int kmax,
+                                                                   const double* __restrict__ scale,
+                                                                   double* __restrict__ out) {
+  __shared__ Welford sw[FINAL_THREADS];
+  const int t = threadIdx.x, k = t >> 5, j = t & 31;
+  Welford acc{0.0, 0.0, 0.0};
+  if (k < kmax) {
+    const int lo = (int)((int64_t)nb * j / 32), hi = (int)((int64_t)nb * (j + 1) / 32);
+    for (int b = lo; b < hi; ++b) acc = chan_merge(acc, part[(int64_t)b * KMAX + k]);
   }
-  out[2 * KMAX] = scale[1];
+  sw[t] = acc;
+  __syncthreads();
+  for (int s = 16; s > 0; s >>= 1) {
+    if (j < s) sw[t] = chan_merge(sw[t], sw[t + s]);
+    __syncthreads();
+  }
+  const int e = (int)scale[0];
+  if (j == 0 && k < kmax) {
+    const Welford w = sw[t];
+    out[2 * k] = ldexp(w.mean, e * (k + 1));
+    out[2 * k + 1] = w.n > 1.0 ? ldexp(sqrt(w.m2 / (w.n - 1.0) / w.n), e * (k + 1)) : 0.0;
+  }
+  if (t == 0) out[2 * KMAX] = scale[1];
 }
 
 static int red_blocks(int64_t n) {
@@ -177,7 +191,7 @@ static int frame_potential_on(const double* d_trace, int64_t n, int kmax, double
   hipLaunchKernelGGL(red_max_kernel, dim3(nb), dim3(RED_THREADS), 0, s, d_trace, n, part);
   hipLaunchKernelGGL(red_max_final, dim3(1), dim3(RED_THREADS), 0, s, part, nb, scale);
   hipLaunchKernelGGL(red_moments_kernel, dim3(nb), dim3(RED_THREADS), 0, s, d_trace, n, kmax, scale, wpart);
-  hipLaunchKernelGGL(red_moments_final, dim3(1), dim3(64), 0, s, wpart, nb, kmax, scale, out);
+  hipLaunchKernelGGL(red_moments_final, dim3(1), dim3(FINAL_THREADS), 0, s, wpart, nb, kmax, scale, out);
   int rc = check_launch("frame_potential");
   double host[2 * KMAX + 1];
   if (!rc) rc = check_hip(hipMemcpyAsync(host, out, sizeof(host), hipMemcpyDeviceToHost, s), "copy F");

@@ -8,8 +8,11 @@ true traffic is 256 MiB read and 256 MiB written, so
 
     bytes(kernel) = counter(kernel) [KiB] * 1024 * 256 MiB / (counter(copy) [KiB] * 1024).
 
-The summary lists per-kernel average durations and calibrated HBM bytes per
-dispatch, and ends with one ``traffic-json:`` line that ``bench.py`` reads.
+The summary lists per-kernel average durations, calibrated HBM bytes per
+dispatch and the HBM rate they give, and ends with one ``traffic-json:``
+line that ``bench.py`` reads.  Directories of further counter runs
+(``--counters``, e.g. SQ instruction and cycle counters) add a table of
+per-dispatch averages and, with SQ_WAVES among them, counts per wavefront.
 That line carries a hash of the kernel sources: once any source changes the
 counters no longer describe the kernels and ``bench.py`` reports no traffic.
 
@@ -74,20 +77,61 @@ def summarize(trace, fetch, write):
     return {"fetch_scale": f_scale, "write_scale": w_scale, "kernels": kernels}
 
 
-def render(s, workload, command, trace_cmd):
+def counter_table(dirs, kernels, min_percent=1.0):
+    """Per-dispatch averages of every counter in the runs `dirs`, for the
+    kernels of the trace with at least min_percent of the time."""
+    keep = {k["kernel"] for k in kernels if k["percent"] >= min_percent}
+    vals = collections.defaultdict(dict)
+    names = []
+    for d in dirs:
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        acc = collections.defaultdict(list)
+        for r in rows:
+            acc[(_short(r["Kernel_Name"]), r["Counter_Name"])].append(float(r["Counter_Value"]))
+        for (k, c), v in acc.items():
+            if k in keep:
+                vals[k][c] = sum(v) / len(v)
+                if c not in names:
+                    names.append(c)
+    return names, vals
+
+
+def render(s, workload, command, trace_cmd, counters=None, counter_cmds=()):
     lines = [f"# rocprofv3 summary: {workload}", "",
              "Commands (repository root, one MI355X):", "",
              f"    {trace_cmd}",
              f"    {command.replace('PMC', 'FETCH_SIZE')}",
-             f"    {command.replace('PMC', 'WRITE_SIZE')}", "",
-             "Counter calibration by the 256 MiB copy of the same run: FETCH_SIZE x "
-             f"{s['fetch_scale']:.3f}, WRITE_SIZE x {s['write_scale']:.3f}.", "",
-             "| kernel | calls | avg us | % time | HBM read MB/dispatch | HBM write MB/dispatch |",
-             "|---|---|---|---|---|---|"]
+             f"    {command.replace('PMC', 'WRITE_SIZE')}"]
+    lines += [f"    {c}" for c in counter_cmds]
+    lines += ["",
+              "Counter calibration by the 256 MiB copy of the same run: FETCH_SIZE x "
+              f"{s['fetch_scale']:.3f}, WRITE_SIZE x {s['write_scale']:.3f}.  HBM GB/s = calibrated "
+              "(read + write) bytes per dispatch / average duration (MI355X peak 8000 GB/s).", "",
+              "| kernel | calls | avg us | % time | HBM read MB/dispatch | HBM write MB/dispatch | HBM GB/s |",
+              "|---|---|---|---|---|---|---|"]
     for k in s["kernels"]:
         fr = "-" if k["fetch_bytes"] is None else f"{k['fetch_bytes'] / 1e6:.2f}"
         wr = "-" if k["write_bytes"] is None else f"{k['write_bytes'] / 1e6:.2f}"
-        lines.append(f"| {k['kernel']} | {k['calls']} | {k['avg_us']:.1f} | {k['percent']:.2f} | {fr} | {wr} |")
+        gbs = "-"
+        if k["fetch_bytes"] is not None and k["write_bytes"] is not None and k["avg_us"] > 0:
+            gbs = f"{(k['fetch_bytes'] + k['write_bytes']) / (k['avg_us'] * 1e3):.0f}"
+        lines.append(f"| {k['kernel']} | {k['calls']} | {k['avg_us']:.1f} | {k['percent']:.2f} | {fr} | {wr} "
+                     f"| {gbs} |")
+    if counters:
+        names, vals = counters
+        lines += ["", "Counters, average per dispatch (kernels with at least 1 % of the time):", "",
+                  "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+        for k, v in vals.items():
+            lines.append(f"| {k} | " + " | ".join(f"{v[c]:.4g}" if c in v else "-" for c in names) + " |")
+        if "SQ_WAVES" in names:
+            per = [c for c in names if c.startswith("SQ_INSTS_")]
+            lines += ["", "Instructions per wavefront (SQ_INSTS_* / SQ_WAVES):", "",
+                      "| kernel | " + " | ".join(per) + " |", "|---|" + "---|" * len(per)]
+            for k, v in vals.items():
+                w = v.get("SQ_WAVES")
+                if w:
+                    lines.append(f"| {k} | " + " | ".join(f"{v[c] / w:.4g}" if c in v else "-" for c in per)
+                                 + " |")
     lines += ["", "traffic-json: " + json.dumps({
         "workload": workload, "sources": sources_hash(),
         "bytes_per_dispatch": {k["kernel"]: (k["fetch_bytes"] or 0.0) + (k["write_bytes"] or 0.0)
@@ -117,8 +161,12 @@ def main():
     ap.add_argument("--command", required=True, help="counter command with PMC in place of the counter name")
     ap.add_argument("--trace-command", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--counters", nargs="*", default=[], help="directories of further counter runs")
+    ap.add_argument("--counter-command", action="append", default=[], help="the command of each such run")
     a = ap.parse_args()
-    text = render(summarize(a.trace, a.fetch, a.write), a.workload, a.command, a.trace_command)
+    s = summarize(a.trace, a.fetch, a.write)
+    ctr = counter_table(a.counters, s["kernels"]) if a.counters else None
+    text = render(s, a.workload, a.command, a.trace_command, ctr, a.counter_command)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
