@@ -1,12 +1,14 @@
-"""Runs sample + contract + reduce on one fixed-topology ensemble, for
-profiling single workloads (brickwork, HEA, Pauli-rotation HEA, qudit
-brickwork) under rocprofv3.
+"""Runs sample + contract + reduce on one ensemble (brickwork, local random,
+HEA, Pauli-rotation HEA, qudit brickwork), for profiling single workloads
+under rocprofv3 and for timing batches one after another.
 
     python -m paper_2205_09900_amd.run_ensemble --ansatz brickwork --n 20 --depth 2 \\
         --pairs 100000 --steps 5 [--precision c64] [--local-dim 3] [--with-copy]
 
-Every step samples the pairs' gates, contracts every pair and reduces F^(k),
-k = 1..3, on one stream; the first step is a warm-up.  --with-copy also runs
+Every step samples the pairs' gates (step i takes global pairs
+[i P, (i+1) P)), contracts every pair and reduces F^(k), k = 1..3, on one
+stream; --warmup steps (default 1) run untimed first, and every timed step
+prints one progress line on stderr.  --with-copy also runs
 one 256 MiB device copy, whose counter values calibrate FETCH_SIZE and
 WRITE_SIZE (see profile_summary).  Prints one JSON line: pairs/s over the
 timed steps, F^(k) and the sweep classes' event time and flops per step.
@@ -14,6 +16,7 @@ timed steps, F^(k) and the sweep classes' event time and flops per step.
 
 import argparse
 import json
+import sys
 import time
 
 ANSATZ = {"brickwork": 0, "local_random": 1, "hea": 2, "pauli_cnot": 3, "pauli_cz": 4, "qudit": 5}
@@ -28,6 +31,7 @@ def main():
     ap.add_argument("--local-dim", type=int, default=0, help="q of a qudit brickwork")
     ap.add_argument("--pairs", type=int, default=100000)
     ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="c64", choices=sorted(PRECISION))
     ap.add_argument("--seed", type=int, default=12345)
     ap.add_argument("--with-copy", action="store_true")
@@ -54,13 +58,16 @@ def main():
         fp.fp_contract_trace_batch(ens, args.pairs, prec, gates, trace, ws)
         return fp.fp_frame_potential(trace, args.pairs, 3)
 
-    step(0)
+    for i in range(args.warmup):
+        step(i)
     torch.cuda.synchronize()
     fp.fp_profile_begin()
     t0 = time.perf_counter()
     f = None
-    for i in range(1, args.steps + 1):
+    for i in range(args.warmup, args.warmup + args.steps):
         f = step(i)
+        print(f"[run_ensemble] step {i - args.warmup + 1}/{args.steps} done at "
+              f"{time.perf_counter() - t0:.2f} s, F = {f[0]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = fp.fp_profile_end()
