@@ -392,6 +392,42 @@ def hea_mixed(fp, torch, pairs, steps=3):
                       for i, e in enumerate(ens)}
     progress(f"HEA n=30 L=1..8 mixed: default {out['default_mixed_launch_pairs_per_s']:.4g}, tuned "
              f"{out['tuned_mixed_launch_pairs_per_s']:.4g}, per-L calls {out['per_L_calls_pairs_per_s']:.4g} pairs/s")
+    out["many_small_groups"] = hea_many_groups(fp, torch, steps)
+    return out
+
+
+def hea_many_groups(fp, torch, steps=3, n_groups=64, pairs=2000):
+    """Uneven batches of many small groups: HEA n = 30, 64 groups of 2000
+    pairs with L = 1..8 in turn (the tuning table of hea_mixed applies), in
+    one fp_contract_trace_groups call against one fp_contract_trace_batch call
+    per group on the same gates.  Contraction only."""
+    import synth
+    ens = [fp.Ensemble(fp.HEA, 30, 1 + g % 8) for g in range(n_groups)]
+    bufs = [fp.sample(e, pairs, synth.workload_seed(30, g), 0, fp.C64) for g, e in enumerate(ens)]
+    groups = [(g, fp.C64, 0, pairs) for g in range(n_groups)]
+    tr = torch.empty(2 * pairs * n_groups, dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(256, fp.fp_workspace_bytes_groups(ens, groups)), dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return pairs * n_groups * steps / (time.perf_counter() - t0)
+
+    def mixed():
+        fp.fp_contract_trace_groups(ens, groups, bufs, tr, ws)
+
+    def per_group():
+        for g, e in enumerate(ens):
+            fp.fp_contract_trace_batch(e, pairs, fp.C64, bufs[g], tr[2 * g * pairs: 2 * (g + 1) * pairs])
+
+    out = {"groups": n_groups, "pairs_per_group": pairs, "mixed_launch_pairs_per_s": timed(mixed),
+           "per_group_calls_pairs_per_s": timed(per_group)}
+    progress(f"HEA n=30, {n_groups} groups of {pairs} pairs: one mixed call {out['mixed_launch_pairs_per_s']:.4g}, "
+             f"per-group calls {out['per_group_calls_pairs_per_s']:.4g} pairs/s")
     return out
 
 

@@ -338,16 +338,22 @@ int fp_contract_trace_groups(const fp_ensemble_t* ens, int n_ens, const fp_group
  * synthetic gates drawn by fp_sample_gates, keep the fastest in the
  * library's tuning table, and write its index to *out_choice:
  *   choice = 3 * lane_class + task_size,
- *   lane_class 0: 64 lanes per pair, 4 pairs per workgroup (registers up to
- *                 2^10 entries, 2^9 in FP_C128); 1: one workgroup per pair;
+ *   lane_class 0 "tiny":  16 lanes per pair, 16 pairs per workgroup;
+ *              1 "small": 64 lanes per pair, 4 pairs per workgroup;
+ *              2 "mid":   256 lanes, one pair per workgroup;
+ *              3 "large": 1024 lanes (512 in FP_C128), one pair per workgroup;
+ *              a class is a candidate only while its workgroup holds its
+ *              pairs' registers in LDS;
  *   task_size 0, 1, 2: about 5e6, 2e7, 8e7 algorithmic flops per task taken
  *                 from the launch's counter.
  * fp_contract_trace_groups uses the table's entry of every group's ensemble
- * and precision (else class 0 where the register fits and 2e7 flops per
- * task).  Synchronous.  Uses d_ws (ws_bytes) as scratch, which must hold
+ * and precision, else the class the per-ensemble launch takes for the
+ * register width (tiny up to 2^6 entries, small up to 2^10 (2^9 in
+ * FP_C128), mid up to 2^12, large beyond) and 2e7 flops per task; it makes
+ * one persistent launch per lane class and register-size bucket.  Synchronous.  Uses d_ws (ws_bytes) as scratch, which must hold
  * fp_autotune_workspace_bytes bytes (0 for an ensemble it cannot tune).
  * fp_autotune_table writes the table as text, one line per tuned key,
- *   "<arch> <ansatz> <n> <depth> <precision> small|large <task flops> <ms>",
+ *   "<arch> <ansatz> <n> <depth> <precision> tiny|small|mid|large <task flops> <ms>",
  * into buf (capacity cap, NUL-terminated); fp_autotune_load reads such text.
  * Errors: FP_EINVAL, FP_ETOOBIG (workspace), FP_ENOTIMPL (local random,
  * qudit brickworks, or a boundary beyond LDS), FP_EDEVICE.

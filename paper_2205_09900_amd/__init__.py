@@ -427,7 +427,7 @@ def fp_autotune(ens, precision, d_ws=None, stream=None):
 
 
 # fp_autotune's choices: 3 * lane class + task size
-AUTOTUNE_CLASSES = ("small", "large")
+AUTOTUNE_CLASSES = ("tiny", "small", "mid", "large")
 AUTOTUNE_TASK_FLOPS = (5e6, 2e7, 8e7)
 
 

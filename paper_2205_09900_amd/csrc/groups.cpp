@@ -1,5 +1,7 @@
 // fp_contract_trace_groups: uneven batches (different depths and qubit
-// counts) in one persistent launch per LDS class, tasks ordered by cost.
+// counts) in one persistent launch per lane class and register-size bucket
+// (so that a workgroup's LDS slot is sized for the registers it runs, not for
+// the widest group of the call), tasks ordered by cost.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -34,6 +36,16 @@ struct GroupPlan {
 
 constexpr double DEFAULT_TASK_FLOPS = 2e7;
 
+// Register-size buckets of the persistent launches: bucket k holds groups of
+// 2k - 1 or 2k register bits (bits 0 .. 2 in bucket 1).
+constexpr int NBUCKET = 9;
+constexpr int NLISTS = 3 * PCLASS_COUNT * 2 * NBUCKET;  // precision x lane class x group kind x bucket
+constexpr size_t COUNTER_BYTES = 4 * 4 * NLISTS;  // one 16-byte counter per list
+inline int size_bucket(int bits) {
+  const int k = (bits + 1) / 2;
+  return k < 1 ? 1 : (k >= NBUCKET ? NBUCKET - 1 : k);
+}
+
 // Pairs per task: about task_flops of work per task, between 1 and 256 pairs.
 int pairs_per_task(double cost, double task_flops) {
   double c = task_flops / (cost > 1.0 ? cost : 1.0);
@@ -43,17 +55,18 @@ int pairs_per_task(double cost, double task_flops) {
 }
 
 // Lane class and task size of a persistent group: `force` if given, else the
-// tuning table's entry, else 64 lanes for registers up to 2^small_bits
-// entries and a whole workgroup beyond, with DEFAULT_TASK_FLOPS per task.
+// tuning table's entry, else the class the per-ensemble launches take for the
+// register width (pclass_default), with DEFAULT_TASK_FLOPS per task.  A class
+// whose workgroup cannot hold its pairs' registers falls back to the default.
 void choose_launch(const fp_ensemble_t* e, int prec, int bits, const GroupLaunch* force, GroupPlan* gp) {
-  const int small_bits = prec == FP_C128 ? 9 : 10;  // 64 lanes x 4 pairs per workgroup
-  GroupLaunch c{bits <= small_bits ? PCLASS_SMALL : PCLASS_LARGE, DEFAULT_TASK_FLOPS};
+  const bool hea = e->ansatz == FP_HEA_RYRZ_CZ;
+  GroupLaunch c{pclass_default(bits, prec), DEFAULT_TASK_FLOPS};
   GroupLaunch t;
   if (force)
     c = *force;
   else if (tune_group_lookup(e, prec, &t))
     c = t;
-  if (c.cls == PCLASS_SMALL && bits > small_bits) c.cls = PCLASS_LARGE;  // the register must fit 4 per workgroup
+  if (c.cls < 0 || c.cls >= PCLASS_COUNT || !pclass_fits(c.cls, bits, hea, prec)) c.cls = pclass_default(bits, prec);
   gp->cls = c.cls;
   gp->task_flops = c.task_flops > 0.0 ? c.task_flops : DEFAULT_TASK_FLOPS;
 }
@@ -100,6 +113,12 @@ int plan_group(const fp_ensemble_t* e, const fp_group_t* g, bool upload_plan, co
     gp->sep_ws = (b + 255) & ~(size_t)255;
   } else {
     gp->per_task = pairs_per_task(gp->pair_cost, gp->task_flops);
+    // and small enough that every lane group of the class on every compute
+    // unit gets tasks several times over (cheap pairs otherwise leave a few
+    // groups working through long tasks alone)
+    const int64_t target = (int64_t)device_cus() * pclass_pairs(gp->cls) * 16;
+    const int64_t cap = (g->num_pairs + target - 1) / target;
+    if (gp->per_task > cap) gp->per_task = (int)(cap > 1 ? cap : 1);
     gp->ntasks = (g->num_pairs + gp->per_task - 1) / gp->per_task;
   }
   return FP_OK;
@@ -133,7 +152,7 @@ int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_grou
   int rc = check_groups(ens, n_ens, groups, n_groups);
   if (rc) return rc;
   if (!out_bytes) return set_error(FP_EINVAL, "out_bytes is NULL");
-  size_t total = 256 + (size_t)n_groups * sizeof(GroupDesc);
+  size_t total = ((COUNTER_BYTES + 255) & ~(size_t)255) + (size_t)n_groups * sizeof(GroupDesc);
   total = (total + 255) & ~(size_t)255;
   int64_t ntasks = 0;  // at most one task per pair, whatever the launch choice
   for (int g = 0; g < n_groups; ++g) {
@@ -145,7 +164,7 @@ int fp_workspace_bytes_groups(const fp_ensemble_t* ens, int n_ens, const fp_grou
     else
       ntasks += groups[g].num_pairs;
   }
-  total += (size_t)ntasks * sizeof(Task) + 6 * 256;
+  total += (size_t)ntasks * sizeof(Task) + NLISTS * 256;
   *out_bytes = total;
   return FP_OK;
 }
@@ -174,9 +193,9 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
 
   std::vector<GroupPlan> gps(n_groups);
   std::vector<GroupDesc> descs(n_groups);
-  // tasks per (precision index, class): precision index 0 = c128, 1 = c64, 2 = bf16x3
-  std::vector<Task> tasks[3][2];
-  int slot_bytes[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  // tasks per (precision index, class, size bucket): precision index 0 = c128, 1 = c64, 2 = bf16x3
+  std::vector<Task> tasks[3][PCLASS_COUNT][2][NBUCKET];  // [.][.][GROUP_PROGRAM or GROUP_HEA][.]
+  int slot_bytes[3][PCLASS_COUNT][2][NBUCKET] = {};
   int64_t offset = 0;
   for (int g = 0; g < n_groups; ++g) {
     const fp_ensemble_t* e = &ens[groups[g].ensemble_index];
@@ -207,47 +226,55 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
     }
     if (gp.route == ROUTE_PERSISTENT && gr.num_pairs > 0) {
       const int pi = gr.precision == FP_C128 ? 0 : gr.precision == FP_C64 ? 1 : 2;
-      const int rb = gr.precision == FP_C128 ? 8 : 4;
-      const int nt = gp.cls == PCLASS_SMALL ? 64 : (gr.precision == FP_C128 ? 512 : 1024);
-      const size_t sb = e->ansatz == FP_HEA_RYRZ_CZ ? ((hea_smem_bytes(gp.bits, nt, rb) + 15) & ~(size_t)15)
-                                                      : program_slot_bytes(d.m, nt, rb);
-      if ((int)sb > slot_bytes[pi][gp.cls]) slot_bytes[pi][gp.cls] = (int)sb;
+      const size_t sb = e->ansatz == FP_HEA_RYRZ_CZ ? pclass_slot_bytes(gp.cls, gp.bits, true, gr.precision)
+                                                      : pclass_slot_bytes(gp.cls, d.m, false, gr.precision);
+      const int bk = size_bucket(gp.bits);
+      const int kd = d.kind;
+      if ((int)sb > slot_bytes[pi][gp.cls][kd][bk]) slot_bytes[pi][gp.cls][kd][bk] = (int)sb;
       for (int64_t p = 0; p < gr.num_pairs; p += gp.per_task) {
         Task t;
         t.group = g;
         t.first = p;
         t.count = (int32_t)std::min<int64_t>(gp.per_task, gr.num_pairs - p);
-        tasks[pi][gp.cls].push_back(t);
+        tasks[pi][gp.cls][kd][bk].push_back(t);
       }
     }
     offset += gr.num_pairs;
   }
   // largest first
   for (int pi = 0; pi < 3; ++pi)
-    for (int c = 0; c < 2; ++c)
-      std::stable_sort(tasks[pi][c].begin(), tasks[pi][c].end(), [&](const Task& a, const Task& b) {
-        return gps[a.group].pair_cost * a.count > gps[b.group].pair_cost * b.count;
-      });
+    for (int c = 0; c < PCLASS_COUNT; ++c)
+      for (int kd = 0; kd < 2; ++kd)
+        for (int bk = 0; bk < NBUCKET; ++bk)
+          std::stable_sort(tasks[pi][c][kd][bk].begin(), tasks[pi][c][kd][bk].end(),
+                           [&](const Task& a, const Task& b) {
+                             return gps[a.group].pair_cost * a.count > gps[b.group].pair_cost * b.count;
+                           });
   // workspace: counters | descriptors | task lists | separate-route slices
   unsigned char* w = (unsigned char*)d_ws;
   unsigned int* counters = (unsigned int*)w;
-  GroupDesc* d_desc = (GroupDesc*)(w + 256);
-  size_t off = (256 + (size_t)n_groups * sizeof(GroupDesc) + 255) & ~(size_t)255;
-  Task* d_tasks[3][2];
+  const size_t desc_off = (COUNTER_BYTES + 255) & ~(size_t)255;
+  GroupDesc* d_desc = (GroupDesc*)(w + desc_off);
+  size_t off = (desc_off + (size_t)n_groups * sizeof(GroupDesc) + 255) & ~(size_t)255;
+  Task* d_tasks[3][PCLASS_COUNT][2][NBUCKET];
   for (int pi = 0; pi < 3; ++pi)
-    for (int c = 0; c < 2; ++c) {
-      d_tasks[pi][c] = (Task*)(w + off);
-      off += ((tasks[pi][c].size() * sizeof(Task)) + 255) & ~(size_t)255;
-    }
-  rc = check_hip(hipMemsetAsync(counters, 0, 256, s), "memset counters");
+    for (int c = 0; c < PCLASS_COUNT; ++c)
+      for (int kd = 0; kd < 2; ++kd)
+        for (int bk = 0; bk < NBUCKET; ++bk) {
+          d_tasks[pi][c][kd][bk] = (Task*)(w + off);
+          off += ((tasks[pi][c][kd][bk].size() * sizeof(Task)) + 255) & ~(size_t)255;
+        }
+  rc = check_hip(hipMemsetAsync(counters, 0, COUNTER_BYTES, s), "memset counters");
   if (!rc) rc = check_hip(hipMemcpyAsync(d_desc, descs.data(), sizeof(GroupDesc) * n_groups, hipMemcpyHostToDevice, s),
                           "upload groups");
   for (int pi = 0; pi < 3 && !rc; ++pi)
-    for (int c = 0; c < 2 && !rc; ++c)
-      if (!tasks[pi][c].empty())
-        rc = check_hip(hipMemcpyAsync(d_tasks[pi][c], tasks[pi][c].data(), sizeof(Task) * tasks[pi][c].size(),
-                                      hipMemcpyHostToDevice, s),
-                       "upload tasks");
+    for (int c = 0; c < PCLASS_COUNT && !rc; ++c)
+      for (int kd = 0; kd < 2 && !rc; ++kd)
+        for (int bk = 0; bk < NBUCKET && !rc; ++bk)
+          if (!tasks[pi][c][kd][bk].empty())
+            rc = check_hip(hipMemcpyAsync(d_tasks[pi][c][kd][bk], tasks[pi][c][kd][bk].data(),
+                                          sizeof(Task) * tasks[pi][c][kd][bk].size(), hipMemcpyHostToDevice, s),
+                           "upload tasks");
   // the host vectors are released when this call returns
   if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(upload)");
   if (rc) return rc;
@@ -255,38 +282,32 @@ int contract_groups(const fp_ensemble_t* ens, int n_ens, const fp_group_t* group
   rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
   if (!rc) rc = check_hip(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
   if (rc) return rc;
-  Aux aux;
-  rc = get_aux(&aux, s);
-  if (rc) return rc;
-  rc = check_hip(hipEventRecord(aux.fork, s), "fork");
-  if (rc) return rc;
-  // persistent launches: class SMALL on s, LARGE on aux stream 0 (both precisions)
-  int used = 0;
-  for (int c = 0; c < 2; ++c) {
-    hipStream_t sx = c == 0 ? s : aux.s[0];
-    if (c == 1) {
-      rc = check_hip(hipStreamWaitEvent(sx, aux.fork, 0), "fork wait");
-      if (rc) return rc;
-    }
+  // persistent launches, one after another on s, widest registers first
+  // (launches of different slot sizes side by side were slower: a workgroup
+  // of the widest bucket needs a whole compute unit's LDS)
+  for (int c = PCLASS_COUNT - 1; c >= 0; --c) {
+    const int kc = c == PCLASS_TINY    ? KCLASS_LDS16
+                   : c == PCLASS_SMALL ? KCLASS_LDS64
+                   : c == PCLASS_MID   ? KCLASS_LDS256
+                                       : KCLASS_LDS1024;
     for (int pi = 0; pi < 3; ++pi) {
-      if (tasks[pi][c].empty()) continue;
-      const int prec = pi == 0 ? FP_C128 : pi == 1 ? FP_C64 : FP_BF16X3;
-      profile_launch_begin(c == 0 ? KCLASS_LDS64 : KCLASS_LDS1024, sx);
-      rc = launch_persistent(prec, c, d_desc, d_tasks[pi][c], (int)tasks[pi][c].size(), counters + 4 * (2 * pi + c),
-                             d_trace, slot_bytes[pi][c], num_cus, sx);
-      double fl = 0.0;
-      for (const Task& t : tasks[pi][c]) fl += gps[t.group].pair_cost * t.count;
-      profile_launch_end(c == 0 ? KCLASS_LDS64 : KCLASS_LDS1024, fl, sx);
-      if (rc) return rc;
-    }
-    if (c == 1) {
-      rc = check_hip(hipEventRecord(aux.join[0], sx), "join");
-      if (rc) return rc;
-      used = 1;
+      for (int kd = 0; kd < 2; ++kd) {
+        for (int bk = NBUCKET - 1; bk >= 0; --bk) {
+          const std::vector<Task>& tl = tasks[pi][c][kd][bk];
+          if (tl.empty()) continue;
+          const int prec = pi == 0 ? FP_C128 : pi == 1 ? FP_C64 : FP_BF16X3;
+          const int list = ((pi * PCLASS_COUNT + c) * 2 + kd) * NBUCKET + bk;
+          profile_launch_begin(kc, s);
+          rc = launch_persistent(prec, kd, c, d_desc, d_tasks[pi][c][kd][bk], (int)tl.size(), counters + 4 * list,
+                                 d_trace, slot_bytes[pi][c][kd][bk], num_cus, s);
+          double fl = 0.0;
+          for (const Task& t : tl) fl += gps[t.group].pair_cost * t.count;
+          profile_launch_end(kc, fl, s);
+          if (rc) return rc;
+        }
+      }
     }
   }
-  if (used) rc = check_hip(hipStreamWaitEvent(s, aux.join[0], 0), "join wait");
-  if (rc) return rc;
   // groups that need per-pair plans or HBM boundaries: after the persistent launches, on s
   // (their own launches fork from s and join back into s)
   for (int g = 0; g < n_groups && !rc; ++g) {

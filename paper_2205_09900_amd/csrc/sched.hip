@@ -16,7 +16,9 @@
 
 namespace fp {
 
-template <typename Real, int NT, int PB, bool BF3>
+// KIND (GROUP_HEA or GROUP_PROGRAM) is the kind of every group of the launch,
+// so each instance holds one contraction path.
+template <typename Real, int NT, int PB, bool BF3, int KIND>
 __global__ void __launch_bounds__(NT* PB) persistent_kernel(const GroupDesc* __restrict__ groups,
                                                             const Task* __restrict__ tasks, int ntasks,
                                                             unsigned int* counter, double* trace, int slot_bytes) {
@@ -46,7 +48,7 @@ __global__ void __launch_bounds__(NT* PB) persistent_kernel(const GroupDesc* __r
       const int64_t pair = tk.first + i;
       const unsigned char* pg = g.gates + (g.gate_first + pair) * g.stride;
       double* out = trace + 2 * (g.trace_offset + pair);
-      if (g.kind == GROUP_HEA) {
+      if constexpr (KIND == GROUP_HEA) {
         const Real* angU = reinterpret_cast<const Real*>(pg);
         const Real* angV = angU + (int64_t)g.depth * g.n * 2;
         hea_pair<Real, NT, BF3>(angU, angV, g.n, g.depth, g.m, my, lane, red, redd, out);
@@ -81,47 +83,97 @@ size_t program_slot_bytes(int bits, int nt, int real_bytes) {
   return ((cb << bits) + (size_t)k * (16 * cb + sizeof(Op)) + 15) & ~(size_t)15;
 }
 
-template <typename Real, int NT, int PB, bool BF3>
+template <typename Real, int NT, int PB, bool BF3, int KIND>
 static int launch_t(const GroupDesc* groups, const Task* tasks, int ntasks, unsigned int* counter, double* trace,
                     int slot_bytes, int num_cus, hipStream_t s) {
   const size_t smem = (size_t)PB * slot_bytes;
   if (smem > 160 * 1024) return set_error(FP_ETOOBIG, "persistent sweep needs %zu bytes of LDS", smem);
   if (smem > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(persistent_kernel<Real, NT, PB, BF3>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(persistent_kernel<Real, NT, PB, BF3, KIND>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) (void)hipGetLastError();
   }
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Real, NT, PB, BF3>, NT * PB, smem);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<Real, NT, PB, BF3, KIND>, NT * PB, smem);
   if (e != hipSuccess || per_cu < 1) {
     (void)hipGetLastError();
     per_cu = 1;
   }
-  int64_t blocks = (int64_t)per_cu * num_cus;
+  // four times the resident count the runtime reports (workgroups beyond the
+  // resident ones start as others finish and leave once the counter has run
+  // out), so that an underestimate does not leave compute units idle
+  int64_t blocks = 4 * (int64_t)per_cu * num_cus;
   const int64_t need = ((int64_t)ntasks + PB - 1) / PB;
   if (blocks > need) blocks = need;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((persistent_kernel<Real, NT, PB, BF3>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, groups, tasks,
+  hipLaunchKernelGGL((persistent_kernel<Real, NT, PB, BF3, KIND>), dim3((unsigned)blocks), dim3(NT * PB), smem, s, groups, tasks,
                      ntasks, counter, trace, slot_bytes);
   return check_launch("persistent_sweep");
 }
 
-int launch_persistent(int precision, int cls, const GroupDesc* groups, const Task* tasks, int ntasks,
+int pclass_lanes(int cls, int precision) {
+  switch (cls) {
+    case PCLASS_TINY: return 16;
+    case PCLASS_SMALL: return 64;
+    case PCLASS_MID: return 256;
+    default: return precision == FP_C128 ? 512 : 1024;
+  }
+}
+
+int pclass_pairs(int cls) { return cls == PCLASS_TINY ? 16 : cls == PCLASS_SMALL ? 4 : 1; }
+
+size_t pclass_slot_bytes(int cls, int bits, bool hea, int precision) {
+  const int nt = pclass_lanes(cls, precision);
+  const size_t rb = precision == FP_C128 ? 8 : 4;
+  return hea ? ((hea_smem_bytes(bits, nt, rb) + 15) & ~(size_t)15) : program_slot_bytes(bits, nt, (int)rb);
+}
+
+bool pclass_fits(int cls, int bits, bool hea, int precision) {
+  return (size_t)pclass_pairs(cls) * pclass_slot_bytes(cls, bits, hea, precision) <= 160 * 1024;
+}
+
+int pclass_default(int bits, int precision) {
+  const int small_bits = precision == FP_C128 ? 9 : 10;
+  if (bits <= 6) return PCLASS_TINY;
+  if (bits <= small_bits) return PCLASS_SMALL;
+  if (bits <= 12) return PCLASS_MID;
+  return PCLASS_LARGE;
+}
+
+template <typename Real, bool BF3, int KIND>
+static int launch_cls(int cls, const GroupDesc* groups, const Task* tasks, int ntasks, unsigned int* counter,
+                      double* trace, int slot_bytes, int num_cus, hipStream_t s) {
+  switch (cls) {
+    case PCLASS_TINY:
+      return launch_t<Real, 16, 16, BF3, KIND>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+    case PCLASS_SMALL:
+      return launch_t<Real, 64, 4, BF3, KIND>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+    case PCLASS_MID:
+      return launch_t<Real, 256, 1, BF3, KIND>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+    default:
+      if constexpr (sizeof(Real) == 8)
+        return launch_t<Real, 512, 1, BF3, KIND>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+      else
+        return launch_t<Real, 1024, 1, BF3, KIND>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+  }
+}
+
+template <typename Real, bool BF3>
+static int launch_kind(int kind, int cls, const GroupDesc* groups, const Task* tasks, int ntasks,
+                       unsigned int* counter, double* trace, int slot_bytes, int num_cus, hipStream_t s) {
+  if (kind == GROUP_HEA)
+    return launch_cls<Real, BF3, GROUP_HEA>(cls, groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+  return launch_cls<Real, BF3, GROUP_PROGRAM>(cls, groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+}
+
+int launch_persistent(int precision, int kind, int cls, const GroupDesc* groups, const Task* tasks, int ntasks,
                       unsigned int* counter, double* trace, int slot_bytes, int num_cus, hipStream_t s) {
   if (ntasks <= 0) return FP_OK;
-  if (precision == FP_C128) {
-    if (cls == PCLASS_SMALL)
-      return launch_t<double, 64, 4, false>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
-    return launch_t<double, 512, 1, false>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
-  }
-  if (precision == FP_BF16X3) {
-    if (cls == PCLASS_SMALL)
-      return launch_t<float, 64, 4, true>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
-    return launch_t<float, 1024, 1, true>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
-  }
-  if (cls == PCLASS_SMALL)
-    return launch_t<float, 64, 4, false>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
-  return launch_t<float, 1024, 1, false>(groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+  if (precision == FP_C128)
+    return launch_kind<double, false>(kind, cls, groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+  if (precision == FP_BF16X3)
+    return launch_kind<float, true>(kind, cls, groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
+  return launch_kind<float, false>(kind, cls, groups, tasks, ntasks, counter, trace, slot_bytes, num_cus, s);
 }
 
 }  // namespace fp

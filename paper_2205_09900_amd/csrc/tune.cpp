@@ -1,10 +1,10 @@
 // Autotuner of the persistent sweep over groups (fp_contract_trace_groups).
 //
 // For one ensemble and precision it times the candidate launch choices of a
-// group on the device -- the lane class (64 lanes with four pairs per
-// workgroup, or a whole workgroup per pair; the first only while the
-// register fits four times in LDS) and the work per task the persistent
-// workgroups take from their counter -- on synthetic pairs drawn by
+// group on the device -- the lane class (16 lanes with 16 pairs per
+// workgroup, 64 lanes with four, 256 lanes, or 1024 (512 in complex128); a
+// class only while its workgroup holds its pairs' registers in LDS) and the
+// work per task the persistent workgroups take from their counter -- on synthetic pairs drawn by
 // fp_sample_gates, and keeps the fastest in a table keyed by the device
 // architecture, the ensemble and the precision.  fp_contract_trace_groups
 // reads the table for every group it launches.  The table can be written
@@ -42,7 +42,7 @@ std::map<Key, Entry> g_table;
 
 // Candidates: choice = 3 * class + task size index.
 constexpr double TASK_FLOPS[3] = {5e6, 2e7, 8e7};
-constexpr int NUM_CHOICES = 6;
+constexpr int NUM_CHOICES = 3 * PCLASS_COUNT;
 
 GroupLaunch choice_launch(int c) { return GroupLaunch{c / 3, TASK_FLOPS[c % 3]}; }
 
@@ -87,7 +87,8 @@ int64_t tune_pairs(double cost) {
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-const char* class_name(int c) { return c == PCLASS_SMALL ? "small" : "large"; }
+const char* const CLASS_NAMES[PCLASS_COUNT] = {"tiny", "small", "mid", "large"};
+const char* class_name(int c) { return c >= 0 && c < PCLASS_COUNT ? CLASS_NAMES[c] : "large"; }
 
 }  // namespace
 
@@ -150,7 +151,7 @@ int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_b
   if (rc) return rc;
   const fp_group_t grp{0, precision, 0, np};
   const void* gptr[1] = {gates};
-  const int small_bits = precision == FP_C128 ? 9 : 10;
+  const bool hea = ens->ansatz == FP_HEA_RYRZ_CZ;
   hipEvent_t a, b;
   if ((rc = check_hip(hipEventCreate(&a), "event"))) return rc;
   if ((rc = check_hip(hipEventCreate(&b), "event"))) {
@@ -161,7 +162,7 @@ int fp_autotune(const fp_ensemble_t* ens, int precision, void* d_ws, size_t ws_b
   double best_ms = 1e300;
   for (int c = 0; c < NUM_CHOICES && !rc; ++c) {
     const GroupLaunch gl = choice_launch(c);
-    if (gl.cls == PCLASS_SMALL && bits > small_bits) continue;  // four registers must fit one workgroup's LDS
+    if (!pclass_fits(gl.cls, bits, hea, precision)) continue;  // the workgroup must hold its pairs' registers
     // warm-up, then the median of three timed runs
     rc = contract_groups(ens, 1, &grp, 1, gptr, trace, gws, gws_bytes, s, &gl);
     std::vector<double> ms;
@@ -226,8 +227,8 @@ int fp_autotune_load(const char* text) {
     if (sscanf(line.c_str(), "%63s %d %d %d %d %15s %lf %lf", arch, &an, &n, &d, &pr, cname, &tf, &ms) != 8)
       return set_error(FP_EINVAL, "bad tuning line: %s", line.c_str());
     int c = -1;
-    if (strcmp(cname, "small") == 0) c = PCLASS_SMALL;
-    if (strcmp(cname, "large") == 0) c = PCLASS_LARGE;
+    for (int k = 0; k < PCLASS_COUNT; ++k)
+      if (strcmp(cname, CLASS_NAMES[k]) == 0) c = k;
     if (c < 0) return set_error(FP_EINVAL, "unknown lane class %s", cname);
     if (!(tf >= 1.0 && tf <= 1e12)) return set_error(FP_EINVAL, "task flops %g outside 1 .. 1e12", tf);
     add[Key(arch, an, n, d, pr)] = Entry{GroupLaunch{c, tf}, ms};

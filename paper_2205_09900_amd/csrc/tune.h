@@ -7,8 +7,7 @@
 namespace fp {
 
 // Launch choice of one group of the persistent sweep: its lane class
-// (PCLASS_SMALL: 64 lanes, 4 pairs per workgroup; PCLASS_LARGE: a whole
-// workgroup per pair) and the algorithmic flops of work per task.
+// (PCLASS_* of sched.h) and the algorithmic flops of work per task.
 struct GroupLaunch {
   int cls;
   double task_flops;
