@@ -70,6 +70,7 @@ def parse():
                     help="comma list of n: layers to an epsilon = 0.1 design of brickworks per n and their slope "
                          "in n (not run by default)")
     ap.add_argument("--layer-scaling-pairs", type=int, default=20000)
+    ap.add_argument("--layer-scaling-ansatz", default="brickwork", choices=["brickwork", "pauli_cnot"])
     ap.add_argument("--with-copy", action="store_true",
                     help="also run one 256 MiB device copy (counter calibration for PMC runs)")
     return ap.parse_args()
@@ -193,18 +194,23 @@ def layer_scaling(fp, torch, traces_by_depth, n, k_max=3, resamples=300, epsilon
     return out
 
 
-def layer_scaling_vs_n(fp, torch, np, synth, ns, pairs, depths=range(2, 11)):
-    """Layers to an epsilon = 0.1 approximate k-design of brickworks (the
-    paper's parallel random unitaries) for every n of `ns` (complex64, `pairs`
-    pairs per depth, the same bootstrap and fit as layer_scaling), and the
-    least-squares slope of those layers in n per k.  The paper reports a
-    slope of 4.38 for k = 2 from its own runs (context, not a target)."""
+def layer_scaling_vs_n(fp, torch, np, synth, ns, pairs, ansatz=None, depths=None):
+    """Layers to an epsilon = 0.1 approximate k-design for every n of `ns`
+    (complex64, `pairs` pairs per depth, the same bootstrap and fit as
+    layer_scaling), and the least-squares slope of those layers in n per k.
+    Brickworks (the paper's parallel random unitaries, depths 2..10; the paper
+    reports a slope of 4.38 for k = 2 from its own runs, context, not a
+    target) or the paper's hardware-efficient ansatz with CNOT walls (layers
+    2..7, the register of 2L - 1 bits in LDS)."""
+    ansatz = fp.BRICKWORK if ansatz is None else ansatz
+    if depths is None:
+        depths = range(2, 11) if ansatz == fp.BRICKWORK else range(2, 8)
     per_n = {}
     for n in ns:
         traces = {}
         for d in depths:
-            _, tr = fixed_topology(fp, torch, fp.BRICKWORK, n, d, pairs, fp.C64, synth.workload_seed(20 + n, d), steps=1,
-                                   chunk=min(pairs, 20000))
+            _, tr = fixed_topology(fp, torch, ansatz, n, d, pairs, fp.C64, synth.workload_seed(20 + 40 * ansatz + n, d),
+                                   steps=1, chunk=min(pairs, 20000))
             traces[d] = tr
         per_n[str(n)] = layer_scaling(fp, torch, traces, n)["layers_to_epsilon"]
         progress(f"layer scaling n={n}: { {k: round(v['median'], 2) for k, v in per_n[str(n)].items()} }")
@@ -215,8 +221,8 @@ def layer_scaling_vs_n(fp, torch, np, synth, ns, pairs, depths=range(2, 11)):
             x, y = np.array(pts, dtype=np.float64).T
             slope, icept = np.polyfit(x, y, 1)
             slopes[k] = {"slope": float(slope), "intercept": float(icept), "points": len(pts)}
-    return {"pairs_per_depth": pairs, "depths": list(depths), "layers_to_epsilon": per_n, "slope_in_n": slopes,
-            "paper_slope_k2": 4.38}
+    return {"ansatz": ansatz, "pairs_per_depth": pairs, "depths": list(depths), "layers_to_epsilon": per_n,
+            "slope_in_n": slopes, "paper_slope_k2": 4.38 if ansatz == fp.BRICKWORK else None}
 
 
 def fixed_topology(fp, torch, ansatz, n, depth, pairs, prec, seed, steps=3, chunk=None, local_dim=0):
@@ -649,7 +655,8 @@ def main():
     scaling_res = None
     if args.layer_scaling_n:
         scaling_res = layer_scaling_vs_n(fp, torch, np, synth, [int(x) for x in args.layer_scaling_n.split(",") if x],
-                                         args.layer_scaling_pairs)
+                                         args.layer_scaling_pairs,
+                                         fp.BRICKWORK if args.layer_scaling_ansatz == "brickwork" else fp.PAULI_CNOT)
         progress(f"layer scaling slopes in n: {scaling_res['slope_in_n']}")
 
     cv_res = None
