@@ -115,6 +115,12 @@ __device__ __forceinline__ T hsum(T v, T* red) {
   return v;
 }
 
+// Position of register entry x in LDS: its low four bits XORed with the next
+// four.  The transform's first pass gives each lane 16 consecutive entries;
+// unswizzled, the lanes of a wavefront would read them 128 bytes apart, all
+// in the same banks.  Only bits 0..3 change, so the position stays below 2^m.
+__device__ __forceinline__ int hsw(int x) { return x ^ ((x >> 4) & 15); }
+
 __device__ __forceinline__ int ins_bits(int g, int s0, int r) {
   return ((g >> s0) << (s0 + r)) | (g & ((1 << s0) - 1));
 }
@@ -127,7 +133,7 @@ __device__ __forceinline__ void wht_pass(HC<Real>* B, int m, int s0, int lane, i
     const int base = ins_bits(g, s0, R);
     HC<Real> v[1 << R];
 #pragma unroll
-    for (int k = 0; k < (1 << R); ++k) v[k] = B[base + (k << s0)];
+    for (int k = 0; k < (1 << R); ++k) v[k] = B[hsw(base + (k << s0))];
     if (scale_e != 0) {
 #pragma unroll
       for (int k = 0; k < (1 << R); ++k) {
@@ -148,7 +154,7 @@ __device__ __forceinline__ void wht_pass(HC<Real>* B, int m, int s0, int lane, i
       }
     }
 #pragma unroll
-    for (int k = 0; k < (1 << R); ++k) B[base + (k << s0)] = v[k];
+    for (int k = 0; k < (1 << R); ++k) B[hsw(base + (k << s0))] = v[k];
   }
 }
 
@@ -262,7 +268,7 @@ __device__ void hea_pair(const Real* angU, const Real* angV, int n, int L, int m
         if (q == 0) {
           v = f;
         } else {
-          const HC<Real> b = B[x];
+          const HC<Real> b = B[hsw(x)];
           v.x = 0;
           v.y = 0;
           cmac<Real, true>(b.x, b.y, f.x, f.y, v.x, v.y);
@@ -273,12 +279,12 @@ __device__ void hea_pair(const Real* angU, const Real* angV, int n, int L, int m
         if (q == 0) {
           v = f;
         } else {
-          const HC<Real> b = B[x];
+          const HC<Real> b = B[hsw(x)];
           v.x = b.x * f.x - b.y * f.y;
           v.y = b.x * f.y + b.y * f.x;
         }
       }
-      B[x] = v;
+      B[hsw(x)] = v;
       mx = fmax(mx, fmax(fabs(v.x), fabs(v.y)));
     }
     mx = hmax<Real, NT>(mx, red);
@@ -294,8 +300,8 @@ __device__ void hea_pair(const Real* angU, const Real* angV, int n, int L, int m
   // Tr = 2^expo * sum_x B(x) 2^-pending
   double sr = 0.0, si = 0.0;
   for (int x = lane; x < (1 << m); x += NT) {
-    sr += ldexp((double)B[x].x, -pending);
-    si += ldexp((double)B[x].y, -pending);
+    sr += ldexp((double)B[hsw(x)].x, -pending);
+    si += ldexp((double)B[hsw(x)].y, -pending);
   }
   sr = hsum<double, NT>(sr, redd);
   si = hsum<double, NT>(si, redd);
