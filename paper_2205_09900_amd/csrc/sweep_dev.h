@@ -271,6 +271,113 @@ __device__ __forceinline__ void gate_groups_u(Cplx<Real>* B, const Real (&Rr)[16
   }
 }
 
+// Two GATEs on four distinct register bits, consecutive in a program, act
+// as one 16x16 complex block: the Kronecker product of their realigned
+// matrices (they commute).  In the BF16x3 arithmetic the block is applied by
+// bf16 matrix cores (v_mfma_f32_32x32x16_bf16): the block and the register
+// entries are split into bf16 hi + lo parts and hi*hi + hi*lo + lo*hi
+// accumulate in float32, the same three products per real product as the
+// vector path.  The complex product is the real product of the 32x32 block
+// [[Fr, -Fi], [Fi, Fr]] with the stacked real and imaginary parts of X, where
+// X[r][c] is the register entry whose gate bits (pa, qa, pb, qb) spell bits
+// 0..3 of r and whose other bits spell c; a wavefront takes 32 columns c at
+// a time, reads all of them before writing any, and no two wavefronts share
+// a column.  Fragment layouts (one wavefront, lane l, h = l / 32, n = l % 32):
+// A[m][k] with m = n, k = 8h + j; B[k][c] with k = 8h + j, c = n; the
+// accumulator element i holds D[8 (i / 4) + 4h + i % 4][n].
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void bf16_split(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;  // round to nearest even
+  lo = (__bf16)(x - (float)hi);
+}
+
+__device__ __forceinline__ int gate_bits_offset(int r, int pa, int qa, int pb, int qb) {
+  return ((r & 1) << pa) + (((r >> 1) & 1) << qa) + (((r >> 2) & 1) << pb) + (((r >> 3) & 1) << qb);
+}
+
+// Registers of 2^b entries, b >= 9 (at least one block of 32 columns); every
+// lane of the group calls it (lane in [0, NT)); scale: the column's pending
+// power of two, taken out of the block (exact).
+template <int NT, bool TRACK, bool SCALE>
+__device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>* Ma, const Cplx<float>* Mb, int pa,
+                                               int qa, int pb, int qb, int b, int lane, int scale, float& lmax) {
+  constexpr int NW = NT / 64;
+  const int wave = lane >> 6, h = (lane >> 5) & 1, n = lane & 31;
+  bf16x8_t a0h, a0l, a1h, a1l;  // k-step 0 multiplies Re X, k-step 1 Im X
+  {
+    const int ro = n & 15;
+    const Cplx<float>* ra = Ma + (ro & 3) * 4;
+    const Cplx<float>* rb = Mb + (ro >> 2) * 4;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * h + j;
+      const Cplx<float> x = ra[k & 3], y = rb[k >> 2];
+      float fr = fmaf(x.x, y.x, -x.y * y.y);
+      float fi = fmaf(x.x, y.y, x.y * y.x);
+      if (SCALE) {
+        fr = ldexpf(fr, -scale);
+        fi = ldexpf(fi, -scale);
+      }
+      const float v0 = n < 16 ? fr : fi;
+      const float v1 = n < 16 ? -fi : fr;
+      __bf16 hh, ll;
+      bf16_split(v0, hh, ll);
+      a0h[j] = hh;
+      a0l[j] = ll;
+      bf16_split(v1, hh, ll);
+      a1h[j] = hh;
+      a1l[j] = ll;
+    }
+  }
+  int off_in[8], off_out[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    off_in[j] = gate_bits_offset(8 * h + j, pa, qa, pb, qb);
+    off_out[j] = gate_bits_offset(8 * (j >> 2) + 4 * h + (j & 3), pa, qa, pb, qb);
+  }
+  // the four gate bits in increasing order
+  int s0 = pa < qa ? pa : qa, s1 = pa < qa ? qa : pa, s2 = pb < qb ? pb : qb, s3 = pb < qb ? qb : pb;
+  if (s2 < s0) { const int t = s0; s0 = s2; s2 = t; }
+  if (s3 < s1) { const int t = s1; s1 = s3; s3 = t; }
+  if (s2 < s1) { const int t = s1; s1 = s2; s2 = t; }
+  const int ntile = 1 << (b - 9);
+  for (int t = wave; t < ntile; t += NW) {
+    const int c = t * 32 + n;
+    const int base = insert_zero(insert_zero(insert_zero(insert_zero(c, s0), s1), s2), s3);
+    Cplx<float> x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = B[base + off_in[j]];
+    bf16x8_t xrh, xrl, xih, xil;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      __bf16 hh, ll;
+      bf16_split(x[j].x, hh, ll);
+      xrh[j] = hh;
+      xrl[j] = ll;
+      bf16_split(x[j].y, hh, ll);
+      xih[j] = hh;
+      xil[j] = ll;
+    }
+    f32x16_t acc = {};
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, xrh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, xrl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, xih, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, xil, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, xrh, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, xih, acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      Cplx<float> y;
+      y.x = acc[j];
+      y.y = acc[j + 8];
+      if (TRACK) lmax = fmax(lmax, fmax(fabs(y.x), fabs(y.y)));
+      B[base + off_out[j]] = y;
+    }
+  }
+}
+
 // Groups per round of gate_groups: one (measured: batching several raised the
 // register count and lost more to occupancy than the overlapped loads gained).
 template <typename Real>
@@ -366,7 +473,35 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
       }
       const int type = op.type & OP_TYPE_MASK;
       const bool track = (op.type & OP_FLAG_TRACK) != 0;
-      if (type == OP_GATE) {
+      bool fused = false;
+      if constexpr (BF3 && NT >= 64) {
+        // this GATE and the next on four distinct bits: one matrix-core block
+        if (type == OP_GATE && !track && b >= 9 && i + 1 < nk) {
+          const unsigned w1 = (unsigned)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(&ops_s[i + 1]));
+          const int p2 = (int)((w1 >> 8) & 0xff), q2 = (int)((w1 >> 16) & 0xff);
+          if ((int)(w1 & OP_TYPE_MASK) == OP_GATE && p2 != op.p && p2 != op.q && q2 != op.p && q2 != op.q) {
+            const bool track2 = (w1 & OP_FLAG_TRACK) != 0;
+            const int sc = __builtin_amdgcn_readfirstlane(pend);
+            const Cplx<float>* ma = reinterpret_cast<const Cplx<float>*>(mats_s + 16 * i);
+            Cplx<float>* Bf = reinterpret_cast<Cplx<float>*>(B);
+            float lm = (float)lmax;
+            if (track2) {
+              if (sc) gate_pair_mfma<NT, true, true>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, sc, lm);
+              else gate_pair_mfma<NT, true, false>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, 0, lm);
+            } else {
+              if (sc) gate_pair_mfma<NT, false, true>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, sc, lm);
+              else gate_pair_mfma<NT, false, false>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, 0, lm);
+            }
+            lmax = (Real)lm;
+            expo += pend;
+            pend = 0;
+            fused = true;
+          }
+        }
+      }
+      if (fused) {
+        ++i;  // the next GATE is applied too
+      } else if (type == OP_GATE) {
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;

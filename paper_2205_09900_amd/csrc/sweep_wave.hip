@@ -8,9 +8,12 @@
 //     at a time into lanes and taken with readlane, so decoding and branching
 //     are scalar;
 //   * the realigned matrices of the GATE ops come precomputed in program
-//     order, prefetched four GATEs ahead by lanes 0..31 and passed through a
-//     32-entry LDS stage that holds the real parts before the imaginary ones,
-//     so 16-byte LDS reads land in the registers the products use;
+//     order, prefetched four GATEs ahead by lanes 0..31 and passed through
+//     two 32-entry LDS stages that hold the real parts before the imaginary
+//     ones, so 16-byte LDS reads land in the registers the products use; the
+//     next GATE's matrix is staged during the current one, so a GATE costs
+//     one LDS fence, and a column's rescale is applied to the staged matrix;
+//   * a column's largest magnitude is reduced across lanes with DPP moves;
 //   * registers of up to 64 entries give each lane one output entry of the
 //     gate (one matrix row, four inputs); larger ones give each lane whole
 //     groups of four entries;
@@ -36,14 +39,40 @@ __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename Real>
-__device__ __forceinline__ Real wave_max(Real v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
+// Lane movement within rows of 16 lanes by DPP (no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long x = __builtin_bit_cast(long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-constexpr int PREFETCH = 4;  // GATE matrices in flight per wavefront
+// Largest value over the wavefront (every lane active): swaps within quads,
+// rotations by 4 and 8 within rows of 16, then the four rows' results.
+template <typename Real>
+__device__ __forceinline__ Real wave_max(Real v) {
+  v = fmax(v, dpp_move<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+  v = fmax(v, dpp_move<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+  v = fmax(v, dpp_move<0x124>(v));  // row_ror 4
+  v = fmax(v, dpp_move<0x128>(v));  // row_ror 8
+  return fmax(fmax(lane_value(v, 0), lane_value(v, 16)), fmax(lane_value(v, 32), lane_value(v, 48)));
+}
+
+constexpr int TOUCH = 4;  // GATEs between a matrix's cache touch and its load
 
 // Registers of up to 64 entries: lane = 4 g + jp computes output jp of group
 // g (g < 2^(b-2)), i.e. row jp of the matrix (stage: real parts at 0..15,
@@ -133,9 +162,10 @@ __device__ __forceinline__ void trace_wave(Cplx<Real>* B, int b, int p, int q, i
 
 }  // namespace
 
+// register of 2^CAP entries, then two 32-real matrix stages
 template <typename Real, int CAP>
 constexpr size_t wave_slot_bytes() {
-  return ((size_t)sizeof(Cplx<Real>) << CAP) + 32 * sizeof(Real);
+  return ((size_t)sizeof(Cplx<Real>) << CAP) + 64 * sizeof(Real);
 }
 
 // One pair (index pidx) on one wavefront, its register in LDS slot `wave`.
@@ -158,29 +188,50 @@ __device__ __forceinline__ void wave_pair(const SweepArgs& a, int64_t pidx, int 
   const int ngate = __builtin_amdgcn_readfirstlane(hdr->num_gate_ops);
   const int log2f = __builtin_amdgcn_readfirstlane(hdr->log2_factor);
   Cplx<Real>* B = reinterpret_cast<Cplx<Real>*>(smem_raw + wave_slot_bytes<Real, CAP>() * wave);
+  // two stages: the next GATE's matrix is staged while the current one is
+  // applied, so the fence that ends an op also publishes the next matrix
   Real* stage = reinterpret_cast<Real*>(B + (1 << CAP));
   const uint2* ops = reinterpret_cast<const uint2*>(a.ops + pidx * a.ops_stride);
   const Real* mats = reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride);
   // lane l < 32 carries real l of a matrix (interleaved re, im) and stages it
   // de-interleaved
-  Real* my_stage = stage + (lane & 1) * 16 + ((lane & 31) >> 1);
+  const int my_off = (lane & 1) * 16 + ((lane & 31) >> 1);
+  const int ml = lane & 31;  // lanes 32..63 load a copy and never stage it
 
-  Real pre[PREFETCH];
-#pragma unroll
-  for (int i = 0; i < PREFETCH; ++i) pre[i] = (lane < 32 && i < ngate) ? mats[i * 32 + lane] : (Real)0;
-  int jg = PREFETCH;  // next matrix to fetch
+  // Matrices reach the stage through one register, `nxt`, reloaded at the
+  // end of every op: lanes 0..31 load the matrix the next GATE stages,
+  // lanes 32..63 touch the one TOUCH GATEs later so that the reload finds
+  // it in cache.  Loaded on every op, `nxt` is never copied (a copy of a
+  // loaded value waits for the load).  Indices are clamped to
+  // [0, ngate - 1]; matrix 0 lies inside the pair's region even when the
+  // program has no GATE.
+  const int last = ngate > 0 ? ngate - 1 : 0;
+  auto mat_index = [&](int m) -> int64_t {
+    const int t = lane < 32 ? m : m + TOUCH;
+    return (int64_t)(t < last ? t : last) * 32 + ml;
+  };
+  Real nxt = mats[mat_index(0)];
   uint2 cur = lane < num_ops ? ops[lane] : make_uint2(0u, 0u);
   uint2 ahead = 64 + lane < num_ops ? ops[64 + lane] : make_uint2(0u, 0u);
 
   int b = 0;
   int64_t expo = 0;  // true boundary = stored boundary * 2^expo
-  int pend = 0;      // exponent to remove at the next GATE (uniform)
+  // exponent taken out of the staged matrix, added to expo when that matrix
+  // is applied (uniform)
+  int pend = 0;
+  int sb = 0;  // stage holding the next GATE's matrix
   bool prev_track = false;
   Real lmax = 0;
   if (lane == 0) {
     B[0].x = (Real)1;
     B[0].y = (Real)0;
   }
+  // the set-up loads land before the op loop, which otherwise waits for
+  // every outstanding load (the ring's too) at each op
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  if (lane < 32) stage[my_off] = nxt;
+  int jst = 1;  // matrix the next GATE stages
+  nxt = mats[mat_index(jst)];
   wave_fence();
   for (int t0 = 0; t0 < num_ops; t0 += 64) {
     const int lim = num_ops - t0 < 64 ? num_ops - t0 : 64;
@@ -190,23 +241,20 @@ __device__ __forceinline__ void wave_pair(const SweepArgs& a, int64_t pidx, int 
       const bool track = (w0 & OP_FLAG_TRACK) != 0;
       const int p = (int)((w0 >> 8) & 0xff), q = (int)((w0 >> 16) & 0xff);
       if (type == OP_GATE) {
-        // the column's pending power of two is taken out of the matrix here
-        // (exact; ldexp by 0 is the identity)
-        if (lane < 32) *my_stage = ldexp(pre[0], -pend);
-#pragma unroll
-        for (int i = 0; i + 1 < PREFETCH; ++i) pre[i] = pre[i + 1];
-        pre[PREFETCH - 1] = (lane < 32 && jg < ngate) ? mats[(int64_t)jg * 32 + lane] : (Real)0;
-        ++jg;
-        wave_fence();
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
+        const Real* st = stage + 32 * sb;
         if (b <= 6) {
-          if (track) gate_small<Real, BF3, true>(B, stage, b, lo, hi, ip, iq, p, q, lane, lmax);
-          else gate_small<Real, BF3, false>(B, stage, b, lo, hi, ip, iq, p, q, lane, lmax);
+          if (track) gate_small<Real, BF3, true>(B, st, b, lo, hi, ip, iq, p, q, lane, lmax);
+          else gate_small<Real, BF3, false>(B, st, b, lo, hi, ip, iq, p, q, lane, lmax);
         } else {
-          if (track) gate_big<Real, BF3, true>(B, stage, b, lo, hi, ip, iq, lane, lmax);
-          else gate_big<Real, BF3, false>(B, stage, b, lo, hi, ip, iq, lane, lmax);
+          if (track) gate_big<Real, BF3, true>(B, st, b, lo, hi, ip, iq, lane, lmax);
+          else gate_big<Real, BF3, false>(B, st, b, lo, hi, ip, iq, lane, lmax);
         }
+        // the other stage was last read by the previous GATE, before its fence
+        sb ^= 1;
+        if (lane < 32) stage[32 * sb + my_off] = nxt;
+        ++jst;
         expo += pend;
         pend = 0;
       } else if (type == OP_BELL) {
@@ -229,19 +277,30 @@ __device__ __forceinline__ void wave_pair(const SweepArgs& a, int64_t pidx, int 
         if (prev_track) {
           const Real m = wave_max<Real>(lmax);
           lmax = 0;
-          pend = 0;
+          int e = 0;
           if (m > (Real)0 && isfinite(m)) {
-            int e;
             frexp(m, &e);
-            pend = __builtin_amdgcn_readfirstlane(e);
+            e = __builtin_amdgcn_readfirstlane(e);
           }
+          // the next GATE's staged matrix takes out 2^e instead of 2^pend
+          // (exact: powers of two)
+          if (e != pend && lane < 32) {
+            Real* x = stage + 32 * sb + my_off;
+            *x = ldexp(*x, pend - e);
+          }
+          pend = e;
         }
       }
       prev_track = track;
       wave_fence();
+      nxt = mats[mat_index(jst)];
     }
     cur = ahead;
-    ahead = t0 + 128 + lane < num_ops ? ops[t0 + 128 + lane] : make_uint2(0u, 0u);
+    __builtin_amdgcn_sched_barrier(0);
+    // unconditional, clamped to the last op (records past it are never
+    // decoded), and after the copy above, so the load writes `ahead` itself
+    const int na = t0 + 128 + lane;
+    ahead = ops[na < num_ops ? na : num_ops - 1];
   }
   const Cplx<Real> v = B[0];
   if (lane == 0) {

@@ -80,3 +80,33 @@ def test_bf16x3_shared_wide_ops_vs_dense(fp):
     want = dense.traces(sampler.sample_pairs(1, 8, 40, seed, 0, n, fp32=True))
     r = rel_errors(got, want)
     assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (float(np.median(r)), float(r.max()))
+
+
+@pytest.mark.parametrize("depth", [6, 7, 8])
+def test_bf16x3_brickwork_n20_matrix_cores_vs_mpo(fp, depth):
+    """Brickwork n = 20 at registers of 2^10, 2^12 and 2^14 entries, where
+    consecutive GATEs on disjoint bits run as one 16x16 block on the bf16
+    matrix cores: sampled pairs of a 4000-pair batch against MPO-zip on the
+    same float32 gates, with the bounds of the vector BF16x3 path."""
+    import oracle_pool
+
+    ens, npairs = (0, 20, depth), 4000
+    assert fp.fp_plan_info(ens)["peak_bits"] == 2 * depth - 2
+    seed = synth.workload_seed(2, depth) + 5
+    g = fp.sample(ens, npairs, seed, 0, fp.C64)
+    got = fp.contract(ens, g, npairs, BF16X3).cpu().numpy()
+    c64 = fp.contract(ens, g, npairs, fp.C64).cpu().numpy()
+    assert np.isfinite(got).all()
+    pairs = sorted(int(x) for x in synth.rng(300 + depth).choice(npairs, 24, replace=False))
+    want = np.array(oracle_pool.traces(0, 20, depth, seed, pairs, fp32=True))
+    r = rel_errors(got[pairs], want)
+    print(f"brickwork n=20 D={depth} BF16x3: median {np.median(r):.3e}, max {r.max():.3e}")
+    assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (depth, float(np.median(r)), float(r.max()))
+    # the whole batch against complex64 on the same gates
+    rc = rel_errors(got, c64)
+    assert np.median(rc) <= 2e-4 and rc.max() <= 3e-2, (depth, float(np.median(rc)), float(rc.max()))
+    assert not np.array_equal(got, c64)
+    fg, _ = estimator.frame_potential(got, 3)
+    fw, _ = estimator.frame_potential(c64, 3)
+    for k in range(3):
+        assert abs(fg[k] - fw[k]) <= 2e-3 * fw[k], (k, fg[k], fw[k])
