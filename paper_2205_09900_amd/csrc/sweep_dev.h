@@ -34,6 +34,13 @@ __device__ __forceinline__ int64_t insert_zero(int64_t x, int pos) {
   return x + (int64_t)((uint64_t)x & (~0ull << pos));
 }
 
+// Place of register entry x in LDS: x XOR ((x >> 5) mod 32).  Entries whose
+// indices differ in bits 5..9 (the strides that the gate bits leave to
+// neighbouring lanes) fall in different LDS banks.  A bijection of [0, 2^b)
+// for every b, and linear over XOR: rsw(x ^ y) = rsw(x) ^ rsw(y), so the
+// partners x ^ 2^p of an entry cost one XOR with a uniform constant.
+__device__ __forceinline__ int rsw(int x) { return x ^ ((x >> 5) & 31); }
+
 // BF16x3 products: x = hi + lo with hi = bf16(x) (round to nearest even)
 // and lo = bf16(x - hi); a*b is taken as hi_a hi_b + hi_a lo_b + lo_a hi_b.
 // Products of bf16 values are exact in float32, so only the accumulation
@@ -189,18 +196,19 @@ template <typename Real, int U, bool BF3 = false>
 __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo,
                                             int hi, int ip, int iq, int ng, int first, int stride, bool track,
                                             Real& lmax) {
+  const int sp = rsw(ip), sq = rsw(iq), spq = sp ^ sq;
   for (int g0 = first; g0 < ng; g0 += stride * U) {
     Cplx<Real> v[U][4];
     int idx[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int g = g0 + u * stride;
-      idx[u] = insert_zero(insert_zero(g, lo), hi);
+      idx[u] = rsw(insert_zero(insert_zero(g, lo), hi));
       if (g < ng) {
         v[u][0] = B[idx[u]];
-        v[u][1] = B[idx[u] + ip];
-        v[u][2] = B[idx[u] + iq];
-        v[u][3] = B[idx[u] + ip + iq];
+        v[u][1] = B[idx[u] ^ sp];
+        v[u][2] = B[idx[u] ^ sq];
+        v[u][3] = B[idx[u] ^ spq];
       }
     }
 #pragma unroll
@@ -217,9 +225,9 @@ __device__ __forceinline__ void gate_groups(Cplx<Real>* B, const Real (&Rr)[16],
         if (track) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
       }
       B[idx[u]] = w[0];
-      B[idx[u] + ip] = w[1];
-      B[idx[u] + iq] = w[2];
-      B[idx[u] + ip + iq] = w[3];
+      B[idx[u] ^ sp] = w[1];
+      B[idx[u] ^ sq] = w[2];
+      B[idx[u] ^ spq] = w[3];
     }
   }
 }
@@ -232,18 +240,19 @@ template <typename Real, int U, bool BF3, bool TRACK, bool SCALE>
 __device__ __forceinline__ void gate_groups_u(Cplx<Real>* B, const Real (&Rr)[16], const Real (&Ri)[16], int lo,
                                               int hi, int ip, int iq, int ng, int first, int stride, int scale,
                                               Real& lmax) {
+  const int sp = rsw(ip), sq = rsw(iq), spq = sp ^ sq;
   for (int g0 = first; g0 < ng; g0 += stride * U) {
     Cplx<Real> v[U][4];
     int idx[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int g = g0 + u * stride;
-      idx[u] = insert_zero(insert_zero(g, lo), hi);
+      idx[u] = rsw(insert_zero(insert_zero(g, lo), hi));
       if (g < ng) {
         v[u][0] = B[idx[u]];
-        v[u][1] = B[idx[u] + ip];
-        v[u][2] = B[idx[u] + iq];
-        v[u][3] = B[idx[u] + ip + iq];
+        v[u][1] = B[idx[u] ^ sp];
+        v[u][2] = B[idx[u] ^ sq];
+        v[u][3] = B[idx[u] ^ spq];
       }
     }
 #pragma unroll
@@ -264,9 +273,9 @@ __device__ __forceinline__ void gate_groups_u(Cplx<Real>* B, const Real (&Rr)[16
         if (TRACK) lmax = fmax(lmax, fmax(fabs(sr), fabs(si)));
       }
       B[idx[u]] = w[0];
-      B[idx[u] + ip] = w[1];
-      B[idx[u] + iq] = w[2];
-      B[idx[u] + ip + iq] = w[3];
+      B[idx[u] ^ sp] = w[1];
+      B[idx[u] ^ sq] = w[2];
+      B[idx[u] ^ spq] = w[3];
     }
   }
 }
@@ -299,8 +308,9 @@ __device__ __forceinline__ int gate_bits_offset(int r, int pa, int qa, int pb, i
 
 // Registers of 2^b entries, b >= 9 (at least one block of 32 columns); every
 // lane of the group calls it (lane in [0, NT)); scale: the column's pending
-// power of two, taken out of the block (exact).
-template <int NT, bool TRACK, bool SCALE>
+// power of two, taken out of the block (exact).  SINGLE: one GATE (Ma on
+// bits pa, qa) as the block Ma x identity on two further bits pb, qb.
+template <int NT, bool TRACK, bool SCALE, bool SINGLE = false>
 __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>* Ma, const Cplx<float>* Mb, int pa,
                                                int qa, int pb, int qb, int b, int lane, int scale, float& lmax) {
   constexpr int NW = NT / 64;
@@ -309,13 +319,21 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
   {
     const int ro = n & 15;
     const Cplx<float>* ra = Ma + (ro & 3) * 4;
-    const Cplx<float>* rb = Mb + (ro >> 2) * 4;
+    const Cplx<float>* rb = SINGLE ? Ma : Mb + (ro >> 2) * 4;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int k = 8 * h + j;
-      const Cplx<float> x = ra[k & 3], y = rb[k >> 2];
-      float fr = fmaf(x.x, y.x, -x.y * y.y);
-      float fi = fmaf(x.x, y.y, x.y * y.x);
+      const Cplx<float> x = ra[k & 3];
+      float fr, fi;
+      if constexpr (SINGLE) {
+        const bool on = (ro >> 2) == (k >> 2);
+        fr = on ? x.x : 0.0f;
+        fi = on ? x.y : 0.0f;
+      } else {
+        const Cplx<float> y = rb[k >> 2];
+        fr = fmaf(x.x, y.x, -x.y * y.y);
+        fi = fmaf(x.x, y.y, x.y * y.x);
+      }
       if (SCALE) {
         fr = ldexpf(fr, -scale);
         fi = ldexpf(fi, -scale);
@@ -334,8 +352,8 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
   int off_in[8], off_out[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    off_in[j] = gate_bits_offset(8 * h + j, pa, qa, pb, qb);
-    off_out[j] = gate_bits_offset(8 * (j >> 2) + 4 * h + (j & 3), pa, qa, pb, qb);
+    off_in[j] = rsw(gate_bits_offset(8 * h + j, pa, qa, pb, qb));
+    off_out[j] = rsw(gate_bits_offset(8 * (j >> 2) + 4 * h + (j & 3), pa, qa, pb, qb));
   }
   // the four gate bits in increasing order
   int s0 = pa < qa ? pa : qa, s1 = pa < qa ? qa : pa, s2 = pb < qb ? pb : qb, s3 = pb < qb ? qb : pb;
@@ -345,10 +363,10 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
   const int ntile = 1 << (b - 9);
   for (int t = wave; t < ntile; t += NW) {
     const int c = t * 32 + n;
-    const int base = insert_zero(insert_zero(insert_zero(insert_zero(c, s0), s1), s2), s3);
+    const int base = rsw(insert_zero(insert_zero(insert_zero(insert_zero(c, s0), s1), s2), s3));
     Cplx<float> x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = B[base + off_in[j]];
+    for (int j = 0; j < 8; ++j) x[j] = B[base ^ off_in[j]];
     bf16x8_t xrh, xrl, xih, xil;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -373,7 +391,7 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
       y.x = acc[j];
       y.y = acc[j + 8];
       if (TRACK) lmax = fmax(lmax, fmax(fabs(y.x), fabs(y.y)));
-      B[base + off_out[j]] = y;
+      B[base ^ off_out[j]] = y;
     }
   }
 }
@@ -473,7 +491,7 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
       }
       const int type = op.type & OP_TYPE_MASK;
       const bool track = (op.type & OP_FLAG_TRACK) != 0;
-      bool fused = false;
+      bool fused = false, single = false;
       if constexpr (BF3 && NT >= 64) {
         // this GATE and the next on four distinct bits: one matrix-core block
         if (type == OP_GATE && !track && b >= 9 && i + 1 < nk) {
@@ -498,9 +516,34 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
             fused = true;
           }
         }
+        if (!fused && type == OP_GATE && b >= 9) {
+          // a GATE without a partner: its matrix times the identity on the two
+          // lowest other bits
+          const int pa = op.p, qa = op.q;
+          int pb = 0;
+          while (pb == pa || pb == qa) ++pb;
+          int qb = pb + 1;
+          while (qb == pa || qb == qa) ++qb;
+          const int sc = __builtin_amdgcn_readfirstlane(pend);
+          const Cplx<float>* ma = reinterpret_cast<const Cplx<float>*>(mats_s + 16 * i);
+          Cplx<float>* Bf = reinterpret_cast<Cplx<float>*>(B);
+          float lm = (float)lmax;
+          if (track) {
+            if (sc) gate_pair_mfma<NT, true, true, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, sc, lm);
+            else gate_pair_mfma<NT, true, false, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, 0, lm);
+          } else {
+            if (sc) gate_pair_mfma<NT, false, true, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, sc, lm);
+            else gate_pair_mfma<NT, false, false, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, 0, lm);
+          }
+          lmax = (Real)lm;
+          expo += pend;
+          pend = 0;
+          single = true;
+        }
       }
       if (fused) {
         ++i;  // the next GATE is applied too
+      } else if (single) {
       } else if (type == OP_GATE) {
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
@@ -536,34 +579,36 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
         pend = 0;
       } else if (type == OP_BELL) {
         const int s = 1 << b;
+        const int s1 = rsw(s), s2 = rsw(2 * s), s3 = s1 ^ s2;
         for (int k = lane; k < s; k += NT) {
-          const Cplx<Real> v = B[k];
+          const int ks = rsw(k);
+          const Cplx<Real> v = B[ks];
           Cplx<Real> z;
           z.x = (Real)0;
           z.y = (Real)0;
-          B[k + s] = z;
-          B[k + 2 * s] = z;
-          B[k + 3 * s] = v;
+          B[ks ^ s1] = z;
+          B[ks ^ s2] = z;
+          B[ks ^ s3] = v;
         }
         b += 2;
       } else if (type == OP_TRACE) {
         const int p = op.p, q = op.q;  // p < q
         const int nout = 1 << (b - 2);
-        const int step = (1 << p) + (1 << q);
+        const int step = rsw((1 << p) + (1 << q));
         for (int j0 = 0; j0 < nout; j0 += NT) {
           const int j = j0 + lane;
           Cplx<Real> acc;
           acc.x = (Real)0;
           acc.y = (Real)0;
           if (j < nout) {
-            const int i0 = insert_zero(insert_zero(j, p), q);
-            const Cplx<Real> a0 = B[i0], a1 = B[i0 + step];
+            const int i0 = rsw(insert_zero(insert_zero(j, p), q));
+            const Cplx<Real> a0 = B[i0], a1 = B[i0 ^ step];
             acc.x = a0.x + a1.x;
             acc.y = a0.y + a1.y;
             if (track) lmax = fmax(lmax, fmax(fabs(acc.x), fabs(acc.y)));
           }
           group_sync<NT>();
-          if (j < nout) B[j] = acc;
+          if (j < nout) B[rsw(j)] = acc;
           group_sync<NT>();
         }
         b -= 2;
