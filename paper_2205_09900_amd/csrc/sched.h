@@ -48,7 +48,7 @@ struct Task {
   int64_t first;   // first pair, relative to the group
 };
 
-size_t program_slot_bytes(int bits, int nt, int real_bytes);
+size_t program_slot_bytes(int bits, int nt, int real_bytes, bool bf3);
 // One persistent launch over tasks whose groups are all of `kind` (GROUP_*).
 int launch_persistent(int precision, int kind, int cls, const GroupDesc* groups, const Task* tasks, int ntasks,
                       unsigned int* counter, double* trace, int slot_bytes, int num_cus, hipStream_t s);

@@ -58,7 +58,9 @@ __global__ void __launch_bounds__(NT* PB) persistent_kernel(const GroupDesc* __r
         Cplx<Real>* mats = reinterpret_cast<Cplx<Real>*>(my + ((size_t)sizeof(Cplx<Real>) << g.m));
         Op* ops_s = reinterpret_cast<Op*>(mats + 16 * chunk_ops<NT>());
         double re, im;
-        run_program<Real, NT, BF3>(B, mats, ops_s, g.ops + pair * g.ops_stride, hdr->num_ops, g.wg + pair * g.wg_stride,
+        // 1024 lanes: the task loop's state leaves no registers for the
+        // matrix-core blocks
+        run_program<Real, NT, BF3, (NT < 1024)>(B, mats, ops_s, g.ops + pair * g.ops_stride, hdr->num_ops, g.wg + pair * g.wg_stride,
                               g.fac + pair * g.f_stride, reinterpret_cast<const Real*>(pg), g.G, hdr->log2_factor,
                               lane, red, &re, &im);
         if (lane == 0) {
@@ -77,10 +79,11 @@ __global__ void __launch_bounds__(NT* PB) persistent_kernel(const GroupDesc* __r
   }
 }
 
-size_t program_slot_bytes(int bits, int nt, int real_bytes) {
+size_t program_slot_bytes(int bits, int nt, int real_bytes, bool bf3) {
   const size_t cb = 2 * (size_t)real_bytes;
   const int k = nt <= 16 ? 16 : nt <= 64 ? 32 : 64;
-  return ((cb << bits) + (size_t)k * (16 * cb + sizeof(Op)) + 15) & ~(size_t)15;
+  const size_t blk = bf3 && nt >= 64 ? MFMA_BLOCK_BYTES : 0;  // as stage_bytes
+  return ((cb << bits) + (size_t)k * (16 * cb + sizeof(Op)) + blk + 15) & ~(size_t)15;
 }
 
 template <typename Real, int NT, int PB, bool BF3, int KIND>
@@ -125,7 +128,8 @@ int pclass_pairs(int cls) { return cls == PCLASS_TINY ? 16 : cls == PCLASS_SMALL
 size_t pclass_slot_bytes(int cls, int bits, bool hea, int precision) {
   const int nt = pclass_lanes(cls, precision);
   const size_t rb = precision == FP_C128 ? 8 : 4;
-  return hea ? ((hea_smem_bytes(bits, nt, rb) + 15) & ~(size_t)15) : program_slot_bytes(bits, nt, (int)rb);
+  return hea ? ((hea_smem_bytes(bits, nt, rb) + 15) & ~(size_t)15)
+             : program_slot_bytes(bits, nt, (int)rb, precision == FP_BF16X3);
 }
 
 bool pclass_fits(int cls, int bits, bool hea, int precision) {

@@ -39,7 +39,7 @@ __device__ __forceinline__ void lds_pair(const SweepArgs& a, int64_t pidx, int s
     return;
   }
   if (peak > a.cap_bits || peak <= a.min_bits) return;
-  const size_t per_pair = ((size_t)sizeof(Cplx<Real>) << a.cap_bits) + stage_bytes<Real, NT>();
+  const size_t per_pair = ((size_t)sizeof(Cplx<Real>) << a.cap_bits) + stage_bytes<Real, NT, BF3>();
   unsigned char* base = smem_raw + per_pair * slot;
   Cplx<Real>* B = reinterpret_cast<Cplx<Real>*>(base);
   Cplx<Real>* mats = reinterpret_cast<Cplx<Real>*>(base + ((size_t)sizeof(Cplx<Real>) << a.cap_bits));
@@ -757,7 +757,7 @@ size_t plan_lds_bytes(int G, int n) {
 
 template <typename Real, int NT, int PB, bool BF3>
 static int launch_lds_t(const SweepArgs& a, hipStream_t s) {
-  const size_t smem = (size_t)PB * ((((size_t)1 << a.cap_bits) * sizeof(Cplx<Real>)) + stage_bytes<Real, NT>());
+  const size_t smem = (size_t)PB * ((((size_t)1 << a.cap_bits) * sizeof(Cplx<Real>)) + stage_bytes<Real, NT, BF3>());
   int64_t blocks = (a.num_pairs + PB - 1) / PB;
   if (smem > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(sweep_lds_kernel<Real, NT, PB, BF3>),

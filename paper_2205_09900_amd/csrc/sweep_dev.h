@@ -281,25 +281,37 @@ __device__ __forceinline__ void gate_groups_u(Cplx<Real>* B, const Real (&Rr)[16
 }
 
 // Two GATEs on four distinct register bits, consecutive in a program, act
-// as one 16x16 complex block: the Kronecker product of their realigned
+// as one 16x16 complex block F: the Kronecker product of their realigned
 // matrices (they commute).  In the BF16x3 arithmetic the block is applied by
-// bf16 matrix cores (v_mfma_f32_32x32x16_bf16): the block and the register
-// entries are split into bf16 hi + lo parts and hi*hi + hi*lo + lo*hi
-// accumulate in float32, the same three products per real product as the
-// vector path.  The complex product is the real product of the 32x32 block
-// [[Fr, -Fi], [Fi, Fr]] with the stacked real and imaginary parts of X, where
-// X[r][c] is the register entry whose gate bits (pa, qa, pb, qb) spell bits
-// 0..3 of r and whose other bits spell c; a wavefront takes 32 columns c at
-// a time, reads all of them before writing any, and no two wavefronts share
-// a column.  Fragment layouts (one wavefront, lane l, h = l / 32, n = l % 32):
-// A[m][k] with m = n, k = 8h + j; B[k][c] with k = 8h + j, c = n; the
-// accumulator element i holds D[8 (i / 4) + 4h + i % 4][n].
+// bf16 matrix cores (v_mfma_f32_32x32x16_bf16): F and the register entries
+// are split into bf16 hi + lo parts and hi*hi + hi*lo + lo*hi accumulate in
+// float32, the same three products per real product as the vector path.  The
+// complex product is the real product of the 32x32 block [[Fr, -Fi], [Fi, Fr]]
+// with the stacked real and imaginary parts of X, where X[r][c] is the
+// register entry whose gate bits (pa, qa, pb, qb) spell bits 0..3 of r and
+// whose other bits spell c.  The group first writes F's four bf16 planes
+// (Re hi, Re lo, Im hi, Im lo; 16x16 each, MFMA_BLOCK_BYTES) to LDS; then a
+// wavefront takes 32 columns c at a time, reads all of them before writing
+// any, and no two wavefronts share a column.  Fragment layouts (one
+// wavefront, lane l, h = l / 32, n = l % 32): A[m][k] with m = n, k = 8h + j;
+// B[k][c] with k = 8h + j, c = n; the accumulator element i holds
+// D[8 (i / 4) + 4h + i % 4][n].
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void bf16_split(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;  // round to nearest even
-  lo = (__bf16)(x - (float)hi);
+constexpr size_t MFMA_BLOCK_BYTES = 4 * 256 * 2;
+
+// x0, x1 as packed bf16 pairs: hi = bf16(x) (round to nearest even) and
+// lo = bf16(x - hi); element 0 in the low half
+__device__ __forceinline__ void bf16_split2(float x0, float x1, unsigned& hi, unsigned& lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector((float __attribute__((ext_vector_type(2)))){x0, x1},
+                                                            bf16x2_t));
+  const float h0 = __uint_as_float(hi << 16), h1 = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned,
+                          __builtin_convertvector((float __attribute__((ext_vector_type(2)))){x0 - h0, x1 - h1},
+                                                  bf16x2_t));
 }
 
 __device__ __forceinline__ int gate_bits_offset(int r, int pa, int qa, int pb, int qb) {
@@ -307,54 +319,66 @@ __device__ __forceinline__ int gate_bits_offset(int r, int pa, int qa, int pb, i
 }
 
 // Registers of 2^b entries, b >= 9 (at least one block of 32 columns); every
-// lane of the group calls it (lane in [0, NT)); scale: the column's pending
-// power of two, taken out of the block (exact).  SINGLE: one GATE (Ma on
-// bits pa, qa) as the block Ma x identity on two further bits pb, qb.
+// lane of the group calls it (lane in [0, NT)); fblk: the group's
+// MFMA_BLOCK_BYTES of LDS; scale: the column's pending power of two, taken
+// out of the block (exact).  SINGLE: one GATE (Ma on bits pa, qa) as the
+// block Ma x identity on two further bits pb, qb.
 template <int NT, bool TRACK, bool SCALE, bool SINGLE = false>
-__device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>* Ma, const Cplx<float>* Mb, int pa,
-                                               int qa, int pb, int qb, int b, int lane, int scale, float& lmax) {
+__device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>* Ma, const Cplx<float>* Mb,
+                                               unsigned short* fblk, int pa, int qa, int pb, int qb, int b, int lane,
+                                               int scale, float& lmax) {
   constexpr int NW = NT / 64;
+  // F[r'][r] = Ma[r' % 4][r % 4] Mb[r' / 4][r / 4], planes at e = 16 r' + r
+  for (int e = lane; e < 256; e += NT) {
+    const int ro = e >> 4, k = e & 15;
+    const Cplx<float> x = Ma[(ro & 3) * 4 + (k & 3)];
+    float fr, fi;
+    if constexpr (SINGLE) {
+      const bool on = (ro >> 2) == (k >> 2);
+      fr = on ? x.x : 0.0f;
+      fi = on ? x.y : 0.0f;
+    } else {
+      const Cplx<float> y = Mb[(ro >> 2) * 4 + (k >> 2)];
+      fr = fmaf(x.x, y.x, -x.y * y.y);
+      fi = fmaf(x.x, y.y, x.y * y.x);
+    }
+    if (SCALE) {
+      fr = ldexpf(fr, -scale);
+      fi = ldexpf(fi, -scale);
+    }
+    unsigned hi, lo;
+    bf16_split2(fr, fi, hi, lo);
+    fblk[e] = (unsigned short)hi;
+    fblk[256 + e] = (unsigned short)lo;
+    fblk[512 + e] = (unsigned short)(hi >> 16);
+    fblk[768 + e] = (unsigned short)(lo >> 16);
+  }
+  group_sync<NT>();
   const int wave = lane >> 6, h = (lane >> 5) & 1, n = lane & 31;
   bf16x8_t a0h, a0l, a1h, a1l;  // k-step 0 multiplies Re X, k-step 1 Im X
   {
-    const int ro = n & 15;
-    const Cplx<float>* ra = Ma + (ro & 3) * 4;
-    const Cplx<float>* rb = SINGLE ? Ma : Mb + (ro >> 2) * 4;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = 8 * h + j;
-      const Cplx<float> x = ra[k & 3];
-      float fr, fi;
-      if constexpr (SINGLE) {
-        const bool on = (ro >> 2) == (k >> 2);
-        fr = on ? x.x : 0.0f;
-        fi = on ? x.y : 0.0f;
-      } else {
-        const Cplx<float> y = rb[k >> 2];
-        fr = fmaf(x.x, y.x, -x.y * y.y);
-        fi = fmaf(x.x, y.y, x.y * y.x);
-      }
-      if (SCALE) {
-        fr = ldexpf(fr, -scale);
-        fi = ldexpf(fi, -scale);
-      }
-      const float v0 = n < 16 ? fr : fi;
-      const float v1 = n < 16 ? -fi : fr;
-      __bf16 hh, ll;
-      bf16_split(v0, hh, ll);
-      a0h[j] = hh;
-      a0l[j] = ll;
-      bf16_split(v1, hh, ll);
-      a1h[j] = hh;
-      a1l[j] = ll;
-    }
+    // rows 0..15 of the 32x32 block: (Fr | -Fi), rows 16..31: (Fi | Fr)
+    const int row = (n & 15) * 16 + 8 * h;
+    const bool top = n < 16;
+    const unsigned neg = top ? 0x80008000u : 0u;
+    const u32x4_t* pl = reinterpret_cast<const u32x4_t*>(fblk);
+    const u32x4_t r0h = pl[((top ? 0 : 512) + row) >> 3], r0l = pl[((top ? 256 : 768) + row) >> 3];
+    const u32x4_t r1h = pl[((top ? 512 : 0) + row) >> 3], r1l = pl[((top ? 768 : 256) + row) >> 3];
+    a0h = __builtin_bit_cast(bf16x8_t, r0h);
+    a0l = __builtin_bit_cast(bf16x8_t, r0l);
+    a1h = __builtin_bit_cast(bf16x8_t, r1h ^ neg);
+    a1l = __builtin_bit_cast(bf16x8_t, r1l ^ neg);
   }
+  // entry offsets of the rows a lane reads (8h + j) and writes
+  // (8 (j / 4) + 4h + j % 4): uniform parts, and the lane's half h as one
+  // gate bit (qb for the reads, pb for the writes)
   int off_in[8], off_out[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    off_in[j] = rsw(gate_bits_offset(8 * h + j, pa, qa, pb, qb));
-    off_out[j] = rsw(gate_bits_offset(8 * (j >> 2) + 4 * h + (j & 3), pa, qa, pb, qb));
+    off_in[j] = rsw(gate_bits_offset(j, pa, qa, pb, qb));
+    off_out[j] = rsw(gate_bits_offset(8 * (j >> 2) + (j & 3), pa, qa, pb, qb));
   }
+  const int h_in = h ? rsw(1 << qb) : 0, h_out = h ? rsw(1 << pb) : 0;
   // the four gate bits in increasing order
   int s0 = pa < qa ? pa : qa, s1 = pa < qa ? qa : pa, s2 = pb < qb ? pb : qb, s3 = pb < qb ? qb : pb;
   if (s2 < s0) { const int t = s0; s0 = s2; s2 = t; }
@@ -364,20 +388,23 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
   for (int t = wave; t < ntile; t += NW) {
     const int c = t * 32 + n;
     const int base = rsw(insert_zero(insert_zero(insert_zero(insert_zero(c, s0), s1), s2), s3));
+    const int bin = base ^ h_in, bout = base ^ h_out;
     Cplx<float> x[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = B[base ^ off_in[j]];
-    bf16x8_t xrh, xrl, xih, xil;
+    for (int j = 0; j < 8; ++j) x[j] = B[bin ^ off_in[j]];
+    u32x4_t rh, rl, ih, il;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      __bf16 hh, ll;
-      bf16_split(x[j].x, hh, ll);
-      xrh[j] = hh;
-      xrl[j] = ll;
-      bf16_split(x[j].y, hh, ll);
-      xih[j] = hh;
-      xil[j] = ll;
+    for (int j = 0; j < 4; ++j) {
+      unsigned hh, ll;
+      bf16_split2(x[2 * j].x, x[2 * j + 1].x, hh, ll);
+      rh[j] = hh;
+      rl[j] = ll;
+      bf16_split2(x[2 * j].y, x[2 * j + 1].y, hh, ll);
+      ih[j] = hh;
+      il[j] = ll;
     }
+    const bf16x8_t xrh = __builtin_bit_cast(bf16x8_t, rh), xrl = __builtin_bit_cast(bf16x8_t, rl);
+    const bf16x8_t xih = __builtin_bit_cast(bf16x8_t, ih), xil = __builtin_bit_cast(bf16x8_t, il);
     f32x16_t acc = {};
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, xrh, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, xrl, acc, 0, 0, 0);
@@ -391,7 +418,7 @@ __device__ __forceinline__ void gate_pair_mfma(Cplx<float>* B, const Cplx<float>
       y.x = acc[j];
       y.y = acc[j + 8];
       if (TRACK) lmax = fmax(lmax, fmax(fabs(y.x), fabs(y.y)));
-      B[base ^ off_out[j]] = y;
+      B[bout ^ off_out[j]] = y;
     }
   }
 }
@@ -433,13 +460,18 @@ constexpr int chunk_ops() {
 // lazy: the op that ends a column records the largest magnitude it writes,
 // the column end turns it into an exponent P, and the next GATE multiplies
 // its matrix by 2^-P (exact), so no extra pass over the boundary is made.
-template <typename Real, int NT, bool BF3 = false>
+// MX: BF16x3 GATEs on registers of 2^9 entries or more go to the matrix
+// cores (a caller whose registers are already at the limit keeps them on
+// the vector path).
+template <typename Real, int NT, bool BF3 = false, bool MX = true>
 __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, Op* ops_s, const Op* __restrict__ ops,
                                             int num_ops, const int2* __restrict__ wgates,
                                             const int32_t* __restrict__ factors, const Real* pair_gates, int G,
                                             int log2_factor, int lane, Real* red, double* tr_re, double* tr_im,
                                             const Real* __restrict__ wmat = nullptr, int num_gate_ops = 0) {
   constexpr int K = chunk_ops<NT>();
+  // BF16x3 matrix-core blocks: MFMA_BLOCK_BYTES after the staged op records
+  unsigned short* fblk = reinterpret_cast<unsigned short*>(ops_s + K);
   // with the matrices precomputed in program order (wmat), the first
   // wavefront stages a chunk and numbers its GATEs with a ballot
   const bool pre = NT >= 64 && wmat != nullptr;
@@ -492,7 +524,7 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
       const int type = op.type & OP_TYPE_MASK;
       const bool track = (op.type & OP_FLAG_TRACK) != 0;
       bool fused = false, single = false;
-      if constexpr (BF3 && NT >= 64) {
+      if constexpr (BF3 && MX && NT >= 64) {
         // this GATE and the next on four distinct bits: one matrix-core block
         if (type == OP_GATE && !track && b >= 9 && i + 1 < nk) {
           const unsigned w1 = (unsigned)__builtin_amdgcn_readfirstlane(*reinterpret_cast<const int*>(&ops_s[i + 1]));
@@ -504,11 +536,11 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
             Cplx<float>* Bf = reinterpret_cast<Cplx<float>*>(B);
             float lm = (float)lmax;
             if (track2) {
-              if (sc) gate_pair_mfma<NT, true, true>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, sc, lm);
-              else gate_pair_mfma<NT, true, false>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, 0, lm);
+              if (sc) gate_pair_mfma<NT, true, true>(Bf, ma, ma + 16, fblk, op.p, op.q, p2, q2, b, lane, sc, lm);
+              else gate_pair_mfma<NT, true, false>(Bf, ma, ma + 16, fblk, op.p, op.q, p2, q2, b, lane, 0, lm);
             } else {
-              if (sc) gate_pair_mfma<NT, false, true>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, sc, lm);
-              else gate_pair_mfma<NT, false, false>(Bf, ma, ma + 16, op.p, op.q, p2, q2, b, lane, 0, lm);
+              if (sc) gate_pair_mfma<NT, false, true>(Bf, ma, ma + 16, fblk, op.p, op.q, p2, q2, b, lane, sc, lm);
+              else gate_pair_mfma<NT, false, false>(Bf, ma, ma + 16, fblk, op.p, op.q, p2, q2, b, lane, 0, lm);
             }
             lmax = (Real)lm;
             expo += pend;
@@ -529,11 +561,11 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
           Cplx<float>* Bf = reinterpret_cast<Cplx<float>*>(B);
           float lm = (float)lmax;
           if (track) {
-            if (sc) gate_pair_mfma<NT, true, true, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, sc, lm);
-            else gate_pair_mfma<NT, true, false, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, 0, lm);
+            if (sc) gate_pair_mfma<NT, true, true, true>(Bf, ma, ma, fblk, pa, qa, pb, qb, b, lane, sc, lm);
+            else gate_pair_mfma<NT, true, false, true>(Bf, ma, ma, fblk, pa, qa, pb, qb, b, lane, 0, lm);
           } else {
-            if (sc) gate_pair_mfma<NT, false, true, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, sc, lm);
-            else gate_pair_mfma<NT, false, false, true>(Bf, ma, ma, pa, qa, pb, qb, b, lane, 0, lm);
+            if (sc) gate_pair_mfma<NT, false, true, true>(Bf, ma, ma, fblk, pa, qa, pb, qb, b, lane, sc, lm);
+            else gate_pair_mfma<NT, false, false, true>(Bf, ma, ma, fblk, pa, qa, pb, qb, b, lane, 0, lm);
           }
           lmax = (Real)lm;
           expo += pend;
@@ -548,7 +580,8 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
         const int p = op.p, q = op.q;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         const int ip = 1 << p, iq = 1 << q;
-        constexpr int U = BF3 ? 2 : gate_batch<Real>();
+        // (BF16x3 with 1024 lanes: one group per round, within 128 registers)
+        constexpr int U = BF3 && NT < 1024 ? 2 : gate_batch<Real>();
         Real Rr[16], Ri[16];
         if constexpr (NT >= 64) {
 #pragma unroll
@@ -645,9 +678,11 @@ __device__ __forceinline__ void run_program(Cplx<Real>* B, Cplx<Real>* mats_s, O
   *tr_im = ldexp((double)v.y, (int)(expo + log2_factor));
 }
 
-template <typename Real, int NT>
+// staged matrices and op records of a chunk, then (BF16x3 with a group of
+// 64 lanes or more) the matrix-core block
+template <typename Real, int NT, bool BF3 = false>
 constexpr size_t stage_bytes() {
-  return (size_t)chunk_ops<NT>() * (16 * sizeof(Cplx<Real>) + sizeof(Op));
+  return (size_t)chunk_ops<NT>() * (16 * sizeof(Cplx<Real>) + sizeof(Op)) + (BF3 && NT >= 64 ? MFMA_BLOCK_BYTES : 0);
 }
 
 }  // namespace fp
