@@ -176,6 +176,105 @@ __device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], co
   gate_rounds<Real, NT, U, BF3, I>(B, Rr, Ri, lo, hi, ip, iq, ng, lane, track, lmax);
 }
 
+// A run of m consecutive GATEs on a register of 2^b entries in global memory
+// (H), applied tile by tile through LDS (L): the tile bits are the bits the
+// run touches, topped up with the lowest other bits to nb = log2(entries of
+// L) bits; a tile holds the 2^nb entries that agree on every other bit.  Each
+// tile is read once, takes every GATE of the run in LDS (in order; entries
+// at rsw(local index), as the LDS sweep keeps them), and is written back
+// once: one pass over the register for the run instead of one per GATE.
+// mats/ops: the run's staged matrices and op records; the first matrix comes
+// scaled in (Rr0, Ri0).  Every lane of the workgroup calls it (NT lanes);
+// b > nb.
+template <typename Real, int NT, bool BF3, typename I>
+__device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, int nb, const Real (&Rr0)[16], const Real (&Ri0)[16],
+                               const Cplx<Real>* mats, const uint2* ops, int m, int b, bool track_last, int lane,
+                               Real& lmax) {
+  constexpr int LANE_BITS = NT == 512 ? 9 : NT == 256 ? 8 : 10;
+  static_assert((1 << LANE_BITS) == NT, "tiles take NT lanes per row");
+  uint64_t tmask = 0;
+  for (int g = 0; g < m; ++g) {
+    const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g].x);
+    tmask |= (1ull << ((w >> 8) & 0xff)) | (1ull << ((w >> 16) & 0xff));
+  }
+  for (int bit = 0; __popcll(tmask) < nb; ++bit) tmask |= 1ull << bit;
+  const uint64_t omask = ((b >= 64 ? ~0ull : (1ull << b) - 1)) & ~tmask;
+  // the lane's bits of a local index, deposited at the lowest tile bits
+  I dep_lane = 0;
+  uint64_t hi_mask = tmask;  // tile bits above the lane's
+  for (int j = 0; j < LANE_BITS; ++j) {
+    const int pos = __ffsll((long long)hi_mask) - 1;
+    hi_mask &= hi_mask - 1;
+    if ((lane >> j) & 1) dep_lane += (I)1 << pos;
+  }
+  const int per_lane = 1 << (nb - LANE_BITS);
+  const I ntiles = (I)1 << (b - nb);
+  constexpr int V = 8;  // loads in flight per lane
+  for (I tau = 0; tau < ntiles; ++tau) {
+    I base = 0;  // tau's bits deposited at the other bits (uniform)
+    {
+      uint64_t mm = omask;
+      for (I t = tau; t != 0; t >>= 1) {
+        const int pos = __ffsll((long long)mm) - 1;
+        mm &= mm - 1;
+        if (t & 1) base += (I)1 << pos;
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {  // 0: read the tile, 1: write it back
+      if (pass == 1) {
+        for (int g = 0; g < m; ++g) {
+          const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g].x);
+          const int p = (int)((w >> 8) & 0xff), q = (int)((w >> 16) & 0xff);
+          const int lp = __popcll(tmask & ((1ull << p) - 1)), lq = __popcll(tmask & ((1ull << q) - 1));
+          Real Rr[16], Ri[16];
+#pragma unroll
+          for (int k = 0; k < 16; ++k) {
+            const Cplx<Real> r = mats[16 * g + k];
+            Rr[k] = g == 0 ? Rr0[k] : r.x;
+            Ri[k] = g == 0 ? Ri0[k] : r.y;
+          }
+          const int lo = lp < lq ? lp : lq, hi = lp < lq ? lq : lp;
+          if (track_last && g == m - 1)
+            gate_groups_u<Real, 1, BF3, true, false>(L, Rr, Ri, lo, hi, 1 << lp, 1 << lq, 1 << (nb - 2), lane, NT, 0,
+                                                     lmax);
+          else
+            gate_groups_u<Real, 1, BF3, false, false>(L, Rr, Ri, lo, hi, 1 << lp, 1 << lq, 1 << (nb - 2), lane, NT,
+                                                      0, lmax);
+          __syncthreads();
+        }
+      }
+      for (int k0 = 0; k0 < per_lane; k0 += V) {
+        I addr[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          I dk = 0;  // (k0 + u)'s bits deposited at the tile bits above the lane's (uniform)
+          uint64_t mm = hi_mask;
+          for (int kk = k0 + u; kk != 0; kk >>= 1) {
+            const int pos = __ffsll((long long)mm) - 1;
+            mm &= mm - 1;
+            if (kk & 1) dk += (I)1 << pos;
+          }
+          addr[u] = base + dep_lane + dk;
+        }
+        if (pass == 0) {
+          Cplx<Real> v[V];
+#pragma unroll
+          for (int u = 0; u < V; ++u)
+            if (k0 + u < per_lane) v[u] = H[addr[u]];
+#pragma unroll
+          for (int u = 0; u < V; ++u)
+            if (k0 + u < per_lane) L[rsw(lane + (k0 + u) * NT)] = v[u];
+        } else {
+#pragma unroll
+          for (int u = 0; u < V; ++u)
+            if (k0 + u < per_lane) H[addr[u]] = L[rsw(lane + (k0 + u) * NT)];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // BELL from b to b + 2 bits: dst[k + 3s] = src[k], dst[k + s] = dst[k + 2s] = 0
 // (s = 2^b), and dst[k] = src[k] when the boundary moves (COPY); entries
 // k = base .. base + n - 1.
@@ -474,13 +573,35 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         expo += pend;
         pend = 0;
         const int lo = p < q ? p : q, hi = p < q ? q : p;
-        if (in_lds)
+        // consecutive GATEs that a tile of LB bits holds (uniform)
+        int run = 1;
+        if (!in_lds && !track) {
+          uint64_t mask = (1ull << p) | (1ull << q);
+          while (i + run < nk) {
+            const unsigned w1 = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i + run].x);
+            if ((int)(w1 & OP_TYPE_MASK) != OP_GATE) break;
+            const uint64_t m2 = mask | (1ull << ((w1 >> 8) & 0xff)) | (1ull << ((w1 >> 16) & 0xff));
+            if (__popcll(m2) > LB) break;
+            mask = m2;
+            ++run;
+            if (w1 & OP_FLAG_TRACK) break;  // the column's last writing op
+          }
+        }
+        if (in_lds) {
           gate_any<Real, NT, U, BF3, int>(L, Rr, Ri, lo, hi, 1 << p, 1 << q, 1 << (b - 2), lane, track, lmax);
-        else if (share(b))
+        } else if (share(b)) {
           failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_GATE, b, p, q, track, Rr, Ri, mats_s + 16 * i, sc, H,
                                                      H, lane, sh, lmax);
-        else
+        } else if (run >= 2) {
+          const unsigned wl = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i + run - 1].x);
+          const bool tl = (wl & OP_FLAG_TRACK) != 0;
+          gate_run_tiled<Real, NT, BF3, I>(H, L, LB, Rr, Ri, mats_s + 16 * i, ops_s + i, run, b, tl, lane, lmax);
+          i += run - 1;
+          prev_track = tl;
+          continue;  // the tiled pass ended at a barrier
+        } else {
           gate_any<Real, NT, U, BF3, I>(H, Rr, Ri, lo, hi, (I)1 << p, (I)1 << q, (I)1 << (b - 2), lane, track, lmax);
+        }
       } else if (type == OP_BELL) {
         if (!in_lds && share(b + 2)) {
           failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_BELL, b, p, q, false, Rr0, Ri0, mats_s, 0, H, H,
