@@ -588,7 +588,9 @@ def main():
     # time: with batches in flight a kernel's events also span the other
     # batches' work on the GPU (that duration is reported beside it)
     sprof = serial["prof"]
-    dom = max(SWEEP_CLASSES, key=lambda c: sprof[c]["ms"])
+    # the sweep class that does most of the step's algorithmic flops (the
+    # longest launch can be a class with few pairs, e.g. the widest ones)
+    dom = max(SWEEP_CLASSES, key=lambda c: sprof[c]["flops"])
     d = sprof[dom]
     peak = PEAK_FP32_TFLOPS if prec == fp.C64 else PEAK_FP64_TFLOPS
     achieved = (d["flops"] / d["launches"]) / (d["ms"] / d["launches"] * 1e-3) / 1e12 if d["launches"] else 0.0
@@ -608,6 +610,10 @@ def main():
     step_kernels = {c: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                         "gflop_per_step": v["flops"] / args.steps / 1e9, "gb_per_step": v["bytes"] / args.steps / 1e9}
                     for c, v in prof.items() if v["launches"]}
+    serial_kernels = {c: {"ms_per_launch": v["ms"] / v["launches"], "gflop_per_launch": v["flops"] / v["launches"] / 1e9}
+                      for c, v in sprof.items() if v["launches"]}
+    progress("one batch at a time, ms per launch: " + ", ".join(f"{c} {v['ms_per_launch']:.3f}"
+                                                                  for c, v in serial_kernels.items()))
 
     per_depth = {}
     if args.per_depth:
@@ -696,6 +702,7 @@ def main():
     full.update({
         "ms_per_step_with_events": timed["wall_s"] / args.steps * 1e3,
         "serial_ms_per_step": serial["wall_s"] / args.steps * 1e3,
+        "serial_kernels": serial_kernels,
         "F_k": head["F"], "SE_k": head["SE"],
         "step_kernels_ms": step_kernels,
         "per_depth": per_depth,

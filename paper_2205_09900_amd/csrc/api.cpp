@@ -260,6 +260,10 @@ constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at
 constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
 constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
+// HBM-slot sweep with tiled GATE runs when at least 1/LR_TILED_SHARE of a
+// batch's pairs are in its class (S = 100 at n = 50: 0.7 %, a few of them
+// beyond LDS; S = 150: most of the class beyond LDS)
+constexpr int LR_TILED_SHARE = 64;
 constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;        // registers predicted up to 2^31 entries
 constexpr int64_t POOL_BUDGET_DEEP = (int64_t)192 << 30;  // beyond: most of the device's 288 GB
 
@@ -668,6 +672,10 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // exceed 2^31 entries: known exactly once the set-up is read back, else
   // from the last batch of the ensemble or, for the first, from the depth.
   bool wide_hbm = n >= 32 && lr_predicted_bits_raw(n, G) > 27;
+  // and with the tiled runs of GATEs when registers leave LDS in more than
+  // a few pairs (the variant without them runs LDS-resident pairs faster;
+  // both give the same results)
+  bool tiled_hbm = lr_predicted_bits_raw(n, G) > lds_bits_max(c.precision);
   // flops < 0: the class's MAC count is read from the device afterwards
   auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
                           double flops) -> int {
@@ -691,7 +699,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     }
     profile_launch_begin(cls[k].kclass, sx);
     if (k == 4)
-      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx, wide_hbm);
+      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx, wide_hbm, tiled_hbm);
     else  // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
       r = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
                           : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
@@ -728,6 +736,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     if (rc) return rc;
     lr_hint_set(c.key, h.d, np);
     wide_hbm = h.d.max_bits > 31;
+    tiled_hbm = h.d.max_bits > lds_bits_max(c.precision) && h.d.range[4][1] * LR_TILED_SHARE >= np;
     for (int k = 0; k < 5; ++k) dev_first[k] = h.d.range[k][0];
     int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
     int act[5], na = 0;
@@ -759,6 +768,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // order needs no cross-stream wait, so its long pairs start first.
   int grid = LR_MAX_OWNERS + LR_HELPERS;
   if (hinted) wide_hbm = hint.max_bits > 31 || wide_hbm;
+  if (hinted) tiled_hbm = hint.max_bits > lds_bits_max(c.precision) && hint.frac[4] * LR_TILED_SHARE >= 1.0;
   if (hinted) {
     const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
     grid = want < grid ? want : grid;

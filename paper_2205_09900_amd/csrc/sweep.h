@@ -169,8 +169,10 @@ struct LrSetupJob {
 int launch_lr_setup(const LrSetupJob& j, hipStream_t s);
 // HBM-slot sweep of a local random class set up on the device (launch `grid`
 // workgroups; those beyond dev->hbm_workgroups return at once).
+// wide: 64-bit entry indices; tiled: some register may leave LDS (runs of
+// GATEs on it then go tile by tile; either choice gives the same results).
 int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s, bool wide);
+                         hipStream_t s, bool wide, bool tiled);
 // Zero n 32-bit words (a kernel, so that stream capture records no memset node).
 int launch_zero_words(void* p, int64_t n, hipStream_t s);
 // Workgroups of a kernel resident per compute unit (occupancy query, no device work),

@@ -186,12 +186,14 @@ __device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], co
 // mats/ops: the run's staged matrices and op records; the first matrix comes
 // scaled in (Rr0, Ri0).  Every lane of the workgroup calls it (NT lanes);
 // b > nb.
-template <typename Real, int NT, bool BF3, typename I>
-__device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, int nb, const Real (&Rr0)[16], const Real (&Ri0)[16],
+template <typename Real, int NT, int NB, bool BF3, typename I>
+__device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, const Real (&Rr0)[16], const Real (&Ri0)[16],
                                const Cplx<Real>* mats, const uint2* ops, int m, int b, bool track_last, int lane,
                                Real& lmax) {
   constexpr int LANE_BITS = NT == 512 ? 9 : NT == 256 ? 8 : 10;
   static_assert((1 << LANE_BITS) == NT, "tiles take NT lanes per row");
+  constexpr int nb = NB;
+
   uint64_t tmask = 0;
   for (int g = 0; g < m; ++g) {
     const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g].x);
@@ -207,9 +209,9 @@ __device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, int nb, const Real 
     hi_mask &= hi_mask - 1;
     if ((lane >> j) & 1) dep_lane += (I)1 << pos;
   }
-  const int per_lane = 1 << (nb - LANE_BITS);
+  constexpr int per_lane = 1 << (NB - LANE_BITS);
   const I ntiles = (I)1 << (b - nb);
-  constexpr int V = 8;  // loads in flight per lane
+  constexpr int V = per_lane < 8 ? per_lane : 8;  // loads in flight per lane
   for (I tau = 0; tau < ntiles; ++tau) {
     I base = 0;  // tau's bits deposited at the other bits (uniform)
     {
@@ -502,7 +504,10 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
   if (lane == 0) atomicAdd(&rec->done, 1u);
 }
 
-template <typename Real, int NT, int U, bool BF3, typename I>
+// TILED: runs of GATEs on a register in HBM go through gate_run_tiled (its
+// registers cost the LDS-resident path some speed, so batches whose
+// registers never leave LDS take the variant without it).
+template <typename Real, int NT, int U, bool BF3, typename I, bool TILED>
 __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cplx<Real>* mats_s, uint2* ops_s,
                                                 const Op* __restrict__ ops, int num_ops, int num_gate_ops,
                                                 const Real* __restrict__ wmat, const int2* __restrict__ wgates,
@@ -575,7 +580,7 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         const int lo = p < q ? p : q, hi = p < q ? q : p;
         // consecutive GATEs that a tile of LB bits holds (uniform)
         int run = 1;
-        if (!in_lds && !track) {
+        if (TILED && !in_lds && !track) {
           uint64_t mask = (1ull << p) | (1ull << q);
           while (i + run < nk) {
             const unsigned w1 = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i + run].x);
@@ -592,10 +597,10 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         } else if (share(b)) {
           failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_GATE, b, p, q, track, Rr, Ri, mats_s + 16 * i, sc, H,
                                                      H, lane, sh, lmax);
-        } else if (run >= 2) {
+        } else if (TILED && run >= 2) {
           const unsigned wl = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i + run - 1].x);
           const bool tl = (wl & OP_FLAG_TRACK) != 0;
-          gate_run_tiled<Real, NT, BF3, I>(H, L, LB, Rr, Ri, mats_s + 16 * i, ops_s + i, run, b, tl, lane, lmax);
+          gate_run_tiled<Real, NT, LB, BF3, I>(H, L, Rr, Ri, mats_s + 16 * i, ops_s + i, run, b, tl, lane, lmax);
           i += run - 1;
           prev_track = tl;
           continue;  // the tiled pass ended at a barrier
@@ -665,7 +670,7 @@ __device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
 // pairs, the high 32 bits first claims, so the j-th first claim has taken a
 // pair of rank >= j, no wider than slot j.  Every pair below wide_pairs
 // counts in `finished` whatever its path, and helpers leave once all have.
-template <typename Real, int NT, bool BF3, typename I>
+template <typename Real, int NT, bool BF3, typename I, bool TILED>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl_arg,
                                                        HelpArgs h_arg, const LrDev* dev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -740,7 +745,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
           const Real* pg = reinterpret_cast<const Real*>(a.gates + pidx * a.gate_stride);
           const Real* wm = a.wmat ? reinterpret_cast<const Real*>(a.wmat + pidx * a.wmat_stride) : nullptr;
           double re, im;
-          run_program_big<Real, NT, U, BF3, I>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
+          run_program_big<Real, NT, U, BF3, I, TILED>(L, S, mats, ops_s, a.ops + pidx * a.ops_stride, hdr->num_ops,
                                                hdr->num_gate_ops, wm, a.wgates + pidx * a.wg_stride,
                                                a.factors + pidx * a.f_stride, pg, a.G, hdr->log2_factor, lane, red,
                                                &re, &im, rec, A, h.help_bits, helpers, counter, np, sh);
@@ -920,10 +925,10 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
   return a.bf3 ? launch_lds_real<float, true>(a, tile, s) : launch_lds_real<float, false>(a, tile, s);
 }
 
-template <typename Real, bool BF3, typename I>
+template <typename Real, bool BF3, typename I, bool TILED>
 static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, const SlotArgs& sl, int grid,
                          const HelpArgs& h, const LrDev* dev, hipStream_t s) {
-  const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3, I>;
+  const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3, I, TILED>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
@@ -966,15 +971,15 @@ int slot_bits_host(const SlotArgs& sl) {
   return b;
 }
 
-template <typename I>
+template <typename I, bool TILED>
 static void launch_hbm_prec(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl,
                             int grid, const HelpArgs& h, const LrDev* dev, hipStream_t s) {
   if (precision == FP_C128)
-    launch_hbm_t<double, false, I>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<double, false, I, TILED>(a, counter, sl, grid, h, dev, s);
   else if (a.bf3)
-    launch_hbm_t<float, true, I>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<float, true, I, TILED>(a, counter, sl, grid, h, dev, s);
   else
-    launch_hbm_t<float, false, I>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<float, false, I, TILED>(a, counter, sl, grid, h, dev, s);
 }
 
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl, int grid,
@@ -989,23 +994,28 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
     h = *help;
   }
   if (grid < sl.owners || (grid > sl.owners && h.recs == nullptr)) return set_error(FP_EINVAL, "bad HBM grid");
-  if (slot_bits_host(sl) > 31)
-    launch_hbm_prec<int64_t>(a, precision, counter, sl, grid, h, nullptr, s);
+  const int top = slot_bits_host(sl);
+  if (top > 31)
+    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, nullptr, s);
+  else if (top > (precision == FP_C128 ? hbm_lds_bits<double>() : hbm_lds_bits<float>()))
+    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, nullptr, s);
   else
-    launch_hbm_prec<int>(a, precision, counter, sl, grid, h, nullptr, s);
+    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, nullptr, s);
   return check_launch("sweep_hbm");
 }
 
 int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s, bool wide) {
+                         hipStream_t s, bool wide, bool tiled) {
   if (grid <= 0) return FP_OK;
   SlotArgs sl;
   memset(&sl, 0, sizeof(sl));
   const HelpArgs h = {nullptr, nullptr, 0, 0};
   if (wide)
-    launch_hbm_prec<int64_t>(a, precision, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, dev, s);
+  else if (tiled)
+    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, dev, s);
   else
-    launch_hbm_prec<int>(a, precision, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, dev, s);
   return check_launch("sweep_hbm");
 }
 

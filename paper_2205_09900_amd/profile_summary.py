@@ -96,7 +96,7 @@ def counter_table(dirs, kernels, min_percent=1.0):
     return names, vals
 
 
-def render(s, workload, command, trace_cmd, counters=None, counter_cmds=()):
+def render(s, workload, command, trace_cmd, counters=None, counter_cmds=(), mfma_flops=0.0, mfma_peak=0.0):
     lines = [f"# rocprofv3 summary: {workload}", "",
              "Commands (repository root, one MI355X):", "",
              f"    {trace_cmd}",
@@ -132,6 +132,16 @@ def render(s, workload, command, trace_cmd, counters=None, counter_cmds=()):
                 if w:
                     lines.append(f"| {k} | " + " | ".join(f"{v[c] / w:.4g}" if c in v else "-" for c in per)
                                  + " |")
+        if mfma_flops and "SQ_INSTS_MFMA" in names:
+            us = {k["kernel"]: k["avg_us"] for k in s["kernels"]}
+            lines += ["", f"Matrix cores: SQ_INSTS_MFMA x {mfma_flops:.0f} flops per instruction / average "
+                      f"duration, against the dense peak of {mfma_peak:.0f} TFLOP/s:", "",
+                      "| kernel | MFMA instructions | matrix-core TFLOP/s | fraction of peak |", "|---|---|---|---|"]
+            for k, v in vals.items():
+                n = v.get("SQ_INSTS_MFMA", 0.0)
+                if n > 0 and us.get(k):
+                    tf = n * mfma_flops / (us[k] * 1e-6) / 1e12
+                    lines.append(f"| {k} | {n:.4g} | {tf:.1f} | {tf / mfma_peak:.3f} |")
     lines += ["", "traffic-json: " + json.dumps({
         "workload": workload, "sources": sources_hash(),
         "bytes_per_dispatch": {k["kernel"]: (k["fetch_bytes"] or 0.0) + (k["write_bytes"] or 0.0)
@@ -163,10 +173,13 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--counters", nargs="*", default=[], help="directories of further counter runs")
     ap.add_argument("--counter-command", action="append", default=[], help="the command of each such run")
+    ap.add_argument("--mfma-flops", type=float, default=0.0,
+                    help="flops of one MFMA instruction of the profiled kernels (32x32x16 bf16: 32768)")
+    ap.add_argument("--mfma-peak", type=float, default=2500.0, help="dense matrix-core peak, TFLOP/s")
     a = ap.parse_args()
     s = summarize(a.trace, a.fetch, a.write)
     ctr = counter_table(a.counters, s["kernels"]) if a.counters else None
-    text = render(s, a.workload, a.command, a.trace_command, ctr, a.counter_command)
+    text = render(s, a.workload, a.command, a.trace_command, ctr, a.counter_command, a.mfma_flops, a.mfma_peak)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
