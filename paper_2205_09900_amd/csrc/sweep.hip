@@ -189,7 +189,7 @@ __device__ __forceinline__ void gate_any(Cplx<Real>* B, const Real (&Rr)[16], co
 template <typename Real, int NT, int NB, bool BF3, typename I>
 __device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, const Real (&Rr0)[16], const Real (&Ri0)[16],
                                const Cplx<Real>* mats, const uint2* ops, int m, int b, bool track_last, int lane,
-                               Real& lmax) {
+                               Real& lmax, int sc) {
   constexpr int LANE_BITS = NT == 512 ? 9 : NT == 256 ? 8 : 10;
   static_assert((1 << LANE_BITS) == NT, "tiles take NT lanes per row");
   constexpr int nb = NB;
@@ -224,6 +224,49 @@ __device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, const Real (&Rr0)[1
     }
     for (int pass = 0; pass < 2; ++pass) {  // 0: read the tile, 1: write it back
       if (pass == 1) {
+       if constexpr (BF3) {
+        // BF16x3: the run's GATEs as matrix-core blocks on the tile (pairs on
+        // four distinct bits, else one GATE times the identity); the first
+        // block takes out the column's power of two
+        __shared__ __align__(16) unsigned short fblk[MFMA_BLOCK_BYTES / 2];  // the block planes
+        const Cplx<float>* mf = reinterpret_cast<const Cplx<float>*>(mats);
+        Cplx<float>* Lf = reinterpret_cast<Cplx<float>*>(L);
+        float lm = (float)lmax;
+        for (int g = 0; g < m;) {
+          const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g].x);
+          const int p = (int)((w >> 8) & 0xff), q = (int)((w >> 16) & 0xff);
+          const int lp = __popcll(tmask & ((1ull << p) - 1)), lq = __popcll(tmask & ((1ull << q) - 1));
+          const int s0 = g == 0 ? sc : 0;
+          bool paired = false;
+          if (g + 1 < m) {
+            const unsigned w2 = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g + 1].x);
+            const int p2 = (int)((w2 >> 8) & 0xff), q2 = (int)((w2 >> 16) & 0xff);
+            if (p2 != p && p2 != q && q2 != p && q2 != q) {
+              const int lp2 = __popcll(tmask & ((1ull << p2) - 1)), lq2 = __popcll(tmask & ((1ull << q2) - 1));
+              const bool tr = track_last && g + 2 == m;
+              if (tr) gate_pair_mfma<NT, true, true>(Lf, mf + 16 * g, mf + 16 * (g + 1), fblk, lp, lq, lp2, lq2, nb,
+                                                     lane, s0, lm);
+              else gate_pair_mfma<NT, false, true>(Lf, mf + 16 * g, mf + 16 * (g + 1), fblk, lp, lq, lp2, lq2, nb,
+                                                   lane, s0, lm);
+              paired = true;
+            }
+          }
+          if (!paired) {
+            int lb = 0;
+            while (lb == lp || lb == lq) ++lb;
+            int lc = lb + 1;
+            while (lc == lp || lc == lq) ++lc;
+            const bool tr = track_last && g + 1 == m;
+            if (tr) gate_pair_mfma<NT, true, true, true>(Lf, mf + 16 * g, mf + 16 * g, fblk, lp, lq, lb, lc, nb, lane,
+                                                         s0, lm);
+            else gate_pair_mfma<NT, false, true, true>(Lf, mf + 16 * g, mf + 16 * g, fblk, lp, lq, lb, lc, nb, lane,
+                                                       s0, lm);
+          }
+          __syncthreads();
+          g += paired ? 2 : 1;
+        }
+        lmax = (Real)lm;
+       } else {
         for (int g = 0; g < m; ++g) {
           const unsigned w = (unsigned)__builtin_amdgcn_readfirstlane((int)ops[g].x);
           const int p = (int)((w >> 8) & 0xff), q = (int)((w >> 16) & 0xff);
@@ -244,6 +287,7 @@ __device__ void gate_run_tiled(Cplx<Real>* H, Cplx<Real>* L, const Real (&Rr0)[1
                                                       0, lmax);
           __syncthreads();
         }
+       }
       }
       for (int k0 = 0; k0 < per_lane; k0 += V) {
         I addr[V];
@@ -600,7 +644,7 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
         } else if (TILED && run >= 2) {
           const unsigned wl = (unsigned)__builtin_amdgcn_readfirstlane((int)ops_s[i + run - 1].x);
           const bool tl = (wl & OP_FLAG_TRACK) != 0;
-          gate_run_tiled<Real, NT, LB, BF3, I>(H, L, Rr, Ri, mats_s + 16 * i, ops_s + i, run, b, tl, lane, lmax);
+          gate_run_tiled<Real, NT, LB, BF3, I>(H, L, Rr, Ri, mats_s + 16 * i, ops_s + i, run, b, tl, lane, lmax, sc);
           i += run - 1;
           prev_track = tl;
           continue;  // the tiled pass ended at a barrier

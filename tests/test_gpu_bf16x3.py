@@ -110,3 +110,16 @@ def test_bf16x3_brickwork_n20_matrix_cores_vs_mpo(fp, depth):
     fw, _ = estimator.frame_potential(c64, 3)
     for k in range(3):
         assert abs(fg[k] - fw[k]) <= 2e-3 * fw[k], (k, fg[k], fw[k])
+
+
+def test_bf16x3_brickwork_hbm_tiles_vs_dense(fp):
+    """Depth 9 on 10 qubits: 16-bit registers in HBM slots, every run of
+    GATEs applied tile by tile through LDS with the matrix-core blocks,
+    against the dense oracle on the same float32 gates."""
+    ens, n, seed = (0, 10, 9), 12, 4411
+    assert fp.fp_plan_info(ens)["peak_bits"] == 16
+    got = traces(fp, ens, n, seed, BF16X3)
+    want = dense.traces(sampler.sample_pairs(0, 10, 9, seed, 0, n, fp32=True))
+    r = rel_errors(got, want)
+    print(f"brickwork n=10 D=9 BF16x3 (HBM tiles): median {np.median(r):.3e}, max {r.max():.3e}")
+    assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (float(np.median(r)), float(r.max()))
