@@ -35,7 +35,7 @@ SWEEP_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
 LR_KERNELS = {
     "lds16": "fp::sweep_wave_kernel<{r}, 8, 4, false>", "lds64": "fp::sweep_wave_kernel<{r}, 10, 2, false>",
     "lds256": "fp::sweep_lds_kernel<{r}, 256, 1, false>", "lds1024": "fp::sweep_lds_kernel<{r}, {big}, 1, false>",
-    "hbm": "fp::sweep_hbm_kernel<{r}, 512, false>"}
+    "hbm": "fp::sweep_hbm_kernel<{r}, 512, false, int, false>"}
 
 
 def parse():
