@@ -88,6 +88,10 @@ enum {
                    ops, HEA pointwise products) takes each real product as
                    hi_a hi_b + hi_a lo_b + lo_a hi_b with x = hi + lo, hi and
                    lo bf16 (round to nearest even), float32 accumulation.
+                   GATE ops on boundaries of 2^9 entries or more run on the
+                   bf16 matrix cores as 16x16 blocks (two GATEs on four
+                   distinct bits, formed in float32 and then split, or one
+                   GATE times the identity on two further bits).
                    Expected error vs FP_C128 about 2^-16 per product; the
                    HEA one-layer case (a product of 2x2 traces in float64)
                    is the same as FP_C64                                        */

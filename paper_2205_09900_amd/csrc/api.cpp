@@ -260,10 +260,13 @@ constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at
 constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
 constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
-// HBM-slot sweep with tiled GATE runs when at least 1/LR_TILED_SHARE of a
-// batch's pairs are in its class (S = 100 at n = 50: 0.7 %, a few of them
-// beyond LDS; S = 150: most of the class beyond LDS)
-constexpr int LR_TILED_SHARE = 64;
+// HBM-slot sweep with tiled GATE runs when a batch's widest register has
+// more than 2^LR_TILED_BITS entries.  Local random columns interleave BELL
+// and TRACE with short runs of GATEs, and the tiled variant runs the rest of
+// the kernel slower; measured at n = 50 (10^4 pairs): S = 150 and 200 (widest
+// 2^22) 9 and 18 % slower with tiles, S = 250 (2^28) unchanged, S = 300
+// (2^32) 36 % faster.
+constexpr int LR_TILED_BITS = 22;
 constexpr int64_t POOL_BUDGET = (int64_t)48 << 30;        // registers predicted up to 2^31 entries
 constexpr int64_t POOL_BUDGET_DEEP = (int64_t)192 << 30;  // beyond: most of the device's 288 GB
 
@@ -672,10 +675,9 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // exceed 2^31 entries: known exactly once the set-up is read back, else
   // from the last batch of the ensemble or, for the first, from the depth.
   bool wide_hbm = n >= 32 && lr_predicted_bits_raw(n, G) > 27;
-  // and with the tiled runs of GATEs when registers leave LDS in more than
-  // a few pairs (the variant without them runs LDS-resident pairs faster;
-  // both give the same results)
-  bool tiled_hbm = lr_predicted_bits_raw(n, G) > lds_bits_max(c.precision);
+  // and with the tiled runs of GATEs for the widest batches (both variants
+  // give the same results)
+  bool tiled_hbm = lr_predicted_bits_raw(n, G) > LR_TILED_BITS;
   // flops < 0: the class's MAC count is read from the device afterwards
   auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
                           double flops) -> int {
@@ -736,7 +738,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     if (rc) return rc;
     lr_hint_set(c.key, h.d, np);
     wide_hbm = h.d.max_bits > 31;
-    tiled_hbm = h.d.max_bits > lds_bits_max(c.precision) && h.d.range[4][1] * LR_TILED_SHARE >= np;
+    tiled_hbm = h.d.max_bits > LR_TILED_BITS;
     for (int k = 0; k < 5; ++k) dev_first[k] = h.d.range[k][0];
     int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
     int act[5], na = 0;
@@ -768,7 +770,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // order needs no cross-stream wait, so its long pairs start first.
   int grid = LR_MAX_OWNERS + LR_HELPERS;
   if (hinted) wide_hbm = hint.max_bits > 31 || wide_hbm;
-  if (hinted) tiled_hbm = hint.max_bits > lds_bits_max(c.precision) && hint.frac[4] * LR_TILED_SHARE >= 1.0;
+  if (hinted) tiled_hbm = hint.max_bits > LR_TILED_BITS;
   if (hinted) {
     const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
     grid = want < grid ? want : grid;
