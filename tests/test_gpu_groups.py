@@ -80,3 +80,36 @@ def test_autotune_choices_and_tuned_launches_vs_oracle(fp):
                 got = _group_traces(fp, [ens], [buf], n)
                 assert np.isfinite(got).all()
                 assert _floored(got[pick], want, 1) <= 1e-5, (ens, cls, tf)
+
+
+def test_bf16x3_groups_every_lane_class_vs_mpo(fp):
+    """BF16x3 brickwork n = 20 at D = 6 and 7 (registers of 2^10 and 2^12
+    entries) in one persistent launch with each lane class forced through the
+    tuning table: the 64- and 256-lane classes apply the GATEs as matrix-core
+    blocks, the 16- and 1024-lane classes with vector products.  Sampled pairs
+    against MPO-zip on the same float32 gates."""
+    import oracle_pool
+    bf3 = 2
+    cases = [(0, 20, 6), (0, 20, 7)]
+    n, pick = 160, [0, 3, 64, 101, 159]
+    bufs, want = [], []
+    for ens in cases:
+        seed = synth.workload_seed(41, ens[2])
+        bufs.append(fp.sample(ens, n, seed, 0, fp.C64))
+        want.append(np.array(oracle_pool.traces(ens[0], ens[1], ens[2], seed, pick, fp32=True)))
+    groups = [(i, bf3, 0, n) for i in range(len(cases))]
+    # table entries of these two BF16x3 keys only (loading merges entries)
+    for cls in fp.AUTOTUNE_CLASSES:
+        table = "".join(f"gfx950 {e[0]} {e[1]} {e[2]} {bf3} {cls} {fp.AUTOTUNE_TASK_FLOPS[1]:.0f} 0\n"
+                        for e in cases)
+        fp.fp_autotune_load(table)
+        tr = torch.empty(2 * n * len(cases), dtype=torch.float64, device="cuda")
+        ws = torch.empty(max(256, fp.fp_workspace_bytes_groups(cases, groups)), dtype=torch.uint8, device="cuda")
+        fp.fp_contract_trace_groups(cases, groups, bufs, tr, ws)
+        got = torch.view_as_complex(tr.view(-1, 2)).cpu().numpy()
+        assert np.isfinite(got).all(), cls
+        for i in range(len(cases)):
+            g = got[i * n:(i + 1) * n][pick]
+            rms = np.sqrt(np.mean(np.abs(want[i]) ** 2))
+            r = np.abs(g - want[i]) / np.maximum(np.abs(want[i]), 1e-3 * rms)
+            assert np.median(r) <= 2e-4 and r.max() <= 5e-3, (cls, cases[i], float(np.median(r)), float(r.max()))
