@@ -13,7 +13,8 @@ their own); kernel durations, the roofline and the step breakdown come from
 runs with events (ms_per_step_with_events, serial_ms_per_step).  Inputs are
 synthetic and seeded.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU
+(how the work would shard across GPUs is a design, not code).
 """
 
 import argparse
@@ -502,7 +503,7 @@ def cpu_baseline(n, depth, seed_base, seconds=8.0, runs=3):
     """The oracle (MPO-zip, complex128, with its own sampler) on a bounded
     sample: `runs` windows of `seconds` each over fresh pairs of the
     workload, handed out one at a time to one process per core the bench may
-    use (at most 16: a GPU machine allots 16 CPUs to its one GPU).  Pairs still
+    use (at most 16 host threads per GPU).  Pairs still
     running at the end of a window are dropped with their processes (so the
     window's rate counts completed pairs only); the median window is
     reported."""
@@ -548,7 +549,7 @@ def cpu_baseline(n, depth, seed_base, seconds=8.0, runs=3):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only",
+        print(json.dumps({"error": "the library runs on one GPU; sharding across GPUs is a design, not code",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import numpy as np

@@ -45,7 +45,7 @@ enum {
                        buffer smaller than the call needs                      */
   FP_ETOOBIG = -2,  /* a boundary tensor exceeds the workspace or the limits  */
   FP_EDEVICE = -3,  /* a HIP runtime error (text in fp_last_error)            */
-  FP_ENOTIMPL = -4, /* combination not provided by this build                 */
+  FP_ENOTIMPL = -4, /* combination the library does not provide             */
   FP_ENUMERIC = -5  /* a non-finite trace reached the reduction               */
 };
 
