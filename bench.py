@@ -32,6 +32,10 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector, published
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
 PEAK_HBM_GBS = 8000.0
 SWEEP_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
+# sweep rate assumed when a deep batch is planned: batches at 300 and 350
+# steps ran their HBM-slot sweeps at about 2 TFLOP/s (pairs of 2^34 entries
+# included); the cap takes a quarter of that
+DEEP_PLAN_TFLOPS = 0.5
 # kernel of each sweep class for local random batches (names as rocprofv3 shows them)
 LR_KERNELS = {
     "lds16": "fp::sweep_wave_kernel<{r}, 8, 4, false>", "lds64": "fp::sweep_wave_kernel<{r}, 10, 2, false>",
@@ -52,6 +56,14 @@ def parse():
     ap.add_argument("--depth-steps", type=int, default=6, help="batches timed per step count of --per-depth")
     ap.add_argument("--per-depth", default="50,100,150,200,250,300",
                     help="comma list of step counts measured besides the headline ('' = none)")
+    ap.add_argument("--deep-depths", default="350",
+                    help="comma list of step counts past --per-depth, timed on small batches one at a time "
+                         "('' = none)")
+    ap.add_argument("--deep-pairs", type=int, default=1000, help="pairs per batch of --deep-depths")
+    ap.add_argument("--deep-batches", type=int, default=2, help="batches timed per step count of --deep-depths")
+    ap.add_argument("--deep-cap-s", type=float, default=60.0,
+                    help="a --deep-depths batch whose planned sweep work would take longer than this at "
+                         "DEEP_PLAN_TFLOPS is reported with its plan and not run")
     ap.add_argument("--feasibility", default=",".join(str(x) for x in range(50, 801, 50)),
                     help="comma list of step counts whose register widths are reported ('' = none)")
     ap.add_argument("--feasibility-pairs", type=int, default=0,
@@ -108,7 +120,7 @@ def progress(msg):
 
 
 def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pipeline=True, in_flight=2,
-                 profile=True):
+                 profile=True, say_batches=False):
     """Times `steps` batches.  Pipelined: `in_flight` buffers (gates, traces,
     workspace) on streams of their own.  Sampling runs in_flight - 1 batches
     ahead of contraction: batch i + in_flight - 1 is sampled as soon as batch
@@ -116,7 +128,8 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     the host waits for batch i's plans (the contraction reads the planner's
     register widths back), the device runs batch i - 1's sweeps, batch i's
     planner and the next samplers side by side.  Every batch is sampled,
-    contracted and reduced exactly once inside the timed region."""
+    contracted and reduced exactly once inside the timed region.  One at a
+    time, `say_batches` prints a line as each batch ends."""
     ens = fp.Ensemble(fp.LOCAL_RANDOM, n, depth)
     nbuf = in_flight if pipeline else 1
     gates = [fp.alloc_gates(ens, pairs, prec) for _ in range(nbuf)]
@@ -158,10 +171,16 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
                 sample(i)
                 contract(i)
                 f = finish(i)
+                f_batches.append(f[0])
+                if say_batches:
+                    progress(f"S={depth}: batch {i + 1} of {end} done")
         return f
+
+    f_batches = []
 
     run(0, warmup)
     torch.cuda.synchronize()
+    f_batches.clear()
     if profile:  # HIP events around every launch (they cost time of their own)
         fp.fp_profile_begin()
     t0 = time.perf_counter()
@@ -171,7 +190,7 @@ def run_workload(fp, torch, n, depth, pairs, prec, steps, warmup, seed_base, pip
     prof = fp.fp_profile_end() if profile else None
     progress(f"S={depth}: {steps} batches, {'pipelined' if pipeline else 'one at a time'}"
              f"{' with events' if profile else ''}: {wall / steps * 1e3:.3f} ms per batch")
-    return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb}
+    return {"wall_s": wall, "prof": prof, "F": f[0], "SE": f[1], "ws_bytes": wsb, "F_batches": f_batches}
 
 
 def layer_scaling(fp, torch, traces_by_depth, n, k_max=3, resamples=300, epsilon=0.1):
@@ -441,6 +460,26 @@ def hea_many_groups(fp, torch, steps=3, n_groups=64, pairs=2000):
 LR_MAX_BITS = 36  # widest slot of the HBM-slot sweep: 2^36 entries (64-bit entry indices beyond 2^31)
 
 
+def planned_pairs(fp, np, n, s, seed_base, first, count):
+    """Pairs first .. first + count - 1 of the local random workload at s
+    steps, sampled by the product's sampler and planned by its host planner:
+    the widest register of each pair and its complex multiply-adds."""
+    ens = fp.Ensemble(fp.LOCAL_RANDOM, n, s)
+    off = 2 * s * 32 * 4  # bonds follow the complex64 gates of U and V
+    peaks, macs = [], []
+    for lo in range(first, first + count, 1000):
+        cnt = min(1000, first + count - lo)
+        g = fp.sample(ens, cnt, seed_base | (s << 32), lo, fp.C64).view(cnt, -1)
+        bonds = g[:, off: off + 8 * s].cpu().numpy()
+        del g
+        for p in range(cnt):
+            b = np.frombuffer(bonds[p].tobytes(), dtype=np.int32).reshape(2, s)
+            r = fp.fp_plan_local_random_host(n, b[0], b[1])
+            peaks.append(r["peak_bits"])
+            macs.append(r["macs"])
+    return np.array(peaks), np.array(macs)
+
+
 def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
     """Widest register of each pair in a sample per depth (the product's sampler
     and host planner on the sampled bonds), and the fraction of pairs beyond
@@ -453,17 +492,7 @@ def feasibility(fp, np, n, depths, pairs, prec, seed_base, sample_arg):
     for s in depths:
         sample = sample_arg or (pairs if s <= 400 else min(pairs, 2000))
         ens = fp.Ensemble(fp.LOCAL_RANDOM, n, s)
-        off = 2 * s * 32 * 4  # bonds follow the complex64 gates of U and V
-        peaks = []
-        for first in range(0, sample, 1000):
-            cnt = min(1000, sample - first)
-            g = fp.sample(ens, cnt, seed_base | (s << 32), first, fp.C64).view(cnt, -1)
-            bonds = g[:, off: off + 8 * s].cpu().numpy()
-            del g
-            for p in range(cnt):
-                b = np.frombuffer(bonds[p].tobytes(), dtype=np.int32).reshape(2, s)
-                peaks.append(fp.fp_plan_local_random_host(n, b[0], b[1])["peak_bits"])
-        pk = np.array(peaks)
+        pk, _ = planned_pairs(fp, np, n, s, seed_base, 0, sample)
         ws = fp.fp_workspace_bytes(ens, pairs, prec)
         budget = min(LR_MAX_BITS, int(math.floor(math.log2(ws / elem))))
         over = float(np.mean(pk > budget))
@@ -640,6 +669,37 @@ def main():
                                        if v["launches"]},
             }
 
+    # deeper step counts on small batches: the widest pairs set the time
+    # there, so every batch is planned on the host first and one whose sweeps
+    # would outlast the cap at a pessimistic rate is reported, not run
+    if args.deep_depths:
+        for s in [int(x) for x in args.deep_depths.split(",") if x]:
+            nb, npb = args.deep_batches, args.deep_pairs
+            pk, macs = planned_pairs(fp, np, args.n, s, seed_base, 0, nb * npb)
+            tflop = [8.0 * float(macs[i * npb:(i + 1) * npb].sum()) / 1e12 for i in range(nb)]
+            est = [t / DEEP_PLAN_TFLOPS for t in tflop]
+            entry = {"pairs_per_batch": npb, "batches": nb, "batches_in_flight": 1, "widest_bits": int(pk.max()),
+                     "planned_tflop_per_batch": tflop, "planned_s_per_batch": est}
+            if max(est) > args.deep_cap_s:
+                entry["status"] = (f"not timed: a batch plans {max(tflop):.3g} TFLOP of sweeps, over "
+                                   f"{args.deep_cap_s:g} s at {DEEP_PLAN_TFLOPS:g} TFLOP/s")
+                progress(f"S={s}: {entry['status']}")
+            else:
+                torch.cuda.empty_cache()
+                r = run_workload(fp, torch, args.n, s, npb, prec, nb, 0, seed_base, in_flight=1, pipeline=False,
+                                 say_batches=True)
+                flops = sum(r["prof"][c]["flops"] for c in SWEEP_CLASSES)
+                kms = sum(r["prof"][c]["ms"] for c in SWEEP_CLASSES)
+                entry.update({
+                    "status": "measured (one run, with events)",
+                    "contractions_per_s": npb * nb / r["wall_s"],
+                    "sweep_tflops": flops / (kms * 1e-3) / 1e12 if kms else 0.0,
+                    "F": r["F"], "SE": r["SE"], "F_per_batch": r["F_batches"],
+                    "all_finite": bool(all(math.isfinite(x) for fb in r["F_batches"] for x in fb)),
+                    "kernel_ms_per_step": {k: v["ms"] / nb for k, v in r["prof"].items() if v["launches"]},
+                })
+            per_depth[str(s)] = entry
+
     # register widths per depth, and which depths a batch fits: contractions/s
     # only where measured above, every other depth named with what it needs
     feas = {}
@@ -647,7 +707,7 @@ def main():
         feas = feasibility(fp, np, args.n, [int(x) for x in args.feasibility.split(",") if x], args.pairs, prec,
                            seed_base, args.feasibility_pairs)
         for k, v in feas.items():
-            if k in per_depth:
+            if k in per_depth and "contractions_per_s" in per_depth[k]:
                 v["contractions_per_s"] = per_depth[k]["contractions_per_s"]
                 v["status"] = "measured" if v["over_budget_frac"] == 0 else v["status"]
                 per_depth[k].update({q: v[q] for q in ("median_bits", "p99_bits", "max_bits")})
@@ -722,7 +782,8 @@ def main():
     out["roofline"] = {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
                                                 "kernel_ms_per_launch")}
     out["F_k"] = [float(f"{x:.6g}") for x in head["F"]]
-    out["per_S_contractions_per_s"] = {k: float(f"{v['contractions_per_s']:.4g}") for k, v in per_depth.items()}
+    out["per_S_contractions_per_s"] = {k: float(f"{v['contractions_per_s']:.4g}") for k, v in per_depth.items()
+                                       if "contractions_per_s" in v}
     if cv_res:
         out["control_variate"] = {k: (float(f"{cv_res[k]:.4g}") if isinstance(cv_res[k], float) else cv_res[k])
                                   for k in ("workload", "time_to_1pct_plain_s", "time_to_1pct_cv_s", "rho_holdout",

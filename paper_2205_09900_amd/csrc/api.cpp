@@ -258,7 +258,7 @@ static int64_t lr_fixed_bytes(int64_t num_pairs, const LrLayout& l) {
 constexpr int LR_SMALL_BITS = 10;  // wave per pair
 constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at most
 constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
-constexpr int LR_HELPERS = 64;      // workgroups that only help, at most
+constexpr int LR_HELPERS = 256;     // workgroups that only help, at most (one per compute unit)
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 // HBM-slot sweep with tiled GATE runs when a batch's widest register has
 // more than 2^LR_TILED_BITS entries.  Local random columns interleave BELL

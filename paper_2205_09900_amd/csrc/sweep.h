@@ -123,6 +123,7 @@ struct HelpRec {
   unsigned int done;           // chunks finished
   int type, b, p, q, track, chunk_bits, pad;
   unsigned long long src, dst;  // device addresses of the boundary before and after the op
+  unsigned long long base;      // first item of the task (chunk c covers base + c * 2^chunk_bits ...)
   unsigned long long mat[32];   // realigned GATE matrix, pending scale applied (bits of doubles)
 };
 constexpr int HELP_MAX = 32;  // records per launch

@@ -409,6 +409,21 @@ __device__ __forceinline__ void trace_op(const Cplx<Real>* src, Cplx<Real>* dst,
   trace_rounds<Real, NT, U, INPLACE, I>(src, dst, nout, p, q, lane, track, lmax);
 }
 
+// TRACE outputs base .. base + nout - 1 (nout a power of two) in place with
+// no barrier between reads and writes: for ranges where no output lands on
+// an input of another output of the range (the rounds of a shared TRACE).
+template <typename Real, int NT, int U, typename I>
+__device__ __forceinline__ void trace_range(Cplx<Real>* B, I nout, int p, int q, int lane, bool track, Real& lmax,
+                                            I base) {
+  if constexpr (U > 1) {
+    if (nout < NT * U) {
+      trace_range<Real, NT, U / 2, I>(B, nout, p, q, lane, track, lmax, base);
+      return;
+    }
+  }
+  trace_rounds<Real, NT, U, false, I>(B, B, nout, p, q, lane, track, lmax, base);
+}
+
 // ---- work sharing among workgroups (widest pairs) ----
 // Publication follows release/acquire at device scope: the owner fences its
 // boundary writes and the record before it opens a task, a helper fences
@@ -417,7 +432,7 @@ __device__ __forceinline__ void trace_op(const Cplx<Real>* src, Cplx<Real>* dst,
 // wait is bounded: an owner waits only for chunks that running helpers hold,
 // and helpers leave once every pair with a record has finished.
 constexpr int HELP_WAIT_POLLS = 1 << 20;  // owner: polls for its helpers' chunks (each sleeps; about a second)
-constexpr int HELP_IDLE_POLLS = 1 << 21;  // helper: polls that found no open task (a few seconds)
+constexpr int HELP_IDLE_POLLS = 1 << 21;  // helper: polls in a row that found no open task (a few seconds)
 
 __device__ __forceinline__ unsigned long long claim_word(unsigned seq, unsigned nch) {
   return ((unsigned long long)seq << 40) | ((unsigned long long)nch << 20);
@@ -460,13 +475,16 @@ __device__ __forceinline__ bool pairs_exhausted(const unsigned long long* counte
 
 // The owner's side of a shared op, called by every lane of its workgroup.
 // GATE: (Rr, Ri) is the scaled matrix in registers, `mat` the unscaled one in
-// LDS and sc the scale exponent removed from it.  Returns false if the
-// helpers' chunks did not all finish within the wait bound.
+// LDS and sc the scale exponent removed from it.  The task covers items
+// base .. base + 2^ibits - 1 (ibits < 0: all of the op's items, from 0;
+// ibits >= 12 otherwise).  Returns false if the helpers' chunks did not all
+// finish within the wait bound.
 template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, int q, bool track,
                            const Real (&Rr)[16], const Real (&Ri)[16], const Cplx<Real>* mat, int sc,
-                           Cplx<Real>* src, Cplx<Real>* dst, int lane, unsigned long long* sh, Real& lmax) {
-  const int cbits = type == OP_BELL ? b : b - 2;  // log2 of the op's items
+                           Cplx<Real>* src, Cplx<Real>* dst, int lane, unsigned long long* sh, Real& lmax,
+                           I base = 0, int ibits = -1) {
+  const int cbits = ibits >= 0 ? ibits : type == OP_BELL ? b : b - 2;  // log2 of the task's items
   int chb = cbits - 8;                            // at most 256 chunks of 2^12 .. 2^15 items,
   chb = chb < 12 ? 12 : chb > 15 ? 15 : chb;      // more for the widest registers
   if (cbits - chb > 19) chb = cbits - 19;         // (the claim word counts up to 2^20 chunks)
@@ -487,6 +505,7 @@ __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, 
     rec->chunk_bits = chb;
     rec->src = (unsigned long long)src;
     rec->dst = (unsigned long long)dst;
+    rec->base = (unsigned long long)base;
     rec->maxbits = 0;
     rec->done = 0;
   }
@@ -500,7 +519,8 @@ __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, 
     const unsigned c = claim_next(sh[0]);
     __syncthreads();
     if (c >= nch) break;
-    shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, (I)c << chb, (I)1 << chb, lane, lmax);
+    shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, base + ((I)c << chb), (I)1 << chb, lane,
+                                      lmax);
     ++mine;
   }
   if (lane == 0) {
@@ -529,6 +549,7 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
   const bool track = load_agent(&rec->track) != 0;
   Cplx<Real>* src = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->src));
   Cplx<Real>* dst = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->dst));
+  const I base = (I)load_agent(&rec->base);
   __syncthreads();
   Real Rr[16], Ri[16];
 #pragma unroll
@@ -537,8 +558,8 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
     Ri[k] = hmat[2 * k + 1];
   }
   Real lmax = 0;
-  shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, (I)claim_next(w) << chb, (I)1 << chb,
-                                    lane, lmax);
+  shared_chunk<Real, NT, U, BF3, I>(type, b, p, q, track, Rr, Ri, src, dst, base + ((I)claim_next(w) << chb),
+                                    (I)1 << chb, lane, lmax);
   if (track) {
     const Real m = group_max<Real, NT>(lmax, red);
     if (lane == 0) atomicMax(&rec->maxbits, (unsigned long long)__double_as_longlong((double)m));
@@ -678,6 +699,27 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
           Cplx<Real>* t = H;
           H = H2;
           H2 = t;
+        } else if (b - 2 > LB && share(b)) {
+          // In place, in rounds of outputs: [0, 2^(p+1)), then [2^k, 2^(k+1))
+          // for k = p+1 .. b-3.  Output j lands on entry j; the inputs of
+          // output j are entries i0(j) and i0(j) + 2^p + 2^q, both >= j.  An
+          // entry y of round k that some other output reads belongs to output
+          // y with bits p and q removed, which is below 2^k (an earlier round,
+          // already done); below 2^(p+1) such entries are either the output's
+          // own first input (j < 2^p) or read by no one.  So the outputs of a
+          // round are independent and the rounds run one after another.
+          const int nb = b - 2;
+          const int k0 = p + 1 < nb ? p + 1 : nb;
+          for (int k = k0 - 1; k < nb; ++k) {
+            const I rb = k < k0 ? (I)0 : (I)1 << k;  // the round's first output
+            const int rbits = k < k0 ? k0 : k;       // log2 of its outputs
+            if (rbits >= 16 && share(b))
+              failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_TRACE, b, p, q, track, Rr0, Ri0, mats_s, 0, H,
+                                                         H, lane, sh, lmax, rb, rbits);
+            else
+              trace_range<Real, NT, U, I>(H, (I)1 << rbits, p, q, lane, track, lmax, rb);
+            __syncthreads();
+          }
         } else if (b - 2 > LB) {
           trace_op<Real, NT, U, true, I>(H, H, b, p, q, lane, track, lmax);
         } else {
@@ -844,6 +886,7 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
       __builtin_amdgcn_s_sleep(8);
       continue;
     }
+    idle = 0;  // the bound is on polls in a row without a task
     help_chunk<Real, NT, U, BF3, I>(h.recs + (flag - 1), w, lane, red, hmat);
   }
 }
@@ -1073,8 +1116,8 @@ int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* 
 // the HBM slots (slot j as wide as the class's j-th widest pair, widths
 // clipped to 2^SLOT_BITS entries; as many owners as the pool holds, up to
 // max_owners; second slots for the first HELP_MAX when that keeps at least
-// half of the owners; helpers-only workgroups where the pool, not the pairs,
-// leaves compute units free).  It also clears the chunk's HBM counter and
+// half of the owners; helpers-only workgroups on the compute units the owners
+// leave free, when the class has pairs that share ops).  It also clears the chunk's HBM counter and
 // work-sharing records.  Lane b holds width b; sums over widths are
 // wavefront reductions.
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
@@ -1193,7 +1236,7 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     h.wide_pairs = wide;
     h.help_bits = j.help_bits;
     int extra = 0;
-    if (h.recs != nullptr && owners < wmax) {
+    if (h.recs != nullptr) {  // the compute units the owners leave free help the widest pairs
       extra = j.num_cus - owners;
       extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
     }
