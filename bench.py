@@ -57,8 +57,8 @@ def parse():
     ap.add_argument("--per-depth", default="50,100,150,200,250,300",
                     help="comma list of step counts measured besides the headline ('' = none)")
     ap.add_argument("--deep-depths", default="350",
-                    help="comma list of step counts past --per-depth, timed on small batches one at a time "
-                         "('' = none)")
+                    help="comma list of step counts past --per-depth, timed on smaller batches one at a time "
+                         "('' = none; skipped too with --per-depth '')")
     ap.add_argument("--deep-pairs", type=int, default=1000, help="pairs per batch of --deep-depths")
     ap.add_argument("--deep-batches", type=int, default=2, help="batches timed per step count of --deep-depths")
     ap.add_argument("--deep-cap-s", type=float, default=60.0,
@@ -672,7 +672,7 @@ def main():
     # deeper step counts on small batches: the widest pairs set the time
     # there, so every batch is planned on the host first and one whose sweeps
     # would outlast the cap at a pessimistic rate is reported, not run
-    if args.deep_depths:
+    if args.deep_depths and args.per_depth:
         for s in [int(x) for x in args.deep_depths.split(",") if x]:
             nb, npb = args.deep_batches, args.deep_pairs
             pk, macs = planned_pairs(fp, np, args.n, s, seed_base, 0, nb * npb)
