@@ -259,6 +259,11 @@ constexpr int LR_SMALL_BITS = 10;  // wave per pair
 constexpr int LR_MAX_OWNERS = 512;  // owner workgroups of the HBM-slot sweep at most
 constexpr int LR_HELP_BITS = 18;    // owners with a task record share ops on registers from 2^18 entries
 constexpr int LR_HELPERS = 256;     // workgroups that only help, at most (one per compute unit)
+// helpers-only workgroups where the pairs, not the pool, limit the owners,
+// once a register has 2^LR_WIDE_HELP_BITS entries: a 2^34-entry pair alone
+// 80 s -> 2.5 s; at S = 100, where a rare pair reaches 2^18, they took
+// compute units from the LDS sweeps (0.39 -> 0.48 ms per wavefront sweep)
+constexpr int LR_WIDE_HELP_BITS = 24;
 constexpr int LR_MID_BITS = 12;    // 256 lanes per pair
 // HBM-slot sweep with tiled GATE runs when a batch's widest register has
 // more than 2^LR_TILED_BITS entries.  Local random columns interleave BELL
@@ -600,6 +605,7 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   sj.max_helpers = LR_HELPERS;
   sj.num_cus = device_cus();
   sj.help_bits = LR_HELP_BITS;
+  sj.wide_bits = LR_WIDE_HELP_BITS;
   sj.recs = (HelpRec*)help_area;
   sj.hbm_counter = hbm_counter;
   sj.dev = dev;

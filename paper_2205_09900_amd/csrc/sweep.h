@@ -121,9 +121,9 @@ struct HelpRec {
   unsigned long long claim;    // task number (bits 40..63), chunks (20..39), next unclaimed chunk (0..19)
   unsigned long long maxbits;  // largest |entry| the helpers wrote (bits of a non-negative double)
   unsigned int done;           // chunks finished
-  int type, b, p, q, track, chunk_bits, pad;
+  int type, b, p, q, track, chunk_bits;
+  int base_bits;                // first item of the task: 2^base_bits (-1: item 0)
   unsigned long long src, dst;  // device addresses of the boundary before and after the op
-  unsigned long long base;      // first item of the task (chunk c covers base + c * 2^chunk_bits ...)
   unsigned long long mat[32];   // realigned GATE matrix, pending scale applied (bits of doubles)
 };
 constexpr int HELP_MAX = 32;  // records per launch
@@ -163,6 +163,8 @@ struct LrSetupJob {
   int elem_shift;                  // log2 of the bytes per complex entry
   int lds_bits;                    // pairs up to 2^lds_bits entries never use their HBM slot
   int max_owners, max_helpers, num_cus, help_bits;
+  int wide_bits;                   // helpers-only workgroups also where the pairs limit the owners, once
+                                   // the widest register has 2^wide_bits entries (>= help_bits)
   HelpRec* recs;                   // the chunk's work-sharing area (HELP_AREA_BYTES, cleared here)
   unsigned long long* hbm_counter; // the chunk's HBM claim word (cleared here)
   LrDev* dev;

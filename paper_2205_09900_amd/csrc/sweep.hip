@@ -476,14 +476,15 @@ __device__ __forceinline__ bool pairs_exhausted(const unsigned long long* counte
 // The owner's side of a shared op, called by every lane of its workgroup.
 // GATE: (Rr, Ri) is the scaled matrix in registers, `mat` the unscaled one in
 // LDS and sc the scale exponent removed from it.  The task covers items
-// base .. base + 2^ibits - 1 (ibits < 0: all of the op's items, from 0;
-// ibits >= 12 otherwise).  Returns false if the helpers' chunks did not all
-// finish within the wait bound.
+// base .. base + 2^ibits - 1 with base = 2^base_bits (0 for base_bits < 0);
+// ibits < 0: all of the op's items, from 0; ibits >= 12 otherwise.  Returns
+// false if the helpers' chunks did not all finish within the wait bound.
 template <typename Real, int NT, int U, bool BF3, typename I>
 __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, int q, bool track,
                            const Real (&Rr)[16], const Real (&Ri)[16], const Cplx<Real>* mat, int sc,
                            Cplx<Real>* src, Cplx<Real>* dst, int lane, unsigned long long* sh, Real& lmax,
-                           I base = 0, int ibits = -1) {
+                           int base_bits = -1, int ibits = -1) {
+  const I base = base_bits < 0 ? (I)0 : (I)1 << base_bits;
   const int cbits = ibits >= 0 ? ibits : type == OP_BELL ? b : b - 2;  // log2 of the task's items
   int chb = cbits - 8;                            // at most 256 chunks of 2^12 .. 2^15 items,
   chb = chb < 12 ? 12 : chb > 15 ? 15 : chb;      // more for the widest registers
@@ -505,7 +506,7 @@ __device__ bool run_shared(HelpRec* rec, unsigned& seq, int type, int b, int p, 
     rec->chunk_bits = chb;
     rec->src = (unsigned long long)src;
     rec->dst = (unsigned long long)dst;
-    rec->base = (unsigned long long)base;
+    rec->base_bits = base_bits;
     rec->maxbits = 0;
     rec->done = 0;
   }
@@ -549,7 +550,8 @@ __device__ void help_chunk(HelpRec* rec, unsigned long long w, int lane, Real* r
   const bool track = load_agent(&rec->track) != 0;
   Cplx<Real>* src = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->src));
   Cplx<Real>* dst = reinterpret_cast<Cplx<Real>*>(load_agent(&rec->dst));
-  const I base = (I)load_agent(&rec->base);
+  const int base_bits = load_agent(&rec->base_bits);
+  const I base = base_bits < 0 ? (I)0 : (I)1 << base_bits;
   __syncthreads();
   Real Rr[16], Ri[16];
 #pragma unroll
@@ -711,13 +713,14 @@ __device__ __forceinline__ void run_program_big(Cplx<Real>* L, Cplx<Real>* H, Cp
           const int nb = b - 2;
           const int k0 = p + 1 < nb ? p + 1 : nb;
           for (int k = k0 - 1; k < nb; ++k) {
-            const I rb = k < k0 ? (I)0 : (I)1 << k;  // the round's first output
-            const int rbits = k < k0 ? k0 : k;       // log2 of its outputs
+            const int rbase = k < k0 ? -1 : k;  // the round's first output: 2^rbase (0 for -1)
+            const int rbits = k < k0 ? k0 : k;  // log2 of its outputs
             if (rbits >= 16 && share(b))
               failed |= !run_shared<Real, NT, U, BF3, I>(rec, seq, OP_TRACE, b, p, q, track, Rr0, Ri0, mats_s, 0, H,
-                                                         H, lane, sh, lmax, rb, rbits);
+                                                         H, lane, sh, lmax, rbase, rbits);
             else
-              trace_range<Real, NT, U, I>(H, (I)1 << rbits, p, q, lane, track, lmax, rb);
+              trace_range<Real, NT, U, I>(H, (I)1 << rbits, p, q, lane, track, lmax,
+                                          rbase < 0 ? (I)0 : (I)1 << rbase);
             __syncthreads();
           }
         } else if (b - 2 > LB) {
@@ -1117,7 +1120,7 @@ int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* 
 // clipped to 2^SLOT_BITS entries; as many owners as the pool holds, up to
 // max_owners; second slots for the first HELP_MAX when that keeps at least
 // half of the owners; helpers-only workgroups on the compute units the owners
-// leave free, when the class has pairs that share ops).  It also clears the chunk's HBM counter and
+// leave free, where the pool limits the owners or a register is very wide).  It also clears the chunk's HBM counter and
 // work-sharing records.  Lane b holds width b; sums over widths are
 // wavefront reductions.
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
@@ -1220,6 +1223,7 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
   const long long total = __shfl(suf, 0, 64), atotal = __shfl(asuf, 0, 64);
   const long long wide = count > 0 ? pos(j.help_bits) : 0;
   const long long beyond = pos(SLOT_BITS + 1);  // pairs wider than the widest slot
+  const long long widest = pos(j.wide_bits);    // pairs of 2^wide_bits entries or more
   SlotArgs& sl = d->sl;
   if (lane <= SLOT_TOP) {
     sl.ge[lane] = lane < SLOT_TOP ? g0 : 0;
@@ -1235,8 +1239,13 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     h.finished = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(j.recs) + HELP_MAX * sizeof(HelpRec));
     h.wide_pairs = wide;
     h.help_bits = j.help_bits;
+    // the compute units the owners leave free help the widest pairs: where
+    // the pool limits the owners, or where a register has 2^wide_bits
+    // entries or more (narrower shared registers are left to the owners'
+    // quarter that helps: helpers-only workgroups would hold compute units
+    // the batch's LDS sweeps run on)
     int extra = 0;
-    if (h.recs != nullptr) {  // the compute units the owners leave free help the widest pairs
+    if (h.recs != nullptr && (owners < wmax || widest > 0)) {
       extra = j.num_cus - owners;
       extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
     }
@@ -1250,7 +1259,8 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
 }
 
 int launch_lr_setup(const LrSetupJob& j, hipStream_t s) {
-  if (j.help_bits < 16 || j.max_owners < 1 || j.elem_shift < 3 || !j.recs || !j.hbm_counter || j.lds_bits < j.cap_bits)
+  if (j.help_bits < 16 || j.wide_bits < j.help_bits || j.max_owners < 1 || j.elem_shift < 3 || !j.recs ||
+      !j.hbm_counter || j.lds_bits < j.cap_bits)
     return set_error(FP_EINVAL, "bad set-up arguments");
   hipLaunchKernelGGL(lr_setup_kernel, dim3(1), dim3(64), 0, s, j);
   return check_launch("lr_setup");
