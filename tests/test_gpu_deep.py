@@ -108,3 +108,36 @@ def test_full_batch_at_300_steps(fp):
     print(f"S=300: F = {f}, SE = {se}")
     del g, ws, out
     torch.cuda.empty_cache()
+
+
+def test_shared_trace_in_place(fp):
+    """A pair alone in a workspace with room for one slot of its width: no
+    second slot fits, so its shared TRACEs run in place, in rounds of outputs,
+    with helpers on every free compute unit (its register reaches 2^30
+    entries).  U = V gives 2^n; V differing from U in one gate gives the
+    closed form."""
+    prec = 1
+    ens = (1, N, S)
+    cand = 400
+    g = fp.sample(ens, cand, synth.workload_seed(82, 1), 0, prec).view(cand, -1)
+    pk = [fp.fp_plan_local_random_host(N, b[0], b[0])["peak_bits"] for b in _bonds(fp, ens, g, prec, cand)]
+    pick = [i for i, p in enumerate(pk) if p == 30][:1]
+    assert pick, sorted(pk)[-8:]
+    rb, k = 4, 101
+    gb, half = 32 * rb, S * 32 * rb
+    u = g[pick].clone()
+    u[:, half:2 * half] = u[:, :half]
+    u[:, 2 * half + 4 * S: 2 * half + 8 * S] = u[:, 2 * half: 2 * half + 4 * S]
+    d = u.clone()
+    d[:, half + k * gb: half + (k + 1) * gb] = g[pick, half + k * gb: half + (k + 1) * gb]
+    ws = fp.workspace(ens, 1, prec)
+    both = torch.cat([u, d])
+    tr = [fp.contract(ens, both[i].reshape(-1), 1, prec, ws).cpu().numpy()[0] for i in range(2)]
+    assert abs(tr[0] - 2.0 ** N) <= TOL[prec] * 2.0 ** N, tr[0]
+    a = d.cpu().numpy()
+    gu = np.frombuffer(a[0, k * gb:(k + 1) * gb].tobytes(), np.float32).astype(np.float64).reshape(4, 4, 2)
+    gv = np.frombuffer(a[0, half + k * gb: half + (k + 1) * gb].tobytes(), np.float32).astype(np.float64).reshape(4, 4, 2)
+    want = closed_forms.one_gate_difference(N, gu[..., 0] + 1j * gu[..., 1], gv[..., 0] + 1j * gv[..., 1])
+    assert abs(tr[1] - want) <= 1e-5 * abs(want), (tr[1], want)
+    del g, u, d, both, ws
+    torch.cuda.empty_cache()
