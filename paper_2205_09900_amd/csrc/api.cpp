@@ -237,7 +237,7 @@ static LrLayout lr_layout(int n, int G, int precision) {
 // per-pair plans, the work-sharing records and the HBM slots.  Chunk header:
 //   +0   int max_peak, num_large, num_failed
 //   +16  double class MACs[5]
-//   +64  uint64 counter of the HBM launch
+//   +64  uint64 counters of the HBM launches (one per phase)
 //   +128 int hist[PLAN_HIST]   pairs per peak width
 //   +384 int cursor[PLAN_HIST] fill counters of the ordering pass
 //   +1024 LrDev  launch set-up written on the device
@@ -685,8 +685,9 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
   // give the same results)
   bool tiled_hbm = lr_predicted_bits_raw(n, G) > LR_TILED_BITS;
   // flops < 0: the class's MAC count is read from the device afterwards
+  // phase: the HBM class's launch (k = 4 only)
   auto launch_class = [&](int k, int ai, const long long* range, int64_t count, int64_t grid_pairs,
-                          double flops) -> int {
+                          double flops, int phase = 0) -> int {
     hipStream_t sx;
     int r = side(ai, &sx);
     if (r) return r;
@@ -707,7 +708,8 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     }
     profile_launch_begin(cls[k].kclass, sx);
     if (k == 4)
-      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter, dev, (int)grid_pairs, sx, wide_hbm, tiled_hbm);
+      r = launch_sweep_hbm_dev(ax, c.precision, hbm_counter + phase, dev, phase, (int)grid_pairs, sx, wide_hbm,
+                               tiled_hbm);
     else  // up to 2^10 entries: one wavefront per pair; larger: the LDS sweep
       r = cls[k].hi <= 10 ? launch_sweep_wave(ax, c.precision, cls[k].hi, sx)
                           : launch_sweep_lds(ax, c.precision, cls[k].tile, sx);
@@ -743,8 +745,6 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     if (!rc) rc = check_hip(hipStreamSynchronize(s), "sync(plan)");
     if (rc) return rc;
     lr_hint_set(c.key, h.d, np);
-    wide_hbm = h.d.max_bits > 31;
-    tiled_hbm = h.d.max_bits > LR_TILED_BITS;
     for (int k = 0; k < 5; ++k) dev_first[k] = h.d.range[k][0];
     int slot_of[5] = {-1, -1, -1, -1, -1};  // -1: s; 0..2: side streams
     int act[5], na = 0;
@@ -764,7 +764,17 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     for (int k = 4; k >= 1; --k) {
       const int64_t count = h.d.range[k][1];
       if (count <= 0) continue;
-      rc = launch_class(k, slot_of[k], nullptr, count, k == 4 ? h.d.hbm_workgroups : 0, 8.0 * h.macs[k]);
+      if (k == 4) {  // its launches in order on one stream, each with the whole slot pool
+        for (int ph = 0; ph < HBM_PHASES && !rc; ++ph) {
+          if (h.d.ph[ph].count <= 0) continue;
+          wide_hbm = h.d.ph[ph].max_bits > 31;
+          tiled_hbm = h.d.ph[ph].max_bits > LR_TILED_BITS;
+          rc = launch_class(4, slot_of[4], nullptr, count, h.d.ph[ph].workgroups, ph == 0 ? 8.0 * h.macs[4] : 0.0,
+                            ph);
+        }
+      } else {
+        rc = launch_class(k, slot_of[k], nullptr, count, 0, 8.0 * h.macs[k]);
+      }
       if (rc) return rc;
     }
     return FP_OK;
@@ -781,7 +791,11 @@ static int lr_chunk(LrCtx& c, int chunk, int64_t p0, int64_t np, hipStream_t s) 
     const int want = hint.hbm_workgroups + hint.hbm_workgroups / 8 + 4;
     grid = want < grid ? want : grid;
   }
-  rc = launch_class(4, -1, dev->range[4], 0, grid, -1.0);
+  // the HBM class's launches: the second (narrower pairs, when the set-up
+  // split the class) never needs 64-bit indices
+  rc = launch_class(4, -1, dev->range[4], 0, grid, -1.0, 0);
+  wide_hbm = false;
+  if (!rc) rc = launch_class(4, -1, dev->range[4], 0, grid, 0.0, 1);
   for (int k = 3; k >= 1 && !rc; --k) {
     if (cls[k].hi <= cls[k].lo) continue;
     const int64_t gp = hinted ? (int64_t)(hint.frac[k] * 1.05 * (double)np) + 2 : 0;

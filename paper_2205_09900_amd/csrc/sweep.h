@@ -144,14 +144,24 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
 // lr_setup_kernel from the planner's statistics and read by the ordering pass
 // and the sweeps, so that the host enqueues the whole chunk without waiting.
 // Classes k = 0..4 as the planner's class MACs: registers up to tiny, small,
-// mid and cap bits, then HBM slots.
+// mid and cap bits, then HBM slots.  The HBM class runs as up to two launches
+// on one stream, each with the whole slot pool: the pairs wider than a
+// compute unit's share of the pool first (their slots would leave few owners
+// for the rest), then the others.
+struct HbmPhase {
+  SlotArgs sl;             // slots (owners 0: the phase's pairs get NaN)
+  HelpArgs help;           // work sharing (recs null: none)
+  long long first, count;  // positions in the class's range of the order
+  int workgroups;          // owners plus helpers-only workgroups (0: nothing to do)
+  int max_bits;            // widest register of the phase's pairs (log2 entries)
+};
+constexpr int HBM_PHASES = 2;
 struct LrDev {
   int32_t first[PLAN_HIST];     // ordering pass: first position of each width
   long long range[5][2];        // class k: first position in the order and count
   unsigned long long claim[5];  // class k: pair counter of its sweep (zero after set-up)
-  SlotArgs sl;                  // HBM slots (owners 0: the class's pairs get NaN)
-  HelpArgs help;                // work sharing (recs null: none)
-  int hbm_workgroups;           // owners plus helpers-only workgroups of the HBM launch
+  HbmPhase ph[HBM_PHASES];      // the HBM class's launches, in order
+  int hbm_workgroups;           // the larger launch's workgroups
   int max_bits;                 // widest register of the chunk's pairs (log2 entries)
   int status;                   // bit 0: a pair wider than 2^SLOT_BITS entries; bit 1: a pair without room in the pool
 };
@@ -166,16 +176,17 @@ struct LrSetupJob {
   int wide_bits;                   // helpers-only workgroups also where the pairs limit the owners, once
                                    // the widest register has 2^wide_bits entries (>= help_bits)
   HelpRec* recs;                   // the chunk's work-sharing area (HELP_AREA_BYTES, cleared here)
-  unsigned long long* hbm_counter; // the chunk's HBM claim word (cleared here)
+  unsigned long long* hbm_counter; // the chunk's HBM claim words, one per phase (cleared here)
   LrDev* dev;
 };
 int launch_lr_setup(const LrSetupJob& j, hipStream_t s);
-// HBM-slot sweep of a local random class set up on the device (launch `grid`
-// workgroups; those beyond dev->hbm_workgroups return at once).
-// wide: 64-bit entry indices; tiled: some register may leave LDS (runs of
-// GATEs on it then go tile by tile; either choice gives the same results).
-int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s, bool wide, bool tiled);
+// HBM-slot sweep of phase `phase` of a local random class set up on the
+// device (launch `grid` workgroups; those beyond the phase's workgroups
+// return at once).  counter: the phase's claim word.  wide: 64-bit entry
+// indices; tiled: some register may leave LDS (runs of GATEs on it then go
+// tile by tile; either choice gives the same results).
+int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int phase,
+                         int grid, hipStream_t s, bool wide, bool tiled);
 // Zero n 32-bit words (a kernel, so that stream capture records no memset node).
 int launch_zero_words(void* p, int64_t n, hipStream_t s);
 // Workgroups of a kernel resident per compute unit (occupancy query, no device work),

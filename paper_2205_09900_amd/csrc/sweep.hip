@@ -766,7 +766,7 @@ __device__ __forceinline__ int slot_bits_of(const SlotArgs& sl, int j) {
 // counts in `finished` whatever its path, and helpers leave once all have.
 template <typename Real, int NT, bool BF3, typename I, bool TILED>
 __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned long long* counter, SlotArgs sl_arg,
-                                                       HelpArgs h_arg, const LrDev* dev) {
+                                                       HelpArgs h_arg, const LrDev* dev, int phase) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Real red[16];
   __shared__ unsigned long long next;
@@ -776,12 +776,13 @@ __global__ void __launch_bounds__(NT) sweep_hbm_kernel(SweepArgs a, unsigned lon
   __shared__ Real hmat[32];
   constexpr int U = hbm_u<Real, BF3>();
   const int lane = threadIdx.x;
-  // launch arguments, or the set-up the device wrote for this class
-  const SlotArgs& sl = dev != nullptr ? dev->sl : sl_arg;
-  const HelpArgs& h = dev != nullptr ? dev->help : h_arg;
-  const long long np = dev != nullptr ? dev->range[4][1] : a.num_pairs;
-  const int32_t* order = dev != nullptr ? a.order + dev->range[4][0] : a.order;
-  const int wgs = dev != nullptr ? dev->hbm_workgroups : (int)gridDim.x;
+  // launch arguments, or the set-up the device wrote for this phase of the class
+  const HbmPhase* ph = dev != nullptr ? &dev->ph[phase] : nullptr;
+  const SlotArgs& sl = ph != nullptr ? ph->sl : sl_arg;
+  const HelpArgs& h = ph != nullptr ? ph->help : h_arg;
+  const long long np = ph != nullptr ? ph->count : a.num_pairs;
+  const int32_t* order = ph != nullptr ? a.order + dev->range[4][0] + ph->first : a.order;
+  const int wgs = ph != nullptr ? ph->workgroups : (int)gridDim.x;
   const int owners = sl.owners;
   if ((int)blockIdx.x >= wgs) return;
   if (owners == 0) {  // no slot fits the pool: every pair of the class gets NaN
@@ -1022,13 +1023,13 @@ int launch_sweep_lds(const SweepArgs& a, int precision, int tile, hipStream_t s)
 
 template <typename Real, bool BF3, typename I, bool TILED>
 static void launch_hbm_t(const SweepArgs& a, unsigned long long* counter, const SlotArgs& sl, int grid,
-                         const HelpArgs& h, const LrDev* dev, hipStream_t s) {
+                         const HelpArgs& h, const LrDev* dev, int phase, hipStream_t s) {
   const auto k = sweep_hbm_kernel<Real, HBM_NT, BF3, I, TILED>;
   const size_t smem = hbm_lds_bytes<Real>();
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)smem);
   if (e != hipSuccess) (void)hipGetLastError();  // the limit may already allow it
-  hipLaunchKernelGGL(k, dim3(grid), dim3(HBM_NT), smem, s, a, counter, sl, h, dev);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(HBM_NT), smem, s, a, counter, sl, h, dev, phase);
 }
 
 void make_slot_args(SlotArgs* sl, unsigned char* base, const int* width, int count, bool with_alt, int elem) {
@@ -1068,13 +1069,13 @@ int slot_bits_host(const SlotArgs& sl) {
 
 template <typename I, bool TILED>
 static void launch_hbm_prec(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl,
-                            int grid, const HelpArgs& h, const LrDev* dev, hipStream_t s) {
+                            int grid, const HelpArgs& h, const LrDev* dev, int phase, hipStream_t s) {
   if (precision == FP_C128)
-    launch_hbm_t<double, false, I, TILED>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<double, false, I, TILED>(a, counter, sl, grid, h, dev, phase, s);
   else if (a.bf3)
-    launch_hbm_t<float, true, I, TILED>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<float, true, I, TILED>(a, counter, sl, grid, h, dev, phase, s);
   else
-    launch_hbm_t<float, false, I, TILED>(a, counter, sl, grid, h, dev, s);
+    launch_hbm_t<float, false, I, TILED>(a, counter, sl, grid, h, dev, phase, s);
 }
 
 int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* counter, const SlotArgs& sl, int grid,
@@ -1091,36 +1092,38 @@ int launch_sweep_hbm(const SweepArgs& a, int precision, unsigned long long* coun
   if (grid < sl.owners || (grid > sl.owners && h.recs == nullptr)) return set_error(FP_EINVAL, "bad HBM grid");
   const int top = slot_bits_host(sl);
   if (top > 31)
-    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, nullptr, s);
+    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, nullptr, 0, s);
   else if (top > (precision == FP_C128 ? hbm_lds_bits<double>() : hbm_lds_bits<float>()))
-    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, nullptr, s);
+    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, nullptr, 0, s);
   else
-    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, nullptr, s);
+    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, nullptr, 0, s);
   return check_launch("sweep_hbm");
 }
 
-int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int grid,
-                         hipStream_t s, bool wide, bool tiled) {
+int launch_sweep_hbm_dev(const SweepArgs& a, int precision, unsigned long long* counter, const LrDev* dev, int phase,
+                         int grid, hipStream_t s, bool wide, bool tiled) {
   if (grid <= 0) return FP_OK;
+  if (phase < 0 || phase >= HBM_PHASES) return set_error(FP_EINVAL, "bad HBM phase");
   SlotArgs sl;
   memset(&sl, 0, sizeof(sl));
   const HelpArgs h = {nullptr, nullptr, 0, 0};
   if (wide)
-    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int64_t, true>(a, precision, counter, sl, grid, h, dev, phase, s);
   else if (tiled)
-    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int, true>(a, precision, counter, sl, grid, h, dev, phase, s);
   else
-    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, dev, s);
+    launch_hbm_prec<int, false>(a, precision, counter, sl, grid, h, dev, phase, s);
   return check_launch("sweep_hbm");
 }
 
 // One wavefront derives a local random chunk's launches from the planner's
 // width histogram: the ordering pass's first positions, the class ranges, and
-// the HBM slots (slot j as wide as the class's j-th widest pair, widths
-// clipped to 2^SLOT_BITS entries; as many owners as the pool holds, up to
-// max_owners; second slots for the first HELP_MAX when that keeps at least
-// half of the owners; helpers-only workgroups on the compute units the owners
-// leave free, where the pool limits the owners or a register is very wide).  It also clears the chunk's HBM counter and
+// for each launch of the HBM class its slots (slot j as wide as the launch's
+// j-th widest pair, widths clipped to 2^SLOT_BITS entries; as many owners as
+// the pool holds, up to max_owners; second slots for the first HELP_MAX when
+// that keeps at least half of the owners; helpers-only workgroups on the
+// compute units the owners leave free, where the pool limits the owners or a
+// register is very wide).  It also clears the chunk's HBM counters and
 // work-sharing records.  Lane b holds width b; sums over widths are
 // wavefront reductions.
 __device__ __forceinline__ long long wave_sum_ll(long long v) {
@@ -1160,97 +1163,131 @@ __global__ void __launch_bounds__(64) lr_setup_kernel(LrSetupJob j) {
     d->range[lane][1] = rc[lane];
     d->claim[lane] = 0;
   }
-  // the chunk's HBM counter and work-sharing records start at zero
+  // the chunk's HBM counters and work-sharing records start at zero
   for (int i = lane; i < (int)(HELP_AREA_BYTES / 8); i += 64) reinterpret_cast<unsigned long long*>(j.recs)[i] = 0ull;
-  if (lane == 0) *j.hbm_counter = 0ull;
-  // HBM class: lane b <= SLOT_BITS holds ge_all[b], class pairs of clipped width >= b
-  const long long count = rc[4];
-  const int wmax = count < j.max_owners ? (int)count : j.max_owners;
-  const long long pa = pos(lane), pa1 = pos(lane + 1);
-  // slot widths: a pair's register width, 0 for a pair that stays in LDS
-  // (at most 2^lds_bits entries); ge_all[0] = count, ge_all[b] = pairs wider
-  // than LDS with width >= b otherwise
-  const long long wide_ge = pos(j.lds_bits + 1);
-  const long long ge = lane > SLOT_BITS ? 0 : lane == 0 ? count : lane <= j.lds_bits + 1 ? wide_ge : pa;
-  const long long ge1 = lane >= SLOT_BITS ? 0 : lane + 1 <= j.lds_bits + 1 ? wide_ge : pa1;
+  if (lane < HBM_PHASES) j.hbm_counter[lane] = 0ull;
   const long long pool_entries = j.pool_bytes > 0 ? j.pool_bytes >> j.elem_shift : 0;
-  // entries of w slots, plus second slots for the first HELP_MAX of them
-  // (slots of width 0 take none)
-  auto entries = [&](int w, bool alt) {
-    const long long na = alt ? (w < HELP_MAX ? w : HELP_MAX) : 0;
-    const long long g0 = ge < w ? ge : w, g1 = ge1 < w ? ge1 : w;
-    const long long a0 = g0 < na ? g0 : na, a1 = g1 < na ? g1 : na;
-    return wave_sum_ll(lane >= 1 && lane <= SLOT_BITS ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
-  };
-  auto largest = [&](bool alt) {
-    int l = 0, h = wmax;
-    while (l < h) {
-      const int m = (l + h + 1) / 2;
-      if (entries(m, alt) <= pool_entries) l = m;
-      else h = m - 1;
-    }
-    return l;
-  };
-  int owners = 0;
-  bool alt = false, none = false;
-  if (count > 0) {
-    const int w0 = largest(false);
-    const int w1 = largest(true);
-    alt = w1 >= 1 && 2 * w1 >= w0;
-    owners = alt ? w1 : w0;
-    if (owners == 0) {  // no room for the widest pair's slot: all slots of width 0, pairs
-      owners = wmax;    // that stay in LDS still run and the others get NaN
-      none = true;
-    }
+  // The class's pairs wider than a compute unit's share of the pool run in
+  // a launch of their own, before the others: slots as wide as theirs would
+  // leave few owners for the rest of the class.
+  int split = -1;
+  {
+    const long long share = j.num_cus > 0 ? pool_entries / j.num_cus : 0;
+    const int sb = share > 0 ? 63 - __clzll(share) : 0;
+    const long long above = pos(sb + 1);
+    if (sb > j.lds_bits && sb < PLAN_HIST - 1 && above > 0 && above < rc[4]) split = sb;
   }
-  // slot layout: ge, then offsets from the widest down (the sums above b, by a suffix scan)
-  const int g0 = none ? (lane == 0 ? owners : 0) : (int)(ge < owners ? ge : owners);
-  const int g1 = none ? 0 : (int)(ge1 < owners ? ge1 : owners);
-  const int nalt = alt ? (owners < HELP_MAX ? owners : HELP_MAX) : 0;
-  long long mine = lane >= 1 && lane <= SLOT_BITS ? (long long)(g0 - g1) << lane : 0;
-  long long amine =
-      lane >= 1 && lane <= SLOT_BITS ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
-  long long suf = mine, asuf = amine;  // inclusive sums over widths >= lane
+  int status = 0;
+  // phase k: the class's pairs of widths wlo .. whi (every lane calls it)
+  auto phase_setup = [&](int k, int wlo, int whi, long long first) {
+    // cnt(b): the phase's pairs of width >= b
+    auto cnt = [&](int b) -> long long { return b > whi ? 0ll : pos(b > wlo ? b : wlo) - pos(whi + 1); };
+    const long long count = whi >= wlo ? cnt(wlo) : 0;
+    const int wmax = count < j.max_owners ? (int)count : j.max_owners;
+    // slot widths: a pair's register width, 0 for a pair that stays in LDS
+    // (at most 2^lds_bits entries); lane b <= SLOT_BITS holds ge[b], pairs of
+    // clipped slot width >= b (ge[0] = count)
+    const long long wide_ge = cnt(j.lds_bits + 1);
+    const long long pa = cnt(lane), pa1 = cnt(lane + 1);
+    const long long ge = lane > SLOT_BITS ? 0 : lane == 0 ? count : lane <= j.lds_bits + 1 ? wide_ge : pa;
+    const long long ge1 = lane >= SLOT_BITS ? 0 : lane + 1 <= j.lds_bits + 1 ? wide_ge : pa1;
+    // entries of w slots, plus second slots for the first HELP_MAX of them
+    // (slots of width 0 take none)
+    auto entries = [&](int w, bool alt) {
+      const long long na = alt ? (w < HELP_MAX ? w : HELP_MAX) : 0;
+      const long long g0 = ge < w ? ge : w, g1 = ge1 < w ? ge1 : w;
+      const long long a0 = g0 < na ? g0 : na, a1 = g1 < na ? g1 : na;
+      return wave_sum_ll(lane >= 1 && lane <= SLOT_BITS ? ((g0 - g1) + (a0 - a1)) << lane : 0ll);
+    };
+    auto largest = [&](bool alt) {
+      int l = 0, h = wmax;
+      while (l < h) {
+        const int m = (l + h + 1) / 2;
+        if (entries(m, alt) <= pool_entries) l = m;
+        else h = m - 1;
+      }
+      return l;
+    };
+    int owners = 0;
+    bool alt = false, none = false;
+    if (count > 0) {
+      const int w0 = largest(false);
+      const int w1 = largest(true);
+      alt = w1 >= 1 && 2 * w1 >= w0;
+      owners = alt ? w1 : w0;
+      if (owners == 0) {  // no room for the widest pair's slot: all slots of width 0, pairs
+        owners = wmax;    // that stay in LDS still run and the others get NaN
+        none = true;
+      }
+    }
+    // slot layout: ge, then offsets from the widest down (the sums above b, by a suffix scan)
+    const int g0 = none ? (lane == 0 ? owners : 0) : (int)(ge < owners ? ge : owners);
+    const int g1 = none ? 0 : (int)(ge1 < owners ? ge1 : owners);
+    const int nalt = alt ? (owners < HELP_MAX ? owners : HELP_MAX) : 0;
+    long long mine = lane >= 1 && lane <= SLOT_BITS ? (long long)(g0 - g1) << lane : 0;
+    long long amine =
+        lane >= 1 && lane <= SLOT_BITS ? (long long)((g0 < nalt ? g0 : nalt) - (g1 < nalt ? g1 : nalt)) << lane : 0;
+    long long suf = mine, asuf = amine;  // inclusive sums over widths >= lane
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const long long t = __shfl_down(suf, off, 64), u = __shfl_down(asuf, off, 64);
-    if (lane + off < 64) {
-      suf += t;
-      asuf += u;
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long t = __shfl_down(suf, off, 64), u = __shfl_down(asuf, off, 64);
+      if (lane + off < 64) {
+        suf += t;
+        asuf += u;
+      }
     }
-  }
-  // cross-lane reads first, with every lane active
-  const long long total = __shfl(suf, 0, 64), atotal = __shfl(asuf, 0, 64);
-  const long long wide = count > 0 ? pos(j.help_bits) : 0;
-  const long long beyond = pos(SLOT_BITS + 1);  // pairs wider than the widest slot
-  const long long widest = pos(j.wide_bits);    // pairs of 2^wide_bits entries or more
-  SlotArgs& sl = d->sl;
-  if (lane <= SLOT_TOP) {
-    sl.ge[lane] = lane < SLOT_TOP ? g0 : 0;
-    sl.off[lane] = lane < SLOT_TOP ? suf - mine : total;  // entries of wider slots; [SLOT_TOP]: all
-    sl.alt_off[lane] = lane < SLOT_TOP ? asuf - amine : atotal;
+    // cross-lane reads first, with every lane active
+    const long long total = __shfl(suf, 0, 64), atotal = __shfl(asuf, 0, 64);
+    const long long wide = count > 0 ? cnt(j.help_bits) : 0;
+    const long long beyond = cnt(SLOT_BITS + 1);  // pairs wider than the widest slot
+    const long long widest = cnt(j.wide_bits);    // pairs of 2^wide_bits entries or more
+    const unsigned long long m = __ballot(lane >= wlo && lane <= whi && lane < PLAN_HIST && j.hist[lane] > 0);
+    HbmPhase& P = d->ph[k];
+    SlotArgs& sl = P.sl;
+    if (lane <= SLOT_TOP) {
+      sl.ge[lane] = lane < SLOT_TOP ? g0 : 0;
+      sl.off[lane] = lane < SLOT_TOP ? suf - mine : total;  // entries of wider slots; [SLOT_TOP]: all
+      sl.alt_off[lane] = lane < SLOT_TOP ? asuf - amine : atotal;
+    }
+    if (lane == 0) {
+      sl.owners = owners;
+      sl.base = j.pool;
+      sl.alt = nalt > 0 ? j.pool + (total << j.elem_shift) : nullptr;
+      HelpArgs& h = P.help;
+      h.recs = owners > 0 && wide > 0 && !none ? j.recs : nullptr;
+      h.finished = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(j.recs) +
+                                                   HELP_MAX * sizeof(HelpRec)) + k;
+      h.wide_pairs = wide;
+      h.help_bits = j.help_bits;
+      // the compute units the owners leave free help the widest pairs: where
+      // the pool limits the owners, or where a register has 2^wide_bits
+      // entries or more (narrower shared registers are left to the owners'
+      // quarter that helps: helpers-only workgroups would hold compute units
+      // the batch's LDS sweeps run on)
+      int extra = 0;
+      if (h.recs != nullptr && (owners < wmax || widest > 0)) {
+        extra = j.num_cus - owners;
+        extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
+      }
+      P.first = first;
+      P.count = count;
+      P.workgroups = owners == 0 ? (count > 0 ? 1 : 0) : owners + extra;
+      P.max_bits = m == 0 ? 0 : 63 - __clzll((long long)m);
+      status |= (beyond > 0 ? 1 : 0) | (none ? 2 : 0);
+    }
+    return count;
+  };
+  if (split >= 0) {
+    const long long c0 = phase_setup(0, split + 1, PLAN_HIST - 1, 0);
+    phase_setup(1, j.cap_bits + 1, split, c0);
+  } else {
+    phase_setup(0, j.cap_bits + 1, PLAN_HIST - 1, 0);
+    phase_setup(1, 1, 0, rc[4]);  // empty
   }
   if (lane == 0) {
-    sl.owners = owners;
-    sl.base = j.pool;
-    sl.alt = nalt > 0 ? j.pool + (total << j.elem_shift) : nullptr;
-    HelpArgs& h = d->help;
-    h.recs = owners > 0 && wide > 0 && !none ? j.recs : nullptr;
-    h.finished = reinterpret_cast<unsigned int*>(reinterpret_cast<unsigned char*>(j.recs) + HELP_MAX * sizeof(HelpRec));
-    h.wide_pairs = wide;
-    h.help_bits = j.help_bits;
-    // the compute units the owners leave free help the widest pairs: where
-    // the pool limits the owners, or where a register has 2^wide_bits
-    // entries or more (narrower shared registers are left to the owners'
-    // quarter that helps: helpers-only workgroups would hold compute units
-    // the batch's LDS sweeps run on)
-    int extra = 0;
-    if (h.recs != nullptr && (owners < wmax || widest > 0)) {
-      extra = j.num_cus - owners;
-      extra = extra < 0 ? 0 : extra > j.max_helpers ? j.max_helpers : extra;
-    }
-    d->hbm_workgroups = owners == 0 ? (count > 0 ? 1 : 0) : owners + extra;
-    d->status = (beyond > 0 ? 1 : 0) | (none ? 2 : 0);
+    const int w0 = d->ph[0].workgroups, w1 = d->ph[1].workgroups;
+    d->hbm_workgroups = w0 > w1 ? w0 : w1;
+    d->status = status;
   }
   {  // widest register: the highest width with pairs
     const unsigned long long m = __ballot(lane < PLAN_HIST && j.hist[lane] > 0);
