@@ -152,16 +152,27 @@ def read_setup(buf):
         _fields_ = [("recs", ctypes.c_uint64), ("finished", ctypes.c_uint64), ("wide", ctypes.c_int64),
                     ("help_bits", ctypes.c_int32)]
 
+    class Phase(ctypes.Structure):
+        _fields_ = [("sl", Slot), ("help", Help), ("first", ctypes.c_int64), ("count", ctypes.c_int64),
+                    ("workgroups", ctypes.c_int32), ("max_bits", ctypes.c_int32)]
+
     class Dev(ctypes.Structure):
         _fields_ = [("first", ctypes.c_int32 * 64), ("range", ctypes.c_int64 * 10), ("claim", ctypes.c_uint64 * 5),
-                    ("sl", Slot), ("help", Help), ("wgs", ctypes.c_int32), ("max_bits", ctypes.c_int32),
+                    ("ph", Phase * 2), ("wgs", ctypes.c_int32), ("max_bits", ctypes.c_int32),
                     ("status", ctypes.c_int32)]
 
+    assert ctypes.sizeof(Dev) <= len(buf)
     d = Dev.from_buffer_copy(bytes(buf[: ctypes.sizeof(Dev)]))
-    return dict(first=list(d.first), range=[(d.range[2 * k], d.range[2 * k + 1]) for k in range(5)],
-                base=d.sl.base, alt=d.sl.alt, owners=d.sl.owners, ge=list(d.sl.ge), off=list(d.sl.off),
-                alt_off=list(d.sl.alt_off), recs=d.help.recs, wide=d.help.wide, help_bits=d.help.help_bits,
-                wgs=d.wgs, max_bits=d.max_bits, status=d.status)
+
+    def phase(p):
+        return dict(base=p.sl.base, alt=p.sl.alt, owners=p.sl.owners, ge=list(p.sl.ge), off=list(p.sl.off),
+                    alt_off=list(p.sl.alt_off), recs=p.help.recs, wide=p.help.wide, help_bits=p.help.help_bits,
+                    first=p.first, count=p.count, wgs=p.workgroups, max_bits=p.max_bits)
+
+    out = dict(first=list(d.first), range=[(d.range[2 * k], d.range[2 * k + 1]) for k in range(5)],
+               phases=[phase(d.ph[0]), phase(d.ph[1])], wgs=d.wgs, max_bits=d.max_bits, status=d.status)
+    out.update({k: v for k, v in out["phases"][0].items() if k not in ("first", "wgs", "max_bits")})
+    return out
 
 
 def test_device_setup_matches_host_plans(fp):
@@ -174,7 +185,10 @@ def test_device_setup_matches_host_plans(fp):
     ws = fp.workspace(ens, n, C64)
     fp.contract(ens, g, n, C64, ws)
     torch.cuda.synchronize()
-    d = read_setup(ws[1024:1024 + 2048].cpu().numpy().tobytes())
+    d = read_setup(ws[1024:4096].cpu().numpy().tobytes())
+    # one launch of the HBM class: no pair is wider than a compute unit's share of the pool
+    assert d["phases"][1]["count"] == 0 and d["phases"][1]["wgs"] == 0
+    assert d["phases"][0]["first"] == 0 and d["phases"][0]["count"] == int((peaks > 12).sum())
     for b in range(64):
         assert d["first"][b] == int((peaks > b).sum()), b
     bounds = [(-1, -1), (-1, 10), (10, 12), (12, 12), (12, 63)]
@@ -210,3 +224,37 @@ def test_device_setup_matches_host_plans(fp):
         assert d["base"] + 8 * (regions[-1][0] + regions[-1][1]) <= ws_end
     assert d["wide"] == int((peaks >= d["help_bits"]).sum())
     assert d["status"] == 0 and d["wgs"] >= owners
+
+
+def test_device_setup_splits_the_widest_pairs(fp):
+    # n = 50, 250 steps, 2000 pairs in a 48 GiB pool: pairs wider than a
+    # compute unit's share of the pool (2^24 entries on 256 compute units)
+    # form the first launch of the HBM class, the others the second; each
+    # launch's slots fit the pool, and every pair is contracted
+    ens, n, seed = (1, 50, 250), 2000, 4545
+    g = fp.sample(ens, n, seed, 0, C64)
+    # widths from the host planner on the sampled bonds (they follow the
+    # complex64 gates of U and V)
+    S, off = ens[2], 2 * ens[2] * 32 * 4
+    a = g.view(n, -1)[:, off: off + 8 * S].cpu().numpy()
+    peaks = np.array([fp.fp_plan_local_random_host(50, *np.frombuffer(a[i].tobytes(), np.int32).reshape(2, S))
+                      ["peak_bits"] for i in range(n)])
+    ws = fp.workspace(ens, n, C64)
+    tr = fp.contract(ens, g, n, C64, ws).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.isfinite(tr).all()
+    d = read_setup(ws[1024:4096].cpu().numpy().tobytes())
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    pool_entries = d["phases"][0]["base"] and (ws.data_ptr() + ws.numel() - d["phases"][0]["base"]) // 8
+    split = int(np.floor(np.log2(pool_entries // cus)))
+    wide, rest = int((peaks > split).sum()), int(((peaks > 12) & (peaks <= split)).sum())
+    assert wide > 0 and rest > 0, (split, wide, rest)
+    p0, p1 = d["phases"]
+    assert (p0["first"], p0["count"], p1["first"], p1["count"]) == (0, wide, wide, rest)
+    assert p0["max_bits"] == int(peaks.max()) and p1["max_bits"] == int(peaks[peaks <= split].max())
+    assert p1["owners"] > p0["owners"]
+    for p in (p0, p1):
+        assert p["wgs"] >= p["owners"] >= 1
+        total = p["off"][SLOT_TOP] + (p["alt_off"][SLOT_TOP] if p["alt"] else 0)
+        assert total <= pool_entries, (total, pool_entries)
+    assert d["status"] == 0
