@@ -33,8 +33,8 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector, published
 PEAK_HBM_GBS = 8000.0
 SWEEP_CLASSES = ("lds16", "lds64", "lds256", "lds1024", "hbm", "hea")
 # sweep rate assumed when a deep batch is planned: batches at 300 and 350
-# steps ran their HBM-slot sweeps at about 2 TFLOP/s (pairs of 2^34 entries
-# included); the cap takes a quarter of that
+# steps ran their sweeps at 1.4-3.5 TFLOP/s (pairs of 2^34 entries
+# included); the cap assumes 0.5
 DEEP_PLAN_TFLOPS = 0.5
 # kernel of each sweep class for local random batches (names as rocprofv3 shows them)
 LR_KERNELS = {
